@@ -1,0 +1,8 @@
+"""CPU FP64 oracle for SFFT image subtraction -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+may import this package.  The product path (the HIP library and its Python
+binding) never imports, links or calls it, and this package imports nothing
+from the product path.
+"""
+from .sfft_oracle import *  # noqa: F401,F403
