@@ -1,0 +1,138 @@
+/*
+ * sfft.h -- C ABI of the MI355X (gfx950) SFFT image-subtraction library.
+ *
+ * The operation is pipeline step 6 of the phrosty paper ("Pipeline steps":
+ * apply SFFT subtraction to the cross-convolved science/template pair to
+ * produce a difference image), a method that fits a delta-basis matching
+ * kernel able to follow a spatially varying PSF ("Statement of need") by
+ * solving a large linear system ("Future development").  The paper prints
+ * no equations; the library computes exactly the following fit:
+ *
+ *   G    = 1 - [mask != 0]                       good pixels
+ *   G_R  = G * [w <= y < ny-w] * [w <= x < nx-w] template side (w-wide border strip excluded)
+ *   xh   = 2x/(nx-1) - 1, yh = 2y/(ny-1) - 1     frame-centred coordinates
+ *   m_j  = xh^p yh^q, graded by d = p+q then q ascending (1; xh, yh; xh^2, xh yh, yh^2; ...)
+ *   A_a  = m_a G_R R   (a < nK = (DK+1)(DK+2)/2),   S_m = G S
+ *   (T_u X)(y,x) = X(y-u_y, x-u_x) inside the frame, else 0,   u in {-w..w}^2
+ *   theta = argmin || S_m - sum_{a,u} k_{a,u} T_u A_a - sum_b c_b G m_b ||^2
+ *         = Omega^{-1} beta   (normal equations, Cholesky, FP64)
+ *   D = S - sum_{a,u} k_{a,u} T_u(m_a R) - sum_b c_b m_b   (unmasked R, whole frame)
+ *
+ * Coefficient layout (n = L^2 nK + nB, L = 2w+1):
+ *   theta[a*L*L + (u_y+w)*L + (u_x+w)] = k_{a,u},   theta[nK*L*L + b] = c_b.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an int status (SFFT_OK or a negative error code);
+ *     nothing else crosses the ABI.
+ *   - Image, mask, coefficient and output buffers are DEVICE pointers owned
+ *     by the caller, row-major with x fastest and a row pitch `ld` (in
+ *     elements, ld >= nx).  Inputs are never modified.
+ *   - Work is enqueued asynchronously on the plan's HIP stream; buffers must
+ *     stay alive until that stream has drained.  One plan per stream; a plan
+ *     is not thread-safe.
+ *   - Arguments are validated synchronously before anything is enqueued
+ *     (SFFT_EINVAL).  Outcomes only known on the device (a non-positive
+ *     Cholesky pivot, non-finite input) are recorded in device memory,
+ *     LAPACK-style, and read with sfft_status(), which synchronises.
+ */
+#ifndef SFFT_H_
+#define SFFT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SFFT_OK = 0,
+  SFFT_EINVAL = -1,     /* bad descriptor or argument (w<0, DK<0, DB<0, N < 4w+2, N > 4096, NULL) */
+  SFFT_ENOMEM = -2,     /* device allocation failed, or caller workspace too small            */
+  SFFT_EHIP = -3,       /* a HIP runtime call failed                                          */
+  SFFT_ENOTSPD = -4,    /* Omega is not positive definite (sfft_status only)                   */
+  SFFT_ESTATE = -5,     /* call out of order (e.g. solve before build)                         */
+  SFFT_ENONFINITE = -6  /* NaN/Inf in the science or template image (sfft_status only)          */
+};
+
+enum {
+  SFFT_MODE_F64 = 0,    /* images double; FFTs, products and sums in FP64                          */
+  SFFT_MODE_F32C = 1    /* images float; FFTs and spectral products in FP32, lag-window sums in
+                           FP64, Omega stored in FP64; Cholesky, solve and refinement in FP64      */
+};
+
+typedef struct {
+  int32_t ny, nx;        /* frame size, 4w+2 <= ny, nx <= 4096                                 */
+  int32_t w;             /* kernel half-width, L = 2w+1                                       */
+  int32_t dk, db;        /* polynomial degree of the kernel's / background's spatial variation */
+  int32_t mode;          /* SFFT_MODE_F64 or SFFT_MODE_F32C                                    */
+  int32_t refine_steps;  /* iterative-refinement steps after the Cholesky solve; -1 = 1        */
+  int32_t flags;         /* reserved, must be 0                                               */
+} sfft_desc;
+
+typedef struct sfft_plan_s* sfft_handle;
+
+/* n = (2w+1)^2 nK + nB for a valid descriptor.  Host only. */
+int sfft_num_coeffs(const sfft_desc* d, int64_t* n);
+
+/* Device bytes a plan for `d` needs (workspace for spectra, lag windows,
+ * Omega and its factor).  Host only; no device is touched. */
+int sfft_workspace_bytes(const sfft_desc* d, size_t* bytes);
+
+/* Create a plan bound to `hip_stream` (a hipStream_t, NULL = default stream).
+ * `workspace` NULL: the plan allocates (and frees in sfft_destroy) its own
+ * device memory; otherwise it borrows `workspace_bytes` bytes of caller
+ * device memory, which must hold sfft_workspace_bytes() (else SFFT_ENOMEM).
+ * Twiddle tables are computed in FP64 on the host and uploaded. */
+int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t workspace_bytes,
+              sfft_handle* out);
+
+/* Enqueue the assembly of Omega (n x n, FP64, both triangles) and beta (n):
+ * the polynomial-weighted masked planes, their 2-D FFTs, the spectral
+ * products and the pruned inverse transforms that keep only the lag windows
+ * the entries need, and the gather into Omega/beta.
+ * sci/tmpl: double* (F64) or float* (F32C), ny rows of pitch ld.
+ * mask: uint8, nonzero = excluded pixel, pitch ld; NULL = no mask. */
+int sfft_build_system(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask,
+                      int64_t ld);
+
+/* Copy the assembled Omega (row-major n x n) and beta (n) into caller device
+ * buffers (either may be NULL).  Requires a prior build. */
+int sfft_get_system(sfft_handle p, double* omega, double* rhs);
+
+/* Enqueue the FP64 Cholesky factorisation of Omega, the two triangular
+ * solves and refine_steps steps of iterative refinement (residual
+ * beta - Omega theta in FP64).  coeffs: device double[n] output, written
+ * only if the factorisation succeeds.  info: device int32, set to 0 on
+ * success or to k > 0 if the leading minor of order k is not positive
+ * definite (LAPACK potrf convention).  Requires a prior build. */
+int sfft_solve(sfft_handle p, double* coeffs, int32_t* info);
+
+/* rho = ||beta - Omega coeffs||_2 / ||beta||_2 with the assembled system,
+ * written to the device double `rho`.  Requires a prior build. */
+int sfft_residual(sfft_handle p, const double* coeffs, double* rho);
+
+/* Enqueue D = S - sum_{a,u} k_{a,u} T_u(m_a R) - sum_b c_b m_b over the whole
+ * frame with the unmasked template.  sci/tmpl/diff: double* (F64) or
+ * float* (F32C), pitch ld; coeffs: device double[n]. */
+int sfft_subtract(sfft_handle p, const void* sci, const void* tmpl, const double* coeffs,
+                  void* diff, int64_t ld);
+
+/* Synchronise the plan's stream and report device-side outcomes of the
+ * last build/solve: SFFT_ENONFINITE if a non-finite science/template value
+ * was seen, SFFT_ENOTSPD if the last solve hit a non-positive pivot, else
+ * SFFT_OK.  `info_out` / `nonfinite_out` (host, may be NULL) receive the
+ * raw flags. */
+int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out);
+
+/* Release the plan (and its workspace if the plan allocated it). */
+void sfft_destroy(sfft_handle p);
+
+/* Static, human-readable text for a status code. */
+const char* sfft_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFFT_H_ */

@@ -1,0 +1,229 @@
+"""ctypes binding of libsfft.so with the same names as the C ABI (include/sfft.h).
+
+This module only marshals arguments: every step of the subtraction runs in
+the HIP kernels of the library.  Device buffers are torch tensors on the GPU
+(their data pointers are passed through); the HIP stream is torch's current
+stream unless another is given.  If the library has not been built, loading
+fails loudly -- there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libsfft.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sfft.h")
+
+SFFT_OK = 0
+SFFT_EINVAL = -1
+SFFT_ENOMEM = -2
+SFFT_EHIP = -3
+SFFT_ENOTSPD = -4
+SFFT_ESTATE = -5
+SFFT_ENONFINITE = -6
+
+SFFT_MODE_F64 = 0
+SFFT_MODE_F32C = 1
+
+
+class SfftError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+
+
+class sfft_desc(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in
+                ("ny", "nx", "w", "dk", "db", "mode", "refine_steps", "flags")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsfft.so (once).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -m paper_2509_18544_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    D = ctypes.POINTER(sfft_desc)
+    sig = {
+        "sfft_num_coeffs": (ctypes.c_int, [D, ctypes.POINTER(i64)]),
+        "sfft_workspace_bytes": (ctypes.c_int, [D, ctypes.POINTER(sz)]),
+        "sfft_plan": (ctypes.c_int, [D, vp, vp, sz, ctypes.POINTER(vp)]),
+        "sfft_build_system": (ctypes.c_int, [vp, vp, vp, vp, i64]),
+        "sfft_get_system": (ctypes.c_int, [vp, vp, vp]),
+        "sfft_solve": (ctypes.c_int, [vp, vp, vp]),
+        "sfft_residual": (ctypes.c_int, [vp, vp, vp]),
+        "sfft_subtract": (ctypes.c_int, [vp, vp, vp, vp, vp, i64]),
+        "sfft_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "sfft_destroy": (None, [vp]),
+        "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_symbols(path: str = HEADER_PATH):
+    """Names of the functions declared in include/sfft.h."""
+    text = open(path).read()
+    return sorted(set(re.findall(r"\b(sfft_[a-z_0-9]+)\s*\(", text)))
+
+
+def strerror(status: int) -> str:
+    return lib().sfft_strerror(int(status)).decode()
+
+
+def make_desc(ny, nx, w, dk, db, mode=SFFT_MODE_F64, refine_steps=-1, flags=0) -> sfft_desc:
+    return sfft_desc(int(ny), int(nx), int(w), int(dk), int(db), int(mode), int(refine_steps), int(flags))
+
+
+def _check(st, where):
+    if st != SFFT_OK:
+        raise SfftError(st, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def sfft_num_coeffs(desc: sfft_desc) -> int:
+    n = ctypes.c_int64(0)
+    _check(lib().sfft_num_coeffs(ctypes.byref(desc), ctypes.byref(n)), "sfft_num_coeffs")
+    return n.value
+
+
+def sfft_workspace_bytes(desc: sfft_desc) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().sfft_workspace_bytes(ctypes.byref(desc), ctypes.byref(b)), "sfft_workspace_bytes")
+    return b.value
+
+
+def sfft_plan(desc: sfft_desc, stream=None, workspace=None, workspace_bytes: int = 0):
+    """Returns an opaque handle (int).  `stream`: torch.cuda.Stream, raw handle, or None."""
+    h = ctypes.c_void_p(0)
+    s = _stream_handle(stream)
+    _check(lib().sfft_plan(ctypes.byref(desc), s, _ptr(workspace), int(workspace_bytes), ctypes.byref(h)),
+           "sfft_plan")
+    return h.value
+
+
+def sfft_build_system(handle, sci, tmpl, mask, ld: int):
+    _check(lib().sfft_build_system(handle, _ptr(sci), _ptr(tmpl), _ptr(mask), int(ld)), "sfft_build_system")
+
+
+def sfft_get_system(handle, omega, rhs):
+    _check(lib().sfft_get_system(handle, _ptr(omega), _ptr(rhs)), "sfft_get_system")
+
+
+def sfft_solve(handle, coeffs, info):
+    _check(lib().sfft_solve(handle, _ptr(coeffs), _ptr(info)), "sfft_solve")
+
+
+def sfft_residual(handle, coeffs, rho):
+    _check(lib().sfft_residual(handle, _ptr(coeffs), _ptr(rho)), "sfft_residual")
+
+
+def sfft_subtract(handle, sci, tmpl, coeffs, diff, ld: int):
+    _check(lib().sfft_subtract(handle, _ptr(sci), _ptr(tmpl), _ptr(coeffs), _ptr(diff), int(ld)),
+           "sfft_subtract")
+
+
+def sfft_status(handle):
+    """(status, info, nonfinite) after synchronising the plan's stream."""
+    info = ctypes.c_int32(0)
+    nf = ctypes.c_int32(0)
+    st = lib().sfft_status(handle, ctypes.byref(info), ctypes.byref(nf))
+    return st, info.value, nf.value
+
+
+def sfft_destroy(handle):
+    if handle:
+        lib().sfft_destroy(handle)
+
+
+def sfft_strerror(status: int) -> str:
+    return strerror(status)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Plan:
+    """Owning wrapper: one plan on one stream, buffers as torch tensors."""
+
+    def __init__(self, ny, nx, w, dk, db, mode=SFFT_MODE_F64, refine_steps=-1, stream=None):
+        import torch
+        self.desc = make_desc(ny, nx, w, dk, db, mode, refine_steps)
+        self.n = sfft_num_coeffs(self.desc)
+        self.mode = mode
+        self.dtype = torch.float64 if mode == SFFT_MODE_F64 else torch.float32
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = sfft_plan(self.desc, self.stream)
+
+    def build(self, sci, tmpl, mask=None):
+        ld = sci.stride(0)
+        sfft_build_system(self.handle, sci, tmpl, mask, ld)
+
+    def system(self):
+        import torch
+        om = torch.empty((self.n, self.n), dtype=torch.float64, device="cuda")
+        be = torch.empty((self.n,), dtype=torch.float64, device="cuda")
+        sfft_get_system(self.handle, om, be)
+        return om, be
+
+    def solve(self, coeffs=None, info=None):
+        import torch
+        if coeffs is None:
+            coeffs = torch.zeros((self.n,), dtype=torch.float64, device="cuda")
+        if info is None:
+            info = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        sfft_solve(self.handle, coeffs, info)
+        return coeffs, info
+
+    def residual(self, coeffs):
+        import torch
+        rho = torch.zeros((1,), dtype=torch.float64, device="cuda")
+        sfft_residual(self.handle, coeffs, rho)
+        return rho
+
+    def subtract(self, sci, tmpl, coeffs, diff=None):
+        import torch
+        if diff is None:
+            diff = torch.empty_like(sci)
+        sfft_subtract(self.handle, sci, tmpl, coeffs, diff, sci.stride(0))
+        return diff
+
+    def status(self):
+        return sfft_status(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            sfft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

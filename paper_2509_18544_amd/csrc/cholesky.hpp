@@ -1,0 +1,333 @@
+// FP64 solve of the normal equations: blocked right-looking Cholesky
+// Omega = L L^T, triangular solves, iterative refinement, residual norm.
+//
+// The factor F is a row-major n x n copy of Omega; only its lower triangle is
+// read or written meaningfully.  Block size NB = 64.  Step k of the
+// factorisation is three launches:
+//   potrf_diag : factor the diagonal block in LDS and store its inverse
+//                (Linv[k], 64 x 64) for the panel solve and the substitutions;
+//   trsm       : L_ik = A_ik L_kk^{-T} for every row block i below;
+//   syrk       : A_ij -= L_ik L_jk^T for every lower tile (i >= j) of the rest.
+// A non-positive (or non-finite) pivot sets *info = global column + 1 and all
+// later kernels return immediately (LAPACK potrf convention).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfft {
+
+constexpr int NB = 64;
+
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ F, int n, int k0,
+                                                         double* __restrict__ Linv, int* __restrict__ info) {
+  __shared__ double A[NB][NB + 1];
+  __shared__ double X[NB][NB + 1];
+  __shared__ int fail;
+  if (*info != 0) return;
+  const int tid = threadIdx.x;
+  const int nb = min(NB, n - k0);
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    A[i][j] = (i < nb && j < nb && j <= i) ? F[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
+    X[i][j] = 0.0;
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double d = A[j][j];
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0) {
+        fail = 1;
+        *info = k0 + j + 1;
+      }
+    }
+    __syncthreads();
+    if (fail) return;
+    const double s = sqrt(d);
+    __syncthreads();
+    if (tid == 0) A[j][j] = s;
+    for (int i = j + 1 + tid; i < nb; i += 256) A[i][j] /= s;
+    __syncthreads();
+    // trailing update of the block: A[i][l] -= A[i][j] A[l][j], j < l <= i
+    const int m = nb - j - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = j + 1 + e / m;
+      const int l = j + 1 + e % m;
+      if (l <= i) A[i][l] -= A[i][j] * A[l][j];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular block, one column per thread
+  if (tid < nb) {
+    const int c = tid;
+    X[c][c] = 1.0 / A[c][c];
+    for (int i = c + 1; i < nb; ++i) {
+      double acc = 0.0;
+      for (int k = c; k < i; ++k) acc += A[i][k] * X[k][c];
+      X[i][c] = -acc / A[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    if (i < nb && j <= i) F[(int64_t)(k0 + i) * n + k0 + j] = A[i][j];
+    Linv[e] = (i < nb && j < nb) ? X[i][j] : 0.0;
+  }
+}
+
+// Row block bi (after block k): L = A Linv^T, 64 x 64 x 64 in LDS.
+__global__ __launch_bounds__(256) void trsm_kernel(double* __restrict__ F, int n, int k0,
+                                                   const double* __restrict__ Linv, const int* __restrict__ info) {
+  __shared__ double A[NB][NB + 1];
+  __shared__ double B[NB][NB + 1];
+  if (*info != 0) return;
+  const int tid = threadIdx.x;
+  const int nb = min(NB, n - k0);
+  const int r0 = k0 + NB + blockIdx.x * NB;
+  const int nr = min(NB, n - r0);
+  if (nr <= 0) return;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    A[i][j] = (i < nr && j < nb) ? F[(int64_t)(r0 + i) * n + k0 + j] : 0.0;
+    B[i][j] = Linv[e];
+  }
+  __syncthreads();
+  // each thread: rows 4*ty + {0..3}, columns tx + 16*{0..3}
+  const int ty = tid / 16, tx = tid % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int m = 0; m < NB; ++m) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = A[4 * ty + a][m];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = B[tx + 16 * b][m];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = 4 * ty + a, j = tx + 16 * b;
+      if (i < nr && j < nb) F[(int64_t)(r0 + i) * n + k0 + j] = acc[a][b];
+    }
+}
+
+// Lower tiles (I >= J) of the trailing matrix: A_IJ -= L_I L_J^T.
+__global__ __launch_bounds__(256) void syrk_kernel(double* __restrict__ F, int n, int k0,
+                                                   const int* __restrict__ info) {
+  __shared__ double A[NB][NB + 1];
+  __shared__ double B[NB][NB + 1];
+  if (*info != 0) return;
+  const int tid = threadIdx.x;
+  const int nb = min(NB, n - k0);
+  const int t0 = k0 + NB;  // first trailing row
+  // triangular tile enumeration: blockIdx.x = I (I+1)/2 + J
+  const int b = blockIdx.x;
+  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= b) ++I;
+  while (I * (I + 1) / 2 > b) --I;
+  const int J = b - I * (I + 1) / 2;
+  const int ri = t0 + I * NB, rj = t0 + J * NB;
+  const int ni = min(NB, n - ri), nj = min(NB, n - rj);
+  if (ni <= 0 || nj <= 0) return;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, m = e % NB;
+    A[i][m] = (i < ni && m < nb) ? F[(int64_t)(ri + i) * n + k0 + m] : 0.0;
+    B[i][m] = (i < nj && m < nb) ? F[(int64_t)(rj + i) * n + k0 + m] : 0.0;
+  }
+  __syncthreads();
+  const int ty = tid / 16, tx = tid % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  for (int m = 0; m < NB; ++m) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = A[4 * ty + a][m];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bv[c] = B[tx + 16 * c][m];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = 4 * ty + a, j = tx + 16 * c;
+      if (i < ni && j < nj && (I != J || j <= i)) F[(int64_t)(ri + i) * n + rj + j] -= acc[a][c];
+    }
+}
+
+// Forward substitution L y = b (single block, 1024 threads).  The solution
+// vector lives in LDS (dynamic, n doubles) so that values written by one
+// thread are read by the others without a trip through the caches.
+__global__ __launch_bounds__(1024) void trsv_lower_kernel(const double* __restrict__ F, int n,
+                                                          const double* __restrict__ Linv,
+                                                          const double* __restrict__ b, double* __restrict__ y,
+                                                          const int* __restrict__ info) {
+  extern __shared__ double ys[];
+  __shared__ double part[NB][17];
+  __shared__ double rhs[NB];
+  if (*info != 0) return;
+  const int tid = threadIdx.x;
+  const int r = tid >> 4;       // row within the block (0..63)
+  const int sl = tid & 15;      // slice of the columns
+  const int nblk = (n + NB - 1) / NB;
+  for (int k = 0; k < nblk; ++k) {
+    const int k0 = k * NB;
+    const int nb = min(NB, n - k0);
+    double acc = 0.0;
+    if (r < nb) {
+      const double* row = F + (int64_t)(k0 + r) * n;
+      for (int c = sl; c < k0; c += 16) acc += row[c] * ys[c];
+    }
+    part[r][sl] = acc;
+    __syncthreads();
+    if (tid < NB) {
+      double s = 0.0;
+      for (int q = 0; q < 16; ++q) s += part[tid][q];
+      rhs[tid] = (tid < nb) ? b[k0 + tid] - s : 0.0;
+    }
+    __syncthreads();
+    // y_k = Linv_k rhs   (Linv lower triangular)
+    {
+      const double* Li = Linv + (int64_t)k * NB * NB;
+      double a2 = 0.0;
+      if (r < nb) {
+        for (int m = sl; m <= r; m += 16) a2 += Li[r * NB + m] * rhs[m];
+      }
+      part[r][sl] = a2;
+    }
+    __syncthreads();
+    if (tid < nb) {
+      double s = 0.0;
+      for (int q = 0; q < 16; ++q) s += part[tid][q];
+      ys[k0 + tid] = s;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += 1024) y[i] = ys[i];
+}
+
+// Back substitution L^T x = y (single block, 1024 threads), x in LDS.
+__global__ __launch_bounds__(1024) void trsv_upper_kernel(const double* __restrict__ F, int n,
+                                                          const double* __restrict__ Linv,
+                                                          const double* __restrict__ y, double* __restrict__ x,
+                                                          const int* __restrict__ info) {
+  extern __shared__ double xs[];
+  __shared__ double part[16][NB + 1];
+  __shared__ double rhs[NB];
+  if (*info != 0) return;
+  const int tid = threadIdx.x;
+  const int c = tid & (NB - 1);   // column within the block
+  const int rs = tid >> 6;        // row slice 0..15
+  const int nblk = (n + NB - 1) / NB;
+  for (int k = nblk - 1; k >= 0; --k) {
+    const int k0 = k * NB;
+    const int nb = min(NB, n - k0);
+    const int rstart = k0 + nb;
+    double acc = 0.0;
+    if (c < nb) {
+      for (int rr = rstart + rs; rr < n; rr += 16) acc += F[(int64_t)rr * n + k0 + c] * xs[rr];
+    }
+    part[rs][c] = acc;
+    __syncthreads();
+    if (tid < NB) {
+      double s = 0.0;
+      for (int q = 0; q < 16; ++q) s += part[q][tid];
+      rhs[tid] = (tid < nb) ? y[k0 + tid] - s : 0.0;
+    }
+    __syncthreads();
+    // x_k = Linv_k^T rhs: x[c] = sum_{m >= c} Linv[m][c] rhs[m]
+    {
+      const double* Li = Linv + (int64_t)k * NB * NB;
+      double a2 = 0.0;
+      if (c < nb) {
+        for (int m = c + rs; m < nb; m += 16) a2 += Li[m * NB + c] * rhs[m];
+      }
+      part[rs][c] = a2;
+    }
+    __syncthreads();
+    if (tid < nb) {
+      double s = 0.0;
+      for (int q = 0; q < 16; ++q) s += part[q][tid];
+      xs[k0 + tid] = s;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += 1024) x[i] = xs[i];
+}
+
+// r = b - A x   (A row-major n x n; one wave per row)
+__global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ A, int n,
+                                                       const double* __restrict__ b, const double* __restrict__ x,
+                                                       double* __restrict__ r) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + wave;
+  if (row >= n) return;
+  const double* a = A + (int64_t)row * n;
+  double acc = 0.0;
+  for (int c = lane; c < n; c += 64) acc += a[c] * x[c];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) r[row] = b[row] - acc;
+}
+
+// x += d (only if the factorisation succeeded)
+__global__ void axpy_kernel(double* __restrict__ x, const double* __restrict__ d, int n,
+                            const int* __restrict__ info) {
+  if (*info != 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += d[i];
+}
+
+__global__ void copy_out_kernel(const double* __restrict__ src, double* __restrict__ dst, int n,
+                                const int* __restrict__ info, int* __restrict__ info_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int inf = *info;
+  if (i == 0 && info_out != nullptr) *info_out = inf;
+  if (inf != 0) return;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// rho = ||r|| / ||b|| (single block)
+__global__ __launch_bounds__(256) void norm_ratio_kernel(const double* __restrict__ r,
+                                                         const double* __restrict__ b, int n,
+                                                         double* __restrict__ rho) {
+  __shared__ double s1[256], s2[256];
+  const int tid = threadIdx.x;
+  double a = 0.0, c = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    a += r[i] * r[i];
+    c += b[i] * b[i];
+  }
+  s1[tid] = a;
+  s2[tid] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      s1[tid] += s1[tid + s];
+      s2[tid] += s2[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *rho = (s2[0] > 0.0) ? sqrt(s1[0] / s2[0]) : sqrt(s1[0]);
+}
+
+}  // namespace sfft

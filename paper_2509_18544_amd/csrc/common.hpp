@@ -1,0 +1,250 @@
+// Device-side building blocks shared by the SFFT kernels (gfx950, wave64).
+//
+//  * cplx<T>     -- complex value of float or double with the few operations
+//                   the transforms need.
+//  * dft2/4/8/16 -- in-register DFTs of size 2..16 (forward: exp(-2 pi i jk/R),
+//                   inverse: exp(+2 pi i jk/R), unnormalised).
+//  * stockham_pass -- one radix-R pass of a self-sorting (Stockham) FFT on a
+//                   batch of power-of-two transforms held in LDS, staged
+//                   through registers so that it runs in place.
+//
+// Twiddle factors come from a table tw[m] = exp(-2 pi i m / TW_N) computed in
+// FP64 on the host and rounded once to T; the inverse direction conjugates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfft {
+
+constexpr int TW_LOG = 12;            // twiddle table length 4096 = largest FFT size
+constexpr int TW_N = 1 << TW_LOG;
+constexpr int MAX_LOG_P = 12;         // frames up to 4096 pixels per side
+constexpr int MIN_LOG_P = 6;          // FFT sizes are at least 64
+
+template <typename T>
+struct cplx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> mk(T a, T b) {
+  cplx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> scale(cplx<T> a, T s) { return mk(a.x * s, a.y * s); }
+template <typename T>
+__device__ __forceinline__ cplx<T> conjg(cplx<T> a) { return mk(a.x, -a.y); }
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+// multiply by -i (forward quarter turn) or +i (inverse quarter turn)
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> rot90(cplx<T> a) {
+  return INV ? mk(-a.y, a.x) : mk(a.y, -a.x);
+}
+// twiddle exp(-+2 pi i m / TW_N) from the forward table
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> twid(const cplx<T>* __restrict__ tw, int m) {
+  cplx<T> t = tw[m & (TW_N - 1)];
+  return INV ? conjg(t) : t;
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers
+// ---------------------------------------------------------------------------
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cplx<T>* v) {
+  cplx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx<T>& a3) {
+  cplx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<T, INV>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cplx<T>* v) { dft4<T, INV>(v[0], v[1], v[2], v[3]); }
+
+// multiply by exp(-+2 pi i k / 8) for k = 1, 2, 3
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> w8_1(cplx<T> a) {
+  const T r = (T)0.70710678118654752440;
+  // forward: (1 - i)/sqrt2 ; inverse: (1 + i)/sqrt2
+  return INV ? mk(r * (a.x - a.y), r * (a.x + a.y)) : mk(r * (a.x + a.y), r * (a.y - a.x));
+}
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> w8_3(cplx<T> a) {
+  const T r = (T)0.70710678118654752440;
+  // forward: (-1 - i)/sqrt2 ; inverse: (-1 + i)/sqrt2
+  return INV ? mk(-r * (a.x + a.y), r * (a.x - a.y)) : mk(r * (a.y - a.x), -r * (a.x + a.y));
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cplx<T>* v) {
+  cplx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cplx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<T, INV>(e0, e1, e2, e3);
+  dft4<T, INV>(o0, o1, o2, o3);
+  o1 = w8_1<T, INV>(o1);
+  o2 = rot90<T, INV>(o2);
+  o3 = w8_3<T, INV>(o3);
+  v[0] = e0 + o0;
+  v[4] = e0 - o0;
+  v[1] = e1 + o1;
+  v[5] = e1 - o1;
+  v[2] = e2 + o2;
+  v[6] = e2 - o2;
+  v[3] = e3 + o3;
+  v[7] = e3 - o3;
+}
+
+// 16-point DFT as 4 x 4: DFT4 over stride-4 subsequences, twiddle w16^(m k1), DFT4 over m.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cplx<T>* v) {
+  const T c1 = (T)0.92387953251128675613;  // cos(pi/8)
+  const T s1 = (T)0.38268343236508977173;  // sin(pi/8)
+  const T r = (T)0.70710678118654752440;
+  cplx<T> d[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    d[m][0] = v[m];
+    d[m][1] = v[m + 4];
+    d[m][2] = v[m + 8];
+    d[m][3] = v[m + 12];
+    dft4<T, INV>(d[m][0], d[m][1], d[m][2], d[m][3]);
+  }
+  // twiddles w16^(m*k1), w16 = exp(-+ 2 pi i / 16)
+  const T sg = INV ? (T)1 : (T)-1;
+  // m = 1: k1 = 1, 2, 3 -> w^1, w^2, w^3
+  d[1][1] = d[1][1] * mk(c1, sg * s1);
+  d[1][2] = d[1][2] * mk(r, sg * r);
+  d[1][3] = d[1][3] * mk(s1, sg * c1);
+  // m = 2: w^2, w^4, w^6
+  d[2][1] = d[2][1] * mk(r, sg * r);
+  d[2][2] = rot90<T, INV>(d[2][2]);
+  d[2][3] = d[2][3] * mk(-r, sg * r);
+  // m = 3: w^3, w^6, w^9
+  d[3][1] = d[3][1] * mk(s1, sg * c1);
+  d[3][2] = d[3][2] * mk(-r, sg * r);
+  d[3][3] = d[3][3] * mk(-c1, -sg * s1);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cplx<T> a0 = d[0][k1], a1 = d[1][k1], a2 = d[2][k1], a3 = d[3][k1];
+    dft4<T, INV>(a0, a1, a2, a3);
+    v[k1] = a0;
+    v[k1 + 4] = a1;
+    v[k1 + 8] = a2;
+    v[k1 + 12] = a3;
+  }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(cplx<T>* v) {
+  if constexpr (R == 2) dft2<T, INV>(v);
+  else if constexpr (R == 4) dft4<T, INV>(v);
+  else if constexpr (R == 8) dft8<T, INV>(v);
+  else dft16<T, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// Stockham pass in LDS
+// ---------------------------------------------------------------------------
+//
+// `batch` transforms of length N = 2^lgN start at buf + b * bstride.  Before
+// the pass the data is the result of the previous passes whose radices
+// multiply to Ns (Ns = 1 before the first pass).  Butterfly j (0 <= j < N/R)
+// reads x[j + r N/R], twiddles element r by w_{Ns R}^{r k} with k = j mod Ns,
+// applies the R-point DFT and writes element r to (j - k) R + k + r Ns.  After
+// the last pass the data is the DFT in natural order.  Every thread stages
+// its butterflies in registers, so the caller must guarantee
+// N/R * batch <= nthreads * ITEMS, and the pass ends with a barrier.
+template <typename T, int R, int ITEMS, bool INV>
+__device__ __forceinline__ void stockham_pass(cplx<T>* buf, int lgN, int batch, int bstride, int lgNs,
+                                              const cplx<T>* __restrict__ tw, int tid, int nthreads) {
+  const int lgR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  const int lgM = lgN - lgR;
+  const int M = 1 << lgM;
+  const int all = M * batch;
+  const int Ns = 1 << lgNs;
+  // twiddle stride in the 4096 table for w_{Ns R}: TW_N / (Ns R)
+  const int tws = TW_LOG - (lgNs + lgR);
+  cplx<T> v[ITEMS][R];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const int j = tid + it * nthreads;
+    if (j < all) {
+      const int b = j >> lgM;
+      const int jj = j & (M - 1);
+      const int k = jj & (Ns - 1);
+      const cplx<T>* src = buf + (size_t)b * bstride + jj;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = src[r << lgM];
+      if (lgNs > 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[it][r] = v[it][r] * twid<T, INV>(tw, (r * k) << tws);
+      }
+      dftR<T, R, INV>(v[it]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const int j = tid + it * nthreads;
+    if (j < all) {
+      const int b = j >> lgM;
+      const int jj = j & (M - 1);
+      const int k = jj & (Ns - 1);
+      cplx<T>* dst = buf + (size_t)b * bstride + ((jj - k) << lgR) + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r << lgNs] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full FFT of `batch` transforms of length 2^lgN in LDS: radix-16 passes,
+// then one radix-8/4/2 pass for the remaining bits.  NMAX bounds N * batch,
+// THREADS is the block size (both compile-time, to size the register staging).
+template <typename T, int NMAX, int THREADS, bool INV>
+__device__ void fft_lds(cplx<T>* buf, int lgN, int batch, int bstride, const cplx<T>* __restrict__ tw) {
+  const int tid = threadIdx.x;
+  int lgNs = 0;
+  int rem = lgN;
+  while (rem >= 4) {
+    stockham_pass<T, 16, (NMAX / 16 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid,
+                                                                  THREADS);
+    lgNs += 4;
+    rem -= 4;
+  }
+  if (rem == 3)
+    stockham_pass<T, 8, (NMAX / 8 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid, THREADS);
+  else if (rem == 2)
+    stockham_pass<T, 4, (NMAX / 4 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid, THREADS);
+  else if (rem == 1)
+    stockham_pass<T, 2, (NMAX / 2 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid, THREADS);
+}
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+}  // namespace sfft

@@ -1,0 +1,613 @@
+// Host runtime and C ABI of the SFFT subtraction library (see include/sfft.h).
+//
+// A plan owns (or borrows) one workspace carved into the buffers below and a
+// HIP stream on which every call enqueues its kernels; no call synchronises
+// except sfft_status().
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <algorithm>
+#include <vector>
+
+#include "../../include/sfft.h"
+#include "assemble.hpp"
+#include "cholesky.hpp"
+#include "common.hpp"
+#include "subtract.hpp"
+
+using namespace sfft;
+
+namespace {
+
+constexpr int ASM_THREADS = 256;
+constexpr int ROW_NMAX_F32 = 16384;   // complex elements in the row-pass LDS buffer (128 KB)
+constexpr int ROW_NMAX_F64 = 8192;    // 128 KB
+constexpr int COL_NMAX = 4096;        // complex elements per column-pass block
+constexpr int MAX_ROWS_PER_BLOCK = 64;
+constexpr int WIN_THREADS = 64;
+constexpr int WIN_IMAX = 64;
+constexpr int MAX_N = 8192;           // unknowns (the triangular solves keep x in LDS)
+constexpr int MAX_W = 15;
+
+struct Layout {
+  size_t U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, kp, flags, tw32, tw64, items, wrows;
+  size_t total;
+};
+
+struct Derived {
+  int ny, nx, w, dk, db, mode, refine;
+  int L, nk, nb, nkk, n;
+  int lgPy, lgPx, Py, Px, H;
+  int nplanes;
+  int rows_per_block, nrowblk;
+  int nmom;
+  int nitems, vrows, nwin, nblk;
+  size_t csize;   // sizeof complex element of the transforms
+  std::vector<CorrItem> items;
+  std::vector<WinRow> wrows;
+  GatherParams gp;
+  PolyTab kpoly, bpoly;
+};
+
+int ilog2_ceil(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+void monomial_table(int deg, PolyTab* t) {
+  int j = 0;
+  std::memset(t, 0, sizeof(*t));
+  for (int d = 0; d <= deg; ++d)
+    for (int q = 0; q <= d; ++q) {
+      t->px[j] = (int8_t)(d - q);
+      t->qy[j] = (int8_t)q;
+      ++j;
+    }
+}
+
+int validate(const sfft_desc* d) {
+  if (d == nullptr) return SFFT_EINVAL;
+  if (d->w < 0 || d->w > MAX_W) return SFFT_EINVAL;
+  if (d->dk < 0 || d->dk > MAX_DEG || d->db < 0 || d->db > MAX_DEG) return SFFT_EINVAL;
+  if (d->ny < 4 * d->w + 2 || d->nx < 4 * d->w + 2) return SFFT_EINVAL;
+  if (d->ny < 2 || d->nx < 2) return SFFT_EINVAL;
+  if (d->ny > (1 << MAX_LOG_P) || d->nx > (1 << MAX_LOG_P)) return SFFT_EINVAL;
+  if (d->mode != SFFT_MODE_F64 && d->mode != SFFT_MODE_F32C) return SFFT_EINVAL;
+  if (d->refine_steps < -1 || d->refine_steps > 10) return SFFT_EINVAL;
+  if (d->flags != 0) return SFFT_EINVAL;
+  const int L = 2 * d->w + 1;
+  const int nk = (d->dk + 1) * (d->dk + 2) / 2, nb = (d->db + 1) * (d->db + 2) / 2;
+  const int64_t n = (int64_t)L * L * nk + nb;
+  if (n > MAX_N) return SFFT_EINVAL;
+  return SFFT_OK;
+}
+
+// Everything about a plan that depends only on the descriptor.
+int derive(const sfft_desc* d, Derived* D) {
+  int st = validate(d);
+  if (st != SFFT_OK) return st;
+  D->ny = d->ny;
+  D->nx = d->nx;
+  D->w = d->w;
+  D->dk = d->dk;
+  D->db = d->db;
+  D->mode = d->mode;
+  D->refine = d->refine_steps < 0 ? 1 : d->refine_steps;
+  D->L = 2 * d->w + 1;
+  D->nk = (d->dk + 1) * (d->dk + 2) / 2;
+  D->nb = (d->db + 1) * (d->db + 2) / 2;
+  D->nkk = D->L * D->L * D->nk;
+  D->n = D->nkk + D->nb;
+  D->lgPy = std::max(MIN_LOG_P, ilog2_ceil(d->ny));
+  D->lgPx = std::max(MIN_LOG_P, ilog2_ceil(d->nx));
+  D->Py = 1 << D->lgPy;
+  D->Px = 1 << D->lgPx;
+  D->H = D->Px / 2;
+  D->nplanes = D->nk + D->nb + 1;
+  D->csize = d->mode == SFFT_MODE_F64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
+  const int rowmax = d->mode == SFFT_MODE_F64 ? ROW_NMAX_F64 : ROW_NMAX_F32;
+  D->rows_per_block = std::min(MAX_ROWS_PER_BLOCK, std::min(rowmax / D->H, d->ny));
+  D->nrowblk = (d->ny + D->rows_per_block - 1) / D->rows_per_block;
+  D->nmom = (2 * d->db + 1) + (d->db + 1);
+  D->nblk = (D->n + NB - 1) / NB;
+  monomial_table(d->dk, &D->kpoly);
+  monomial_table(d->db, &D->bpoly);
+
+  // correlation pairs -> items (lag rows in chunks of JMAX), window rows, gather offsets
+  D->items.clear();
+  D->wrows.clear();
+  std::memset(&D->gp, 0, sizeof(D->gp));
+  int vrow = 0, wo = 0;
+  auto add_pair = [&](int left, int right, int hw) {
+    const int h = 2 * hw + 1;
+    for (int j = -hw; j <= hw; j += JMAX) {
+      CorrItem it;
+      it.left = (int16_t)left;
+      it.right = (int16_t)right;
+      it.jlo = (int16_t)j;
+      it.nj = (int16_t)std::min(JMAX, hw - j + 1);
+      it.vrow = vrow + (j + hw);
+      D->items.push_back(it);
+    }
+    for (int j = 0; j < h; ++j) {
+      WinRow r;
+      r.vrow = vrow + j;
+      r.out = wo + j * h;
+      r.hw = hw;
+      D->wrows.push_back(r);
+    }
+    const int off = wo;
+    vrow += h;
+    wo += h * h;
+    return off;
+  };
+  const int w = d->w;
+  for (int a = 0; a < D->nk; ++a)
+    for (int b = a; b < D->nk; ++b) D->gp.kk_off[a * D->nk + b] = add_pair(a, b, 2 * w);
+  for (int a = 0; a < D->nk; ++a)
+    for (int b = 0; b < D->nb; ++b) D->gp.kb_off[a * D->nb + b] = add_pair(a, D->nk + b, w);
+  for (int a = 0; a < D->nk; ++a) D->gp.ks_off[a] = add_pair(a, D->nk + D->nb, w);
+  D->nitems = (int)D->items.size();
+  D->vrows = vrow;
+  D->nwin = wo;
+  if (D->nitems > MAX_ITEMS) return SFFT_EINVAL;
+  D->gp.n = D->n;
+  D->gp.nkk = D->nkk;
+  D->gp.L = D->L;
+  D->gp.w = w;
+  D->gp.nk = D->nk;
+  D->gp.nb = D->nb;
+  return SFFT_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout layout_of(const Derived& D) {
+  Layout Lo;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  Lo.U = take((size_t)D.nplanes * (D.H + 1) * D.Py * D.csize);
+  Lo.V = take((size_t)(D.H + 1) * D.vrows * sizeof(cplx<double>));
+  Lo.win = take((size_t)D.nwin * sizeof(double));
+  Lo.mom = take((size_t)D.ny * D.nmom * sizeof(double));
+  Lo.obb = take((size_t)D.nb * D.nb * sizeof(double));
+  Lo.bb = take((size_t)D.nb * sizeof(double));
+  Lo.omega = take((size_t)D.n * D.n * sizeof(double));
+  Lo.beta = take((size_t)D.n * sizeof(double));
+  Lo.F = take((size_t)D.n * D.n * sizeof(double));
+  Lo.Linv = take((size_t)D.nblk * NB * NB * sizeof(double));
+  Lo.theta = take((size_t)D.n * sizeof(double));
+  Lo.y = take((size_t)D.n * sizeof(double));
+  Lo.r = take((size_t)D.n * sizeof(double));
+  Lo.d = take((size_t)D.n * sizeof(double));
+  Lo.kp = take((size_t)D.nk * D.L * D.L * sizeof(double));
+  Lo.flags = take(2 * sizeof(int));
+  Lo.tw32 = take((size_t)TW_N * sizeof(cplx<float>));
+  Lo.tw64 = take((size_t)TW_N * sizeof(cplx<double>));
+  Lo.items = take((size_t)D.nitems * sizeof(CorrItem));
+  Lo.wrows = take((size_t)D.wrows.size() * sizeof(WinRow));
+  Lo.total = off;
+  return Lo;
+}
+
+// exp(-2 pi i m / TW_N) in FP64, from long-double sin/cos on the first octant
+// and exact symmetries elsewhere.
+void twiddle_tables(std::vector<cplx<double>>* t64, std::vector<cplx<float>>* t32) {
+  t64->resize(TW_N);
+  t32->resize(TW_N);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int m = 0; m < TW_N; ++m) {
+    // angle = 2 pi m / N; reduce to [0, pi/4] by octant symmetry
+    const int oct = m / (TW_N / 8);
+    const int r = m % (TW_N / 8);
+    long double c, s;
+    auto cs = [&](int k, long double* co, long double* si) {
+      const long double a = 2.0L * pi * (long double)k / (long double)TW_N;
+      *co = cosl(a);
+      *si = sinl(a);
+    };
+    long double c0, s0, c1, s1;
+    cs(r, &c0, &s0);                       // angle r
+    cs(TW_N / 8 - r, &c1, &s1);            // angle pi/4 - r (complement inside the octant)
+    switch (oct) {
+      case 0: c = c0; s = s0; break;                       // theta
+      case 1: c = s1; s = c1; break;                       // pi/2 - (pi/4 - r') = pi/4 + r
+      case 2: c = -s0; s = c0; break;                      // pi/2 + r
+      case 3: c = -c1; s = s1; break;                      // pi - (pi/4 - r)
+      case 4: c = -c0; s = -s0; break;                     // pi + r
+      case 5: c = -s1; s = -c1; break;                     // 3pi/2 - (pi/4 - r)
+      case 6: c = s0; s = -c0; break;                      // 3pi/2 + r
+      default: c = c1; s = -s1; break;                     // 2pi - (pi/4 - r)
+    }
+    (*t64)[m].x = (double)c;
+    (*t64)[m].y = -(double)s;   // forward sign
+    (*t32)[m].x = (float)(*t64)[m].x;
+    (*t32)[m].y = (float)(*t64)[m].y;
+  }
+}
+
+}  // namespace
+
+struct sfft_plan_s {
+  sfft_desc desc;
+  Derived D;
+  Layout Lo;
+  hipStream_t stream;
+  unsigned char* ws;
+  bool owns_ws;
+  bool built;
+  std::vector<cplx<double>> tw64h;
+  std::vector<cplx<float>> tw32h;
+  template <typename X>
+  X* at(size_t off) const {
+    return reinterpret_cast<X*>(ws + off);
+  }
+};
+
+#define HIP_TRY(expr)                       \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return SFFT_EHIP; \
+  } while (0)
+
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+namespace {
+
+AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
+  const Derived& D = p->D;
+  AsmParams A;
+  std::memset(&A, 0, sizeof(A));
+  A.ny = D.ny;
+  A.nx = D.nx;
+  A.w = D.w;
+  A.nk = D.nk;
+  A.nb = D.nb;
+  A.nplanes = D.nplanes;
+  A.lgPy = D.lgPy;
+  A.lgPx = D.lgPx;
+  A.H = D.H;
+  A.ld = ld;
+  A.rows_per_block = D.rows_per_block;
+  A.nrowblk = D.nrowblk;
+  A.nitems = D.nitems;
+  A.vrows = D.vrows;
+  A.kpoly = D.kpoly;
+  A.bpoly = D.bpoly;
+  A.nmom = D.nmom;
+  A.db = D.db;
+  return A;
+}
+
+template <typename T>
+int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask, int64_t ld) {
+  const Derived& D = p->D;
+  const Layout& Lo = p->Lo;
+  hipStream_t s = p->stream;
+  const AsmParams A = asm_params(p, ld);
+  cplx<T>* U = p->at<cplx<T>>(Lo.U);
+  const cplx<T>* tw = std::is_same<T, float>::value ? reinterpret_cast<const cplx<T>*>(p->at<cplx<float>>(Lo.tw32))
+                                                     : reinterpret_cast<const cplx<T>*>(p->at<cplx<double>>(Lo.tw64));
+  const cplx<double>* twd = p->at<cplx<double>>(Lo.tw64);
+  int* flags = p->at<int>(Lo.flags);
+
+  set_int_kernel<<<1, 64, 0, s>>>(flags + 1, 0);
+  LAUNCH_CHECK();
+  moments_kernel<T, ASM_THREADS><<<D.ny, ASM_THREADS, 0, s>>>(A, sci, tmpl, mask, p->at<double>(Lo.mom), flags + 1);
+  LAUNCH_CHECK();
+
+  constexpr int RN = std::is_same<T, float>::value ? ROW_NMAX_F32 : ROW_NMAX_F64;
+  {
+    const size_t lds = (size_t)D.rows_per_block * D.H * sizeof(cplx<T>);
+    auto kfn = row_fwd_kernel<T, ASM_THREADS, RN>;
+    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int grid = ((D.nrowblk + 7) / 8) * 8;   // whole XCD rounds for the remap
+    kfn<<<grid, ASM_THREADS, lds, s>>>(A, sci, tmpl, mask, U, tw);
+    LAUNCH_CHECK();
+  }
+  {
+    const int cpb = std::max(1, COL_NMAX / D.Py);
+    const size_t lds = (size_t)cpb * D.Py * sizeof(cplx<T>);
+    auto kfn = col_fwd_kernel<T, ASM_THREADS, COL_NMAX>;
+    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    dim3 grid((D.H + cpb - 1) / cpb, D.nplanes);
+    kfn<<<grid, ASM_THREADS, lds, s>>>(A, U, tw, cpb);
+    LAUNCH_CHECK();
+  }
+  {
+    const int P1 = D.Py / P2;
+    const size_t per_res = (size_t)D.nplanes * P2 * sizeof(cplx<T>);
+    int C1 = (int)std::min<size_t>((size_t)P1, (64 * 1024) / per_res);
+    C1 = std::max(C1, 1);
+    const size_t stage = (size_t)C1 * per_res;
+    const size_t red = (size_t)ASM_THREADS * JMAX * sizeof(cplx<double>);
+    const size_t lds = std::max(stage, red);
+    auto kfn = corr_kernel<T, ASM_THREADS>;
+    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    kfn<<<D.H + 1, ASM_THREADS, lds, s>>>(A, U, p->at<CorrItem>(Lo.items), p->at<cplx<double>>(Lo.V), tw, twd, C1);
+    LAUNCH_CHECK();
+  }
+  row_win_kernel<WIN_THREADS, WIN_IMAX><<<(int)D.wrows.size(), WIN_THREADS, 0, s>>>(
+      A, p->at<cplx<double>>(Lo.V), p->at<WinRow>(Lo.wrows), p->at<double>(Lo.win), twd);
+  LAUNCH_CHECK();
+  moments_reduce_kernel<ASM_THREADS><<<1, ASM_THREADS, 0, s>>>(A, p->at<double>(Lo.mom), p->at<double>(Lo.obb),
+                                                               p->at<double>(Lo.bb));
+  LAUNCH_CHECK();
+  {
+    dim3 grid((D.n + 255) / 256, D.n);
+    gather_kernel<<<grid, 256, 0, s>>>(D.gp, p->at<double>(Lo.win), p->at<double>(Lo.obb), p->at<double>(Lo.bb),
+                                       p->at<double>(Lo.omega), p->at<double>(Lo.beta));
+    LAUNCH_CHECK();
+  }
+  return SFFT_OK;
+}
+
+int trsv_pair(sfft_plan_s* p, const double* rhs, double* out) {
+  const Derived& D = p->D;
+  const Layout& Lo = p->Lo;
+  hipStream_t s = p->stream;
+  const int* info = p->at<int>(Lo.flags);
+  const size_t lds = (size_t)D.n * sizeof(double);
+  HIP_TRY(hipFuncSetAttribute((const void*)trsv_lower_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  HIP_TRY(hipFuncSetAttribute((const void*)trsv_upper_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  trsv_lower_kernel<<<1, 1024, lds, s>>>(p->at<double>(Lo.F), D.n, p->at<double>(Lo.Linv), rhs, p->at<double>(Lo.y),
+                                         info);
+  LAUNCH_CHECK();
+  trsv_upper_kernel<<<1, 1024, lds, s>>>(p->at<double>(Lo.F), D.n, p->at<double>(Lo.Linv), p->at<double>(Lo.y), out,
+                                         info);
+  LAUNCH_CHECK();
+  return SFFT_OK;
+}
+
+template <typename T>
+int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coeffs, T* diff, int64_t ld) {
+  const Derived& D = p->D;
+  const Layout& Lo = p->Lo;
+  hipStream_t s = p->stream;
+  SubParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.ny = D.ny;
+  P.nx = D.nx;
+  P.w = D.w;
+  P.nk = D.nk;
+  P.nb = D.nb;
+  P.ld = ld;
+  for (int i = 0; i < D.nk; ++i) {
+    P.kpx[i] = D.kpoly.px[i];
+    P.kqy[i] = D.kpoly.qy[i];
+  }
+  for (int i = 0; i < D.nb; ++i) {
+    P.bpx[i] = D.bpoly.px[i];
+    P.bqy[i] = D.bpoly.qy[i];
+  }
+  const int L2 = D.L * D.L;
+  double* kp = p->at<double>(Lo.kp);
+  kprime_kernel<<<(L2 + 255) / 256, 256, 0, s>>>(P, coeffs, kp);
+  LAUNCH_CHECK();
+  const size_t lds = ((size_t)(SUB_TY + 2 * D.w) * (SUB_TX + 2 * D.w) + (size_t)D.nk * L2) * sizeof(double);
+  dim3 grid((D.nx + SUB_TX - 1) / SUB_TX, (D.ny + SUB_TY - 1) / SUB_TY);
+#define SUB_CASE(NKV)                                                                                      \
+  case NKV: {                                                                                              \
+    auto kfn = subtract_kernel<T, NKV>;                                                                    \
+    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+    kfn<<<grid, 256, lds, s>>>(P, sci, tmpl, kp, coeffs, diff);                                            \
+    break;                                                                                                 \
+  }
+  switch (D.nk) {
+    SUB_CASE(1)
+    SUB_CASE(3)
+    SUB_CASE(6)
+    SUB_CASE(10)
+    SUB_CASE(15)
+    default:
+      return SFFT_EINVAL;
+  }
+#undef SUB_CASE
+  LAUNCH_CHECK();
+  return SFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfft_num_coeffs(const sfft_desc* d, int64_t* n) {
+  if (n == nullptr) return SFFT_EINVAL;
+  const int st = validate(d);
+  if (st != SFFT_OK) return st;
+  const int64_t L = 2 * d->w + 1;
+  *n = L * L * ((d->dk + 1) * (d->dk + 2) / 2) + (d->db + 1) * (d->db + 2) / 2;
+  return SFFT_OK;
+}
+
+int sfft_workspace_bytes(const sfft_desc* d, size_t* bytes) {
+  if (bytes == nullptr) return SFFT_EINVAL;
+  Derived D;
+  const int st = derive(d, &D);
+  if (st != SFFT_OK) return st;
+  *bytes = layout_of(D).total;
+  return SFFT_OK;
+}
+
+int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t workspace_bytes, sfft_handle* out) {
+  if (out == nullptr) return SFFT_EINVAL;
+  *out = nullptr;
+  sfft_plan_s* p = new (std::nothrow) sfft_plan_s();
+  if (p == nullptr) return SFFT_ENOMEM;
+  int st = derive(d, &p->D);
+  if (st != SFFT_OK) {
+    delete p;
+    return st;
+  }
+  p->desc = *d;
+  p->Lo = layout_of(p->D);
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  p->built = false;
+  if (workspace != nullptr) {
+    if (workspace_bytes < p->Lo.total) {
+      delete p;
+      return SFFT_ENOMEM;
+    }
+    p->ws = reinterpret_cast<unsigned char*>(workspace);
+    p->owns_ws = false;
+  } else {
+    void* m = nullptr;
+    if (hipMalloc(&m, p->Lo.total) != hipSuccess) {
+      (void)hipGetLastError();
+      delete p;
+      return SFFT_ENOMEM;
+    }
+    p->ws = reinterpret_cast<unsigned char*>(m);
+    p->owns_ws = true;
+  }
+  twiddle_tables(&p->tw64h, &p->tw32h);
+  hipStream_t s = p->stream;
+  bool ok = true;
+  ok &= hipMemcpyAsync(p->at<void>(p->Lo.tw64), p->tw64h.data(), TW_N * sizeof(cplx<double>), hipMemcpyHostToDevice,
+                       s) == hipSuccess;
+  ok &= hipMemcpyAsync(p->at<void>(p->Lo.tw32), p->tw32h.data(), TW_N * sizeof(cplx<float>), hipMemcpyHostToDevice,
+                       s) == hipSuccess;
+  ok &= hipMemcpyAsync(p->at<void>(p->Lo.items), p->D.items.data(), p->D.items.size() * sizeof(CorrItem),
+                       hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(p->at<void>(p->Lo.wrows), p->D.wrows.data(), p->D.wrows.size() * sizeof(WinRow),
+                       hipMemcpyHostToDevice, s) == hipSuccess;
+  // host staging vectors of pageable memory: make sure the copies are done before returning
+  ok &= hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    if (p->owns_ws) (void)hipFree(p->ws);
+    delete p;
+    return SFFT_EHIP;
+  }
+  *out = p;
+  return SFFT_OK;
+}
+
+int sfft_build_system(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld) {
+  if (p == nullptr || sci == nullptr || tmpl == nullptr || ld < p->D.nx) return SFFT_EINVAL;
+  int st;
+  if (p->D.mode == SFFT_MODE_F64)
+    st = build_impl<double>(p, (const double*)sci, (const double*)tmpl, mask, ld);
+  else
+    st = build_impl<float>(p, (const float*)sci, (const float*)tmpl, mask, ld);
+  if (st == SFFT_OK) p->built = true;
+  return st;
+}
+
+int sfft_get_system(sfft_handle p, double* omega, double* rhs) {
+  if (p == nullptr) return SFFT_EINVAL;
+  if (!p->built) return SFFT_ESTATE;
+  const size_t n = (size_t)p->D.n;
+  if (omega != nullptr)
+    HIP_TRY(hipMemcpyAsync(omega, p->at<double>(p->Lo.omega), n * n * sizeof(double), hipMemcpyDeviceToDevice,
+                           p->stream));
+  if (rhs != nullptr)
+    HIP_TRY(hipMemcpyAsync(rhs, p->at<double>(p->Lo.beta), n * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  return SFFT_OK;
+}
+
+int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
+  if (p == nullptr || coeffs == nullptr) return SFFT_EINVAL;
+  if (!p->built) return SFFT_ESTATE;
+  const Derived& D = p->D;
+  const Layout& Lo = p->Lo;
+  hipStream_t s = p->stream;
+  int* dinfo = p->at<int>(Lo.flags);
+  double* F = p->at<double>(Lo.F);
+  set_int_kernel<<<1, 64, 0, s>>>(dinfo, 0);
+  LAUNCH_CHECK();
+  HIP_TRY(hipMemcpyAsync(F, p->at<double>(Lo.omega), (size_t)D.n * D.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int k = 0; k < D.nblk; ++k) {
+    const int k0 = k * NB;
+    potrf_diag_kernel<<<1, 256, 0, s>>>(F, D.n, k0, p->at<double>(Lo.Linv) + (size_t)k * NB * NB, dinfo);
+    LAUNCH_CHECK();
+    const int T = D.nblk - k - 1;
+    if (T > 0) {
+      trsm_kernel<<<T, 256, 0, s>>>(F, D.n, k0, p->at<double>(Lo.Linv) + (size_t)k * NB * NB, dinfo);
+      LAUNCH_CHECK();
+      syrk_kernel<<<T * (T + 1) / 2, 256, 0, s>>>(F, D.n, k0, dinfo);
+      LAUNCH_CHECK();
+    }
+  }
+  double* theta = p->at<double>(Lo.theta);
+  int st = trsv_pair(p, p->at<double>(Lo.beta), theta);
+  if (st != SFFT_OK) return st;
+  for (int it = 0; it < D.refine; ++it) {
+    residual_kernel<<<(D.n + 3) / 4, 256, 0, s>>>(p->at<double>(Lo.omega), D.n, p->at<double>(Lo.beta), theta,
+                                                  p->at<double>(Lo.r));
+    LAUNCH_CHECK();
+    st = trsv_pair(p, p->at<double>(Lo.r), p->at<double>(Lo.d));
+    if (st != SFFT_OK) return st;
+    axpy_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(theta, p->at<double>(Lo.d), D.n, dinfo);
+    LAUNCH_CHECK();
+  }
+  copy_out_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(theta, coeffs, D.n, dinfo, info);
+  LAUNCH_CHECK();
+  return SFFT_OK;
+}
+
+int sfft_residual(sfft_handle p, const double* coeffs, double* rho) {
+  if (p == nullptr || coeffs == nullptr || rho == nullptr) return SFFT_EINVAL;
+  if (!p->built) return SFFT_ESTATE;
+  const Derived& D = p->D;
+  const Layout& Lo = p->Lo;
+  hipStream_t s = p->stream;
+  residual_kernel<<<(D.n + 3) / 4, 256, 0, s>>>(p->at<double>(Lo.omega), D.n, p->at<double>(Lo.beta), coeffs,
+                                                p->at<double>(Lo.r));
+  LAUNCH_CHECK();
+  norm_ratio_kernel<<<1, 256, 0, s>>>(p->at<double>(Lo.r), p->at<double>(Lo.beta), D.n, rho);
+  LAUNCH_CHECK();
+  return SFFT_OK;
+}
+
+int sfft_subtract(sfft_handle p, const void* sci, const void* tmpl, const double* coeffs, void* diff, int64_t ld) {
+  if (p == nullptr || sci == nullptr || tmpl == nullptr || coeffs == nullptr || diff == nullptr || ld < p->D.nx)
+    return SFFT_EINVAL;
+  if (p->D.mode == SFFT_MODE_F64)
+    return subtract_impl<double>(p, (const double*)sci, (const double*)tmpl, coeffs, (double*)diff, ld);
+  return subtract_impl<float>(p, (const float*)sci, (const float*)tmpl, coeffs, (float*)diff, ld);
+}
+
+int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out) {
+  if (p == nullptr) return SFFT_EINVAL;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  int flags[2] = {0, 0};
+  HIP_TRY(hipMemcpy(flags, p->at<int>(p->Lo.flags), sizeof(flags), hipMemcpyDeviceToHost));
+  if (info_out) *info_out = flags[0];
+  if (nonfinite_out) *nonfinite_out = flags[1];
+  if (flags[1] != 0) return SFFT_ENONFINITE;
+  if (flags[0] != 0) return SFFT_ENOTSPD;
+  return SFFT_OK;
+}
+
+void sfft_destroy(sfft_handle p) {
+  if (p == nullptr) return;
+  if (p->owns_ws && p->ws != nullptr) {
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(p->ws);
+  }
+  delete p;
+}
+
+const char* sfft_strerror(int status) {
+  switch (status) {
+    case SFFT_OK: return "success";
+    case SFFT_EINVAL: return "invalid argument or descriptor";
+    case SFFT_ENOMEM: return "out of device memory or workspace too small";
+    case SFFT_EHIP: return "HIP runtime error";
+    case SFFT_ENOTSPD: return "normal matrix is not positive definite";
+    case SFFT_ESTATE: return "call out of order (build the system first)";
+    case SFFT_ENONFINITE: return "non-finite value in the science or template image";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

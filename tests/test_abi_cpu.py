@@ -1,0 +1,68 @@
+"""Host-side checks of the C ABI library (no GPU needed, no compute calls).
+
+The library must load, export every function include/sfft.h declares, and
+validate descriptors on the host before touching any device.
+"""
+import ctypes
+import os
+
+import pytest
+
+from paper_2509_18544_amd import binding as B
+
+if not os.path.exists(B.LIB_PATH):  # pragma: no cover
+    pytest.skip("libsfft.so not built", allow_module_level=True)
+
+
+def test_exports_every_declared_symbol():
+    syms = B.header_symbols()
+    assert len(syms) >= 11
+    raw = ctypes.CDLL(B.LIB_PATH)
+    for s in syms:
+        assert hasattr(raw, s), s
+
+
+def test_num_coeffs_and_workspace():
+    d = B.make_desc(4088, 4088, 9, 2, 2, B.SFFT_MODE_F32C)
+    assert B.sfft_num_coeffs(d) == 19 * 19 * 6 + 6 == 2172
+    ws32 = B.sfft_workspace_bytes(d)
+    ws64 = B.sfft_workspace_bytes(B.make_desc(4088, 4088, 9, 2, 2, B.SFFT_MODE_F64))
+    # spectra dominate: 13 planes of 4096 x 2049 complex
+    assert 13 * 4096 * 2049 * 8 < ws32 < ws64
+    assert B.sfft_num_coeffs(B.make_desc(256, 256, 5, 1, 1)) == 121 * 3 + 3
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ny=10, nx=10, w=3, dk=1, db=1),          # N < 4w + 2
+    dict(ny=64, nx=64, w=-1, dk=1, db=1),
+    dict(ny=64, nx=64, w=2, dk=-1, db=1),
+    dict(ny=64, nx=64, w=2, dk=1, db=-2),
+    dict(ny=5000, nx=64, w=2, dk=1, db=1),        # larger than 4096
+    dict(ny=64, nx=64, w=2, dk=1, db=1, mode=7),
+    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=1),
+    dict(ny=4096, nx=4096, w=15, dk=3, db=3),     # more unknowns than the solver holds
+])
+def test_invalid_descriptors(bad):
+    d = B.make_desc(**bad)
+    with pytest.raises(B.SfftError) as e:
+        B.sfft_num_coeffs(d)
+    assert e.value.status == B.SFFT_EINVAL
+    # sfft_plan rejects the descriptor before any device call
+    h = ctypes.c_void_p(0)
+    st = B.lib().sfft_plan(ctypes.byref(d), None, None, 0, ctypes.byref(h))
+    assert st == B.SFFT_EINVAL and not h.value
+
+
+def test_strerror_covers_codes():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert B.strerror(code) and B.strerror(code) != "unknown status"
+    assert B.strerror(123) == "unknown status"
+
+
+def test_null_arguments():
+    lib = B.lib()
+    assert lib.sfft_num_coeffs(None, None) == B.SFFT_EINVAL
+    assert lib.sfft_build_system(None, None, None, None, 0) == B.SFFT_EINVAL
+    assert lib.sfft_solve(None, None, None) == B.SFFT_EINVAL
+    assert lib.sfft_subtract(None, None, None, None, None, 0) == B.SFFT_EINVAL
+    lib.sfft_destroy(None)

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Tolerances (relative 2-norm errors against the oracle, as in the project's
+target): FP64 mode <= 1e-9 on the coefficients and on the difference image;
+FP32C mode <= 1e-5 on the coefficients and <= 1e-5 on the difference image
+for the sizes where the FP32 transforms allow it (see the 4088 notes in the
+design document).  Normal-matrix entries are compared element by element
+relative to max |Omega|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2509_18544_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_util import run_pair  # noqa: E402
+
+F64, F32C = B.SFFT_MODE_F64, B.SFFT_MODE_F32C
+TOL = {F64: dict(theta=1e-9, diff=1e-9, omega=1e-12), F32C: dict(theta=1e-5, diff=1e-5, omega=2e-6)}
+
+
+def _check_against_oracle(p, mode, res, ref=None, tol=None):
+    tol = tol or TOL[mode]
+    if ref is None:
+        ref = oracle.fit(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db)
+    assert res["info"] == 0 and res["status"] == B.SFFT_OK
+    if "omega" in res:
+        scale = np.abs(ref["omega"]).max()
+        err = np.abs(res["omega"] - ref["omega"]).max() / scale
+        assert err <= tol["omega"], f"Omega entry error {err:.3e}"
+        berr = np.abs(res["beta"] - ref["beta"]).max() / np.abs(ref["beta"]).max()
+        assert berr <= tol["omega"], f"beta entry error {berr:.3e}"
+    et = oracle.rel_err(res["theta"], ref["theta"])
+    ed = oracle.rel_err(res["diff"], ref["diff"])
+    assert et <= tol["theta"], f"e_theta {et:.3e}"
+    assert ed <= tol["diff"], f"e_D {ed:.3e}"
+    return et, ed
+
+
+SMALL = [
+    # ny, nx, w, dk, db, mask_frac, seed
+    (64, 64, 2, 1, 1, 0.10, 1),
+    (100, 90, 3, 2, 2, 0.05, 2),     # not a power of two, rectangular
+    (128, 200, 4, 2, 1, 0.10, 3),    # Px = 256, Py = 128
+    (37, 41, 1, 0, 0, 0.00, 4),      # smallest transform size (64)
+    (70, 66, 0, 2, 2, 0.10, 5),      # w = 0
+    (130, 129, 5, 1, 2, 0.20, 6),    # ragged tails past a power of two
+]
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+@pytest.mark.parametrize("case", SMALL)
+def test_small_parity(case, mode):
+    ny, nx, w, dk, db, frac, seed = case
+    p = synth.random_pair(seed, ny, nx, w, dk, db, mask_frac=frac, stars=True)
+    res = run_pair(p.sci, p.tmpl, p.mask, w, dk, db, mode=mode)
+    _check_against_oracle(p, mode, res)
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_c1_parity(mode):
+    p = synth.pair_c1()
+    res = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=mode)
+    et, ed = _check_against_oracle(p, mode, res)
+    print(f"C1 mode={mode} e_theta={et:.3e} e_D={ed:.3e}")
+
+
+@pytest.fixture(scope="module")
+def c2_ref():
+    p = synth.pair_c2()
+    return p, oracle.fit(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode="fft")
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_c2_parity(c2_ref, mode):
+    p, ref = c2_ref
+    res = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=mode)
+    et, ed = _check_against_oracle(p, mode, res, ref=ref)
+    print(f"C2 mode={mode} e_theta={et:.3e} e_D={ed:.3e}")
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_subtract_alone(mode):
+    """sfft_subtract with the oracle's coefficients reproduces the oracle's D."""
+    p = synth.random_pair(21, 150, 140, 4, 2, 2, mask_frac=0.1, stars=True)
+    ref = oracle.fit(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db)
+    res = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=mode, theta_in=ref["theta"],
+                   want_system=False)
+    tol = 1e-13 if mode == F64 else 1e-6
+    if mode == F32C:
+        # same coefficients; S and R rounded to float32 on the way in
+        d_ref = oracle.difference(p.sci.astype(np.float32), p.tmpl.astype(np.float32), ref["theta"],
+                                  p.w, p.dk, p.db)
+    else:
+        d_ref = ref["diff"]
+    assert oracle.rel_err(res["diff"], d_ref) <= tol
+
+
+def test_pitched_rows_and_null_mask():
+    p = synth.random_pair(31, 80, 72, 3, 1, 1, mask_frac=0.0, stars=True)
+    a = run_pair(p.sci, p.tmpl, None, p.w, p.dk, p.db)
+    b = run_pair(p.sci, p.tmpl, np.zeros_like(p.mask), p.w, p.dk, p.db, pitch=96)
+    np.testing.assert_array_equal(a["theta"], b["theta"])
+    np.testing.assert_array_equal(a["diff"], b["diff"])
+    _check_against_oracle(p, F64, a)
+
+
+def test_deterministic_replay():
+    p = synth.random_pair(41, 96, 96, 3, 2, 2, mask_frac=0.1, stars=True)
+    a = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=F32C)
+    b = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=F32C)
+    np.testing.assert_array_equal(a["omega"], b["omega"])
+    np.testing.assert_array_equal(a["theta"], b["theta"])
+    np.testing.assert_array_equal(a["diff"], b["diff"])
+
+
+def test_residual_judge():
+    p = synth.random_pair(51, 64, 64, 2, 1, 1, mask_frac=0.1, stars=True)
+    res = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db)
+    assert res["rho"] <= 1e-12
+
+
+def test_fully_masked_is_not_spd():
+    p = synth.random_pair(61, 40, 40, 2, 1, 1, mask_frac=0.0, stars=True)
+    mask = np.ones_like(p.mask)
+    res = run_pair(p.sci, p.tmpl, mask, p.w, p.dk, p.db, want_system=False)
+    assert res["info"] > 0
+    assert res["status"] == B.SFFT_ENOTSPD
+    assert np.all(res["theta"] == 0.0)      # coefficients left untouched
+
+
+def test_nonfinite_input_flagged():
+    p = synth.random_pair(71, 40, 40, 2, 1, 1, mask_frac=0.0, stars=True)
+    sci = p.sci.copy()
+    sci[5, 7] = np.nan
+    res = run_pair(sci, p.tmpl, p.mask, p.w, p.dk, p.db, want_system=False)
+    assert res["nonfinite"] == 1
+    assert res["status"] == B.SFFT_ENONFINITE
+
+
+def test_solve_before_build_and_bad_args():
+    plan = B.Plan(64, 64, 2, 1, 1)
+    try:
+        c = torch.zeros(plan.n, dtype=torch.float64, device="cuda")
+        i = torch.zeros(1, dtype=torch.int32, device="cuda")
+        with pytest.raises(B.SfftError) as e:
+            B.sfft_solve(plan.handle, c, i)
+        assert e.value.status == B.SFFT_ESTATE
+        x = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+        with pytest.raises(B.SfftError) as e:
+            B.sfft_build_system(plan.handle, x, x, None, 32)     # ld < nx
+        assert e.value.status == B.SFFT_EINVAL
+    finally:
+        plan.close()
+
+
+def test_native_library_is_loaded():
+    B.lib()
+    maps = open("/proc/self/maps").read()
+    assert B.LIB_PATH in maps
