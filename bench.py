@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Throughput of SFFT image subtraction on one MI355X.
+
+One step = the whole subtraction (build the normal system from FFT
+correlations, FP64 Cholesky solve with refinement, convolve-and-subtract) of
+a batch of B distinct synthetic 4088x4088 Roman-detector-like pairs, each
+pair on its own HIP stream.  Inputs are resident in device memory before the
+timed region; the value is pairs per second over the K timed steps.
+
+Also reported, on the same JSON line:
+  * roofline   -- the dominant stage's algorithmic bytes (or flops) per
+                  launch over its average device time, taken live from HIP
+                  events recorded on the stream that launches it;
+  * cpu_baseline -- the CPU FP64 oracle (scipy FFTs + LAPACK Cholesky) timed
+                  on this host on one pair of the same workload;
+  * accuracy   -- relative errors of pair 0's coefficients and difference
+                  image against that oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "4088^2 image pairs/sec subtracted at <=1e-5 rel err vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+WORKLOADS = {
+    "c3": dict(n=4088, w=9, dk=2, db=2, seed0=3000,
+               label="4088x4088 Roman-detector pair, 19x19 delta kernel (w=9), DK=2, DB=2, "
+                     "~40000 stars, bright-star + transient masks"),
+    "c2": dict(n=1024, w=9, dk=2, db=2, seed0=1002,
+               label="1024x1024 pair, 19x19 delta kernel, DK=2, DB=2, 3000 stars, 5% saturation mask"),
+    "c1": dict(n=256, w=5, dk=1, db=1, seed0=1001,
+               label="256x256 pair, 11x11 delta kernel, DK=1, DB=1, ~400 stars"),
+}
+
+
+def _gen(args):
+    name, seed = args
+    import synth
+    if name == "c3":
+        p = synth.pair_c3(seed=seed)
+    elif name == "c2":
+        p = synth.pair_c2(seed=seed)
+    else:
+        p = synth.pair_c1(seed=seed)
+    return p
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    cdir = os.path.join(ROOT, "paper_2509_18544_amd", "csrc")
+    for f in sorted(os.listdir(cdir)):
+        with open(os.path.join(cdir, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stage_cost(stage, D, mode_f64):
+    """Algorithmic bytes (hbm) or flops (alu) of one launch of a stage for one pair."""
+    n, P, H, planes, vrows = D["N"], D["P"], D["P"] // 2, D["nplanes"], D["vrows"]
+    s = 8 if mode_f64 else 4
+    cs = 2 * s
+    nk, L = D["nk"], 2 * D["w"] + 1
+    if stage == "row_fwd":
+        return "hbm", n * n * (2 * s + 1) + planes * n * H * cs
+    if stage == "col_fwd":
+        return "hbm", planes * H * n * cs + planes * (H + 1) * P * cs
+    if stage == "corr":
+        return "hbm", planes * (H + 1) * P * cs + (H + 1) * vrows * 16
+    if stage == "moments":
+        return "hbm", n * n * (2 * s + 1)
+    if stage == "subtract":
+        return "alu", 2.0 * nk * L * L * n * n
+    if stage == "factor":
+        m = D["ncoef"]
+        return "alu", m ** 3 / 3.0
+    return None, None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=4, help="pairs per step (one stream each)")
+    ap.add_argument("--mode", choices=["f32c", "f64"], default="f32c")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs each pair on a single MI355X "
+              "(pairs are independent; see the sharding notes in the design document). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    wl = WORKLOADS[args.workload]
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+
+    # ---- synthetic inputs (CPU, before any GPU use) ----
+    t0 = time.perf_counter()
+    seeds = [wl["seed0"] + i for i in range(args.batch)]
+    workers = max(1, min(args.batch, 8, len(os.sched_getaffinity(0))))
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        pairs = list(ex.map(_gen, [(args.workload, s) for s in seeds]))
+    log(f"[bench] generated {len(pairs)} {args.workload} pairs in {time.perf_counter() - t0:.1f}s")
+
+    import numpy as np
+    import torch
+    from paper_2509_18544_amd import binding as B
+
+    mode = B.SFFT_MODE_F64 if args.mode == "f64" else B.SFFT_MODE_F32C
+    dt = torch.float64 if mode == B.SFFT_MODE_F64 else torch.float32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(args.batch)]
+    bufs, plans = [], []
+    for p, st in zip(pairs, streams):
+        ny, nx = p.sci.shape
+        S = torch.from_numpy(p.sci).to(dev, dt)
+        R = torch.from_numpy(p.tmpl).to(dev, dt)
+        M = torch.from_numpy(p.mask).to(dev)
+        Dd = torch.empty_like(S)
+        plan = B.Plan(ny, nx, p.w, p.dk, p.db, mode=mode, stream=st)
+        coeffs = torch.zeros(plan.n, dtype=torch.float64, device=dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        bufs.append((S, R, M, Dd, coeffs, info))
+        plans.append(plan)
+    torch.cuda.synchronize()
+
+    def step():
+        for plan, (S, R, M, Dd, coeffs, info) in zip(plans, bufs):
+            ld = S.stride(0)
+            B.sfft_build_system(plan.handle, S, R, M, ld)
+            B.sfft_solve(plan.handle, coeffs, info)
+            B.sfft_subtract(plan.handle, S, R, coeffs, Dd, ld)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for plan in plans:
+        B.sfft_timing_read(plan.handle)        # drop warm-up counters
+        B.sfft_timing_enable(plan.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_tot = {}
+    for plan in plans:
+        for k, (ms, cnt) in B.sfft_timing_read(plan.handle).items():
+            a, c = stage_tot.get(k, (0.0, 0))
+            stage_tot[k] = (a + ms, c + cnt)
+        B.sfft_timing_enable(plan.handle, False)
+    for plan in plans:
+        st, inf, nf = plan.status()
+        if st != B.SFFT_OK:
+            raise RuntimeError(f"device status {B.strerror(st)} (info={inf}, nonfinite={nf})")
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = args.batch * args.steps / elapsed
+    stages_avg = {k: (ms / c if c else 0.0) for k, (ms, c) in stage_tot.items()}
+    log("[bench] stage avg ms per pair: " + ", ".join(f"{k}={v:.3f}" for k, v in stages_avg.items()))
+
+    # ---- roofline of the dominant stage ----
+    p0 = plans[0]
+    n_px = pairs[0].sci.shape[0]
+    P = 1 << max(6, (n_px - 1).bit_length())
+    nk = (pairs[0].dk + 1) * (pairs[0].dk + 2) // 2
+    nb = (pairs[0].db + 1) * (pairs[0].db + 2) // 2
+    w = pairs[0].w
+    vrows = (nk * (nk + 1) // 2) * (4 * w + 1) + (nk * nb + nk) * (2 * w + 1)
+    Dinfo = dict(N=n_px, P=P, nplanes=nk + nb + 1, vrows=vrows, nk=nk, w=w, ncoef=p0.n)
+    dom = max(stages_avg, key=lambda k: stages_avg[k])
+    bound, amount = stage_cost(dom, Dinfo, mode == B.SFFT_MODE_F64)
+    roof = None
+    if bound is not None and stages_avg[dom] > 0:
+        sec = stages_avg[dom] / 1000.0
+        if bound == "hbm":
+            ach = amount / sec / 1e9
+            roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+        else:
+            ach = amount / sec / 1e12
+            roof = dict(bound="alu", achieved=round(ach, 2), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=round(ach / FP64_VECTOR_PEAK_TFLOPS, 4), traffic=None)
+        roof.update(kernel=dom, avg_ms=round(stages_avg[dom], 4), per_launch=amount,
+                    src=kernel_source_hash())
+
+    # ---- accuracy of pair 0 and the CPU baseline (the oracle itself) ----
+    S, R, M, Dd, coeffs, info = bufs[0]
+    theta_gpu = coeffs.cpu().numpy()
+    diff_gpu = Dd.cpu().numpy().astype(np.float64)
+    cpu = None
+    acc = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        p = pairs[0]
+        # the oracle sees exactly the values the GPU saw (float32 inputs upcast in FP32C mode)
+        s_in = S.cpu().numpy().astype(np.float64)
+        r_in = R.cpu().numpy().astype(np.float64)
+        t1 = time.perf_counter()
+        ref = oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db, mode="fft")
+        cpu_s = time.perf_counter() - t1
+        cpu = dict(value=round(1.0 / cpu_s, 5), unit="pairs/s", cores=cores, kind="oracle",
+                   sample=f"1 pair of the workload (seed {seeds[0]}): FP64 scipy.fft correlations + "
+                          f"LAPACK Cholesky + FFT difference image, {cpu_s:.1f} s")
+        acc = dict(e_theta=oracle.rel_err(theta_gpu, ref["theta"]),
+                   e_diff=oracle.rel_err(diff_gpu, ref["diff"]))
+        acc["within_1e-5"] = bool(acc["e_theta"] <= 1e-5 and acc["e_diff"] <= 1e-5)
+        log(f"[bench] oracle {cpu_s:.1f}s on {cores} cores; e_theta={acc['e_theta']:.2e} "
+            f"e_diff={acc['e_diff']:.2e}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if mode == B.SFFT_MODE_F64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl["label"] + f"; {args.mode.upper()} mode; batch of {args.batch} "
+                                             f"pairs on {args.batch} streams per step",
+                   "global_batch": args.batch, "frame": n_px, "fft_size": P, "coefficients": p0.n},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy": acc,
+        "stages_ms": {k: round(v, 4) for k, v in stages_avg.items()},
+    }
+    print(json.dumps(out), flush=True)
+    for plan in plans:
+        plan.close()
+
+
+if __name__ == "__main__":
+    main()

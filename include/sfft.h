@@ -125,6 +125,30 @@ int sfft_subtract(sfft_handle p, const void* sci, const void* tmpl, const double
  * raw flags. */
 int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out);
 
+/* Stages timed by the optional per-plan event timer. */
+enum {
+  SFFT_STAGE_MOMENTS = 0,   /* background moments + non-finite scan            */
+  SFFT_STAGE_ROW_FWD = 1,   /* plane generation + R2C along x                  */
+  SFFT_STAGE_COL_FWD = 2,   /* FFT along y                                     */
+  SFFT_STAGE_CORR = 3,      /* spectral products + pruned inverse along y      */
+  SFFT_STAGE_ROW_WIN = 4,   /* lag-window inverse along x                      */
+  SFFT_STAGE_GATHER = 5,    /* moments reduction + Omega/beta gather           */
+  SFFT_STAGE_FACTOR = 6,    /* Cholesky factorisation                          */
+  SFFT_STAGE_SOLVE = 7,     /* triangular solves + refinement                  */
+  SFFT_STAGE_SUBTRACT = 8,  /* convolve-and-subtract                           */
+  SFFT_NUM_STAGES = 9
+};
+
+/* Enable (1) or disable (0) HIP-event timing of every stage enqueued on the
+ * plan's stream from now on.  Events are recorded on that stream around each
+ * stage, so the numbers are device time of that stage alone. */
+int sfft_timing_enable(sfft_handle p, int enable);
+
+/* Synchronise the plan's stream and return, per stage, the total milliseconds
+ * and the number of timed executions since the last read (host arrays of
+ * SFFT_NUM_STAGES entries, either may be NULL), then reset the counters. */
+int sfft_timing_read(sfft_handle p, double* ms, int64_t* count);
+
 /* Release the plan (and its workspace if the plan allocated it). */
 void sfft_destroy(sfft_handle p);
 

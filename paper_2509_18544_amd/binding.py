@@ -63,6 +63,8 @@ def lib():
         "sfft_residual": (ctypes.c_int, [vp, vp, vp]),
         "sfft_subtract": (ctypes.c_int, [vp, vp, vp, vp, vp, i64]),
         "sfft_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "sfft_timing_enable": (ctypes.c_int, [vp, ctypes.c_int]),
+        "sfft_timing_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "sfft_destroy": (None, [vp]),
         "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -149,6 +151,22 @@ def sfft_status(handle):
     nf = ctypes.c_int32(0)
     st = lib().sfft_status(handle, ctypes.byref(info), ctypes.byref(nf))
     return st, info.value, nf.value
+
+
+STAGES = ("moments", "row_fwd", "col_fwd", "corr", "row_win", "gather", "factor", "solve", "subtract")
+
+
+def sfft_timing_enable(handle, enable: bool = True):
+    _check(lib().sfft_timing_enable(handle, 1 if enable else 0), "sfft_timing_enable")
+
+
+def sfft_timing_read(handle):
+    """{stage: (total_ms, count)} since the last read (synchronises the plan's stream)."""
+    n = len(STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(lib().sfft_timing_read(handle, ms, cnt), "sfft_timing_read")
+    return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
 
 
 def sfft_destroy(handle):

@@ -20,8 +20,9 @@
 //   corr      : per column kx, every needed product conj(X_a) X_b and its
 //               inverse transform along y evaluated only on the lag rows
 //               |j| <= hw, via F_k1(r) = sum_k2 Z(k1 + P1 k2) e^{2 pi i k2 r/P2}
-//               and V(j) = sum_k1 e^{2 pi i k1 j/Py} F_k1(j mod P2); the sum over
-//               k1 is accumulated in FP64.
+//               and V(j) = sum_k1 e^{2 pi i k1 j/Py} F_k1(j mod P2).  Spectra are
+//               stored in the mode's type; products, the inner transform and
+//               the sum over k1 are FP64 in both modes.
 //   row_win   : inverse along x of the lag rows, only on the lag columns, in
 //               FP64, using the Hermitian symmetry of real correlations.
 //   moments   : FP64 per-row sums for the background block; non-finite scan.
@@ -257,11 +258,11 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
     it.nj = 0;
     it.vrow = 0;
     if (active) it = items[item_id];
-    // pre-rotation by s = jlo mod P2
+    // pre-rotation by s = jlo mod P2 (FP64: the correlation arithmetic is FP64 in both modes)
     const int s = ((int)it.jlo % P2 + P2) % P2;
-    cplx<T> rot[P2];
+    cplx<double> rot[P2];
 #pragma unroll
-    for (int k2 = 0; k2 < P2; ++k2) rot[k2] = twid<T, true>(tw, (k2 * s) << (TW_LOG - LG_P2));
+    for (int k2 = 0; k2 < P2; ++k2) rot[k2] = twid<double, true>(twd, (k2 * s) << (TW_LOG - LG_P2));
     cplx<double> acc[JMAX];
 #pragma unroll
     for (int t = 0; t < JMAX; ++t) acc[t] = mk(0.0, 0.0);
@@ -282,10 +283,14 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
         const int k1 = k1c + c;
         const cplx<T>* xa = stage + it.left * per_plane + c * P2;
         const cplx<T>* xb = stage + it.right * per_plane + c * P2;
-        cplx<T> z[P2];
+        cplx<double> z[P2];
 #pragma unroll
-        for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(xa[k2], xb[k2]) * rot[k2];
-        dft16<T, true>(z);
+        for (int k2 = 0; k2 < P2; ++k2) {
+          const cplx<double> a = mk((double)xa[k2].x, (double)xa[k2].y);
+          const cplx<double> b = mk((double)xb[k2].x, (double)xb[k2].y);
+          z[k2] = cmulc(a, b) * rot[k2];
+        }
+        dft16<double, true>(z);
         // outer twiddle e^{2 pi i k1 j / Py} for j = jlo + t, by recurrence in FP64
         const int m0 = ((k1 * (int)it.jlo) % Py + Py) % Py;
         cplx<double> tj = conjg(twd[m0 << (TW_LOG - lgPy)]);
@@ -293,9 +298,7 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
 #pragma unroll
         for (int t = 0; t < JMAX; ++t) {
           if (t < it.nj) {
-            const cplx<T> f = z[t & (P2 - 1)];
-            const cplx<double> fd = mk((double)f.x, (double)f.y);
-            acc[t] = acc[t] + tj * fd;
+            acc[t] = acc[t] + tj * z[t & (P2 - 1)];
             tj = tj * step;
           }
         }

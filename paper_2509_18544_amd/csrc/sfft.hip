@@ -237,8 +237,72 @@ void twiddle_tables(std::vector<cplx<double>>* t64, std::vector<cplx<float>>* t3
 
 }  // namespace
 
+// Optional per-stage device timing with events recorded on the plan's stream.
+struct StageTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[SFFT_NUM_STAGES];
+  double ms[SFFT_NUM_STAGES] = {};
+  int64_t cnt[SFFT_NUM_STAGES] = {};
+  hipEvent_t open_ev = nullptr;
+  int open_stage = -1;
+
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void begin(int st, hipStream_t s) {
+    if (!on) return;
+    open_ev = take();
+    open_stage = st;
+    if (open_ev) (void)hipEventRecord(open_ev, s);
+  }
+  void end(hipStream_t s) {
+    if (!on || open_stage < 0) return;
+    hipEvent_t e = take();
+    if (open_ev && e) {
+      (void)hipEventRecord(e, s);
+      pending[open_stage].push_back({open_ev, e});
+    }
+    open_stage = -1;
+    open_ev = nullptr;
+  }
+  void fold() {
+    for (int st = 0; st < SFFT_NUM_STAGES; ++st) {
+      for (auto& pr : pending[st]) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) {
+          ms[st] += t;
+          cnt[st] += 1;
+        }
+        pool.push_back(pr.first);
+        pool.push_back(pr.second);
+      }
+      pending[st].clear();
+    }
+  }
+  void release() {
+    for (int st = 0; st < SFFT_NUM_STAGES; ++st) {
+      for (auto& pr : pending[st]) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+      pending[st].clear();
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
 struct sfft_plan_s {
   sfft_desc desc;
+  StageTimer timer;
   Derived D;
   Layout Lo;
   hipStream_t stream;
@@ -302,8 +366,10 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
 
   set_int_kernel<<<1, 64, 0, s>>>(flags + 1, 0);
   LAUNCH_CHECK();
+  p->timer.begin(SFFT_STAGE_MOMENTS, s);
   moments_kernel<T, ASM_THREADS><<<D.ny, ASM_THREADS, 0, s>>>(A, sci, tmpl, mask, p->at<double>(Lo.mom), flags + 1);
   LAUNCH_CHECK();
+  p->timer.end(s);
 
   constexpr int RN = std::is_same<T, float>::value ? ROW_NMAX_F32 : ROW_NMAX_F64;
   {
@@ -311,8 +377,10 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     auto kfn = row_fwd_kernel<T, ASM_THREADS, RN>;
     HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int grid = ((D.nrowblk + 7) / 8) * 8;   // whole XCD rounds for the remap
+    p->timer.begin(SFFT_STAGE_ROW_FWD, s);
     kfn<<<grid, ASM_THREADS, lds, s>>>(A, sci, tmpl, mask, U, tw);
     LAUNCH_CHECK();
+    p->timer.end(s);
   }
   {
     const int cpb = std::max(1, COL_NMAX / D.Py);
@@ -320,8 +388,10 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     auto kfn = col_fwd_kernel<T, ASM_THREADS, COL_NMAX>;
     HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     dim3 grid((D.H + cpb - 1) / cpb, D.nplanes);
+    p->timer.begin(SFFT_STAGE_COL_FWD, s);
     kfn<<<grid, ASM_THREADS, lds, s>>>(A, U, tw, cpb);
     LAUNCH_CHECK();
+    p->timer.end(s);
   }
   {
     const int P1 = D.Py / P2;
@@ -333,12 +403,17 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     const size_t lds = std::max(stage, red);
     auto kfn = corr_kernel<T, ASM_THREADS>;
     HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    p->timer.begin(SFFT_STAGE_CORR, s);
     kfn<<<D.H + 1, ASM_THREADS, lds, s>>>(A, U, p->at<CorrItem>(Lo.items), p->at<cplx<double>>(Lo.V), tw, twd, C1);
     LAUNCH_CHECK();
+    p->timer.end(s);
   }
+  p->timer.begin(SFFT_STAGE_ROW_WIN, s);
   row_win_kernel<WIN_THREADS, WIN_IMAX><<<(int)D.wrows.size(), WIN_THREADS, 0, s>>>(
       A, p->at<cplx<double>>(Lo.V), p->at<WinRow>(Lo.wrows), p->at<double>(Lo.win), twd);
   LAUNCH_CHECK();
+  p->timer.end(s);
+  p->timer.begin(SFFT_STAGE_GATHER, s);
   moments_reduce_kernel<ASM_THREADS><<<1, ASM_THREADS, 0, s>>>(A, p->at<double>(Lo.mom), p->at<double>(Lo.obb),
                                                                p->at<double>(Lo.bb));
   LAUNCH_CHECK();
@@ -348,6 +423,7 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
                                        p->at<double>(Lo.omega), p->at<double>(Lo.beta));
     LAUNCH_CHECK();
   }
+  p->timer.end(s);
   return SFFT_OK;
 }
 
@@ -391,6 +467,7 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
   }
   const int L2 = D.L * D.L;
   double* kp = p->at<double>(Lo.kp);
+  p->timer.begin(SFFT_STAGE_SUBTRACT, s);
   kprime_kernel<<<(L2 + 255) / 256, 256, 0, s>>>(P, coeffs, kp);
   LAUNCH_CHECK();
   const size_t lds = ((size_t)(SUB_TY + 2 * D.w) * (SUB_TX + 2 * D.w) + (size_t)D.nk * L2) * sizeof(double);
@@ -413,6 +490,7 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
   }
 #undef SUB_CASE
   LAUNCH_CHECK();
+  p->timer.end(s);
   return SFFT_OK;
 }
 
@@ -524,6 +602,7 @@ int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
   double* F = p->at<double>(Lo.F);
   set_int_kernel<<<1, 64, 0, s>>>(dinfo, 0);
   LAUNCH_CHECK();
+  p->timer.begin(SFFT_STAGE_FACTOR, s);
   HIP_TRY(hipMemcpyAsync(F, p->at<double>(Lo.omega), (size_t)D.n * D.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   for (int k = 0; k < D.nblk; ++k) {
     const int k0 = k * NB;
@@ -537,6 +616,8 @@ int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
       LAUNCH_CHECK();
     }
   }
+  p->timer.end(s);
+  p->timer.begin(SFFT_STAGE_SOLVE, s);
   double* theta = p->at<double>(Lo.theta);
   int st = trsv_pair(p, p->at<double>(Lo.beta), theta);
   if (st != SFFT_OK) return st;
@@ -551,6 +632,7 @@ int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
   }
   copy_out_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(theta, coeffs, D.n, dinfo, info);
   LAUNCH_CHECK();
+  p->timer.end(s);
   return SFFT_OK;
 }
 
@@ -588,8 +670,29 @@ int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out) {
   return SFFT_OK;
 }
 
+int sfft_timing_enable(sfft_handle p, int enable) {
+  if (p == nullptr) return SFFT_EINVAL;
+  p->timer.on = enable != 0;
+  return SFFT_OK;
+}
+
+int sfft_timing_read(sfft_handle p, double* ms, int64_t* count) {
+  if (p == nullptr) return SFFT_EINVAL;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->timer.fold();
+  for (int st = 0; st < SFFT_NUM_STAGES; ++st) {
+    if (ms) ms[st] = p->timer.ms[st];
+    if (count) count[st] = p->timer.cnt[st];
+    p->timer.ms[st] = 0.0;
+    p->timer.cnt[st] = 0;
+  }
+  return SFFT_OK;
+}
+
 void sfft_destroy(sfft_handle p) {
   if (p == nullptr) return;
+  (void)hipStreamSynchronize(p->stream);
+  p->timer.release();
   if (p->owns_ws && p->ws != nullptr) {
     (void)hipStreamSynchronize(p->stream);
     (void)hipFree(p->ws);
