@@ -45,7 +45,8 @@ __all__ = [
     "num_basis", "num_coeffs", "monomial_exponents", "frame_coords", "monomials",
     "good_masks", "design_matrix", "normal_system_direct", "normal_system_fft",
     "normal_system", "solve", "difference_direct", "difference_fft", "difference",
-    "fit", "rel_err", "theta_index", "cond_number",
+    "fit", "rel_err", "theta_index", "cond_number", "omega_entries", "beta_entries",
+    "difference_at",
 ]
 
 _WORKERS = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -323,3 +324,69 @@ def rel_err(x, ref):
     ref = np.asarray(ref, dtype=np.float64)
     den = np.linalg.norm(ref.ravel())
     return float(np.linalg.norm((x - ref).ravel()) / (den if den > 0 else 1.0))
+
+
+# ---------------------------------------------------------------------------
+# single entries and single pixels, straight from the definition (for
+# sampled checks at sizes where the full system is too large to rebuild)
+# ---------------------------------------------------------------------------
+
+def _column(sci, tmpl, mask, w, dk, db, idx):
+    """Column idx of Phi as an image (T_u A_a, or G m_b), and S_m."""
+    sci, tmpl, ny, nx = _check(sci, tmpl, w, dk, db)
+    g, gr = good_masks(mask, ny, nx, w)
+    L = 2 * w + 1
+    nk = num_basis(dk)
+    xh, yh = frame_coords(ny, nx)
+    if idx < nk * L * L:
+        a, u = divmod(idx, L * L)
+        uy, ux = divmod(u, L)
+        p, q = monomial_exponents(dk)[a]
+        aa = np.outer(yh ** q, xh ** p) * gr * tmpl
+        return _shift(aa, uy - w, ux - w)
+    p, q = monomial_exponents(db)[idx - nk * L * L]
+    return g * np.outer(yh ** q, xh ** p)
+
+
+def omega_entries(sci, tmpl, mask, w, dk, db, pairs):
+    """[Omega[r, c] for (r, c) in pairs] as full-frame dot products of two Phi columns."""
+    cache = {}
+
+    def col(i):
+        if i not in cache:
+            cache[i] = _column(sci, tmpl, mask, w, dk, db, i)
+        return cache[i]
+    return np.array([float(np.sum(col(r) * col(c))) for r, c in pairs])
+
+
+def beta_entries(sci, tmpl, mask, w, dk, db, rows):
+    """[beta[r] for r in rows] = column r of Phi dotted with S_m."""
+    sci = np.asarray(sci, dtype=np.float64)
+    g, _ = good_masks(mask, sci.shape[0], sci.shape[1], w)
+    sm = g * sci
+    return np.array([float(np.sum(_column(sci, tmpl, mask, w, dk, db, r) * sm)) for r in rows])
+
+
+def difference_at(sci, tmpl, theta, w, dk, db, ys, xs):
+    """D at the pixels (ys[i], xs[i]) by the explicit sum over kernel taps and background terms."""
+    sci = np.asarray(sci, dtype=np.float64)
+    tmpl = np.asarray(tmpl, dtype=np.float64)
+    ny, nx = sci.shape
+    k, c = _split_theta(theta, w, dk, db)
+    xh, yh = frame_coords(ny, nx)
+    out = []
+    for y, x in zip(ys, xs):
+        acc = 0.0
+        for a, (p, q) in enumerate(monomial_exponents(dk)):
+            for uy in range(-w, w + 1):
+                sy = y - uy
+                if not 0 <= sy < ny:
+                    continue
+                for ux in range(-w, w + 1):
+                    sx = x - ux
+                    if 0 <= sx < nx:
+                        acc += k[a, uy + w, ux + w] * xh[sx] ** p * yh[sy] ** q * tmpl[sy, sx]
+        for b, (p, q) in enumerate(monomial_exponents(db)):
+            acc += c[b] * xh[x] ** p * yh[y] ** q
+        out.append(sci[y, x] - acc)
+    return np.array(out)

@@ -53,8 +53,16 @@ struct CorrItem {
   int32_t vrow;          // row in V where lag row jlo goes
 };
 
+constexpr int MAX_BASE = 2 * MAX_DEG + 3;   // x-weighted base rows: DK+1 + DB+1 + 1
+
 struct AsmParams {
   int ny, nx, w, nk, nb, nplanes;
+  int nbase, nbk, nbb;   // base rows: xh^p G_R R (p <= DK), xh^p G (p <= DB), G S
+  double sx, sy;         // 2/(nx-1), 2/(ny-1): xh = x sx - 1, yh = y sy - 1
+  int8_t base_first[MAX_BASE];   // outputs of base b: out_plane/out_q[base_first[b] .. + base_count[b])
+  int8_t base_count[MAX_BASE];
+  int8_t out_plane[MAX_PLANES];
+  int8_t out_q[MAX_PLANES];
   int lgPy, lgPx;        // transform sizes Py = 2^lgPy, Px = 2^lgPx
   int H;                 // Px / 2
   int64_t ld;            // input row pitch (elements)
@@ -66,35 +74,6 @@ struct AsmParams {
   int nmom;              // per-row moments: (2DB+1) G-moments + (DB+1) S-moments
   int db;
 };
-
-__device__ __forceinline__ double ipow(double x, int p) {
-  double r = 1.0;
-  for (int i = 0; i < p; ++i) r *= x;
-  return r;
-}
-
-// value of plane p at (y, x): A_a = m_a G_R R, G m_b, or G S
-template <typename T>
-__device__ __forceinline__ T plane_value(const AsmParams& P, int p, int y, int x, const T* __restrict__ sci,
-                                         const T* __restrict__ tmpl, const uint8_t* __restrict__ mask) {
-  if (x >= P.nx) return (T)0;
-  const int64_t o = (int64_t)y * P.ld + x;
-  const bool good = (mask == nullptr) || (mask[o] == 0);
-  if (!good) return (T)0;
-  const double xh = 2.0 * (double)x / (double)(P.nx - 1) - 1.0;
-  const double yh = 2.0 * (double)y / (double)(P.ny - 1) - 1.0;
-  if (p < P.nk) {
-    const int w = P.w;
-    if (y < w || y >= P.ny - w || x < w || x >= P.nx - w) return (T)0;
-    const double m = ipow(xh, P.kpoly.px[p]) * ipow(yh, P.kpoly.qy[p]);
-    return (T)(m * (double)tmpl[o]);
-  }
-  if (p < P.nk + P.nb) {
-    const int b = p - P.nk;
-    return (T)(ipow(xh, P.bpoly.px[b]) * ipow(yh, P.bpoly.qy[b]));
-  }
-  return sci[o];
-}
 
 // XCD-aware block order: consecutive row blocks land on the same XCD (blocks
 // are dispatched round-robin over the 8 XCDs), so the transposed 64-byte
@@ -108,13 +87,40 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 }
 
 // ---------------------------------------------------------------------------
-// row_fwd: R2C along x of every plane row; transposed write into U
+// row_fwd: R2C along x of the x-weighted base rows; column-pair tiled write
 // ---------------------------------------------------------------------------
-// LDS: rows_per_block * H complex values.  Each row is packed as
-// z(j) = x(2j) + i x(2j+1), transformed with an H-point FFT and split:
+// Every plane factors as (x part) * (y part): A_(p,q) = yh^q * [xh^p G_R R],
+// G m_(p,q) = yh^q * [xh^p G], S_m = [G S].  Along a row yh is constant, so
+// only the DK+DB+3 bracketed base rows are transformed here; the yh^q weight
+// is applied by the column pass before its transform along y.
+//
+// Base row b at row y is packed as z(j) = x(2j) + i x(2j+1), transformed with
+// an H-point FFT and split:
 //   X(k) = E(k) + e^{-2 pi i k/Px} O(k),  E = (Z(k) + conj Z(H-k))/2,
 //   O = (Z(k) - conj Z(H-k))/(2i);   slot 0 holds (X(0), X(H)).
-template <typename T, int THREADS, int NMAX>
+// Output layout Ub[b][kx/2][y][kx%2]: a block of rows_per_block rows of one
+// column pair is one contiguous 128-byte segment.
+template <typename T>
+__device__ __forceinline__ T base_value(const AsmParams& P, int b, int y, int x, const T* __restrict__ sci,
+                                        const T* __restrict__ tmpl, const uint8_t* __restrict__ mask) {
+  if (x >= P.nx) return (T)0;
+  const int64_t o = (int64_t)y * P.ld + x;
+  const bool good = (mask == nullptr) || (mask[o] == 0);
+  if (!good) return (T)0;
+  if (b < P.nbk) {
+    const int w = P.w;
+    if (y < w || y >= P.ny - w || x < w || x >= P.nx - w) return (T)0;
+    const double xh = (double)x * P.sx - 1.0;
+    return (T)(ipow(xh, b) * (double)tmpl[o]);
+  }
+  if (b < P.nbk + P.nbb) {
+    const double xh = (double)x * P.sx - 1.0;
+    return (T)ipow(xh, b - P.nbk);
+  }
+  return sci[o];
+}
+
+template <typename T, int THREADS, int NMAX, int LGR0>
 __global__ __launch_bounds__(THREADS) void row_fwd_kernel(AsmParams P, const T* __restrict__ sci,
                                                           const T* __restrict__ tmpl,
                                                           const uint8_t* __restrict__ mask, cplx<T>* __restrict__ U,
@@ -128,91 +134,139 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(AsmParams P, const T* 
   const int H = P.H;
   const int lgH = P.lgPx - 1;
   const int Py = 1 << P.lgPy;
-  const int64_t pstride = (int64_t)(H + 1) * Py;
+  const int64_t pstride = (int64_t)H * Py;   // elements per base plane
   const int tid = threadIdx.x;
   const int twsx = TW_LOG - P.lgPx;
-  for (int p = 0; p < P.nplanes; ++p) {
+  auto lds_load = [&](int r, int i) { return buf[lds_pad(r * H + i)]; };
+  auto lds_store = [&](int r, int i, cplx<T> v) { buf[lds_pad(r * H + i)] = v; };
+  for (int b = 0; b < P.nbase; ++b) {
+    __syncthreads();   // the previous base's split has read the buffer
+    // packed base rows z(j) = x(2j) + i x(2j+1), coalesced over j
     for (int e = tid; e < RB * H; e += THREADS) {
       const int r = e >> lgH;
       const int j = e & (H - 1);
       const int y = y0 + r;
       cplx<T> z = mk((T)0, (T)0);
       if (y < P.ny) {
-        z.x = plane_value<T>(P, p, y, 2 * j, sci, tmpl, mask);
-        z.y = plane_value<T>(P, p, y, 2 * j + 1, sci, tmpl, mask);
+        z.x = base_value<T>(P, b, y, 2 * j, sci, tmpl, mask);
+        z.y = base_value<T>(P, b, y, 2 * j + 1, sci, tmpl, mask);
       }
-      buf[e] = z;
+      buf[lds_pad(e)] = z;
     }
     __syncthreads();
-    fft_lds<T, NMAX, THREADS, false>(buf, lgH, RB, H, tw);
-    // split and write: e -> (kx, r) with r fastest so that a column segment is contiguous
-    cplx<T>* Up = U + (int64_t)p * pstride;
+    fft_run<T, NMAX, THREADS, false, true, true, LGR0>(buf, lgH, RB, H, tw, lds_load, lds_store);
+    __syncthreads();
+    // split and write: consecutive threads fill one (column pair, row block) segment
+    cplx<T>* Ub = U + (int64_t)b * pstride;
+    const int seg = 2 * RB;
     for (int e = tid; e < RB * H; e += THREADS) {
-      const int r = e % RB;
-      const int k = e / RB;
+      const int c = e / seg;
+      const int rem = e - c * seg;
+      const int r = rem >> 1;
+      const int k = 2 * c + (rem & 1);
       const int y = y0 + r;
       if (y >= P.ny) continue;
-      const cplx<T>* row = buf + r * H;
-      const cplx<T> zk = row[k];
-      const cplx<T> zm = conjg(row[(H - k) & (H - 1)]);
+      const cplx<T> zk = buf[lds_pad(r * H + k)];
+      const cplx<T> zm = conjg(buf[lds_pad(r * H + ((H - k) & (H - 1)))]);
       cplx<T> out;
       if (k == 0) {
         // E(0) = Re Z0, O(0) = Im Z0; X(0) = E + O, X(H) = E - O
         out = mk(zk.x + zk.y, zk.x - zk.y);
       } else {
-        const cplx<T> e2 = zk + zm;                 // 2 E
+        const cplx<T> e2 = zk + zm;                   // 2 E
         const cplx<T> o2 = rot90<T, false>(zk - zm);  // 2 O = -i (Z - conj Z(H-k))
         const cplx<T> t = twid<T, false>(tw, k << twsx);
         out = scale(e2 + t * o2, (T)0.5);
       }
-      Up[(int64_t)k * Py + y] = out;
+      Ub[((int64_t)c * Py + y) * 2 + (k & 1)] = out;
     }
-    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// col_fwd: FFT along y of every column (in place), residue-major output
+// col_fwd: y-weight, FFT along y, residue-major write of every output plane
 // ---------------------------------------------------------------------------
-// Block = `cpb` consecutive columns of one plane.  Column 0 holds the packed
-// (DC, Nyquist) real-column pair z = x0 + i xN; after the transform
-// X0(ky) = (Z(ky) + conj Z(-ky))/2 and XN(ky) = (Z(ky) - conj Z(-ky))/(2i),
-// written to columns 0 and H.
-template <typename T, int THREADS, int NMAX>
-__global__ __launch_bounds__(THREADS) void col_fwd_kernel(AsmParams P, cplx<T>* __restrict__ U,
-                                                          const cplx<T>* __restrict__ tw, int cpb) {
+// Block = (column pair c >= 1, base b).  For each output plane o built from
+// base b (weight yh^q) the first FFT pass reads the pair block of Ub[b] times
+// yh^q (rows past ny are zero) and the last pass (radix 16, so its output
+// index is ky = k1 + P1 k2 with k1 < P1 = Py/16) writes X[o][kx][k1*P2 + k2]
+// directly.  Pair 0 (which holds the packed DC/Nyquist column) is done by
+// col_fwd_dc_kernel.
+template <typename T>
+__device__ __forceinline__ cplx<T> col_load(const AsmParams& P, const cplx<T>* __restrict__ blk, int kb, int y,
+                                            int q) {
+  if (y >= P.ny) return mk((T)0, (T)0);
+  cplx<T> v = blk[2 * y + kb];
+  if (q > 0) v = scale(v, (T)ipow((double)y * P.sy - 1.0, q));
+  return v;
+}
+
+template <typename T, int THREADS, int NMAX, int LGR0>
+__global__ __launch_bounds__(THREADS) void col_fwd_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
+                                                          cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int p = blockIdx.y;
-  const int kx0 = blockIdx.x * cpb;
+  const int npairs = P.H / 2 - 1;       // pairs 1 .. H/2-1
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  if (id >= npairs * P.nbase) return;
+  const int b = id / npairs;
+  const int c = 1 + (id - b * npairs);
+  const int Py = 1 << P.lgPy;
+  const int lgPy = P.lgPy;
+  const int H = P.H;
+  const cplx<T>* blk = Ub + (int64_t)b * H * Py + (int64_t)c * Py * 2;
+  const int lgP1 = lgPy - LG_P2;
+  const int P1 = 1 << lgP1;
+  for (int oi = 0; oi < P.base_count[b]; ++oi) {
+    const int o = P.out_plane[P.base_first[b] + oi];
+    const int q = P.out_q[P.base_first[b] + oi];
+    cplx<T>* Xc = X + (int64_t)o * (H + 1) * Py + (int64_t)(2 * c) * Py;
+    auto load0 = [&](int kb, int y) -> cplx<T> { return col_load<T>(P, blk, kb, y, q); };
+    auto store_out = [&](int kb, int ky, cplx<T> v) {
+      Xc[(int64_t)kb * Py + ((ky & (P1 - 1)) << LG_P2) + (ky >> lgP1)] = v;
+    };
+    __syncthreads();   // the previous output's LDS reads are done
+    fft_run<T, NMAX, THREADS, false, false, false, LGR0>(buf, lgPy, 2, Py, tw, load0, store_out);
+  }
+}
+
+// Pair 0: column 0 holds the packed (DC, Nyquist) real-column pair
+// z = x0 + i xN; after the transform X0(ky) = (Z(ky) + conj Z(-ky))/2 and
+// XN(ky) = (Z(ky) - conj Z(-ky))/(2i) go to columns 0 and H; column 1 is
+// written as usual.  One block per base.
+template <typename T, int THREADS, int NMAX, int LGR0>
+__global__ __launch_bounds__(THREADS) void col_fwd_dc_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
+                                                             cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int b = blockIdx.x;
   const int Py = 1 << P.lgPy;
   const int lgPy = P.lgPy;
   const int H = P.H;
   const int tid = threadIdx.x;
-  cplx<T>* Up = U + (int64_t)p * (H + 1) * Py;
-  const int ncol = min(cpb, H - kx0);
-  for (int e = tid; e < ncol * Py; e += THREADS) {
-    const int c = e >> lgPy;
-    const int y = e & (Py - 1);
-    buf[e] = (y < P.ny) ? Up[(int64_t)(kx0 + c) * Py + y] : mk((T)0, (T)0);
-  }
-  __syncthreads();
-  fft_lds<T, NMAX, THREADS, false>(buf, lgPy, ncol, Py, tw);
+  const cplx<T>* blk = Ub + (int64_t)b * H * Py;
   const int lgP1 = lgPy - LG_P2;
-  for (int e = tid; e < ncol * Py; e += THREADS) {
-    const int c = e >> lgPy;
-    const int s = e & (Py - 1);           // output slot = k1 * P2 + k2
-    const int k1 = s >> LG_P2;
-    const int k2 = s & (P2 - 1);
-    const int ky = k1 + (k2 << lgP1);
-    const cplx<T>* col = buf + (c << lgPy);
-    if (kx0 + c == 0) {
-      const cplx<T> z = col[ky];
-      const cplx<T> zm = conjg(col[(Py - ky) & (Py - 1)]);
-      Up[s] = scale(z + zm, (T)0.5);
-      Up[(int64_t)H * Py + s] = scale(rot90<T, false>(z - zm), (T)0.5);
-    } else {
-      Up[(int64_t)(kx0 + c) * Py + s] = col[ky];
+  for (int oi = 0; oi < P.base_count[b]; ++oi) {
+    const int o = P.out_plane[P.base_first[b] + oi];
+    const int q = P.out_q[P.base_first[b] + oi];
+    cplx<T>* Xo = X + (int64_t)o * (H + 1) * Py;
+    auto load0 = [&](int kb, int y) -> cplx<T> { return col_load<T>(P, blk, kb, y, q); };
+    auto lds_store = [&](int kb, int ky, cplx<T> v) { buf[lds_pad(kb * Py + ky)] = v; };
+    __syncthreads();
+    fft_run<T, NMAX, THREADS, false, false, true, LGR0>(buf, lgPy, 2, Py, tw, load0, lds_store);
+    __syncthreads();
+    for (int e = tid; e < 2 * Py; e += THREADS) {
+      const int kb = e >> lgPy;
+      const int s = e & (Py - 1);           // output slot = k1 * P2 + k2
+      const int ky = (s >> LG_P2) + ((s & (P2 - 1)) << lgP1);
+      if (kb == 0) {
+        const cplx<T> z = buf[lds_pad(ky)];
+        const cplx<T> zm = conjg(buf[lds_pad((Py - ky) & (Py - 1))]);
+        Xo[s] = scale(z + zm, (T)0.5);
+        Xo[(int64_t)H * Py + s] = scale(rot90<T, false>(z - zm), (T)0.5);
+      } else {
+        Xo[(int64_t)Py + s] = buf[lds_pad(Py + ky)];
+      }
     }
   }
 }
@@ -221,21 +275,33 @@ __global__ __launch_bounds__(THREADS) void col_fwd_kernel(AsmParams P, cplx<T>* 
 // corr: spectral products and pruned inverse along y on the lag rows
 // ---------------------------------------------------------------------------
 // One block per column kx in [0, H].  Residues k1 are processed in chunks of
-// C1; for each chunk all planes' slots [k1*P2, (k1+1)*P2) are staged in LDS.
-// Item i (pair, lag rows) is handled by `lanes` threads that split the
-// residues; at the end the lanes are summed in LDS and written to V.
-// For lag row j = jlo + t: V(j) = sum_k1 e^{2 pi i k1 j/Py} F_k1(j mod P2).  The
-// residue rotation j mod P2 = (jlo + t) mod P2 is folded into the inner DFT by
-// pre-multiplying Z(k2) by e^{2 pi i k2 s/P2}, s = jlo mod P2, so that output t
-// of the DFT is F_k1((jlo + t) mod P2).
+// C1; for each chunk every plane's P2 values X(k1 + P1 k2) are staged in LDS
+// in FP64.  With Z(k2) = conj(X_left(k2)) X_right(k2) and the inner inverse
+// DFT F(r) = sum_k2 Z(k2) e^{2 pi i k2 r/P2}, lag row j = jlo + t accumulates
+//   V(j) += e^{2 pi i k1 j/Py} F((jlo + t) mod P2).
+// The rotation s = jlo mod P2 is a compile-time case of a switch (items are
+// sorted by s, so a wave normally takes one case) to keep every register
+// index static.  Item i (pair, lag rows) is handled by `lanes` consecutive
+// threads that split the residues; at the end the lanes are summed in LDS.
+// Products, the inner transform and the accumulation are FP64 in both modes.
+template <int S>
+__device__ __forceinline__ void corr_accumulate(cplx<double>* acc, const cplx<double>* f, cplx<double> tj,
+                                                const cplx<double> step) {
+  // all JMAX rows are accumulated (rows past the item's count are never written out)
+#pragma unroll
+  for (int t = 0; t < JMAX; ++t) {
+    acc[t] = acc[t] + tj * f[(S + t) & (P2 - 1)];
+    tj = tj * step;
+  }
+}
+
 template <typename T, int THREADS>
 __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T>* __restrict__ U,
                                                        const CorrItem* __restrict__ items,
                                                        cplx<double>* __restrict__ V,
-                                                       const cplx<T>* __restrict__ tw,
                                                        const cplx<double>* __restrict__ twd, int C1) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* stage = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<double>* stage = reinterpret_cast<cplx<double>*>(smem_raw);
   const int kx = blockIdx.x;
   const int H = P.H;
   const int Py = 1 << P.lgPy;
@@ -245,6 +311,7 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
   const int nitems = P.nitems;
   const int lanes = max(1, THREADS / nitems);
   const int64_t pstride = (int64_t)(H + 1) * Py;
+  const int per_plane = C1 * P2;
 
   for (int base = 0; base < nitems * lanes; base += THREADS) {
     const int gt = base + tid;
@@ -258,11 +325,7 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
     it.nj = 0;
     it.vrow = 0;
     if (active) it = items[item_id];
-    // pre-rotation by s = jlo mod P2 (FP64: the correlation arithmetic is FP64 in both modes)
-    const int s = ((int)it.jlo % P2 + P2) % P2;
-    cplx<double> rot[P2];
-#pragma unroll
-    for (int k2 = 0; k2 < P2; ++k2) rot[k2] = twid<double, true>(twd, (k2 * s) << (TW_LOG - LG_P2));
+    const int srot = ((int)it.jlo % P2 + P2) % P2;
     cplx<double> acc[JMAX];
 #pragma unroll
     for (int t = 0; t < JMAX; ++t) acc[t] = mk(0.0, 0.0);
@@ -270,53 +333,60 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
     for (int k1c = 0; k1c < P1; k1c += C1) {
       const int nc = min(C1, P1 - k1c);
       __syncthreads();
-      // stage slots [k1c*P2, (k1c+nc)*P2) of every plane
-      const int per_plane = nc * P2;
-      for (int e = tid; e < P.nplanes * per_plane; e += THREADS) {
-        const int pl = e / per_plane;
-        const int o = e - pl * per_plane;
-        stage[e] = U[pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o];
+      for (int e = tid; e < P.nplanes * nc * P2; e += THREADS) {
+        const int pl = e / (nc * P2);
+        const int o = e - pl * (nc * P2);
+        const cplx<T> x = U[pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o];
+        stage[pl * per_plane + o] = mk((double)x.x, (double)x.y);
       }
       __syncthreads();
       if (!active) continue;
       for (int c = lane; c < nc; c += lanes) {
         const int k1 = k1c + c;
-        const cplx<T>* xa = stage + it.left * per_plane + c * P2;
-        const cplx<T>* xb = stage + it.right * per_plane + c * P2;
+        const cplx<double>* xa = stage + it.left * per_plane + c * P2;
+        const cplx<double>* xb = stage + it.right * per_plane + c * P2;
         cplx<double> z[P2];
 #pragma unroll
-        for (int k2 = 0; k2 < P2; ++k2) {
-          const cplx<double> a = mk((double)xa[k2].x, (double)xa[k2].y);
-          const cplx<double> b = mk((double)xb[k2].x, (double)xb[k2].y);
-          z[k2] = cmulc(a, b) * rot[k2];
-        }
+        for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(xa[k2], xb[k2]);
         dft16<double, true>(z);
         // outer twiddle e^{2 pi i k1 j / Py} for j = jlo + t, by recurrence in FP64
         const int m0 = ((k1 * (int)it.jlo) % Py + Py) % Py;
-        cplx<double> tj = conjg(twd[m0 << (TW_LOG - lgPy)]);
+        const cplx<double> tj = conjg(twd[m0 << (TW_LOG - lgPy)]);
         const cplx<double> step = conjg(twd[k1 << (TW_LOG - lgPy)]);
-#pragma unroll
-        for (int t = 0; t < JMAX; ++t) {
-          if (t < it.nj) {
-            acc[t] = acc[t] + tj * z[t & (P2 - 1)];
-            tj = tj * step;
-          }
+        switch (srot) {
+#define CORR_CASE(SV) \
+  case SV:            \
+    corr_accumulate<SV>(acc, z, tj, step); \
+    break;
+          CORR_CASE(0) CORR_CASE(1) CORR_CASE(2) CORR_CASE(3) CORR_CASE(4) CORR_CASE(5) CORR_CASE(6) CORR_CASE(7)
+          CORR_CASE(8) CORR_CASE(9) CORR_CASE(10) CORR_CASE(11) CORR_CASE(12) CORR_CASE(13) CORR_CASE(14)
+          CORR_CASE(15)
+#undef CORR_CASE
         }
       }
     }
-    // reduce the lanes of each item through LDS (reuse the staging area)
-    __syncthreads();
+    // sum the lanes of each item through LDS, in two halves of the lag rows
     cplx<double>* red = reinterpret_cast<cplx<double>*>(smem_raw);
-    if (active) {
+    constexpr int HALF = (JMAX + 1) / 2;
 #pragma unroll
-      for (int t = 0; t < JMAX; ++t) red[tid * JMAX + t] = acc[t];
-    }
-    __syncthreads();
-    if (active && lane == 0) {
-      for (int t = 0; t < it.nj; ++t) {
-        cplx<double> sum = mk(0.0, 0.0);
-        for (int l = 0; l < lanes; ++l) sum = sum + red[(tid + l) * JMAX + t];
-        V[(int64_t)kx * P.vrows + it.vrow + t] = sum;
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int t = 0; t < HALF; ++t) {
+          const int tt = h * HALF + t;
+          if (tt < JMAX) red[tid * HALF + t] = acc[tt];
+        }
+      }
+      __syncthreads();
+      if (active && lane == 0) {
+        for (int t = 0; t < HALF; ++t) {
+          const int tt = h * HALF + t;
+          if (tt >= it.nj) break;
+          cplx<double> sum = mk(0.0, 0.0);
+          for (int l = 0; l < lanes; ++l) sum = sum + red[(tid + l) * HALF + t];
+          V[(int64_t)kx * P.vrows + it.vrow + tt] = sum;
+        }
       }
     }
     __syncthreads();
@@ -397,83 +467,90 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, const T* 
                                                           double* __restrict__ mom, int* __restrict__ nonfinite) {
   constexpr int NG_MAX = 2 * MAX_DEG + 1;
   constexpr int NS_MAX = MAX_DEG + 1;
-  __shared__ double red[THREADS];
+  constexpr int NM = NG_MAX + NS_MAX;
+  constexpr int NW = THREADS / 64;
+  __shared__ double red[NW][NM];
   const int y = blockIdx.x;
   const int tid = threadIdx.x;
   const int nG = 2 * P.db + 1;
   const int nS = P.db + 1;
-  double ag[NG_MAX], as[NS_MAX];
+  double acc[NM];
 #pragma unroll
-  for (int i = 0; i < NG_MAX; ++i) ag[i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < NS_MAX; ++i) as[i] = 0.0;
+  for (int i = 0; i < NM; ++i) acc[i] = 0.0;
   bool bad = false;
+  const T* srow = sci + (int64_t)y * P.ld;
+  const T* rrow = tmpl + (int64_t)y * P.ld;
+  const uint8_t* mrow = mask ? mask + (int64_t)y * P.ld : nullptr;
   for (int x = tid; x < P.nx; x += THREADS) {
-    const int64_t o = (int64_t)y * P.ld + x;
-    const double s = (double)sci[o];
-    const double r = (double)tmpl[o];
-    bad |= !isfinite(s) || !isfinite(r);
-    const bool good = (mask == nullptr) || (mask[o] == 0);
-    if (!good) continue;
-    const double xh = 2.0 * (double)x / (double)(P.nx - 1) - 1.0;
+    const T sv = srow[x];
+    const T rv = rrow[x];
+    const bool good = (mrow == nullptr) || (mrow[x] == 0);
+    bad |= !isfinite(sv) || !isfinite(rv);
+    const double g = good ? 1.0 : 0.0;
+    const double s = good ? (double)sv : 0.0;
+    const double xh = (double)x * P.sx - 1.0;
     double pw = 1.0;
 #pragma unroll
     for (int p = 0; p < NG_MAX; ++p) {
-      if (p < nG) ag[p] += pw;
-      if (p < NS_MAX && p < nS) as[p] += pw * s;
+      acc[p] += g * pw;
+      if (p < NS_MAX) acc[NG_MAX + p] += s * pw;
       pw *= xh;
     }
   }
   if (bad) atomicOr(nonfinite, 1);
+  const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
-  for (int i = 0; i < NG_MAX + NS_MAX; ++i) {
-    const bool use = (i < NG_MAX) ? (i < nG) : (i - NG_MAX < nS);
-    if (use) {
-      red[tid] = (i < NG_MAX) ? ag[i < NG_MAX ? i : 0] : as[i >= NG_MAX ? i - NG_MAX : 0];
-      __syncthreads();
-      for (int s2 = THREADS / 2; s2 > 0; s2 >>= 1) {
-        if (tid < s2) red[tid] += red[tid + s2];
-        __syncthreads();
-      }
-      if (tid == 0) mom[(int64_t)y * P.nmom + ((i < NG_MAX) ? i : nG + (i - NG_MAX))] = red[0];
-      __syncthreads();
+  for (int i = 0; i < NM; ++i) {
+    double v = acc[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][i] = v;
+  }
+  __syncthreads();
+  if (tid < NM) {
+    double v = 0.0;
+    for (int k = 0; k < NW; ++k) v += red[k][tid];
+    const int i = tid;
+    if (i < NG_MAX) {
+      if (i < nG) mom[(int64_t)y * P.nmom + i] = v;
+    } else if (i - NG_MAX < nS) {
+      mom[(int64_t)y * P.nmom + nG + (i - NG_MAX)] = v;
     }
   }
 }
 
-// One block: Omega_BB and beta_B from the per-row moments (fixed summation order).
+// Omega_BB and beta_B from the per-row moments: one block per output, fixed
+// summation order (deterministic).
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, const double* __restrict__ mom,
                                                                  double* __restrict__ obb, double* __restrict__ bb) {
-  __shared__ double red[THREADS];
+  __shared__ double red[THREADS / 64];
   const int tid = threadIdx.x;
   const int nb = P.nb;
   const int nG = 2 * P.db + 1;
-  for (int q = 0; q < nb * nb + nb; ++q) {
-    double acc = 0.0;
-    for (int y = tid; y < P.ny; y += THREADS) {
-      const double yh = 2.0 * (double)y / (double)(P.ny - 1) - 1.0;
-      if (q < nb * nb) {
-        const int b = q / nb, c = q % nb;
-        const int p = P.bpoly.px[b] + P.bpoly.px[c];
-        const int e = P.bpoly.qy[b] + P.bpoly.qy[c];
-        acc += ipow(yh, e) * mom[(int64_t)y * P.nmom + p];
-      } else {
-        const int b = q - nb * nb;
-        acc += ipow(yh, P.bpoly.qy[b]) * mom[(int64_t)y * P.nmom + nG + P.bpoly.px[b]];
-      }
-    }
-    red[tid] = acc;
-    __syncthreads();
-    for (int s = THREADS / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    if (tid == 0) {
-      if (q < nb * nb) obb[q] = red[0];
-      else bb[q - nb * nb] = red[0];
-    }
-    __syncthreads();
+  const int q = blockIdx.x;
+  double acc = 0.0;
+  int col, e;
+  if (q < nb * nb) {
+    const int b = q / nb, c = q % nb;
+    col = P.bpoly.px[b] + P.bpoly.px[c];
+    e = P.bpoly.qy[b] + P.bpoly.qy[c];
+  } else {
+    const int b = q - nb * nb;
+    col = nG + P.bpoly.px[b];
+    e = P.bpoly.qy[b];
+  }
+  for (int y = tid; y < P.ny; y += THREADS) {
+    const double yh = (double)y * P.sy - 1.0;
+    acc += ipow(yh, e) * mom[(int64_t)y * P.nmom + col];
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double v = 0.0;
+    for (int k = 0; k < THREADS / 64; ++k) v += red[k];
+    if (q < nb * nb) obb[q] = v;
+    else bb[q - nb * nb] = v;
   }
 }
 

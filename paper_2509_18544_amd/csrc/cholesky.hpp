@@ -19,61 +19,77 @@ namespace sfft {
 
 constexpr int NB = 64;
 
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ F, int n, int k0,
-                                                         double* __restrict__ Linv, int* __restrict__ info) {
-  __shared__ double A[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  __shared__ int fail;
+// Diagonal block: one wave of 64 lanes.
+//  Factorisation: lane i holds row i of the block in registers.  At column j
+//  every lane publishes its A[i][j] in LDS; the pivot d = A[j][j] is read back
+//  by all lanes, lanes i > j scale their entry by 1/sqrt(d) and publish it
+//  again, then lane i applies A[i][l] -= L[i][j] L[l][j] for j < l <= i with
+//  L[l][j] read as an LDS broadcast (independent reads, pipelined).
+//  Inverse X = L^{-1}: lane c holds column c, initialised to e_c, and the
+//  right-looking sweep X[j][c] /= L[j][j]; X[i][c] -= L[i][j] X[j][c] (i > j)
+//  reads L[i][j] as a broadcast from LDS.  Loops over the block are fully
+//  unrolled so that register indices are static.
+__global__ __launch_bounds__(64) void potrf_diag_kernel(double* __restrict__ F, int n, int k0,
+                                                        double* __restrict__ Linv, int* __restrict__ info) {
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double col[NB];
   if (*info != 0) return;
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   const int nb = min(NB, n - k0);
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    A[i][j] = (i < nb && j < nb && j <= i) ? F[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
-    X[i][j] = 0.0;
+  double row[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    row[c] = (lane < nb && c < nb && c <= lane) ? F[(int64_t)(k0 + lane) * n + k0 + c] : 0.0;
+  int fail = 0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < nb && fail == 0) {
+      col[lane] = row[j];
+      __syncthreads();
+      const double d = col[j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        fail = j + 1;
+      } else {
+        const double sd = sqrt(d);
+        if (lane > j) row[j] *= 1.0 / sd;
+        if (lane == j) row[j] = sd;
+        __syncthreads();
+        col[lane] = row[j];
+        __syncthreads();
+        const double lij = (lane > j) ? row[j] : 0.0;
+#pragma unroll
+        for (int l = j + 1; l < NB; ++l) {
+          if (l < nb && lane >= l) row[l] -= lij * col[l];
+        }
+      }
+      __syncthreads();
+    }
   }
-  if (tid == 0) fail = 0;
+  if (fail) {
+    if (lane == 0) *info = k0 + fail;
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    Ls[lane][c] = row[c];
+    if (lane < nb && c <= lane) F[(int64_t)(k0 + lane) * n + k0 + c] = row[c];
+  }
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    const double d = A[j][j];
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (tid == 0) {
-        fail = 1;
-        *info = k0 + j + 1;
+  double xc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) xc[i] = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < nb) {
+      xc[j] *= 1.0 / Ls[j][j];
+#pragma unroll
+      for (int i = j + 1; i < NB; ++i) {
+        if (i < nb) xc[i] -= Ls[i][j] * xc[j];
       }
     }
-    __syncthreads();
-    if (fail) return;
-    const double s = sqrt(d);
-    __syncthreads();
-    if (tid == 0) A[j][j] = s;
-    for (int i = j + 1 + tid; i < nb; i += 256) A[i][j] /= s;
-    __syncthreads();
-    // trailing update of the block: A[i][l] -= A[i][j] A[l][j], j < l <= i
-    const int m = nb - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = j + 1 + e / m;
-      const int l = j + 1 + e % m;
-      if (l <= i) A[i][l] -= A[i][j] * A[l][j];
-    }
-    __syncthreads();
   }
-  // inverse of the lower-triangular block, one column per thread
-  if (tid < nb) {
-    const int c = tid;
-    X[c][c] = 1.0 / A[c][c];
-    for (int i = c + 1; i < nb; ++i) {
-      double acc = 0.0;
-      for (int k = c; k < i; ++k) acc += A[i][k] * X[k][c];
-      X[i][c] = -acc / A[i][i];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    if (i < nb && j <= i) F[(int64_t)(k0 + i) * n + k0 + j] = A[i][j];
-    Linv[e] = (i < nb && j < nb) ? X[i][j] : 0.0;
-  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) Linv[i * NB + lane] = (i < nb && lane < nb) ? xc[i] : 0.0;
 }
 
 // Row block bi (after block k): L = A Linv^T, 64 x 64 x 64 in LDS.
@@ -191,7 +207,16 @@ __global__ __launch_bounds__(1024) void trsv_lower_kernel(const double* __restri
     double acc = 0.0;
     if (r < nb) {
       const double* row = F + (int64_t)(k0 + r) * n;
-      for (int c = sl; c < k0; c += 16) acc += row[c] * ys[c];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int c = sl;
+      for (; c + 48 < k0; c += 64) {
+        a0 += row[c] * ys[c];
+        a1 += row[c + 16] * ys[c + 16];
+        a2 += row[c + 32] * ys[c + 32];
+        a3 += row[c + 48] * ys[c + 48];
+      }
+      for (; c < k0; c += 16) a0 += row[c] * ys[c];
+      acc = (a0 + a1) + (a2 + a3);
     }
     part[r][sl] = acc;
     __syncthreads();
@@ -240,7 +265,16 @@ __global__ __launch_bounds__(1024) void trsv_upper_kernel(const double* __restri
     const int rstart = k0 + nb;
     double acc = 0.0;
     if (c < nb) {
-      for (int rr = rstart + rs; rr < n; rr += 16) acc += F[(int64_t)rr * n + k0 + c] * xs[rr];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int rr = rstart + rs;
+      for (; rr + 48 < n; rr += 64) {
+        a0 += F[(int64_t)rr * n + k0 + c] * xs[rr];
+        a1 += F[(int64_t)(rr + 16) * n + k0 + c] * xs[rr + 16];
+        a2 += F[(int64_t)(rr + 32) * n + k0 + c] * xs[rr + 32];
+        a3 += F[(int64_t)(rr + 48) * n + k0 + c] * xs[rr + 48];
+      }
+      for (; rr < n; rr += 16) a0 += F[(int64_t)rr * n + k0 + c] * xs[rr];
+      acc = (a0 + a1) + (a2 + a3);
     }
     part[rs][c] = acc;
     __syncthreads();

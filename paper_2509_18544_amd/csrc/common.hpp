@@ -245,6 +245,155 @@ __device__ void fft_lds(cplx<T>* buf, int lgN, int batch, int bstride, const cpl
     stockham_pass<T, 2, (NMAX / 2 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid, THREADS);
 }
 
+// ---------------------------------------------------------------------------
+// Flexible Stockham pass: operands come from / go to arbitrary accessors
+// ---------------------------------------------------------------------------
+// LDS buffers used by these passes are padded by one element every 16
+// (lds_pad) so that the strided Stockham stores do not pile onto one bank.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 4) + 1; }
+
+// One radix-R pass over `batch` transforms of length 2^lgN.  Butterfly j
+// (0 <= j < N/R) takes inputs x[j + r N/R] = load(b, j + r N/R), twiddles input r
+// by w_{Ns R}^{r k} (k = j mod Ns), applies the R-point DFT and hands output r
+// to store(b, (j - k) R + k + r Ns, value).
+//   IN_PLACE = false: each butterfly is loaded, computed and stored in turn
+//                     (source and destination are different buffers).
+//   IN_PLACE = true : every thread first loads all its butterflies (at most
+//                     ITEMS), then a barrier, then the stores.
+// No barrier after the stores.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void fft_butterfly(cplx<T>* v, int k, int lgNs, int tws, const cplx<T>* __restrict__ tw) {
+  if (lgNs > 0) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = v[r] * twid<T, INV>(tw, (r * k) << tws);
+  }
+  dftR<T, R, INV>(v);
+}
+
+template <typename T, int R, int ITEMS, bool INV, bool IN_PLACE, class Load, class Store>
+__device__ __forceinline__ void fft_pass(int lgN, int batch, int lgNs, const cplx<T>* __restrict__ tw, int tid,
+                                         int nthreads, Load load, Store store) {
+  constexpr int lgR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  const int lgM = lgN - lgR;
+  const int M = 1 << lgM;
+  const int all = M * batch;
+  const int Ns = 1 << lgNs;
+  const int tws = TW_LOG - (lgNs + lgR);
+  if (!IN_PLACE) {
+    for (int j = tid; j < all; j += nthreads) {
+      const int b = j >> lgM;
+      const int jj = j & (M - 1);
+      const int k = jj & (Ns - 1);
+      cplx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = load(b, jj + (r << lgM));
+      fft_butterfly<T, R, INV>(v, k, lgNs, tws, tw);
+      const int base = ((jj - k) << lgR) + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(b, base + (r << lgNs), v[r]);
+    }
+    return;
+  }
+  cplx<T> v[ITEMS][R];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const int j = tid + it * nthreads;
+    if (j < all) {
+      const int b = j >> lgM;
+      const int jj = j & (M - 1);
+      const int k = jj & (Ns - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = load(b, jj + (r << lgM));
+      fft_butterfly<T, R, INV>(v[it], k, lgNs, tws, tw);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const int j = tid + it * nthreads;
+    if (j < all) {
+      const int b = j >> lgM;
+      const int jj = j & (M - 1);
+      const int k = jj & (Ns - 1);
+      const int base = ((jj - k) << lgR) + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(b, base + (r << lgNs), v[it][r]);
+    }
+  }
+}
+
+// Dispatch one pass of radix 2^lgR (runtime) to the compiled radix.  An
+// in-place pass holds N * batch / THREADS values per thread whatever the radix.
+template <typename T, int NMAX, int THREADS, bool INV, bool IN_PLACE, class Load, class Store>
+__device__ __forceinline__ void fft_pass_rt(int lgR, int lgN, int batch, int lgNs, const cplx<T>* __restrict__ tw,
+                                            Load load, Store store) {
+  const int tid = threadIdx.x;
+  if (lgR == 4) {
+    fft_pass<T, 16, (NMAX / 16 + THREADS - 1) / THREADS, INV, IN_PLACE>(lgN, batch, lgNs, tw, tid, THREADS, load,
+                                                                      store);
+  } else if (lgR == 3) {
+    fft_pass<T, 8, (NMAX / 8 + THREADS - 1) / THREADS, INV, IN_PLACE>(lgN, batch, lgNs, tw, tid, THREADS, load,
+                                                                    store);
+  } else if (lgR == 2) {
+    fft_pass<T, 4, (NMAX / 4 + THREADS - 1) / THREADS, INV, IN_PLACE>(lgN, batch, lgNs, tw, tid, THREADS, load,
+                                                                    store);
+  } else {
+    fft_pass<T, 2, (NMAX / 2 + THREADS - 1) / THREADS, INV, IN_PLACE>(lgN, batch, lgNs, tw, tid, THREADS, load,
+                                                                    store);
+  }
+}
+
+// Pass plan for a transform of 2^lgN points: the remainder radix first, then
+// radix-16 passes, so that the last pass is always radix 16 (lgN >= 4).
+__device__ __forceinline__ int fft_npasses(int lgN) { return (lgN + 3) >> 2; }
+__device__ __forceinline__ int fft_pass_lgR(int lgN, int pass) {
+  const int rem = lgN & 3;
+  if (rem != 0 && pass == 0) return rem;
+  return 4;
+}
+
+// Complete transform: the first pass reads through `load0`, the last pass
+// writes through `storeN`, the passes in between run in place in the padded
+// LDS buffer `buf` (index b * bstride + i).  FIRST_IN_LDS says that load0
+// reads `buf` and LAST_IN_LDS that storeN writes it (those passes then run
+// in place).  LGR0 must equal fft_pass_lgR(lgN, 0).  Barriers
+// separate the passes; there is none after the final stores.
+template <typename T, int NMAX, int THREADS, bool INV, bool FIRST_IN_LDS, bool LAST_IN_LDS, int LGR0, class Load0,
+          class StoreN>
+__device__ void fft_run(cplx<T>* buf, int lgN, int batch, int bstride, const cplx<T>* __restrict__ tw, Load0 load0,
+                        StoreN storeN) {
+  const int np = fft_npasses(lgN);
+  auto lds_load = [&](int b, int i) { return buf[lds_pad(b * bstride + i)]; };
+  auto lds_store = [&](int b, int i, cplx<T> v) { buf[lds_pad(b * bstride + i)] = v; };
+  int lgNs = 0;
+  constexpr int I16 = (NMAX / 16 + THREADS - 1) / THREADS;
+  const int tid = threadIdx.x;
+  // first pass: the only one whose radix (2^LGR0, LGR0 = lgN mod 4 or 4) can be below 16
+  constexpr int R0 = 1 << LGR0;
+  constexpr int I0 = (NMAX / R0 + THREADS - 1) / THREADS;
+  const int lgR0 = LGR0;
+  if (np == 1) {
+    fft_pass<T, R0, I0, INV, FIRST_IN_LDS || LAST_IN_LDS>(lgN, batch, 0, tw, tid, THREADS, load0, storeN);
+    return;
+  }
+  fft_pass<T, R0, I0, INV, FIRST_IN_LDS>(lgN, batch, 0, tw, tid, THREADS, load0, lds_store);
+  __syncthreads();
+  lgNs = lgR0;
+  for (int ps = 1; ps < np - 1; ++ps) {
+    fft_pass<T, 16, I16, INV, true>(lgN, batch, lgNs, tw, tid, THREADS, lds_load, lds_store);
+    __syncthreads();
+    lgNs += 4;
+  }
+  fft_pass<T, 16, I16, INV, LAST_IN_LDS>(lgN, batch, lgNs, tw, tid, THREADS, lds_load, storeN);
+}
+
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+__device__ __forceinline__ double ipow(double x, int p) {
+  double r = 1.0;
+  for (int i = 0; i < p; ++i) r *= x;
+  return r;
+}
 
 }  // namespace sfft

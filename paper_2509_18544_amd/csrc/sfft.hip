@@ -24,9 +24,11 @@ using namespace sfft;
 namespace {
 
 constexpr int ASM_THREADS = 256;
-constexpr int ROW_NMAX_F32 = 16384;   // complex elements in the row-pass LDS buffer (128 KB)
-constexpr int ROW_NMAX_F64 = 8192;    // 128 KB
-constexpr int COL_NMAX = 4096;        // complex elements per column-pass block
+constexpr int FFT_THREADS = 512;     // row and column transform blocks
+constexpr int SUB_NMAX = 4096;       // complex FP64 elements per subtraction row-transform block (64 KB)
+constexpr int ROW_NMAX_F32 = 8192;    // complex elements in the row-pass LDS buffer (64 KB)
+constexpr int ROW_NMAX_F64 = 4096;    // 64 KB
+constexpr int COL_NMAX = 8192;        // complex elements per column-pass block (two columns)
 constexpr int MAX_ROWS_PER_BLOCK = 64;
 constexpr int WIN_THREADS = 64;
 constexpr int WIN_IMAX = 64;
@@ -34,7 +36,7 @@ constexpr int MAX_N = 8192;           // unknowns (the triangular solves keep x 
 constexpr int MAX_W = 15;
 
 struct Layout {
-  size_t U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, kp, flags, tw32, tw64, items, wrows;
+  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, kp, flags, tw32, tw64, items, wrows;
   size_t total;
 };
 
@@ -43,6 +45,8 @@ struct Derived {
   int L, nk, nb, nkk, n;
   int lgPy, lgPx, Py, Px, H;
   int nplanes;
+  int nbase, nbk, nbb;
+  int8_t base_first[MAX_BASE], base_count[MAX_BASE], out_plane[MAX_PLANES], out_q[MAX_PLANES];
   int rows_per_block, nrowblk;
   int nmom;
   int nitems, vrows, nwin, nblk;
@@ -109,6 +113,43 @@ int derive(const sfft_desc* d, Derived* D) {
   D->Px = 1 << D->lgPx;
   D->H = D->Px / 2;
   D->nplanes = D->nk + D->nb + 1;
+  // base rows and the output planes built from each (plane index, y-power)
+  D->nbk = d->dk + 1;
+  D->nbb = d->db + 1;
+  D->nbase = D->nbk + D->nbb + 1;
+  {
+    int cursor = 0;
+    for (int b = 0; b < D->nbase; ++b) {
+      D->base_first[b] = (int8_t)cursor;
+      int cnt = 0;
+      if (b < D->nbk) {
+        for (int j = 0, dd = 0; dd <= d->dk; ++dd)
+          for (int q = 0; q <= dd; ++q, ++j)
+            if (dd - q == b) {
+              D->out_plane[cursor] = (int8_t)j;
+              D->out_q[cursor] = (int8_t)q;
+              ++cursor;
+              ++cnt;
+            }
+      } else if (b < D->nbk + D->nbb) {
+        const int pb = b - D->nbk;
+        for (int j = 0, dd = 0; dd <= d->db; ++dd)
+          for (int q = 0; q <= dd; ++q, ++j)
+            if (dd - q == pb) {
+              D->out_plane[cursor] = (int8_t)(D->nk + j);
+              D->out_q[cursor] = (int8_t)q;
+              ++cursor;
+              ++cnt;
+            }
+      } else {
+        D->out_plane[cursor] = (int8_t)(D->nk + D->nb);
+        D->out_q[cursor] = 0;
+        ++cursor;
+        cnt = 1;
+      }
+      D->base_count[b] = (int8_t)cnt;
+    }
+  }
   D->csize = d->mode == SFFT_MODE_F64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
   const int rowmax = d->mode == SFFT_MODE_F64 ? ROW_NMAX_F64 : ROW_NMAX_F32;
   D->rows_per_block = std::min(MAX_ROWS_PER_BLOCK, std::min(rowmax / D->H, d->ny));
@@ -121,7 +162,6 @@ int derive(const sfft_desc* d, Derived* D) {
   // correlation pairs -> items (lag rows in chunks of JMAX), window rows, gather offsets
   D->items.clear();
   D->wrows.clear();
-  std::memset(&D->gp, 0, sizeof(D->gp));
   int vrow = 0, wo = 0;
   auto add_pair = [&](int left, int right, int hw) {
     const int h = 2 * hw + 1;
@@ -152,6 +192,11 @@ int derive(const sfft_desc* d, Derived* D) {
   for (int a = 0; a < D->nk; ++a)
     for (int b = 0; b < D->nb; ++b) D->gp.kb_off[a * D->nb + b] = add_pair(a, D->nk + b, w);
   for (int a = 0; a < D->nk; ++a) D->gp.ks_off[a] = add_pair(a, D->nk + D->nb, w);
+  // items sorted by their residue rotation (jlo mod P2) so that a wave of the
+  // correlation kernel normally takes a single case of its rotation switch
+  std::stable_sort(D->items.begin(), D->items.end(), [](const CorrItem& x, const CorrItem& y) {
+    return ((x.jlo % P2) + P2) % P2 < ((y.jlo % P2) + P2) % P2;
+  });
   D->nitems = (int)D->items.size();
   D->vrows = vrow;
   D->nwin = wo;
@@ -167,6 +212,10 @@ int derive(const sfft_desc* d, Derived* D) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// radix (log2) of the first pass of a 2^lgN-point transform: the remainder of
+// lgN mod 4, or 4 (the later passes are all radix 16)
+int first_radix_log(int lgN) { return (lgN & 3) ? (lgN & 3) : 4; }
+
 Layout layout_of(const Derived& D) {
   Layout Lo;
   size_t off = 0;
@@ -175,7 +224,15 @@ Layout layout_of(const Derived& D) {
     off += align256(bytes);
     return o;
   };
-  Lo.U = take((size_t)D.nplanes * (D.H + 1) * D.Py * D.csize);
+  Lo.Ub = take((size_t)D.nbase * D.H * D.Py * D.csize);
+  {
+    // the subtraction's spectra reuse the assembly's spectra region (not live at the same time)
+    const size_t asm_bytes = (size_t)D.nplanes * (D.H + 1) * D.Py * D.csize;
+    const size_t sub_bytes = align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>)) +
+                             align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>)) +
+                             align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>));
+    Lo.U = take(std::max(asm_bytes, sub_bytes));
+  }
   Lo.V = take((size_t)(D.H + 1) * D.vrows * sizeof(cplx<double>));
   Lo.win = take((size_t)D.nwin * sizeof(double));
   Lo.mom = take((size_t)D.ny * D.nmom * sizeof(double));
@@ -349,6 +406,19 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
   A.bpoly = D.bpoly;
   A.nmom = D.nmom;
   A.db = D.db;
+  A.nbase = D.nbase;
+  A.nbk = D.nbk;
+  A.nbb = D.nbb;
+  A.sx = 2.0 / (double)(D.nx - 1);
+  A.sy = 2.0 / (double)(D.ny - 1);
+  for (int b = 0; b < MAX_BASE; ++b) {
+    A.base_first[b] = D.base_first[b];
+    A.base_count[b] = b < D.nbase ? D.base_count[b] : 0;
+  }
+  for (int i = 0; i < MAX_PLANES; ++i) {
+    A.out_plane[i] = D.out_plane[i];
+    A.out_q[i] = D.out_q[i];
+  }
   return A;
 }
 
@@ -373,38 +443,59 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
 
   constexpr int RN = std::is_same<T, float>::value ? ROW_NMAX_F32 : ROW_NMAX_F64;
   {
-    const size_t lds = (size_t)D.rows_per_block * D.H * sizeof(cplx<T>);
-    auto kfn = row_fwd_kernel<T, ASM_THREADS, RN>;
-    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const size_t lds = (size_t)lds_padded_size(D.rows_per_block * D.H) * sizeof(cplx<T>);
     const int grid = ((D.nrowblk + 7) / 8) * 8;   // whole XCD rounds for the remap
     p->timer.begin(SFFT_STAGE_ROW_FWD, s);
-    kfn<<<grid, ASM_THREADS, lds, s>>>(A, sci, tmpl, mask, U, tw);
+    switch (first_radix_log(D.lgPx - 1)) {
+#define ROW_CASE(LG)                                                                                       \
+  case LG: {                                                                                               \
+    auto kfn = row_fwd_kernel<T, FFT_THREADS, RN, LG>;                                                     \
+    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+    kfn<<<grid, FFT_THREADS, lds, s>>>(A, sci, tmpl, mask, p->at<cplx<T>>(Lo.Ub), tw);                  \
+    break;                                                                                                 \
+  }
+      ROW_CASE(1) ROW_CASE(2) ROW_CASE(3) ROW_CASE(4)
+#undef ROW_CASE
+    }
     LAUNCH_CHECK();
     p->timer.end(s);
   }
   {
-    const int cpb = std::max(1, COL_NMAX / D.Py);
-    const size_t lds = (size_t)cpb * D.Py * sizeof(cplx<T>);
-    auto kfn = col_fwd_kernel<T, ASM_THREADS, COL_NMAX>;
-    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    dim3 grid((D.H + cpb - 1) / cpb, D.nplanes);
+    const size_t lds = (size_t)lds_padded_size(2 * D.Py) * sizeof(cplx<T>);
+    const int nblk = (D.H / 2 - 1) * D.nbase;
+    const int grid = ((nblk + 7) / 8) * 8;
     p->timer.begin(SFFT_STAGE_COL_FWD, s);
-    kfn<<<grid, ASM_THREADS, lds, s>>>(A, U, tw, cpb);
+    switch (first_radix_log(D.lgPy)) {
+#define COL_CASE(LG)                                                                                        \
+  case LG: {                                                                                                \
+    auto kfn = col_fwd_kernel<T, FFT_THREADS, COL_NMAX, LG>;                                                \
+    auto kdc = col_fwd_dc_kernel<T, FFT_THREADS, COL_NMAX, LG>;                                             \
+    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
+    HIP_TRY(hipFuncSetAttribute((const void*)kdc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
+    kdc<<<D.nbase, FFT_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.Ub), U, tw);                               \
+    if (nblk > 0) kfn<<<grid, FFT_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.Ub), U, tw);                     \
+    break;                                                                                                  \
+  }
+      COL_CASE(1) COL_CASE(2) COL_CASE(3) COL_CASE(4)
+#undef COL_CASE
+    }
     LAUNCH_CHECK();
     p->timer.end(s);
   }
   {
     const int P1 = D.Py / P2;
-    const size_t per_res = (size_t)D.nplanes * P2 * sizeof(cplx<T>);
+    const int lanes = std::max(1, ASM_THREADS / D.nitems);
+    const size_t per_res = (size_t)D.nplanes * P2 * sizeof(cplx<double>);
     int C1 = (int)std::min<size_t>((size_t)P1, (64 * 1024) / per_res);
+    if (C1 >= lanes) C1 = (C1 / lanes) * lanes;   // whole rounds of the item lanes
     C1 = std::max(C1, 1);
     const size_t stage = (size_t)C1 * per_res;
-    const size_t red = (size_t)ASM_THREADS * JMAX * sizeof(cplx<double>);
+    const size_t red = (size_t)ASM_THREADS * ((JMAX + 1) / 2) * sizeof(cplx<double>);
     const size_t lds = std::max(stage, red);
     auto kfn = corr_kernel<T, ASM_THREADS>;
     HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     p->timer.begin(SFFT_STAGE_CORR, s);
-    kfn<<<D.H + 1, ASM_THREADS, lds, s>>>(A, U, p->at<CorrItem>(Lo.items), p->at<cplx<double>>(Lo.V), tw, twd, C1);
+    kfn<<<D.H + 1, ASM_THREADS, lds, s>>>(A, U, p->at<CorrItem>(Lo.items), p->at<cplx<double>>(Lo.V), twd, C1);
     LAUNCH_CHECK();
     p->timer.end(s);
   }
@@ -414,7 +505,7 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
   LAUNCH_CHECK();
   p->timer.end(s);
   p->timer.begin(SFFT_STAGE_GATHER, s);
-  moments_reduce_kernel<ASM_THREADS><<<1, ASM_THREADS, 0, s>>>(A, p->at<double>(Lo.mom), p->at<double>(Lo.obb),
+  moments_reduce_kernel<ASM_THREADS><<<D.nb * D.nb + D.nb, ASM_THREADS, 0, s>>>(A, p->at<double>(Lo.mom), p->at<double>(Lo.obb),
                                                                p->at<double>(Lo.bb));
   LAUNCH_CHECK();
   {
@@ -449,29 +540,115 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
   const Derived& D = p->D;
   const Layout& Lo = p->Lo;
   hipStream_t s = p->stream;
-  SubParams P;
-  std::memset(&P, 0, sizeof(P));
-  P.ny = D.ny;
-  P.nx = D.nx;
-  P.w = D.w;
-  P.nk = D.nk;
-  P.nb = D.nb;
-  P.ld = ld;
-  for (int i = 0; i < D.nk; ++i) {
-    P.kpx[i] = D.kpoly.px[i];
-    P.kqy[i] = D.kpoly.qy[i];
-  }
-  for (int i = 0; i < D.nb; ++i) {
-    P.bpx[i] = D.bpoly.px[i];
-    P.bqy[i] = D.bpoly.qy[i];
-  }
-  const int L2 = D.L * D.L;
-  double* kp = p->at<double>(Lo.kp);
+  const cplx<double>* twd = p->at<cplx<double>>(Lo.tw64);
   p->timer.begin(SFFT_STAGE_SUBTRACT, s);
-  kprime_kernel<<<(L2 + 255) / 256, 256, 0, s>>>(P, coeffs, kp);
-  LAUNCH_CHECK();
-  const size_t lds = ((size_t)(SUB_TY + 2 * D.w) * (SUB_TX + 2 * D.w) + (size_t)D.nk * L2) * sizeof(double);
-  dim3 grid((D.nx + SUB_TX - 1) / SUB_TX, (D.ny + SUB_TY - 1) / SUB_TY);
+  // columns the circular x-convolution cannot produce exactly: [0, xl) and [xr, nx)
+  const int xl = std::max(0, std::min(D.nx, D.w - (D.Px - D.nx)));
+  const int xr = std::max(xl, std::min(D.nx, D.Px - D.w));
+  if (xr > xl) {
+    SpecParams S;
+    std::memset(&S, 0, sizeof(S));
+    S.ny = D.ny;
+    S.nx = D.nx;
+    S.w = D.w;
+    S.nk = D.nk;
+    S.nb = D.nb;
+    S.lgPx = D.lgPx;
+    S.H = D.H;
+    S.ld = ld;
+    S.rows_per_block = std::max(1, std::min(D.ny, SUB_NMAX / D.H));
+    S.nrowblk = (D.ny + S.rows_per_block - 1) / S.rows_per_block;
+    S.sx = 2.0 / (double)(D.nx - 1);
+    S.sy = 2.0 / (double)(D.ny - 1);
+    for (int i = 0; i < D.nk; ++i) {
+      S.kpx[i] = D.kpoly.px[i];
+      S.kqy[i] = D.kpoly.qy[i];
+    }
+    for (int i = 0; i < D.nb; ++i) {
+      S.bpx[i] = D.bpoly.px[i];
+      S.bqy[i] = D.bpoly.qy[i];
+    }
+    unsigned char* base = p->ws + Lo.U;
+    cplx<double>* Uq = reinterpret_cast<cplx<double>*>(base);
+    cplx<double>* Mh =
+        reinterpret_cast<cplx<double>*>(base + align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>)));
+    cplx<double>* K = reinterpret_cast<cplx<double>*>(
+        reinterpret_cast<unsigned char*>(Mh) + align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>)));
+    const size_t lds = (size_t)lds_padded_size(S.rows_per_block * D.H) * sizeof(cplx<double>);
+    switch (first_radix_log(D.lgPx - 1)) {
+#define SUBF_CASE(LG)                                                                                       \
+  case LG: {                                                                                                \
+    auto kf = sub_rowfwd_kernel<T, FFT_THREADS, SUB_NMAX, LG>;                                              \
+    HIP_TRY(hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
+    kf<<<S.nrowblk, FFT_THREADS, lds, s>>>(S, tmpl, Uq, twd, D.dk + 1);                                     \
+    break;                                                                                                  \
+  }
+      SUBF_CASE(1) SUBF_CASE(2) SUBF_CASE(3) SUBF_CASE(4)
+#undef SUBF_CASE
+    }
+    LAUNCH_CHECK();
+    {
+      dim3 g((D.H + 1 + 255) / 256, D.nk * D.L);
+      sub_kspec_kernel<<<g, 256, 0, s>>>(S, coeffs, K, twd);
+      LAUNCH_CHECK();
+    }
+    {
+      dim3 g((D.H + 1 + 255) / 256, (D.ny + SUBC_TY - 1) / SUBC_TY);
+      switch (D.w) {
+#define CONV_CASE(WV)                                     \
+  case WV:                                                \
+    sub_conv_kernel<WV><<<g, 256, 0, s>>>(S, Uq, K, Mh); \
+    break;
+        CONV_CASE(0) CONV_CASE(1) CONV_CASE(2) CONV_CASE(3) CONV_CASE(4) CONV_CASE(5) CONV_CASE(6) CONV_CASE(7)
+        CONV_CASE(8) CONV_CASE(9) CONV_CASE(10) CONV_CASE(11) CONV_CASE(12) CONV_CASE(13) CONV_CASE(14) CONV_CASE(15)
+#undef CONV_CASE
+        default:
+          return SFFT_EINVAL;
+      }
+      LAUNCH_CHECK();
+    }
+    switch (first_radix_log(D.lgPx - 1)) {
+#define SUBI_CASE(LG)                                                                                       \
+  case LG: {                                                                                                \
+    auto ki = sub_rowinv_kernel<T, FFT_THREADS, SUB_NMAX, LG>;                                              \
+    HIP_TRY(hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
+    ki<<<S.nrowblk, FFT_THREADS, lds, s>>>(S, Mh, sci, coeffs, diff, twd, xl, xr);                          \
+    break;                                                                                                  \
+  }
+      SUBI_CASE(1) SUBI_CASE(2) SUBI_CASE(3) SUBI_CASE(4)
+#undef SUBI_CASE
+    }
+    LAUNCH_CHECK();
+  }
+  // border columns (or the whole frame when the spectral route has no exact interior)
+  if (xl > 0 || xr < D.nx) {
+    SubParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.ny = D.ny;
+    P.nx = D.nx;
+    P.w = D.w;
+    P.nk = D.nk;
+    P.nb = D.nb;
+    P.ld = ld;
+    for (int i = 0; i < D.nk; ++i) {
+      P.kpx[i] = D.kpoly.px[i];
+      P.kqy[i] = D.kpoly.qy[i];
+    }
+    for (int i = 0; i < D.nb; ++i) {
+      P.bpx[i] = D.bpoly.px[i];
+      P.bqy[i] = D.bpoly.qy[i];
+    }
+    const int L2 = D.L * D.L;
+    double* kp = p->at<double>(Lo.kp);
+    kprime_kernel<<<(L2 + 255) / 256, 256, 0, s>>>(P, coeffs, kp);
+    LAUNCH_CHECK();
+    const size_t lds = ((size_t)(SUB_TY + 2 * D.w) * (SUB_TX + 2 * D.w) + (size_t)D.nk * L2) * sizeof(double);
+    const int bands[2][2] = {{0, xl}, {xr, D.nx}};
+    for (int bnd = 0; bnd < 2; ++bnd) {
+      P.xbeg = bands[bnd][0];
+      P.xend = bands[bnd][1];
+      if (P.xend <= P.xbeg) continue;
+      dim3 grid((P.xend - P.xbeg + SUB_TX - 1) / SUB_TX, (D.ny + SUB_TY - 1) / SUB_TY);
 #define SUB_CASE(NKV)                                                                                      \
   case NKV: {                                                                                              \
     auto kfn = subtract_kernel<T, NKV>;                                                                    \
@@ -479,17 +656,19 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
     kfn<<<grid, 256, lds, s>>>(P, sci, tmpl, kp, coeffs, diff);                                            \
     break;                                                                                                 \
   }
-  switch (D.nk) {
-    SUB_CASE(1)
-    SUB_CASE(3)
-    SUB_CASE(6)
-    SUB_CASE(10)
-    SUB_CASE(15)
-    default:
-      return SFFT_EINVAL;
-  }
+      switch (D.nk) {
+        SUB_CASE(1)
+        SUB_CASE(3)
+        SUB_CASE(6)
+        SUB_CASE(10)
+        SUB_CASE(15)
+        default:
+          return SFFT_EINVAL;
+      }
 #undef SUB_CASE
-  LAUNCH_CHECK();
+      LAUNCH_CHECK();
+    }
+  }
   p->timer.end(s);
   return SFFT_OK;
 }
@@ -606,7 +785,7 @@ int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
   HIP_TRY(hipMemcpyAsync(F, p->at<double>(Lo.omega), (size_t)D.n * D.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   for (int k = 0; k < D.nblk; ++k) {
     const int k0 = k * NB;
-    potrf_diag_kernel<<<1, 256, 0, s>>>(F, D.n, k0, p->at<double>(Lo.Linv) + (size_t)k * NB * NB, dinfo);
+    potrf_diag_kernel<<<1, 64, 0, s>>>(F, D.n, k0, p->at<double>(Lo.Linv) + (size_t)k * NB * NB, dinfo);
     LAUNCH_CHECK();
     const int T = D.nblk - k - 1;
     if (T > 0) {

@@ -11,7 +11,9 @@
 //
 // kprime_kernel : k' from theta (FP64).
 // subtract_kernel: LDS-tiled direct convolution (16 x 64 output tile per block,
-//                  4 pixels x nK accumulators per thread, FP64 accumulation).
+//                  4 pixels x nK accumulators per thread, FP64 accumulation);
+//                  used for the border columns that the spectral route below
+//                  cannot produce exactly.
 #pragma once
 
 #include "common.hpp"
@@ -20,6 +22,7 @@ namespace sfft {
 
 struct SubParams {
   int ny, nx, w, nk, nb;
+  int xbeg, xend;        // the direct kernel writes columns [xbeg, xend) only
   int64_t ld;
   int8_t kpx[15], kqy[15];
   int8_t bpx[15], bqy[15];
@@ -71,7 +74,7 @@ __global__ __launch_bounds__(256) void subtract_kernel(SubParams P, const T* __r
   double* tile = sm;
   double* kps = sm + TW * TH;
   const int y0 = blockIdx.y * SUB_TY;
-  const int x0 = blockIdx.x * SUB_TX;
+  const int x0 = P.xbeg + blockIdx.x * SUB_TX;
   const int tid = threadIdx.x;
   for (int e = tid; e < TW * TH; e += 256) {
     const int r = e / TW, c = e % TW;
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(256) void subtract_kernel(SubParams P, const T* __r
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int x = x0 + tx + i;
-    if (x >= P.nx) continue;
+    if (x >= P.xend) continue;
     const double xh = 2.0 * (double)x / (double)(P.nx - 1) - 1.0;
     double model = 0.0;
 #pragma unroll
@@ -127,6 +130,213 @@ __global__ __launch_bounds__(256) void subtract_kernel(SubParams P, const T* __r
     }
     const int64_t o = (int64_t)y * P.ld + x;
     diff[o] = (T)((double)sci[o] - model);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Spectral route for the interior (x-direction by FFT, y-direction direct)
+// ---------------------------------------------------------------------------
+// With m_a = xh^p yh^q, the kernel term is
+//   sum_{u_y} yh(y-u_y)^q [ sum_{u_x} k_a(u_y,u_x) (xh^p R)(y-u_y, x-u_x) ].
+// Along x the bracket is a convolution: with U_p(y, kx) the R2C transform of
+// the row xh^p R and K_a(u_y, kx) = sum_{u_x} k_a(u_y, u_x) e^{-2 pi i kx u_x/Px},
+//   M(y, kx) = sum_a sum_{u_y} K_a(u_y, kx) yh(y-u_y)^q U_p(y-u_y, kx)   (0 <= y-u_y < ny)
+// is the row transform of the model; a C2R transform per row gives the model,
+// exact wherever the circular x-convolution does not wrap into the frame
+// (x >= w - (Px - nx) and x < Px - w); the remaining border columns are
+// recomputed by the direct kernel above.  All of it in FP64.
+struct SpecParams {
+  int ny, nx, w, nk, nb;
+  int lgPx, H;           // Px = 2^lgPx, H = Px / 2; spectra rows hold H + 1 values
+  int64_t ld;
+  int rows_per_block;
+  int nrowblk;
+  double sx, sy;
+  int8_t kpx[15], kqy[15];
+  int8_t bpx[15], bqy[15];
+};
+
+// R2C of the rows xh^p R (p = 0..DK) -> Uq[p][y][0..H]
+template <typename T, int THREADS, int NMAX, int LGR0>
+__global__ __launch_bounds__(THREADS) void sub_rowfwd_kernel(SpecParams P, const T* __restrict__ tmpl,
+                                                             cplx<double>* __restrict__ Uq,
+                                                             const cplx<double>* __restrict__ tw, int npow) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
+  const int RB = P.rows_per_block;
+  const int y0 = blockIdx.x * RB;
+  const int H = P.H;
+  const int lgH = P.lgPx - 1;
+  const int tid = threadIdx.x;
+  const int twsx = TW_LOG - P.lgPx;
+  auto lds_load = [&](int r, int i) { return buf[lds_pad(r * H + i)]; };
+  auto lds_store = [&](int r, int i, cplx<double> v) { buf[lds_pad(r * H + i)] = v; };
+  for (int p = 0; p < npow; ++p) {
+    __syncthreads();
+    for (int e = tid; e < RB * H; e += THREADS) {
+      const int r = e >> lgH;
+      const int j = e & (H - 1);
+      const int y = y0 + r;
+      double v0 = 0.0, v1 = 0.0;
+      if (y < P.ny) {
+        const int x0 = 2 * j, x1 = 2 * j + 1;
+        const T* row = tmpl + (int64_t)y * P.ld;
+        if (x0 < P.nx) v0 = ipow((double)x0 * P.sx - 1.0, p) * (double)row[x0];
+        if (x1 < P.nx) v1 = ipow((double)x1 * P.sx - 1.0, p) * (double)row[x1];
+      }
+      buf[lds_pad(e)] = mk(v0, v1);
+    }
+    __syncthreads();
+    fft_run<double, NMAX, THREADS, false, true, true, LGR0>(buf, lgH, RB, H, tw, lds_load, lds_store);
+    __syncthreads();
+    for (int e = tid; e < RB * (H + 1); e += THREADS) {
+      const int r = e / (H + 1);
+      const int k = e - r * (H + 1);
+      const int y = y0 + r;
+      if (y >= P.ny) continue;
+      const cplx<double> z0 = buf[lds_pad(r * H)];
+      cplx<double> out;
+      if (k == 0) {
+        out = mk(z0.x + z0.y, 0.0);
+      } else if (k == H) {
+        out = mk(z0.x - z0.y, 0.0);
+      } else {
+        const cplx<double> zk = buf[lds_pad(r * H + k)];
+        const cplx<double> zm = conjg(buf[lds_pad(r * H + H - k)]);
+        const cplx<double> e2 = zk + zm;
+        const cplx<double> o2 = rot90<double, false>(zk - zm);
+        out = scale(e2 + twid<double, false>(tw, k << twsx) * o2, 0.5);
+      }
+      Uq[((int64_t)p * P.ny + y) * (H + 1) + k] = out;
+    }
+  }
+}
+
+// K[a][u_y][kx] = sum_{u_x} k_{a,u} e^{-2 pi i kx u_x / Px}
+__global__ void sub_kspec_kernel(SpecParams P, const double* __restrict__ theta, cplx<double>* __restrict__ K,
+                                 const cplx<double>* __restrict__ tw) {
+  const int L = 2 * P.w + 1;
+  const int H = P.H;
+  const int row = blockIdx.y;            // a * L + (u_y + w)
+  const int kx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kx > H) return;
+  const int a = row / L;
+  const int uyi = row - a * L;
+  const int twsx = TW_LOG - P.lgPx;
+  const int Px = 2 * H;
+  cplx<double> acc = mk(0.0, 0.0);
+  for (int uxi = 0; uxi < L; ++uxi) {
+    const int ux = uxi - P.w;
+    const double k = theta[a * L * L + uyi * L + uxi];
+    const int m = (int)(((int64_t)kx * (ux + Px)) & (Px - 1));
+    acc = acc + scale(twid<double, false>(tw, m << twsx), k);
+  }
+  K[(int64_t)row * (H + 1) + kx] = acc;
+}
+
+// M(y, kx) for a block of SUBC_TY rows; one thread per kx.  For each
+// monomial the SUBC_TY + 2W source rows (times yh^q) are loaded once into
+// registers and reused by every tap (W = w is a template parameter so that
+// every register index is static).
+constexpr int SUBC_TY = 8;   // output rows per thread
+
+template <int W>
+__global__ __launch_bounds__(256) void sub_conv_kernel(SpecParams P, const cplx<double>* __restrict__ Uq,
+                                                       const cplx<double>* __restrict__ K,
+                                                       cplx<double>* __restrict__ Mh) {
+  constexpr int L = 2 * W + 1;
+  constexpr int WIN = SUBC_TY + 2 * W;
+  const int H = P.H;
+  const int kx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y0 = blockIdx.y * SUBC_TY;
+  if (kx > H) return;
+  cplx<double> acc[SUBC_TY];
+#pragma unroll
+  for (int t = 0; t < SUBC_TY; ++t) acc[t] = mk(0.0, 0.0);
+  for (int a = 0; a < P.nk; ++a) {
+    const int p = P.kpx[a], q = P.kqy[a];
+    const cplx<double>* Up = Uq + (int64_t)p * P.ny * (H + 1) + kx;
+    const cplx<double>* Ka = K + (int64_t)a * L * (H + 1) + kx;
+    // win[i] = yh(ys)^q U_p(ys, kx), ys = y0 - W + i
+    cplx<double> win[WIN];
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) {
+      const int ys = y0 - W + i;
+      cplx<double> u = mk(0.0, 0.0);
+      if (ys >= 0 && ys < P.ny) {
+        u = Up[(int64_t)ys * (H + 1)];
+        if (q > 0) u = scale(u, ipow((double)ys * P.sy - 1.0, q));
+      }
+      win[i] = u;
+    }
+#pragma unroll
+    for (int uyi = 0; uyi < L; ++uyi) {
+      const cplx<double> kv = Ka[(int64_t)uyi * (H + 1)];
+      // output row y0 + t takes source row y0 + t - u_y = window index t + 2W - uyi
+#pragma unroll
+      for (int t = 0; t < SUBC_TY; ++t) acc[t] = acc[t] + kv * win[t + 2 * W - uyi];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < SUBC_TY; ++t) {
+    const int y = y0 + t;
+    if (y < P.ny) Mh[(int64_t)y * (H + 1) + kx] = acc[t];
+  }
+}
+
+// C2R of M(y, .) and D = S - model - background on the columns [xlo, xhi).
+// E(k) = (X(k) + conj X(H-k))/2, O(k) = (X(k) - conj X(H-k)) e^{2 pi i k/Px}/2,
+// z = IDFT_H(E + i O)/H, model(2j) = Re z(j), model(2j+1) = Im z(j).
+template <typename T, int THREADS, int NMAX, int LGR0>
+__global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const cplx<double>* __restrict__ Mh,
+                                                             const T* __restrict__ sci,
+                                                             const double* __restrict__ theta, T* __restrict__ diff,
+                                                             const cplx<double>* __restrict__ tw, int xlo, int xhi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
+  const int RB = P.rows_per_block;
+  const int y0 = blockIdx.x * RB;
+  const int H = P.H;
+  const int lgH = P.lgPx - 1;
+  const int tid = threadIdx.x;
+  const int twsx = TW_LOG - P.lgPx;
+  for (int e = tid; e < RB * H; e += THREADS) {
+    const int r = e >> lgH;
+    const int k = e & (H - 1);
+    const int y = y0 + r;
+    cplx<double> z = mk(0.0, 0.0);
+    if (y < P.ny) {
+      const cplx<double>* row = Mh + (int64_t)y * (H + 1);
+      const cplx<double> xk = row[k];
+      const cplx<double> xm = conjg(row[H - k]);
+      const cplx<double> e2 = xk + xm;                                       // 2 E
+      const cplx<double> o2 = twid<double, true>(tw, k << twsx) * (xk - xm);  // 2 O
+      z = scale(e2 + rot90<double, true>(o2), 0.5);                          // E + i O
+    }
+    buf[lds_pad(e)] = z;
+  }
+  __syncthreads();
+  auto lds_load = [&](int r, int i) { return buf[lds_pad(r * H + i)]; };
+  auto lds_store = [&](int r, int i, cplx<double> v) { buf[lds_pad(r * H + i)] = v; };
+  fft_run<double, NMAX, THREADS, true, true, true, LGR0>(buf, lgH, RB, H, tw, lds_load, lds_store);
+  __syncthreads();
+  const int L2 = (2 * P.w + 1) * (2 * P.w + 1);
+  const int nkk = P.nk * L2;
+  const double invH = 1.0 / (double)H;
+  const int span = xhi - xlo;
+  for (int e = tid; e < RB * span; e += THREADS) {
+    const int r = e / span;
+    const int x = xlo + (e - r * span);
+    const int y = y0 + r;
+    if (y >= P.ny) continue;
+    const cplx<double> z = buf[lds_pad(r * H + (x >> 1))];
+    const double model = ((x & 1) ? z.y : z.x) * invH;
+    const double xh = (double)x * P.sx - 1.0;
+    const double yh = (double)y * P.sy - 1.0;
+    double bg = 0.0;
+    for (int b = 0; b < P.nb; ++b) bg += theta[nkk + b] * ipow(xh, P.bpx[b]) * ipow(yh, P.bqy[b]);
+    const int64_t o = (int64_t)y * P.ld + x;
+    diff[o] = (T)((double)sci[o] - model - bg);
   }
 }
 

@@ -316,3 +316,24 @@ def test_planted_mistakes_are_caught():
             blk = om[a * L * L:(a + 1) * L * L, b * L * L:(b + 1) * L * L]
             flipped[a * L * L:(a + 1) * L * L, b * L * L:(b + 1) * L * L] = blk.T
     assert np.abs(flipped - ref).max() > 1e-6 * np.abs(ref).max()
+
+
+def test_single_entry_and_pixel_functions_agree_with_full_system():
+    """omega_entries / beta_entries / difference_at (used for sampled checks) match the full oracle."""
+    p = synth.random_pair(81, 30, 34, 2, 2, 1, mask_frac=0.1, stars=True)
+    om, be = oracle.normal_system_direct(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db)
+    rng = np.random.default_rng(3)
+    n = om.shape[0]
+    pairs = [tuple(x) for x in rng.integers(0, n, (25, 2))] + [(n - 1, n - 2), (0, n - 1)]
+    got = oracle.omega_entries(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, pairs)
+    ref = np.array([om[r, c] for r, c in pairs])
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(om).max())
+    rows = list(rng.integers(0, n, 10)) + [n - 1]
+    np.testing.assert_allclose(oracle.beta_entries(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, rows), be[rows],
+                               rtol=0, atol=1e-12 * np.abs(be).max())
+    th = oracle.solve(om, be)
+    D = oracle.difference(p.sci, p.tmpl, th, p.w, p.dk, p.db, mode="direct")
+    ys = [0, 0, 29, 15, 3, 29]
+    xs = [0, 33, 33, 17, 1, 0]
+    np.testing.assert_allclose(oracle.difference_at(p.sci, p.tmpl, th, p.w, p.dk, p.db, ys, xs),
+                               D[ys, xs], rtol=0, atol=1e-12 * np.abs(p.sci).max())
