@@ -149,6 +149,30 @@ int sfft_timing_enable(sfft_handle p, int enable);
  * SFFT_NUM_STAGES entries, either may be NULL), then reset the counters. */
 int sfft_timing_read(sfft_handle p, double* ms, int64_t* count);
 
+/* ---- batches: S x T science/template pairs, sizes may differ per pair ----
+ * The pairing of every science image with every template gives S x T
+ * difference images (paper, "Pipeline steps", step 1; the paper runs them
+ * serially, step 10).  A batch plan holds one single-pair plan per pair on
+ * one stream and runs the assembly of every pair, then ONE blocked FP64
+ * Cholesky + solve whose launches serve all pairs at once (the latency-bound
+ * part), then the subtraction of every pair. */
+
+/* Device bytes of a batch plan for `npairs` descriptors. Host only. */
+int sfft_batch_workspace_bytes(const sfft_desc* descs, int32_t npairs, size_t* bytes);
+
+/* Create a batch plan (allocates its workspace) bound to `hip_stream`.  Single-
+ * pair calls on a batch handle return SFFT_EINVAL; sfft_status, sfft_timing_*
+ * and sfft_destroy accept it. */
+int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sfft_handle* out);
+
+/* Enqueue build + solve + subtract for every pair.  sci, tmpl, mask, ld,
+ * coeffs, diff: HOST arrays of npairs entries holding DEVICE pointers (mask
+ * array or entries may be NULL) and row pitches; info: device int32[npairs]
+ * (may be NULL), LAPACK-style per pair, and a failed pair does not affect
+ * the others. */
+int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
+                   const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info);
+
 /* Release the plan (and its workspace if the plan allocated it). */
 void sfft_destroy(sfft_handle p);
 

@@ -65,6 +65,10 @@ def lib():
         "sfft_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "sfft_timing_enable": (ctypes.c_int, [vp, ctypes.c_int]),
         "sfft_timing_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+        "sfft_batch_workspace_bytes": (ctypes.c_int, [D, i32, ctypes.POINTER(sz)]),
+        "sfft_batch_plan": (ctypes.c_int, [D, i32, vp, ctypes.POINTER(vp)]),
+        "sfft_batch_run": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                          ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "sfft_destroy": (None, [vp]),
         "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -167,6 +171,37 @@ def sfft_timing_read(handle):
     cnt = (ctypes.c_int64 * n)()
     _check(lib().sfft_timing_read(handle, ms, cnt), "sfft_timing_read")
     return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def _desc_array(descs):
+    arr = (sfft_desc * len(descs))()
+    for i, d in enumerate(descs):
+        arr[i] = d
+    return arr
+
+
+def sfft_batch_workspace_bytes(descs) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().sfft_batch_workspace_bytes(_desc_array(descs), len(descs), ctypes.byref(b)),
+           "sfft_batch_workspace_bytes")
+    return b.value
+
+
+def sfft_batch_plan(descs, stream=None):
+    h = ctypes.c_void_p(0)
+    _check(lib().sfft_batch_plan(_desc_array(descs), len(descs), _stream_handle(stream), ctypes.byref(h)),
+           "sfft_batch_plan")
+    return h.value
+
+
+def sfft_batch_run(handle, sci, tmpl, mask, ld, coeffs, diff, info=None):
+    """sci/tmpl/mask/coeffs/diff: lists of tensors (mask entries may be None); ld: list of ints."""
+    n = len(sci)
+    P = ctypes.c_void_p * n
+    arr = lambda xs: P(*[_ptr(x) for x in xs])  # noqa: E731
+    _check(lib().sfft_batch_run(handle, arr(sci), arr(tmpl), None if mask is None else arr(mask),
+                                (ctypes.c_int64 * n)(*[int(v) for v in ld]), arr(coeffs), arr(diff), _ptr(info)),
+           "sfft_batch_run")
 
 
 def sfft_destroy(handle):

@@ -19,6 +19,21 @@ namespace sfft {
 
 constexpr int NB = 64;
 
+// One pair's solve: every kernel below takes a device table of jobs and
+// finds its pair from the block index, so that one launch serves a batch.
+struct SolveJob {
+  double* F;            // n x n factor (row-major, lower triangle used)
+  double* Linv;         // nblk blocks of NB x NB: inverses of the diagonal blocks
+  const double* omega;  // assembled normal matrix (kept for the residual)
+  const double* beta;
+  double* theta;
+  double* y;
+  double* r;
+  double* d;
+  int* info;
+  int n, nblk;
+};
+
 // Diagonal block: one wave of 64 lanes.
 //  Factorisation: lane i holds row i of the block in registers.  At column j
 //  every lane publishes its A[i][j] in LDS; the pivot d = A[j][j] is read back
@@ -29,11 +44,16 @@ constexpr int NB = 64;
 //  right-looking sweep X[j][c] /= L[j][j]; X[i][c] -= L[i][j] X[j][c] (i > j)
 //  reads L[i][j] as a broadcast from LDS.  Loops over the block are fully
 //  unrolled so that register indices are static.
-__global__ __launch_bounds__(64) void potrf_diag_kernel(double* __restrict__ F, int n, int k0,
-                                                        double* __restrict__ Linv, int* __restrict__ info) {
+__global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restrict__ jobs, int k) {
   __shared__ double Ls[NB][NB + 1];
   __shared__ double col[NB];
-  if (*info != 0) return;
+  const SolveJob J = jobs[blockIdx.x];
+  if (k >= J.nblk || *J.info != 0) return;
+  double* __restrict__ F = J.F;
+  const int n = J.n;
+  const int k0 = k * NB;
+  double* __restrict__ Linv = J.Linv + (size_t)k * NB * NB;
+  int* __restrict__ info = J.info;
   const int lane = threadIdx.x;
   const int nb = min(NB, n - k0);
   double row[NB];
@@ -93,11 +113,15 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(double* __restrict__ F, 
 }
 
 // Row block bi (after block k): L = A Linv^T, 64 x 64 x 64 in LDS.
-__global__ __launch_bounds__(256) void trsm_kernel(double* __restrict__ F, int n, int k0,
-                                                   const double* __restrict__ Linv, const int* __restrict__ info) {
+__global__ __launch_bounds__(256) void trsm_kernel(const SolveJob* __restrict__ jobs, int k) {
   __shared__ double A[NB][NB + 1];
   __shared__ double B[NB][NB + 1];
-  if (*info != 0) return;
+  const SolveJob J = jobs[blockIdx.y];
+  if (k >= J.nblk - 1 || *J.info != 0) return;
+  double* __restrict__ F = J.F;
+  const int n = J.n;
+  const int k0 = k * NB;
+  const double* __restrict__ Linv = J.Linv + (size_t)k * NB * NB;
   const int tid = threadIdx.x;
   const int nb = min(NB, n - k0);
   const int r0 = k0 + NB + blockIdx.x * NB;
@@ -137,11 +161,18 @@ __global__ __launch_bounds__(256) void trsm_kernel(double* __restrict__ F, int n
 }
 
 // Lower tiles (I >= J) of the trailing matrix: A_IJ -= L_I L_J^T.
-__global__ __launch_bounds__(256) void syrk_kernel(double* __restrict__ F, int n, int k0,
-                                                   const int* __restrict__ info) {
+__global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ jobs, int k) {
   __shared__ double A[NB][NB + 1];
   __shared__ double B[NB][NB + 1];
-  if (*info != 0) return;
+  const SolveJob job = jobs[blockIdx.y];
+  if (k >= job.nblk - 1 || *job.info != 0) return;
+  double* __restrict__ F = job.F;
+  const int n = job.n;
+  const int k0 = k * NB;
+  {
+    const int T = job.nblk - k - 1;
+    if ((int)blockIdx.x >= T * (T + 1) / 2) return;
+  }
   const int tid = threadIdx.x;
   const int nb = min(NB, n - k0);
   const int t0 = k0 + NB;  // first trailing row
@@ -189,14 +220,18 @@ __global__ __launch_bounds__(256) void syrk_kernel(double* __restrict__ F, int n
 // Forward substitution L y = b (single block, 1024 threads).  The solution
 // vector lives in LDS (dynamic, n doubles) so that values written by one
 // thread are read by the others without a trip through the caches.
-__global__ __launch_bounds__(1024) void trsv_lower_kernel(const double* __restrict__ F, int n,
-                                                          const double* __restrict__ Linv,
-                                                          const double* __restrict__ b, double* __restrict__ y,
-                                                          const int* __restrict__ info) {
+// which = 0: L y = beta; which = 1: L y = r
+__global__ __launch_bounds__(1024) void trsv_lower_kernel(const SolveJob* __restrict__ jobs, int which) {
   extern __shared__ double ys[];
   __shared__ double part[NB][17];
   __shared__ double rhs[NB];
-  if (*info != 0) return;
+  const SolveJob J = jobs[blockIdx.x];
+  if (*J.info != 0) return;
+  const double* __restrict__ F = J.F;
+  const int n = J.n;
+  const double* __restrict__ Linv = J.Linv;
+  const double* __restrict__ b = which == 0 ? J.beta : J.r;
+  double* __restrict__ y = J.y;
   const int tid = threadIdx.x;
   const int r = tid >> 4;       // row within the block (0..63)
   const int sl = tid & 15;      // slice of the columns
@@ -247,14 +282,18 @@ __global__ __launch_bounds__(1024) void trsv_lower_kernel(const double* __restri
 }
 
 // Back substitution L^T x = y (single block, 1024 threads), x in LDS.
-__global__ __launch_bounds__(1024) void trsv_upper_kernel(const double* __restrict__ F, int n,
-                                                          const double* __restrict__ Linv,
-                                                          const double* __restrict__ y, double* __restrict__ x,
-                                                          const int* __restrict__ info) {
+// which = 0: L^T theta = y; which = 1: L^T d = y
+__global__ __launch_bounds__(1024) void trsv_upper_kernel(const SolveJob* __restrict__ jobs, int which) {
   extern __shared__ double xs[];
   __shared__ double part[16][NB + 1];
   __shared__ double rhs[NB];
-  if (*info != 0) return;
+  const SolveJob J = jobs[blockIdx.x];
+  if (*J.info != 0) return;
+  const double* __restrict__ F = J.F;
+  const int n = J.n;
+  const double* __restrict__ Linv = J.Linv;
+  const double* __restrict__ y = J.y;
+  double* __restrict__ x = which == 0 ? J.theta : J.d;
   const int tid = threadIdx.x;
   const int c = tid & (NB - 1);   // column within the block
   const int rs = tid >> 6;        // row slice 0..15
@@ -317,6 +356,41 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
   for (int c = lane; c < n; c += 64) acc += a[c] * x[c];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) r[row] = b[row] - acc;
+}
+
+// F <- Omega for every job (grid: chunks x jobs)
+__global__ __launch_bounds__(256) void copy_omega_kernel(const SolveJob* __restrict__ jobs) {
+  const SolveJob J = jobs[blockIdx.y];
+  const int64_t total = (int64_t)J.n * J.n;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+    J.F[i] = J.omega[i];
+}
+
+// r = beta - Omega theta for every job (one wave per row)
+__global__ __launch_bounds__(256) void residual_jobs_kernel(const SolveJob* __restrict__ jobs) {
+  const SolveJob J = jobs[blockIdx.y];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + wave;
+  if (row >= J.n || *J.info != 0) return;
+  const double* a = J.omega + (int64_t)row * J.n;
+  double acc = 0.0;
+  for (int c = lane; c < J.n; c += 64) acc += a[c] * J.theta[c];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) J.r[row] = J.beta[row] - acc;
+}
+
+// theta += d for every job whose factorisation succeeded
+__global__ __launch_bounds__(256) void axpy_jobs_kernel(const SolveJob* __restrict__ jobs) {
+  const SolveJob J = jobs[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < J.n && *J.info == 0) J.theta[i] += J.d[i];
+}
+
+// info reset for every job
+__global__ void reset_info_kernel(const SolveJob* __restrict__ jobs, int njobs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < njobs) *jobs[i].info = 0;
 }
 
 // x += d (only if the factorisation succeeded)

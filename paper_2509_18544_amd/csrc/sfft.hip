@@ -36,7 +36,7 @@ constexpr int MAX_N = 8192;           // unknowns (the triangular solves keep x 
 constexpr int MAX_W = 15;
 
 struct Layout {
-  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, kp, flags, tw32, tw64, items, wrows;
+  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, kp, flags, tw32, tw64, items, wrows, job;
   size_t total;
 };
 
@@ -252,6 +252,7 @@ Layout layout_of(const Derived& D) {
   Lo.tw64 = take((size_t)TW_N * sizeof(cplx<double>));
   Lo.items = take((size_t)D.nitems * sizeof(CorrItem));
   Lo.wrows = take((size_t)D.wrows.size() * sizeof(WinRow));
+  Lo.job = take(sizeof(SolveJob));
   Lo.total = off;
   return Lo;
 }
@@ -360,6 +361,13 @@ struct StageTimer {
 struct sfft_plan_s {
   sfft_desc desc;
   StageTimer timer;
+  // a batch handle owns one single-pair plan per pair (all on the batch's
+  // stream) and a device table of their solve jobs
+  bool is_batch = false;
+  std::vector<sfft_plan_s*> members;
+  SolveJob* jobs_dev = nullptr;
+  std::vector<SolveJob> jobs_host;
+  int max_n = 0, max_nblk = 0;
   Derived D;
   Layout Lo;
   hipStream_t stream;
@@ -518,21 +526,68 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
   return SFFT_OK;
 }
 
-int trsv_pair(sfft_plan_s* p, const double* rhs, double* out) {
-  const Derived& D = p->D;
-  const Layout& Lo = p->Lo;
-  hipStream_t s = p->stream;
-  const int* info = p->at<int>(Lo.flags);
-  const size_t lds = (size_t)D.n * sizeof(double);
+// FP64 Cholesky, triangular solves and refinement for a table of jobs: one
+// launch per block step serves every pair of the table.
+int solve_jobs(hipStream_t s, const SolveJob* jobs, int njobs, int max_n, int max_nblk, int refine,
+               StageTimer* tm) {
+  tm->begin(SFFT_STAGE_FACTOR, s);
+  reset_info_kernel<<<(njobs + 63) / 64, 64, 0, s>>>(jobs, njobs);
+  LAUNCH_CHECK();
+  {
+    const int chunks = std::min(1024, (int)(((int64_t)max_n * max_n + 255) / 256));
+    dim3 g(chunks, njobs);
+    copy_omega_kernel<<<g, 256, 0, s>>>(jobs);
+    LAUNCH_CHECK();
+  }
+  for (int k = 0; k < max_nblk; ++k) {
+    potrf_diag_kernel<<<njobs, 64, 0, s>>>(jobs, k);
+    LAUNCH_CHECK();
+    const int T = max_nblk - k - 1;
+    if (T > 0) {
+      trsm_kernel<<<dim3(T, njobs), 256, 0, s>>>(jobs, k);
+      LAUNCH_CHECK();
+      syrk_kernel<<<dim3(T * (T + 1) / 2, njobs), 256, 0, s>>>(jobs, k);
+      LAUNCH_CHECK();
+    }
+  }
+  tm->end(s);
+  tm->begin(SFFT_STAGE_SOLVE, s);
+  const size_t lds = (size_t)max_n * sizeof(double);
   HIP_TRY(hipFuncSetAttribute((const void*)trsv_lower_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   HIP_TRY(hipFuncSetAttribute((const void*)trsv_upper_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  trsv_lower_kernel<<<1, 1024, lds, s>>>(p->at<double>(Lo.F), D.n, p->at<double>(Lo.Linv), rhs, p->at<double>(Lo.y),
-                                         info);
+  trsv_lower_kernel<<<njobs, 1024, lds, s>>>(jobs, 0);
   LAUNCH_CHECK();
-  trsv_upper_kernel<<<1, 1024, lds, s>>>(p->at<double>(Lo.F), D.n, p->at<double>(Lo.Linv), p->at<double>(Lo.y), out,
-                                         info);
+  trsv_upper_kernel<<<njobs, 1024, lds, s>>>(jobs, 0);
   LAUNCH_CHECK();
+  for (int it = 0; it < refine; ++it) {
+    residual_jobs_kernel<<<dim3((max_n + 3) / 4, njobs), 256, 0, s>>>(jobs);
+    LAUNCH_CHECK();
+    trsv_lower_kernel<<<njobs, 1024, lds, s>>>(jobs, 1);
+    LAUNCH_CHECK();
+    trsv_upper_kernel<<<njobs, 1024, lds, s>>>(jobs, 1);
+    LAUNCH_CHECK();
+    axpy_jobs_kernel<<<dim3((max_n + 255) / 256, njobs), 256, 0, s>>>(jobs);
+    LAUNCH_CHECK();
+  }
+  tm->end(s);
   return SFFT_OK;
+}
+
+SolveJob job_of(sfft_plan_s* p) {
+  const Layout& Lo = p->Lo;
+  SolveJob J;
+  J.F = p->at<double>(Lo.F);
+  J.Linv = p->at<double>(Lo.Linv);
+  J.omega = p->at<double>(Lo.omega);
+  J.beta = p->at<double>(Lo.beta);
+  J.theta = p->at<double>(Lo.theta);
+  J.y = p->at<double>(Lo.y);
+  J.r = p->at<double>(Lo.r);
+  J.d = p->at<double>(Lo.d);
+  J.info = p->at<int>(Lo.flags);
+  J.n = p->D.n;
+  J.nblk = p->D.nblk;
+  return J;
 }
 
 template <typename T>
@@ -737,6 +792,9 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
                        hipMemcpyHostToDevice, s) == hipSuccess;
   ok &= hipMemcpyAsync(p->at<void>(p->Lo.wrows), p->D.wrows.data(), p->D.wrows.size() * sizeof(WinRow),
                        hipMemcpyHostToDevice, s) == hipSuccess;
+  p->jobs_host.assign(1, job_of(p));
+  ok &= hipMemcpyAsync(p->at<void>(p->Lo.job), p->jobs_host.data(), sizeof(SolveJob), hipMemcpyHostToDevice, s) ==
+        hipSuccess;
   // host staging vectors of pageable memory: make sure the copies are done before returning
   ok &= hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
@@ -749,7 +807,7 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
 }
 
 int sfft_build_system(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld) {
-  if (p == nullptr || sci == nullptr || tmpl == nullptr || ld < p->D.nx) return SFFT_EINVAL;
+  if (p == nullptr || p->is_batch || sci == nullptr || tmpl == nullptr || ld < p->D.nx) return SFFT_EINVAL;
   int st;
   if (p->D.mode == SFFT_MODE_F64)
     st = build_impl<double>(p, (const double*)sci, (const double*)tmpl, mask, ld);
@@ -760,7 +818,7 @@ int sfft_build_system(sfft_handle p, const void* sci, const void* tmpl, const ui
 }
 
 int sfft_get_system(sfft_handle p, double* omega, double* rhs) {
-  if (p == nullptr) return SFFT_EINVAL;
+  if (p == nullptr || p->is_batch) return SFFT_EINVAL;
   if (!p->built) return SFFT_ESTATE;
   const size_t n = (size_t)p->D.n;
   if (omega != nullptr)
@@ -772,51 +830,20 @@ int sfft_get_system(sfft_handle p, double* omega, double* rhs) {
 }
 
 int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
-  if (p == nullptr || coeffs == nullptr) return SFFT_EINVAL;
+  if (p == nullptr || coeffs == nullptr || p->is_batch) return SFFT_EINVAL;
   if (!p->built) return SFFT_ESTATE;
   const Derived& D = p->D;
   const Layout& Lo = p->Lo;
   hipStream_t s = p->stream;
-  int* dinfo = p->at<int>(Lo.flags);
-  double* F = p->at<double>(Lo.F);
-  set_int_kernel<<<1, 64, 0, s>>>(dinfo, 0);
-  LAUNCH_CHECK();
-  p->timer.begin(SFFT_STAGE_FACTOR, s);
-  HIP_TRY(hipMemcpyAsync(F, p->at<double>(Lo.omega), (size_t)D.n * D.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  for (int k = 0; k < D.nblk; ++k) {
-    const int k0 = k * NB;
-    potrf_diag_kernel<<<1, 64, 0, s>>>(F, D.n, k0, p->at<double>(Lo.Linv) + (size_t)k * NB * NB, dinfo);
-    LAUNCH_CHECK();
-    const int T = D.nblk - k - 1;
-    if (T > 0) {
-      trsm_kernel<<<T, 256, 0, s>>>(F, D.n, k0, p->at<double>(Lo.Linv) + (size_t)k * NB * NB, dinfo);
-      LAUNCH_CHECK();
-      syrk_kernel<<<T * (T + 1) / 2, 256, 0, s>>>(F, D.n, k0, dinfo);
-      LAUNCH_CHECK();
-    }
-  }
-  p->timer.end(s);
-  p->timer.begin(SFFT_STAGE_SOLVE, s);
-  double* theta = p->at<double>(Lo.theta);
-  int st = trsv_pair(p, p->at<double>(Lo.beta), theta);
+  int st = solve_jobs(s, p->at<SolveJob>(Lo.job), 1, D.n, D.nblk, D.refine, &p->timer);
   if (st != SFFT_OK) return st;
-  for (int it = 0; it < D.refine; ++it) {
-    residual_kernel<<<(D.n + 3) / 4, 256, 0, s>>>(p->at<double>(Lo.omega), D.n, p->at<double>(Lo.beta), theta,
-                                                  p->at<double>(Lo.r));
-    LAUNCH_CHECK();
-    st = trsv_pair(p, p->at<double>(Lo.r), p->at<double>(Lo.d));
-    if (st != SFFT_OK) return st;
-    axpy_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(theta, p->at<double>(Lo.d), D.n, dinfo);
-    LAUNCH_CHECK();
-  }
-  copy_out_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(theta, coeffs, D.n, dinfo, info);
+  copy_out_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(p->at<double>(Lo.theta), coeffs, D.n, p->at<int>(Lo.flags), info);
   LAUNCH_CHECK();
-  p->timer.end(s);
   return SFFT_OK;
 }
 
 int sfft_residual(sfft_handle p, const double* coeffs, double* rho) {
-  if (p == nullptr || coeffs == nullptr || rho == nullptr) return SFFT_EINVAL;
+  if (p == nullptr || p->is_batch || coeffs == nullptr || rho == nullptr) return SFFT_EINVAL;
   if (!p->built) return SFFT_ESTATE;
   const Derived& D = p->D;
   const Layout& Lo = p->Lo;
@@ -830,7 +857,7 @@ int sfft_residual(sfft_handle p, const double* coeffs, double* rho) {
 }
 
 int sfft_subtract(sfft_handle p, const void* sci, const void* tmpl, const double* coeffs, void* diff, int64_t ld) {
-  if (p == nullptr || sci == nullptr || tmpl == nullptr || coeffs == nullptr || diff == nullptr || ld < p->D.nx)
+  if (p == nullptr || p->is_batch || sci == nullptr || tmpl == nullptr || coeffs == nullptr || diff == nullptr || ld < p->D.nx)
     return SFFT_EINVAL;
   if (p->D.mode == SFFT_MODE_F64)
     return subtract_impl<double>(p, (const double*)sci, (const double*)tmpl, coeffs, (double*)diff, ld);
@@ -841,7 +868,17 @@ int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out) {
   if (p == nullptr) return SFFT_EINVAL;
   HIP_TRY(hipStreamSynchronize(p->stream));
   int flags[2] = {0, 0};
-  HIP_TRY(hipMemcpy(flags, p->at<int>(p->Lo.flags), sizeof(flags), hipMemcpyDeviceToHost));
+  if (p->is_batch) {
+    // worst outcome over the pairs: the first non-zero info, any non-finite flag
+    for (sfft_plan_s* m : p->members) {
+      int f[2] = {0, 0};
+      HIP_TRY(hipMemcpy(f, m->at<int>(m->Lo.flags), sizeof(f), hipMemcpyDeviceToHost));
+      if (flags[0] == 0) flags[0] = f[0];
+      flags[1] |= f[1];
+    }
+  } else {
+    HIP_TRY(hipMemcpy(flags, p->at<int>(p->Lo.flags), sizeof(flags), hipMemcpyDeviceToHost));
+  }
   if (info_out) *info_out = flags[0];
   if (nonfinite_out) *nonfinite_out = flags[1];
   if (flags[1] != 0) return SFFT_ENONFINITE;
@@ -852,6 +889,7 @@ int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out) {
 int sfft_timing_enable(sfft_handle p, int enable) {
   if (p == nullptr) return SFFT_EINVAL;
   p->timer.on = enable != 0;
+  for (sfft_plan_s* m : p->members) m->timer.on = enable != 0;
   return SFFT_OK;
 }
 
@@ -859,6 +897,15 @@ int sfft_timing_read(sfft_handle p, double* ms, int64_t* count) {
   if (p == nullptr) return SFFT_EINVAL;
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->timer.fold();
+  for (sfft_plan_s* m : p->members) {
+    m->timer.fold();
+    for (int st = 0; st < SFFT_NUM_STAGES; ++st) {
+      p->timer.ms[st] += m->timer.ms[st];
+      p->timer.cnt[st] += m->timer.cnt[st];
+      m->timer.ms[st] = 0.0;
+      m->timer.cnt[st] = 0;
+    }
+  }
   for (int st = 0; st < SFFT_NUM_STAGES; ++st) {
     if (ms) ms[st] = p->timer.ms[st];
     if (count) count[st] = p->timer.cnt[st];
@@ -872,11 +919,101 @@ void sfft_destroy(sfft_handle p) {
   if (p == nullptr) return;
   (void)hipStreamSynchronize(p->stream);
   p->timer.release();
+  for (sfft_plan_s* m : p->members) sfft_destroy(m);
+  p->members.clear();
+  if (p->jobs_dev != nullptr) (void)hipFree(p->jobs_dev);
   if (p->owns_ws && p->ws != nullptr) {
     (void)hipStreamSynchronize(p->stream);
     (void)hipFree(p->ws);
   }
   delete p;
+}
+
+int sfft_batch_workspace_bytes(const sfft_desc* descs, int32_t npairs, size_t* bytes) {
+  if (descs == nullptr || bytes == nullptr || npairs <= 0) return SFFT_EINVAL;
+  size_t tot = 0;
+  for (int i = 0; i < npairs; ++i) {
+    size_t b = 0;
+    const int st = sfft_workspace_bytes(&descs[i], &b);
+    if (st != SFFT_OK) return st;
+    tot += b;
+  }
+  *bytes = tot + align256((size_t)npairs * sizeof(SolveJob));
+  return SFFT_OK;
+}
+
+int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sfft_handle* out) {
+  if (out == nullptr || descs == nullptr || npairs <= 0) return SFFT_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < npairs; ++i) {
+    const int st = validate(&descs[i]);
+    if (st != SFFT_OK) return st;
+  }
+  sfft_plan_s* b = new (std::nothrow) sfft_plan_s();
+  if (b == nullptr) return SFFT_ENOMEM;
+  b->is_batch = true;
+  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  b->ws = nullptr;
+  b->owns_ws = false;
+  b->built = false;
+  for (int i = 0; i < npairs; ++i) {
+    sfft_handle m = nullptr;
+    const int st = sfft_plan(&descs[i], hip_stream, nullptr, 0, &m);
+    if (st != SFFT_OK) {
+      sfft_destroy(b);
+      return st;
+    }
+    b->members.push_back(m);
+    b->jobs_host.push_back(job_of(m));
+    b->max_n = std::max(b->max_n, m->D.n);
+    b->max_nblk = std::max(b->max_nblk, m->D.nblk);
+  }
+  void* jd = nullptr;
+  if (hipMalloc(&jd, (size_t)npairs * sizeof(SolveJob)) != hipSuccess) {
+    (void)hipGetLastError();
+    sfft_destroy(b);
+    return SFFT_ENOMEM;
+  }
+  b->jobs_dev = reinterpret_cast<SolveJob*>(jd);
+  if (hipMemcpy(b->jobs_dev, b->jobs_host.data(), (size_t)npairs * sizeof(SolveJob), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    sfft_destroy(b);
+    return SFFT_EHIP;
+  }
+  *out = b;
+  return SFFT_OK;
+}
+
+int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
+                   const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info) {
+  if (b == nullptr || !b->is_batch || sci == nullptr || tmpl == nullptr || ld == nullptr || coeffs == nullptr ||
+      diff == nullptr)
+    return SFFT_EINVAL;
+  const int np = (int)b->members.size();
+  for (int i = 0; i < np; ++i)
+    if (sci[i] == nullptr || tmpl[i] == nullptr || coeffs[i] == nullptr || diff[i] == nullptr ||
+        ld[i] < b->members[i]->D.nx)
+      return SFFT_EINVAL;
+  hipStream_t s = b->stream;
+  // assembly of every pair (each launch fills the device)
+  for (int i = 0; i < np; ++i) {
+    const int st = sfft_build_system(b->members[i], sci[i], tmpl[i], mask ? mask[i] : nullptr, ld[i]);
+    if (st != SFFT_OK) return st;
+  }
+  // one batched factorisation and solve for all pairs
+  int st = solve_jobs(s, b->jobs_dev, np, b->max_n, b->max_nblk, b->members[0]->D.refine, &b->timer);
+  if (st != SFFT_OK) return st;
+  for (int i = 0; i < np; ++i) {
+    sfft_plan_s* m = b->members[i];
+    copy_out_kernel<<<(m->D.n + 255) / 256, 256, 0, s>>>(m->at<double>(m->Lo.theta), coeffs[i], m->D.n,
+                                                       m->at<int>(m->Lo.flags), info ? info + i : nullptr);
+    LAUNCH_CHECK();
+  }
+  for (int i = 0; i < np; ++i) {
+    st = sfft_subtract(b->members[i], sci[i], tmpl[i], coeffs[i], diff[i], ld[i]);
+    if (st != SFFT_OK) return st;
+  }
+  return SFFT_OK;
 }
 
 const char* sfft_strerror(int status) {

@@ -1,0 +1,86 @@
+"""Batched path: S x T pairs of uneven sizes through sfft_batch_run.
+
+Every pair of the batch must equal the single-pair API on the same inputs
+(same kernels, same schedule: bitwise), and each pair must meet the oracle
+bar.  A failed pair (fully masked) reports its own info and leaves the others
+untouched.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2509_18544_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_util import run_pair  # noqa: E402
+
+F64, F32C = B.SFFT_MODE_F64, B.SFFT_MODE_F32C
+
+SHAPES = [(96, 80, 3, 2, 2), (128, 128, 5, 1, 1), (70, 100, 2, 2, 1), (64, 64, 4, 0, 0), (150, 131, 6, 1, 2)]
+
+
+def _pairs():
+    return [synth.random_pair(200 + i, ny, nx, w, dk, db, mask_frac=0.1, stars=True)
+            for i, (ny, nx, w, dk, db) in enumerate(SHAPES)]
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_batch_equals_single_and_oracle(mode):
+    pairs = _pairs()
+    dt = torch.float64 if mode == F64 else torch.float32
+    descs = [B.make_desc(p.sci.shape[0], p.sci.shape[1], p.w, p.dk, p.db, mode) for p in pairs]
+    h = B.sfft_batch_plan(descs)
+    try:
+        S = [torch.from_numpy(p.sci).to("cuda", dt) for p in pairs]
+        R = [torch.from_numpy(p.tmpl).to("cuda", dt) for p in pairs]
+        M = [torch.from_numpy(p.mask).cuda() for p in pairs]
+        C = [torch.zeros(B.sfft_num_coeffs(d), dtype=torch.float64, device="cuda") for d in descs]
+        Dd = [torch.empty_like(s) for s in S]
+        info = torch.full((len(pairs),), -7, dtype=torch.int32, device="cuda")
+        B.sfft_batch_run(h, S, R, M, [s.stride(0) for s in S], C, Dd, info)
+        st, inf, nf = B.sfft_status(h)
+        assert st == B.SFFT_OK
+        assert info.cpu().tolist() == [0] * len(pairs)
+        for i, p in enumerate(pairs):
+            single = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=mode, want_system=False)
+            np.testing.assert_array_equal(C[i].cpu().numpy(), single["theta"])
+            np.testing.assert_array_equal(Dd[i].cpu().numpy().astype(np.float64), single["diff"])
+            cast = np.float64 if mode == F64 else np.float32
+            ref = oracle.fit(p.sci.astype(cast).astype(np.float64), p.tmpl.astype(cast).astype(np.float64),
+                             p.mask, p.w, p.dk, p.db)
+            tol = 1e-9 if mode == F64 else 1e-5
+            assert oracle.rel_err(C[i].cpu().numpy(), ref["theta"]) <= tol
+    finally:
+        B.sfft_destroy(h)
+
+
+def test_failed_pair_is_isolated():
+    pairs = _pairs()[:3]
+    pairs[1].mask[:] = 1          # pair 1: every pixel excluded -> not positive definite
+    descs = [B.make_desc(p.sci.shape[0], p.sci.shape[1], p.w, p.dk, p.db) for p in pairs]
+    h = B.sfft_batch_plan(descs)
+    try:
+        S = [torch.from_numpy(p.sci).cuda() for p in pairs]
+        R = [torch.from_numpy(p.tmpl).cuda() for p in pairs]
+        M = [torch.from_numpy(p.mask).cuda() for p in pairs]
+        C = [torch.zeros(B.sfft_num_coeffs(d), dtype=torch.float64, device="cuda") for d in descs]
+        Dd = [torch.empty_like(s) for s in S]
+        info = torch.zeros(len(pairs), dtype=torch.int32, device="cuda")
+        B.sfft_batch_run(h, S, R, M, [s.stride(0) for s in S], C, Dd, info)
+        st, inf, nf = B.sfft_status(h)
+        assert st == B.SFFT_ENOTSPD
+        got = info.cpu().tolist()
+        assert got[0] == 0 and got[1] > 0 and got[2] == 0
+        assert torch.all(C[1] == 0)
+        for i in (0, 2):
+            p = pairs[i]
+            ref = oracle.fit(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db)
+            assert oracle.rel_err(C[i].cpu().numpy(), ref["theta"]) <= 1e-9
+    finally:
+        B.sfft_destroy(h)
