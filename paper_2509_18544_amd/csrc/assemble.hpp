@@ -73,6 +73,7 @@ struct AsmParams {
   PolyTab kpoly, bpoly;
   int nmom;              // per-row moments: (2DB+1) G-moments + (DB+1) S-moments
   int db;
+  int corr_lanes;        // threads per correlation item (divides into 64)
 };
 
 // XCD-aware block order: consecutive row blocks land on the same XCD (blocks
@@ -188,10 +189,11 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(AsmParams P, const T* 
 // ---------------------------------------------------------------------------
 // Block = (column pair c >= 1, base b).  For each output plane o built from
 // base b (weight yh^q) the first FFT pass reads the pair block of Ub[b] times
-// yh^q (rows past ny are zero) and the last pass (radix 16, so its output
-// index is ky = k1 + P1 k2 with k1 < P1 = Py/16) writes X[o][kx][k1*P2 + k2]
-// directly.  Pair 0 (which holds the packed DC/Nyquist column) is done by
-// col_fwd_dc_kernel.
+// yh^q (rows past ny are zero); the last pass (radix 16, so its output index
+// is ky = k1 + P1 k2 with k1 < P1 = Py/16) places X(ky) at slot k1*P2 + k2 in
+// LDS, and the two columns are copied out as one contiguous block of
+// X[o][kx][slot].  Pair 0 (which holds the packed DC/Nyquist column) is done
+// by col_fwd_dc_kernel.
 template <typename T>
 __device__ __forceinline__ cplx<T> col_load(const AsmParams& P, const cplx<T>* __restrict__ blk, int kb, int y,
                                             int q) {
@@ -217,16 +219,21 @@ __global__ __launch_bounds__(THREADS) void col_fwd_kernel(AsmParams P, const cpl
   const cplx<T>* blk = Ub + (int64_t)b * H * Py + (int64_t)c * Py * 2;
   const int lgP1 = lgPy - LG_P2;
   const int P1 = 1 << lgP1;
+  const int tid = threadIdx.x;
   for (int oi = 0; oi < P.base_count[b]; ++oi) {
     const int o = P.out_plane[P.base_first[b] + oi];
     const int q = P.out_q[P.base_first[b] + oi];
-    cplx<T>* Xc = X + (int64_t)o * (H + 1) * Py + (int64_t)(2 * c) * Py;
+    cplx<T>* Xc = X + (int64_t)o * (H + 1) * Py + (int64_t)(2 * c) * Py;   // columns 2c, 2c+1: contiguous
     auto load0 = [&](int kb, int y) -> cplx<T> { return col_load<T>(P, blk, kb, y, q); };
-    auto store_out = [&](int kb, int ky, cplx<T> v) {
-      Xc[(int64_t)kb * Py + ((ky & (P1 - 1)) << LG_P2) + (ky >> lgP1)] = v;
+    // the last pass puts ky = k1 + P1 k2 at slot k1*P2 + k2 of the LDS buffer ...
+    auto store_res = [&](int kb, int ky, cplx<T> v) {
+      buf[lds_pad(kb * Py + ((ky & (P1 - 1)) << LG_P2) + (ky >> lgP1))] = v;
     };
-    __syncthreads();   // the previous output's LDS reads are done
-    fft_run<T, NMAX, THREADS, false, false, false, LGR0>(buf, lgPy, 2, Py, tw, load0, store_out);
+    __syncthreads();   // the previous output's copy-out has read the buffer
+    fft_run<T, NMAX, THREADS, false, false, true, LGR0>(buf, lgPy, 2, Py, tw, load0, store_res);
+    __syncthreads();
+    // ... and the two columns leave as one contiguous, coalesced block
+    for (int e = tid; e < 2 * Py; e += THREADS) Xc[e] = buf[lds_pad(e)];
   }
 }
 
@@ -308,16 +315,19 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
   const int lgPy = P.lgPy;
   const int P1 = Py >> LG_P2;
   const int tid = threadIdx.x;
-  const int nitems = P.nitems;
-  const int lanes = max(1, THREADS / nitems);
+  const int nitems = P.nitems;           // item slots, padded so rotation groups start on a wave
+  const int lanes = P.corr_lanes;        // threads per item; items never straddle a wave
+  const int ipw = 64 / lanes;            // items per wave
+  const int nwaves = (nitems + ipw - 1) / ipw;
   const int64_t pstride = (int64_t)(H + 1) * Py;
   const int per_plane = C1 * P2;
 
-  for (int base = 0; base < nitems * lanes; base += THREADS) {
-    const int gt = base + tid;
-    const int item_id = gt / lanes;
-    const int lane = gt % lanes;
-    const bool active = item_id < nitems;
+  for (int wbase = 0; wbase < nwaves; wbase += THREADS / 64) {
+    const int wv = wbase + (tid >> 6);
+    const int wl = tid & 63;
+    const int item_id = wv * ipw + wl / lanes;
+    const int lane = wl % lanes;
+    const bool active = (wl < ipw * lanes) && (item_id < nitems) && items[min(item_id, nitems - 1)].nj > 0;
     CorrItem it;
     it.left = 0;
     it.right = 0;

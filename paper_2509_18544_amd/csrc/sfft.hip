@@ -50,6 +50,7 @@ struct Derived {
   int rows_per_block, nrowblk;
   int nmom;
   int nitems, vrows, nwin, nblk;
+  int corr_lanes;
   size_t csize;   // sizeof complex element of the transforms
   std::vector<CorrItem> items;
   std::vector<WinRow> wrows;
@@ -197,6 +198,55 @@ int derive(const sfft_desc* d, Derived* D) {
   std::stable_sort(D->items.begin(), D->items.end(), [](const CorrItem& x, const CorrItem& y) {
     return ((x.jlo % P2) + P2) % P2 < ((y.jlo % P2) + P2) % P2;
   });
+  // threads per item: the largest count (<= 64) that keeps all real items in
+  // one pass of the block; each rotation group is padded with empty items
+  // (nj = 0) to a whole number of waves so that a wave takes one switch case.
+  {
+    const int real = (int)D->items.size();
+    int lanes = 1;
+    for (int l = 64; l >= 1; --l) {
+      const int ipw = 64 / l;
+      // waves needed with group padding
+      int waves = 0;
+      size_t i = 0;
+      while (i < D->items.size()) {
+        const int rot = ((D->items[i].jlo % P2) + P2) % P2;
+        int cnt = 0;
+        while (i < D->items.size() && ((D->items[i].jlo % P2) + P2) % P2 == rot) {
+          ++cnt;
+          ++i;
+        }
+        waves += (cnt + ipw - 1) / ipw;
+      }
+      if (waves * 64 <= 256 * 4) {   // at most four passes of a 256-thread block
+        if (waves <= 4) {
+          lanes = l;
+          break;
+        }
+      }
+      (void)real;
+    }
+    D->corr_lanes = lanes;
+    const int ipw = 64 / lanes;
+    std::vector<CorrItem> padded;
+    size_t i = 0;
+    while (i < D->items.size()) {
+      const int rot = ((D->items[i].jlo % P2) + P2) % P2;
+      int cnt = 0;
+      while (i < D->items.size() && ((D->items[i].jlo % P2) + P2) % P2 == rot) {
+        padded.push_back(D->items[i]);
+        ++cnt;
+        ++i;
+      }
+      while (cnt % ipw != 0) {
+        CorrItem e = padded.back();
+        e.nj = 0;
+        padded.push_back(e);
+        ++cnt;
+      }
+    }
+    D->items.swap(padded);
+  }
   D->nitems = (int)D->items.size();
   D->vrows = vrow;
   D->nwin = wo;
@@ -409,6 +459,7 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
   A.rows_per_block = D.rows_per_block;
   A.nrowblk = D.nrowblk;
   A.nitems = D.nitems;
+  A.corr_lanes = D.corr_lanes;
   A.vrows = D.vrows;
   A.kpoly = D.kpoly;
   A.bpoly = D.bpoly;
@@ -492,7 +543,7 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
   }
   {
     const int P1 = D.Py / P2;
-    const int lanes = std::max(1, ASM_THREADS / D.nitems);
+    const int lanes = D.corr_lanes;
     const size_t per_res = (size_t)D.nplanes * P2 * sizeof(cplx<double>);
     int C1 = (int)std::min<size_t>((size_t)P1, (64 * 1024) / per_res);
     if (C1 >= lanes) C1 = (C1 / lanes) * lanes;   // whole rounds of the item lanes
