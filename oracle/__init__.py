@@ -6,3 +6,4 @@ binding) never imports, links or calls it, and this package imports nothing
 from the product path.
 """
 from .sfft_oracle import *  # noqa: F401,F403
+from . import mlp_oracle  # noqa: F401,E402
