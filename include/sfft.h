@@ -112,6 +112,14 @@ int sfft_solve(sfft_handle p, double* coeffs, int32_t* info);
  * written to the device double `rho`.  Requires a prior build. */
 int sfft_residual(sfft_handle p, const double* coeffs, double* rho);
 
+/* Least-squares background for a given kernel: reads the kernel part
+ * coeffs[0 .. nK L^2) (device double) and overwrites the background part
+ * coeffs[nK L^2 .. n) with the solution c of Omega_BB c = beta_B - Omega_BK k
+ * (the normal equations restricted to the background columns, FP64).  Used
+ * to complete a predicted kernel before judging it with sfft_residual.  A
+ * singular Omega_BB leaves NaN there.  Requires a prior build (SFFT_ESTATE). */
+int sfft_fit_background(sfft_handle p, double* coeffs);
+
 /* Enqueue D = S - sum_{a,u} k_{a,u} T_u(m_a R) - sum_b c_b m_b over the whole
  * frame with the unmasked template.  sci/tmpl/diff: double* (F64) or
  * float* (F32C), pitch ld; coeffs: device double[n]. */

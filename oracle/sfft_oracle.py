@@ -46,7 +46,7 @@ __all__ = [
     "good_masks", "design_matrix", "normal_system_direct", "normal_system_fft",
     "normal_system", "solve", "difference_direct", "difference_fft", "difference",
     "fit", "rel_err", "theta_index", "cond_number", "omega_entries", "beta_entries",
-    "difference_at",
+    "difference_at", "fit_background", "residual_ratio",
 ]
 
 _WORKERS = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -390,3 +390,22 @@ def difference_at(sci, tmpl, theta, w, dk, db, ys, xs):
             acc += c[b] * xh[x] ** p * yh[y] ** q
         out.append(sci[y, x] - acc)
     return np.array(out)
+
+
+def fit_background(omega, beta, theta, nkk):
+    """Least-squares background for the fixed kernel theta[:nkk]: the normal
+    equations restricted to the background columns, Omega_BB c = beta_B -
+    Omega_BK k (the quantity a predicted kernel is completed with before
+    its residual is judged).  Returns theta with its background replaced."""
+    omega = np.asarray(omega, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)
+    k = np.asarray(theta, dtype=np.float64)[:nkk]
+    rhs = beta[nkk:] - omega[nkk:, :nkk] @ k
+    c = scipy.linalg.solve(omega[nkk:, nkk:], rhs, assume_a="pos")
+    return np.concatenate([k, c])
+
+
+def residual_ratio(omega, beta, theta):
+    """rho = ||beta - Omega theta|| / ||beta||: how far theta is from solving the normal equations."""
+    r = np.asarray(beta, dtype=np.float64) - np.asarray(omega, dtype=np.float64) @ np.asarray(theta, dtype=np.float64)
+    return float(np.linalg.norm(r) / np.linalg.norm(beta))

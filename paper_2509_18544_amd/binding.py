@@ -9,6 +9,7 @@ fails loudly -- there is no fallback of any kind.
 from __future__ import annotations
 
 import ctypes
+import glob
 import os
 import re
 
@@ -61,6 +62,7 @@ def lib():
         "sfft_get_system": (ctypes.c_int, [vp, vp, vp]),
         "sfft_solve": (ctypes.c_int, [vp, vp, vp]),
         "sfft_residual": (ctypes.c_int, [vp, vp, vp]),
+        "sfft_fit_background": (ctypes.c_int, [vp, vp]),
         "sfft_subtract": (ctypes.c_int, [vp, vp, vp, vp, vp, i64]),
         "sfft_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "sfft_timing_enable": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -71,6 +73,16 @@ def lib():
                                           ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "sfft_destroy": (None, [vp]),
         "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "sfft_mlp_create": (ctypes.c_int, [ctypes.POINTER(i32), i32, i32, vp, ctypes.POINTER(vp)]),
+        "sfft_mlp_param_count": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
+        "sfft_mlp_forward": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+        "sfft_mlp_backward": (ctypes.c_int, [vp, vp, vp, vp, i32, vp]),
+        "sfft_mlp_mse": (ctypes.c_int, [vp, vp, vp, i32, vp, vp]),
+        "sfft_mlp_adam_step": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
+                                              ctypes.c_float, ctypes.c_float]),
+        "sfft_mlp_set_weights_bf16": (ctypes.c_int, [vp, vp]),
+        "sfft_mlp_infer": (ctypes.c_int, [vp, vp, i32, vp, vp, vp, i64]),
+        "sfft_mlp_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -80,9 +92,10 @@ def lib():
     return L
 
 
-def header_symbols(path: str = HEADER_PATH):
-    """Names of the functions declared in include/sfft.h."""
-    text = open(path).read()
+def header_symbols(path: str = None):
+    """Names of the functions declared in include/*.h (or in one header)."""
+    paths = [path] if path else sorted(glob.glob(os.path.join(os.path.dirname(HEADER_PATH), "*.h")))
+    text = "".join(open(p).read() for p in paths)
     return sorted(set(re.findall(r"\b(sfft_[a-z_0-9]+)\s*\(", text)))
 
 
@@ -142,6 +155,10 @@ def sfft_solve(handle, coeffs, info):
 
 def sfft_residual(handle, coeffs, rho):
     _check(lib().sfft_residual(handle, _ptr(coeffs), _ptr(rho)), "sfft_residual")
+
+
+def sfft_fit_background(handle, coeffs):
+    _check(lib().sfft_fit_background(handle, _ptr(coeffs)), "sfft_fit_background")
 
 
 def sfft_subtract(handle, sci, tmpl, coeffs, diff, ld: int):
@@ -260,6 +277,10 @@ class Plan:
         sfft_residual(self.handle, coeffs, rho)
         return rho
 
+    def fit_background(self, coeffs):
+        sfft_fit_background(self.handle, coeffs)
+        return coeffs
+
     def subtract(self, sci, tmpl, coeffs, diff=None):
         import torch
         if diff is None:
@@ -280,3 +301,52 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- network (include/sfft_mlp.h)
+
+def sfft_mlp_create(dims, max_batch: int, stream=None):
+    nl = len(dims) - 1
+    arr = (ctypes.c_int32 * len(dims))(*[int(d) for d in dims])
+    h = ctypes.c_void_p(0)
+    _check(lib().sfft_mlp_create(arr, nl, int(max_batch), _stream_handle(stream), ctypes.byref(h)),
+           "sfft_mlp_create")
+    return h
+
+
+def sfft_mlp_param_count(handle) -> int:
+    n = ctypes.c_int64(0)
+    _check(lib().sfft_mlp_param_count(handle, ctypes.byref(n)), "sfft_mlp_param_count")
+    return n.value
+
+
+def sfft_mlp_forward(handle, params, x, batch: int, y):
+    _check(lib().sfft_mlp_forward(handle, _ptr(params), _ptr(x), int(batch), _ptr(y)), "sfft_mlp_forward")
+
+
+def sfft_mlp_backward(handle, params, x, dy, batch: int, grad):
+    _check(lib().sfft_mlp_backward(handle, _ptr(params), _ptr(x), _ptr(dy), int(batch), _ptr(grad)),
+           "sfft_mlp_backward")
+
+
+def sfft_mlp_mse(handle, y, t, batch: int, dy, loss):
+    _check(lib().sfft_mlp_mse(handle, _ptr(y), _ptr(t), int(batch), _ptr(dy), _ptr(loss)), "sfft_mlp_mse")
+
+
+def sfft_mlp_adam_step(handle, params, grad, m1, m2, step: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    _check(lib().sfft_mlp_adam_step(handle, _ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), int(step), float(lr),
+                                    float(b1), float(b2), float(eps)), "sfft_mlp_adam_step")
+
+
+def sfft_mlp_set_weights_bf16(handle, params):
+    _check(lib().sfft_mlp_set_weights_bf16(handle, _ptr(params)), "sfft_mlp_set_weights_bf16")
+
+
+def sfft_mlp_infer(handle, x, batch: int, scale, shift, theta, ld_theta: int):
+    _check(lib().sfft_mlp_infer(handle, _ptr(x), int(batch), _ptr(scale), _ptr(shift), _ptr(theta),
+                                int(ld_theta)), "sfft_mlp_infer")
+
+
+def sfft_mlp_destroy(handle):
+    if handle:
+        lib().sfft_mlp_destroy(handle)

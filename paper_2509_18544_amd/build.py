@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libsfft.so")
+SOURCES = ("sfft.hip", "mlp.hip")
 
 ARCH = "gfx950"
 FLAGS = [
@@ -34,7 +35,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, os.path.join(CSRC, "sfft.hip"), "-o", tmp]
+    cmd = [hipcc(), *FLAGS, *(os.path.join(CSRC, f) for f in SOURCES), "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -438,4 +438,59 @@ __global__ __launch_bounds__(256) void norm_ratio_kernel(const double* __restric
   if (tid == 0) *rho = (s2[0] > 0.0) ? sqrt(s1[0] / s2[0]) : sqrt(s1[0]);
 }
 
+// Background for a fixed kernel: x[nkk..n) <- solution of
+// Omega_BB c = beta_B - Omega_BK k with k = x[0..nkk) (one block of 256;
+// nb = n - nkk <= 15).  The nb x nb system is factored by one thread
+// (Cholesky, FP64); a non-positive pivot leaves NaN in the background.
+constexpr int FITBG_MAX_NB = 15;
+__global__ __launch_bounds__(256) void fit_background_kernel(const double* __restrict__ A, int n, int nkk,
+                                                             const double* __restrict__ b, double* __restrict__ x) {
+  __shared__ double rhs[FITBG_MAX_NB];
+  __shared__ double M[FITBG_MAX_NB * FITBG_MAX_NB];
+  const int nb = n - nkk;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  for (int r = wave; r < nb; r += 4) {
+    const double* a = A + (int64_t)(nkk + r) * n;
+    double acc = 0.0;
+    for (int c = lane; c < nkk; c += 64) acc += a[c] * x[c];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) rhs[r] = b[nkk + r] - acc;
+  }
+  for (int i = threadIdx.x; i < nb * nb; i += 256) M[i] = A[(int64_t)(nkk + i / nb) * n + nkk + i % nb];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  bool ok = true;
+  for (int j = 0; j < nb && ok; ++j) {
+    double d = M[j * nb + j];
+    for (int k = 0; k < j; ++k) d -= M[j * nb + k] * M[j * nb + k];
+    if (!(d > 0.0)) {
+      ok = false;
+      break;
+    }
+    d = sqrt(d);
+    M[j * nb + j] = d;
+    for (int i = j + 1; i < nb; ++i) {
+      double s = M[i * nb + j];
+      for (int k = 0; k < j; ++k) s -= M[i * nb + k] * M[j * nb + k];
+      M[i * nb + j] = s / d;
+    }
+  }
+  if (!ok) {
+    for (int i = 0; i < nb; ++i) x[nkk + i] = __builtin_nan("");
+    return;
+  }
+  for (int i = 0; i < nb; ++i) {            // L y = rhs
+    double s = rhs[i];
+    for (int k = 0; k < i; ++k) s -= M[i * nb + k] * rhs[k];
+    rhs[i] = s / M[i * nb + i];
+  }
+  for (int i = nb - 1; i >= 0; --i) {       // L^T c = y
+    double s = rhs[i];
+    for (int k = i + 1; k < nb; ++k) s -= M[k * nb + i] * rhs[k];
+    rhs[i] = s / M[i * nb + i];
+  }
+  for (int i = 0; i < nb; ++i) x[nkk + i] = rhs[i];
+}
+
 }  // namespace sfft

@@ -51,6 +51,8 @@ struct Derived {
   int nmom;
   int nitems, vrows, nwin, nblk;
   int corr_lanes;
+  int njlo;
+  int16_t jlo_list[MAX_JLO];
   size_t csize;   // sizeof complex element of the transforms
   std::vector<CorrItem> items;
   std::vector<WinRow> wrows;
@@ -173,6 +175,8 @@ int derive(const sfft_desc* d, Derived* D) {
       it.jlo = (int16_t)j;
       it.nj = (int16_t)std::min(JMAX, hw - j + 1);
       it.vrow = vrow + (j + hw);
+      it.jidx = 0;
+      it.pad_ = 0;
       D->items.push_back(it);
     }
     for (int j = 0; j < h; ++j) {
@@ -248,6 +252,19 @@ int derive(const sfft_desc* d, Derived* D) {
     D->items.swap(padded);
   }
   D->nitems = (int)D->items.size();
+  // distinct first lag rows (the correlation kernel tabulates their twiddles per chunk)
+  D->njlo = 0;
+  for (CorrItem& it : D->items) {
+    int ji = -1;
+    for (int i = 0; i < D->njlo; ++i)
+      if (D->jlo_list[i] == it.jlo) ji = i;
+    if (ji < 0) {
+      if (D->njlo >= MAX_JLO) return SFFT_EINVAL;
+      D->jlo_list[D->njlo] = it.jlo;
+      ji = D->njlo++;
+    }
+    it.jidx = (int16_t)ji;
+  }
   D->vrows = vrow;
   D->nwin = wo;
   if (D->nitems > MAX_ITEMS) return SFFT_EINVAL;
@@ -460,6 +477,8 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
   A.nrowblk = D.nrowblk;
   A.nitems = D.nitems;
   A.corr_lanes = D.corr_lanes;
+  A.njlo = D.njlo;
+  for (int i = 0; i < MAX_JLO; ++i) A.jlo_list[i] = i < D.njlo ? D.jlo_list[i] : 0;
   A.vrows = D.vrows;
   A.kpoly = D.kpoly;
   A.bpoly = D.bpoly;
@@ -544,8 +563,8 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
   {
     const int P1 = D.Py / P2;
     const int lanes = D.corr_lanes;
-    const size_t per_res = (size_t)D.nplanes * P2 * sizeof(cplx<double>);
-    int C1 = (int)std::min<size_t>((size_t)P1, (64 * 1024) / per_res);
+    const size_t per_res = (size_t)D.nplanes * P2 * sizeof(cplx<double>) + (size_t)D.njlo * JMAX * sizeof(cplx<double>);
+    int C1 = (int)std::min<size_t>((size_t)P1, (76 * 1024) / per_res);
     if (C1 >= lanes) C1 = (C1 / lanes) * lanes;   // whole rounds of the item lanes
     C1 = std::max(C1, 1);
     const size_t stage = (size_t)C1 * per_res;
@@ -754,6 +773,17 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
       P.xbeg = bands[bnd][0];
       P.xend = bands[bnd][1];
       if (P.xend <= P.xbeg) continue;
+      if (P.xend - P.xbeg < SUB_TX / 2) {
+        // narrow band: one thread per pixel
+        const size_t lds_k = (size_t)D.nk * L2 * sizeof(double);
+        HIP_TRY(hipFuncSetAttribute((const void*)subtract_band_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds_k));
+        const int64_t npx = (int64_t)(P.xend - P.xbeg) * D.ny;
+        subtract_band_kernel<<<(int)((npx + 255) / 256), 256, lds_k, s>>>(
+            P, sci, tmpl, std::is_same<T, double>::value ? 1 : 0, kp, coeffs, diff);
+        LAUNCH_CHECK();
+        continue;
+      }
       dim3 grid((P.xend - P.xbeg + SUB_TX - 1) / SUB_TX, (D.ny + SUB_TY - 1) / SUB_TY);
 #define SUB_CASE(NKV)                                                                                      \
   case NKV: {                                                                                              \
@@ -903,6 +933,17 @@ int sfft_residual(sfft_handle p, const double* coeffs, double* rho) {
                                                 p->at<double>(Lo.r));
   LAUNCH_CHECK();
   norm_ratio_kernel<<<1, 256, 0, s>>>(p->at<double>(Lo.r), p->at<double>(Lo.beta), D.n, rho);
+  LAUNCH_CHECK();
+  return SFFT_OK;
+}
+
+int sfft_fit_background(sfft_handle p, double* coeffs) {
+  if (p == nullptr || p->is_batch || coeffs == nullptr) return SFFT_EINVAL;
+  if (!p->built) return SFFT_ESTATE;
+  const Derived& D = p->D;
+  if (D.nb > FITBG_MAX_NB) return SFFT_EINVAL;
+  fit_background_kernel<<<1, 256, 0, p->stream>>>(p->at<double>(p->Lo.omega), D.n, D.nkk, p->at<double>(p->Lo.beta),
+                                                  coeffs);
   LAUNCH_CHECK();
   return SFFT_OK;
 }

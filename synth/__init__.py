@@ -69,7 +69,7 @@ def moffat_stamp(dx, dy, fwhm, beta):
     return img / img.sum(axis=(-2, -1), keepdims=True)
 
 
-def render_stars(ny, nx, xs, ys, fluxes, stamp_fn, chunk=4096):
+def render_stars(ny, nx, xs, ys, fluxes, stamp_fn, chunk=4096, half=STAMP_HALF):
     """Add ``fluxes[i] * stamp_fn(...)`` centred at (xs[i], ys[i]) into an image.
 
     ``stamp_fn(dx, dy, idx)`` returns unit-sum stamps for the star indices
@@ -77,7 +77,7 @@ def render_stars(ny, nx, xs, ys, fluxes, stamp_fn, chunk=4096):
     position.  Parts of a stamp that fall off the frame are dropped.
     """
     img = np.zeros(ny * nx, dtype=np.float64)
-    off = np.arange(-STAMP_HALF, STAMP_HALF + 1)
+    off = np.arange(-half, half + 1)
     for s in range(0, len(xs), chunk):
         idx = np.arange(s, min(s + chunk, len(xs)))
         cx = np.floor(xs[idx] + 0.5).astype(np.int64)
@@ -307,3 +307,66 @@ CONFIGS = {
     "c2": pair_c2,
     "c3": pair_c3,
 }
+
+
+# ---------------------------------------------------------------------------
+# frames at focal-plane positions (training data of the warm-start network)
+# ---------------------------------------------------------------------------
+
+WS_STAMP_HALF = 16      # the network sees 33 x 33 PSF stamps
+WS_SPAN = 0.25          # half-width of one frame in focal-plane units ([-1, 1] across the array)
+WS_CURV_S = 0.15        # science FWHM grows by 15 % from the focal-plane centre to a corner axis
+WS_CURV_T = 0.05
+
+
+def psf_stamp(fwhm, beta, half=WS_STAMP_HALF):
+    """Unit-sum Moffat PSF on a (2 half + 1)^2 grid, centred on the middle pixel."""
+    off = np.arange(-half, half + 1, dtype=np.float64)
+    return moffat_stamp(off[None, :], off[:, None], fwhm, beta)
+
+
+def pair_ws(seed, n=512, w=9, dk=2, db=2, beta=3.0):
+    """One frame of the warm-start workload: a C3-like sky-subtracted Moffat field.
+
+    The frame sits at a random focal-plane position (X, Y) in [-1, 1]^2 and
+    covers +-WS_SPAN around it; the FWHM of each image varies quadratically
+    over the focal plane, FWHM = FWHM0 (1 + curv (Xf^2 + Yf^2)), with
+    per-frame FWHM0 (seeing) drawn for the science image from [1.9, 2.6] and
+    for the template from [1.5, 1.8].  Star density, fluxes, sky, noise, the
+    DB = 2 background and the bright-star masks follow the 4088^2 recipe.
+    ``truth`` carries the network inputs: the two PSF stamps at the frame
+    centre and (X, Y).
+    """
+    rng = np.random.default_rng(seed)
+    X, Y = rng.uniform(-1.0, 1.0, 2)
+    f_s0 = rng.uniform(1.9, 2.6)
+    f_t0 = rng.uniform(1.5, 1.8)
+    nstar = int(round(2.39e-3 * n * n))
+    xs = rng.uniform(-5.0, n + 4.0, nstar)
+    ys = rng.uniform(-5.0, n + 4.0, nstar)
+    flux = powerlaw_fluxes(rng, nstar, 5e2, 5e6)
+    Xf = X + WS_SPAN * _norm_coords(xs, n)
+    Yf = Y + WS_SPAN * _norm_coords(ys, n)
+    fw_s = f_s0 * (1.0 + WS_CURV_S * (Xf * Xf + Yf * Yf))
+    fw_t = f_t0 * (1.0 + WS_CURV_T * (Xf * Xf + Yf * Yf))
+    tmodel = render_stars(n, n, xs, ys, flux,
+                          lambda dx, dy, i: moffat_stamp(dx, dy, fw_t[i][:, None, None], beta), half=12)
+    smodel = render_stars(n, n, xs, ys, flux,
+                          lambda dx, dy, i: moffat_stamp(dx, dy, fw_s[i][:, None, None], beta), half=12)
+    gx = _norm_coords(np.arange(n), n)[None, :]
+    gy = _norm_coords(np.arange(n), n)[:, None]
+    bc = rng.normal(0.0, 1.0, 6)
+    smodel = smodel + 5.0 * (bc[0] + bc[1] * gx + bc[2] * gy + 0.5 * (bc[3] * gx * gx + bc[4] * gx * gy
+                                                                      + bc[5] * gy * gy))
+    sky, read_noise = 1000.0, 8.0
+    tmpl = rng.poisson(tmodel + sky).astype(np.float64) + rng.normal(0.0, read_noise, (n, n)) - sky
+    sci = rng.poisson(smodel + sky).astype(np.float64) + rng.normal(0.0, read_noise, (n, n)) - sky
+    alpha = moffat_alpha(fw_t, beta)
+    peak = flux * (beta - 1.0) / (math.pi * alpha * alpha)
+    bright = peak > 5e4
+    m = disk_mask(n, n, xs[bright], ys[bright], 3.0 * fw_s[bright])
+    c_s = f_s0 * (1.0 + WS_CURV_S * (X * X + Y * Y))
+    c_t = f_t0 * (1.0 + WS_CURV_T * (X * X + Y * Y))
+    return Pair(sci, tmpl, m.astype(np.uint8), w=w, dk=dk, db=db,
+                truth=dict(name="WS", X=float(X), Y=float(Y), stamp_s=psf_stamp(c_s, beta),
+                           stamp_t=psf_stamp(c_t, beta), fwhm_s0=float(f_s0), fwhm_t0=float(f_t0)))

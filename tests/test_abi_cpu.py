@@ -66,3 +66,16 @@ def test_null_arguments():
     assert lib.sfft_solve(None, None, None) == B.SFFT_EINVAL
     assert lib.sfft_subtract(None, None, None, None, None, 0) == B.SFFT_EINVAL
     lib.sfft_destroy(None)
+
+
+@pytest.mark.parametrize("dims,nl,max_batch", [
+    ([10, 0, 5], 2, 4),            # zero width
+    ([10, 9000, 5], 2, 4),         # wider than the kernels take
+    ([10, 5], 0, 4),               # no layer
+    ([10, 5], 1, 0),               # empty batch
+])
+def test_mlp_create_rejects_bad_shapes(dims, nl, max_batch):
+    arr = (ctypes.c_int32 * len(dims))(*dims)
+    h = ctypes.c_void_p(0)
+    st = B.lib().sfft_mlp_create(arr, nl, max_batch, None, ctypes.byref(h))
+    assert st == B.SFFT_EINVAL and not h.value

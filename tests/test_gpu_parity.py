@@ -174,3 +174,39 @@ def test_native_library_is_loaded():
     B.lib()
     maps = open("/proc/self/maps").read()
     assert B.LIB_PATH in maps
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_fit_background_and_residual_of_a_guess(mode):
+    """A perturbed kernel is completed with the GPU's background fit and
+    judged with its residual; both against the oracle on the same guess."""
+    p = synth.random_pair(71, 96, 80, 3, 2, 2, mask_frac=0.1, stars=True)
+    s_in, r_in = inputs_as_seen(p, mode)
+    om, be = oracle.normal_system(s_in, r_in, p.mask, p.w, p.dk, p.db)
+    th = oracle.solve(om, be)
+    nkk = (2 * p.w + 1) ** 2 * oracle.num_basis(p.dk)
+    guess = th.copy()
+    guess[:nkk] += np.random.default_rng(2).normal(0.0, 0.02 * np.abs(th[:nkk]).max(), nkk)
+    guess[nkk:] = 12345.0                                  # must be overwritten
+    ref = oracle.fit_background(om, be, guess, nkk)
+    rho_ref = oracle.residual_ratio(om, be, ref)
+    dt = torch.float64 if mode == F64 else torch.float32
+    plan = B.Plan(*p.sci.shape, p.w, p.dk, p.db, mode=mode)
+    try:
+        plan.build(torch.from_numpy(s_in).to("cuda", dt), torch.from_numpy(r_in).to("cuda", dt),
+                   torch.from_numpy(p.mask).cuda())
+        C = torch.from_numpy(guess).cuda()
+        plan.fit_background(C)
+        rho = plan.residual(C)
+        torch.cuda.synchronize()
+        c = C.cpu().numpy()
+        np.testing.assert_array_equal(c[:nkk], guess[:nkk])
+        # FP32C: the FP32 forward spectra put ~2e-6 relative errors on Omega's entries, which the
+        # cancellation in beta - Omega theta of a near-solution guess amplifies
+        tol_b, tol_r = (1e-9, 1e-9) if mode == F64 else (1e-4, 1e-3)
+        eb = oracle.rel_err(c[nkk:], ref[nkk:])
+        er = abs(rho.item() - rho_ref) / rho_ref
+        print(f"mode {mode}: background {eb:.2e}, rho {rho.item():.3e} vs {rho_ref:.3e}")
+        assert eb <= tol_b and er <= tol_r
+    finally:
+        plan.close()

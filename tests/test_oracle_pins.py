@@ -337,3 +337,41 @@ def test_single_entry_and_pixel_functions_agree_with_full_system():
     xs = [0, 33, 33, 17, 1, 0]
     np.testing.assert_allclose(oracle.difference_at(p.sci, p.tmpl, th, p.w, p.dk, p.db, ys, xs),
                                D[ys, xs], rtol=0, atol=1e-12 * np.abs(p.sci).max())
+
+
+# ---------------------------------------------------------------------------
+# background for a fixed kernel, and the residual ratio that judges a guess
+# ---------------------------------------------------------------------------
+
+def test_fit_background_equals_brute_force_lstsq():
+    """For a fixed (arbitrary) kernel, the restricted normal-equation solve
+    equals an SVD least-squares fit of the background columns of the
+    brute-force design matrix to S_m - Phi_K k (which never forms Omega)."""
+    p = synth.random_pair(61, 18, 17, 2, 1, 2, mask_frac=0.15)
+    S, R, Mk, w, dk, db = p.sci, p.tmpl, p.mask, 2, 1, 2
+    phi, tgt = brute_phi(S, R, Mk, w, dk, db)
+    nkk = (2 * w + 1) ** 2 * oracle.num_basis(dk)
+    k = np.random.default_rng(5).normal(0.0, 0.2, nkk)
+    c_ref, *_ = np.linalg.lstsq(phi[:, nkk:], tgt - phi[:, :nkk] @ k, rcond=None)
+    om, be = oracle.normal_system(S, R, Mk, w, dk, db, mode="direct")
+    th = oracle.fit_background(om, be, np.concatenate([k, np.zeros(len(c_ref))]), nkk)
+    np.testing.assert_array_equal(th[:nkk], k)
+    np.testing.assert_allclose(th[nkk:], c_ref, rtol=1e-9, atol=1e-9 * np.abs(c_ref).max())
+
+
+def test_fit_background_keeps_the_full_solution_and_rho_vanishes():
+    """At the full least-squares solution the background rows already hold,
+    so completing its kernel returns its own background, and rho ~ 0; rho
+    equals ||Phi^T (S_m - Phi theta)|| / ||Phi^T S_m|| for any theta."""
+    p = synth.random_pair(62, 20, 21, 2, 1, 1, mask_frac=0.1)
+    S, R, Mk, w, dk, db = p.sci, p.tmpl, p.mask, 2, 1, 1
+    om, be = oracle.normal_system(S, R, Mk, w, dk, db, mode="direct")
+    th = oracle.solve(om, be)
+    nkk = (2 * w + 1) ** 2 * oracle.num_basis(dk)
+    th2 = oracle.fit_background(om, be, th, nkk)
+    assert oracle.rel_err(th2, th) < 1e-10
+    assert oracle.residual_ratio(om, be, th) < 1e-12
+    phi, tgt = brute_phi(S, R, Mk, w, dk, db)
+    guess = th + np.random.default_rng(1).normal(0.0, 0.01, th.size)
+    ref = np.linalg.norm(phi.T @ (tgt - phi @ guess)) / np.linalg.norm(phi.T @ tgt)
+    assert abs(oracle.residual_ratio(om, be, guess) - ref) <= 1e-9 * ref
