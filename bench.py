@@ -66,21 +66,31 @@ def kernel_source_hash():
 
 
 def stage_cost(stage, D, mode_f64):
-    """Algorithmic bytes (hbm) or flops (alu) of one launch of a stage for one pair."""
+    """Algorithmic amount of one launch of a stage for one pair: ("hbm", bytes) or ("alu", FP64 flops).
+
+    Bytes count each algorithmic read or write once.  The correlation stage
+    is priced in flops: per lag-window pair and residue k1, the P2 = 16
+    spectral products (6 flops each), one 16-point inverse DFT (168 flops) and
+    8 flops per lag row kept; the pair count and lag rows follow the fit.
+    """
     n, P, H, planes, vrows = D["N"], D["P"], D["P"] // 2, D["nplanes"], D["vrows"]
     s = 8 if mode_f64 else 4
     cs = 2 * s
-    nk, L = D["nk"], 2 * D["w"] + 1
+    nk, nb, w, L = D["nk"], D["nb"], D["w"], 2 * D["w"] + 1
+    nbase = D["nbase"]
     if stage == "row_fwd":
-        return "hbm", n * n * (2 * s + 1) + planes * n * H * cs
+        return "hbm", n * n * (2 * s + 1) + nbase * n * H * cs
     if stage == "col_fwd":
-        return "hbm", planes * H * n * cs + planes * (H + 1) * P * cs
-    if stage == "corr":
-        return "hbm", planes * (H + 1) * P * cs + (H + 1) * vrows * 16
+        return "hbm", nbase * H * n * cs + planes * (H + 1) * P * cs
     if stage == "moments":
         return "hbm", n * n * (2 * s + 1)
+    if stage == "corr":
+        residues = P // 16
+        kk = nk * (nk + 1) // 2
+        per_res = kk * (96 + 168 + 8 * (4 * w + 1)) + (nk * nb + nk) * (96 + 168 + 8 * (2 * w + 1))
+        return "alu", float(per_res) * residues * (H + 1)
     if stage == "subtract":
-        return "alu", 2.0 * nk * L * L * n * n
+        return "hbm", 3 * n * n * s
     if stage == "factor":
         m = D["ncoef"]
         return "alu", m ** 3 / 3.0
@@ -172,23 +182,29 @@ def main():
     w = pairs[0].w
     vrows = (nk * (nk + 1) // 2) * (4 * w + 1) + (nk * nb + nk) * (2 * w + 1)
     ncoef = B.sfft_num_coeffs(descs[0])
-    Dinfo = dict(N=n_px, P=P, nplanes=nk + nb + 1, vrows=vrows, nk=nk, w=w, ncoef=ncoef)
+    Dinfo = dict(N=n_px, P=P, nplanes=nk + nb + 1, vrows=vrows, nk=nk, nb=nb, w=w, ncoef=ncoef,
+                 nbase=pairs[0].dk + pairs[0].db + 3)
     # dominant single-pair kernel stage (the factor/solve stages are batched launches)
     dom = max((k for k in stages_avg if k not in ("factor", "solve")), key=lambda k: per_pair[k])
-    bound, amount = stage_cost(dom, Dinfo, mode == B.SFFT_MODE_F64)
-    roof = None
-    if bound is not None and stages_avg[dom] > 0:
-        sec = stages_avg[dom] / 1000.0
+    def roof_of(stage):
+        bound, amount = stage_cost(stage, Dinfo, mode == B.SFFT_MODE_F64)
+        # batched stages run once per step for all pairs: price them per pair
+        ms = per_pair.get(stage, 0.0) if stage in ("factor", "solve") else stages_avg.get(stage, 0.0)
+        if bound is None or ms <= 0:
+            return None
+        sec = ms / 1000.0
         if bound == "hbm":
             ach = amount / sec / 1e9
-            roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
-        else:
-            ach = amount / sec / 1e12
-            roof = dict(bound="alu", achieved=round(ach, 2), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                        frac=round(ach / FP64_VECTOR_PEAK_TFLOPS, 4), traffic=None)
-        roof.update(kernel=dom, avg_ms=round(stages_avg[dom], 4), per_launch=amount,
-                    src=kernel_source_hash())
+            return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(ach / HBM_PEAK_GBS, 4), per_launch=amount, avg_ms=round(ms, 4))
+        ach = amount / sec / 1e12
+        return dict(bound="alu", achieved=round(ach, 2), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / FP64_VECTOR_PEAK_TFLOPS, 4), per_launch=amount, avg_ms=round(ms, 4))
+
+    roof = roof_of(dom)
+    if roof is not None:
+        roof.update(kernel=dom, traffic=None, src=kernel_source_hash())
+    stage_roofs = {k: roof_of(k) for k in stages_avg if roof_of(k) is not None}
 
     # ---- accuracy of pair 0 and the CPU baseline (the oracle itself) ----
     theta_gpu = C[0].cpu().numpy()
@@ -234,6 +250,8 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": acc,
         "stages_ms_per_pair": {k: round(v, 4) for k, v in per_pair.items()},
+        "stage_rooflines": {k: {"bound": v["bound"], "frac": v["frac"], "achieved": v["achieved"],
+                                "unit": v["unit"]} for k, v in stage_roofs.items()},
     }
     print(json.dumps(out), flush=True)
     B.sfft_destroy(handle)

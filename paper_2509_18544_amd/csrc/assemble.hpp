@@ -51,7 +51,11 @@ struct CorrItem {
   int16_t left, right;   // plane indices
   int16_t jlo, nj;       // first lag row (signed) and count (<= JMAX)
   int32_t vrow;          // row in V where lag row jlo goes
+  int16_t jidx;          // index of jlo in the list of distinct first lag rows
+  int16_t pad_;
 };
+
+constexpr int MAX_JLO = 8;  // distinct first lag rows among the items
 
 constexpr int MAX_BASE = 2 * MAX_DEG + 3;   // x-weighted base rows: DK+1 + DB+1 + 1
 
@@ -74,6 +78,8 @@ struct AsmParams {
   int nmom;              // per-row moments: (2DB+1) G-moments + (DB+1) S-moments
   int db;
   int corr_lanes;        // threads per correlation item (divides into 64)
+  int njlo;              // distinct first lag rows and their values
+  int16_t jlo_list[MAX_JLO];
 };
 
 // XCD-aware block order: consecutive row blocks land on the same XCD (blocks
@@ -292,14 +298,11 @@ __global__ __launch_bounds__(THREADS) void col_fwd_dc_kernel(AsmParams P, const 
 // threads that split the residues; at the end the lanes are summed in LDS.
 // Products, the inner transform and the accumulation are FP64 in both modes.
 template <int S>
-__device__ __forceinline__ void corr_accumulate(cplx<double>* acc, const cplx<double>* f, cplx<double> tj,
-                                                const cplx<double> step) {
+__device__ __forceinline__ void corr_accumulate(cplx<double>* acc, const cplx<double>* f,
+                                                const cplx<double>* __restrict__ tw) {
   // all JMAX rows are accumulated (rows past the item's count are never written out)
 #pragma unroll
-  for (int t = 0; t < JMAX; ++t) {
-    acc[t] = acc[t] + tj * f[(S + t) & (P2 - 1)];
-    tj = tj * step;
-  }
+  for (int t = 0; t < JMAX; ++t) acc[t] = acc[t] + tw[t] * f[(S + t) & (P2 - 1)];
 }
 
 template <typename T, int THREADS>
@@ -321,6 +324,8 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
   const int nwaves = (nitems + ipw - 1) / ipw;
   const int64_t pstride = (int64_t)(H + 1) * Py;
   const int per_plane = C1 * P2;
+  // outer twiddles e^{2 pi i k1 (jlo + t)/Py} of the chunk, per distinct jlo, after the spectra
+  cplx<double>* twc = stage + P.nplanes * per_plane;
 
   for (int wbase = 0; wbase < nwaves; wbase += THREADS / 64) {
     const int wv = wbase + (tid >> 6);
@@ -349,6 +354,15 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
         const cplx<T> x = U[pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o];
         stage[pl * per_plane + o] = mk((double)x.x, (double)x.y);
       }
+      for (int e = tid; e < P.njlo * nc * JMAX; e += THREADS) {
+        const int ji = e / (nc * JMAX);
+        const int r = e - ji * (nc * JMAX);
+        const int c = r / JMAX;
+        const int t = r - c * JMAX;
+        const int j = (int)P.jlo_list[ji] + t;
+        const int m = (((k1c + c) * j) % Py + Py) % Py;
+        twc[e] = conjg(twd[m << (TW_LOG - lgPy)]);
+      }
       __syncthreads();
       if (!active) continue;
       for (int c = lane; c < nc; c += lanes) {
@@ -359,14 +373,12 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
 #pragma unroll
         for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(xa[k2], xb[k2]);
         dft16<double, true>(z);
-        // outer twiddle e^{2 pi i k1 j / Py} for j = jlo + t, by recurrence in FP64
-        const int m0 = ((k1 * (int)it.jlo) % Py + Py) % Py;
-        const cplx<double> tj = conjg(twd[m0 << (TW_LOG - lgPy)]);
-        const cplx<double> step = conjg(twd[k1 << (TW_LOG - lgPy)]);
+        const cplx<double>* twt = twc + ((int)it.jidx * nc + c) * JMAX;
+        (void)k1;
         switch (srot) {
 #define CORR_CASE(SV) \
   case SV:            \
-    corr_accumulate<SV>(acc, z, tj, step); \
+    corr_accumulate<SV>(acc, z, twt); \
     break;
           CORR_CASE(0) CORR_CASE(1) CORR_CASE(2) CORR_CASE(3) CORR_CASE(4) CORR_CASE(5) CORR_CASE(6) CORR_CASE(7)
           CORR_CASE(8) CORR_CASE(9) CORR_CASE(10) CORR_CASE(11) CORR_CASE(12) CORR_CASE(13) CORR_CASE(14)

@@ -60,6 +60,61 @@ __global__ void kprime_kernel(SubParams P, const double* __restrict__ theta, dou
 constexpr int SUB_TY = 16;
 constexpr int SUB_TX = 64;
 
+// Direct D on a narrow column band [P.xbeg, P.xend): one thread per pixel,
+// k' in LDS, template pixels through the cache.  Same arithmetic as below.
+__global__ __launch_bounds__(256) void subtract_band_kernel(SubParams P, const void* __restrict__ sci_v,
+                                                            const void* __restrict__ tmpl_v, int is_f64,
+                                                            const double* __restrict__ kp,
+                                                            const double* __restrict__ theta, void* __restrict__ diff_v) {
+  extern __shared__ double kps[];
+  const int w = P.w;
+  const int L = 2 * w + 1;
+  const int L2 = L * L;
+  const int bw = P.xend - P.xbeg;
+  for (int e = threadIdx.x; e < P.nk * L2; e += 256) kps[e] = kp[e];
+  __syncthreads();
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= bw * P.ny) return;
+  const int y = id / bw;
+  const int x = P.xbeg + (id - y * bw);
+  auto tv = [&](int yy, int xx) -> double {
+    const int64_t o = (int64_t)yy * P.ld + xx;
+    return is_f64 ? reinterpret_cast<const double*>(tmpl_v)[o] : (double)reinterpret_cast<const float*>(tmpl_v)[o];
+  };
+  const double yh = 2.0 * (double)y / (double)(P.ny - 1) - 1.0;
+  const double xh = 2.0 * (double)x / (double)(P.nx - 1) - 1.0;
+  double model = 0.0;
+  for (int a = 0; a < P.nk; ++a) {
+    double acc = 0.0;
+    for (int uy = -w; uy <= w; ++uy) {
+      const int sy = y - uy;
+      if (sy < 0 || sy >= P.ny) continue;
+      for (int ux = -w; ux <= w; ++ux) {
+        const int sx = x - ux;
+        if (sx < 0 || sx >= P.nx) continue;
+        acc += kps[a * L2 + (uy + w) * L + (ux + w)] * tv(sy, sx);
+      }
+    }
+    double m = 1.0;
+    for (int t = 0; t < P.kpx[a]; ++t) m *= xh;
+    for (int t = 0; t < P.kqy[a]; ++t) m *= yh;
+    model += m * acc;
+  }
+  const int nkk = P.nk * L2;
+  for (int b = 0; b < P.nb; ++b) {
+    double m = 1.0;
+    for (int t = 0; t < P.bpx[b]; ++t) m *= xh;
+    for (int t = 0; t < P.bqy[b]; ++t) m *= yh;
+    model += theta[nkk + b] * m;
+  }
+  const int64_t o = (int64_t)y * P.ld + x;
+  if (is_f64) {
+    reinterpret_cast<double*>(diff_v)[o] = reinterpret_cast<const double*>(sci_v)[o] - model;
+  } else {
+    reinterpret_cast<float*>(diff_v)[o] = (float)((double)reinterpret_cast<const float*>(sci_v)[o] - model);
+  }
+}
+
 // Dynamic LDS: tile (SUB_TY + 2w) x (SUB_TX + 2w) doubles, then nK * L^2 doubles of k'.
 template <typename T, int NK>
 __global__ __launch_bounds__(256) void subtract_kernel(SubParams P, const T* __restrict__ sci,
