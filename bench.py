@@ -65,6 +65,25 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+STAGE_KERNEL = {"corr": "corr_kernel", "col_fwd": "col_fwd_kernel", "row_fwd": "row_fwd_kernel",
+                "subtract": "sub_conv_kernel", "moments": "moments_kernel", "row_win": "row_win_kernel"}
+
+
+def measured_traffic(stage, mode, src):
+    """HBM bytes per launch of the stage's kernel from the committed rocprofv3 counter
+    summaries (profiles/*.md lines 'traffic: kernel=K mode=M src=H bytes_per_launch=N'),
+    or None when none was taken for the current kernel sources."""
+    import glob
+    import re
+    kern = STAGE_KERNEL.get(stage)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            m = re.match(r"traffic: kernel=(\S+) mode=(\S+) src=(\S+) bytes_per_launch=(\d+)", line.strip())
+            if m and m.group(1) == kern and m.group(2) == mode and m.group(3) == src:
+                return int(m.group(4))
+    return None
+
+
 def stage_cost(stage, D, mode_f64):
     """Algorithmic amount of one launch of a stage for one pair: ("hbm", bytes) or ("alu", FP64 flops).
 
@@ -106,6 +125,7 @@ def main():
     ap.add_argument("--mode", choices=["f32c", "f64"], default="f32c")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default correlation chunk")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -145,6 +165,12 @@ def main():
     info = torch.zeros(len(pairs), dtype=torch.int32, device=dev)
     lds = [x.stride(0) for x in S]
     torch.cuda.synchronize()
+
+    tuned = None
+    if not args.no_autotune:
+        # plan-time tuning on pair 0 (outside the timed region)
+        tuned = B.sfft_autotune(handle, S[0], R[0], M[0], lds[0])
+        log("[bench] autotune (chunk, ms): " + ", ".join(f"({c}, {t:.3f})" for c, t in tuned))
 
     def step():
         B.sfft_batch_run(handle, S, R, M, lds, C, Dd, info)
@@ -203,7 +229,8 @@ def main():
 
     roof = roof_of(dom)
     if roof is not None:
-        roof.update(kernel=dom, traffic=None, src=kernel_source_hash())
+        src = kernel_source_hash()
+        roof.update(kernel=dom, traffic=measured_traffic(dom, args.mode, src), src=src)
     stage_roofs = {k: roof_of(k) for k in stages_avg if roof_of(k) is not None}
 
     # ---- accuracy of pair 0 and the CPU baseline (the oracle itself) ----
@@ -245,7 +272,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["label"] + f"; {args.mode.upper()} mode; batch of {args.batch} "
                                              f"distinct pairs per step (one batched run)",
-                   "global_batch": args.batch, "frame": n_px, "fft_size": P, "coefficients": ncoef},
+                   "global_batch": args.batch, "frame": n_px, "fft_size": P, "coefficients": ncoef,
+                   "corr_chunk_autotune": tuned},
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy": acc,

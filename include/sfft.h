@@ -67,8 +67,23 @@ typedef struct {
   int32_t dk, db;        /* polynomial degree of the kernel's / background's spatial variation */
   int32_t mode;          /* SFFT_MODE_F64 or SFFT_MODE_F32C                                    */
   int32_t refine_steps;  /* iterative-refinement steps after the Cholesky solve; -1 = 1        */
-  int32_t flags;         /* reserved, must be 0                                               */
+  int32_t flags;         /* assembly route, one of SFFT_FLAG_ASSEMBLY_* (other bits must be 0) */
 } sfft_desc;
+
+/* How the lag windows of Omega and beta are computed (sfft_desc.flags).
+ * Both routes give the same sums up to rounding:
+ *   FFT    -- zero-padded transforms, spectral products, pruned inverses
+ *             (cost ~ P^2 log P per plane; the route for large frames);
+ *   DIRECT -- plain FP64 sums over the frame, sum_z X_l(z) X_r(z + d), for
+ *             every lag d of every window (cost ~ lags * N^2; wins for small
+ *             frames; needs nx <= 1024 and w <= 9, else SFFT_EINVAL);
+ *   AUTO   -- DIRECT when it is allowed and needs at most 1e9 multiply-adds,
+ *             else FFT. */
+enum {
+  SFFT_FLAG_ASSEMBLY_AUTO = 0,
+  SFFT_FLAG_ASSEMBLY_FFT = 1,
+  SFFT_FLAG_ASSEMBLY_DIRECT = 2
+};
 
 typedef struct sfft_plan_s* sfft_handle;
 
@@ -180,6 +195,30 @@ int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sf
  * the others. */
 int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
                    const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info);
+
+/* Tune the plan on real inputs (sci/tmpl/mask/ld as for sfft_build_system;
+ * for a batch handle, pair 0's buffers): builds the system once, then times
+ * the correlation kernel for each candidate residue chunk (the number of
+ * spectral residues staged in LDS per step, which sets the LDS per block and
+ * so the blocks per CU) and keeps the fastest in the plan -- and in every
+ * batch member with pair 0's descriptor.  Later builds use it; their results
+ * equal the untuned ones up to rounding (the residue sums are regrouped).
+ * Synchronises the stream.  Optional report (host arrays of capacity cap):
+ * c1_out[i] chunk, ms_out[i] average kernel time; *count_out entries.  A plan
+ * on the direct route has nothing to tune (count 0). */
+int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld, int32_t* c1_out,
+                  float* ms_out, int32_t cap, int32_t* count_out);
+
+/* Capture one sfft_batch_run with these buffers into a HIP graph held by the
+ * batch handle (replacing an earlier capture); nothing runs yet.  The batch
+ * stream must not be the null stream.  Stage timing is suspended during the
+ * capture.  The captured pointers must stay valid while the graph is used. */
+int sfft_batch_capture(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
+                       const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info);
+
+/* Replay the captured batch run on the batch stream: one graph launch for all
+ * pairs.  SFFT_ESTATE without a capture. */
+int sfft_batch_launch(sfft_handle b);
 
 /* Release the plan (and its workspace if the plan allocated it). */
 void sfft_destroy(sfft_handle p);

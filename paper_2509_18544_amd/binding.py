@@ -28,6 +28,10 @@ SFFT_ENONFINITE = -6
 SFFT_MODE_F64 = 0
 SFFT_MODE_F32C = 1
 
+SFFT_FLAG_ASSEMBLY_AUTO = 0
+SFFT_FLAG_ASSEMBLY_FFT = 1
+SFFT_FLAG_ASSEMBLY_DIRECT = 2
+
 
 class SfftError(RuntimeError):
     def __init__(self, status: int, where: str):
@@ -71,6 +75,11 @@ def lib():
         "sfft_batch_plan": (ctypes.c_int, [D, i32, vp, ctypes.POINTER(vp)]),
         "sfft_batch_run": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                           ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
+        "sfft_batch_capture": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                              ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
+        "sfft_batch_launch": (ctypes.c_int, [vp]),
+        "sfft_autotune": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float),
+                                         i32, ctypes.POINTER(i32)]),
         "sfft_destroy": (None, [vp]),
         "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sfft_mlp_create": (ctypes.c_int, [ctypes.POINTER(i32), i32, i32, vp, ctypes.POINTER(vp)]),
@@ -221,6 +230,30 @@ def sfft_batch_run(handle, sci, tmpl, mask, ld, coeffs, diff, info=None):
            "sfft_batch_run")
 
 
+def sfft_batch_capture(handle, sci, tmpl, mask, ld, coeffs, diff, info=None):
+    """As sfft_batch_run, but captured into the handle's HIP graph (nothing runs)."""
+    n = len(sci)
+    P = ctypes.c_void_p * n
+    arr = lambda xs: P(*[_ptr(x) for x in xs])  # noqa: E731
+    _check(lib().sfft_batch_capture(handle, arr(sci), arr(tmpl), None if mask is None else arr(mask),
+                                    (ctypes.c_int64 * n)(*[int(v) for v in ld]), arr(coeffs), arr(diff),
+                                    _ptr(info)), "sfft_batch_capture")
+
+
+def sfft_autotune(handle, sci, tmpl, mask, ld: int, cap: int = 16):
+    """Tune the plan on these inputs; returns [(chunk, ms), ...] of the candidates timed."""
+    c1 = (ctypes.c_int32 * max(cap, 1))()
+    ms = (ctypes.c_float * max(cap, 1))()
+    cnt = ctypes.c_int32(0)
+    _check(lib().sfft_autotune(handle, _ptr(sci), _ptr(tmpl), _ptr(mask), int(ld), c1, ms, int(cap),
+                               ctypes.byref(cnt)), "sfft_autotune")
+    return [(int(c1[i]), float(ms[i])) for i in range(cnt.value)]
+
+
+def sfft_batch_launch(handle):
+    _check(lib().sfft_batch_launch(handle), "sfft_batch_launch")
+
+
 def sfft_destroy(handle):
     if handle:
         lib().sfft_destroy(handle)
@@ -242,9 +275,9 @@ def _stream_handle(stream):
 class Plan:
     """Owning wrapper: one plan on one stream, buffers as torch tensors."""
 
-    def __init__(self, ny, nx, w, dk, db, mode=SFFT_MODE_F64, refine_steps=-1, stream=None):
+    def __init__(self, ny, nx, w, dk, db, mode=SFFT_MODE_F64, refine_steps=-1, stream=None, flags=0):
         import torch
-        self.desc = make_desc(ny, nx, w, dk, db, mode, refine_steps)
+        self.desc = make_desc(ny, nx, w, dk, db, mode, refine_steps, flags)
         self.n = sfft_num_coeffs(self.desc)
         self.mode = mode
         self.dtype = torch.float64 if mode == SFFT_MODE_F64 else torch.float32

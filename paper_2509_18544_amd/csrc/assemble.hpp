@@ -80,6 +80,7 @@ struct AsmParams {
   int corr_lanes;        // threads per correlation item (divides into 64)
   int njlo;              // distinct first lag rows and their values
   int16_t jlo_list[MAX_JLO];
+  int dir_tpr;           // direct route: threads per image row (power of two)
 };
 
 // XCD-aware block order: consecutive row blocks land on the same XCD (blocks
@@ -297,6 +298,15 @@ __global__ __launch_bounds__(THREADS) void col_fwd_dc_kernel(AsmParams P, const 
 // index static.  Item i (pair, lag rows) is handled by `lanes` consecutive
 // threads that split the residues; at the end the lanes are summed in LDS.
 // Products, the inner transform and the accumulation are FP64 in both modes.
+// Staged spectra: residue c of plane pl at stage[pl * corr_plane_stride(C1) + c * CORR_RS].
+// The padded strides (17 complex values per residue, plane stride = 3 mod 16)
+// spread the 16-byte reads of a wave, whose lanes take different residues and
+// planes, over the LDS banks instead of piling them on one bank quad.
+constexpr int CORR_RS = P2 + 1;
+__host__ __device__ constexpr int corr_plane_stride(int c1) {
+  return ((c1 * CORR_RS + 12) & ~15) + 3;
+}
+
 template <int S>
 __device__ __forceinline__ void corr_accumulate(cplx<double>* acc, const cplx<double>* f,
                                                 const cplx<double>* __restrict__ tw) {
@@ -306,7 +316,7 @@ __device__ __forceinline__ void corr_accumulate(cplx<double>* acc, const cplx<do
 }
 
 template <typename T, int THREADS>
-__global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T>* __restrict__ U,
+__global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cplx<T>* __restrict__ U,
                                                        const CorrItem* __restrict__ items,
                                                        cplx<double>* __restrict__ V,
                                                        const cplx<double>* __restrict__ twd, int C1) {
@@ -323,7 +333,7 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
   const int ipw = 64 / lanes;            // items per wave
   const int nwaves = (nitems + ipw - 1) / ipw;
   const int64_t pstride = (int64_t)(H + 1) * Py;
-  const int per_plane = C1 * P2;
+  const int per_plane = corr_plane_stride(C1);
   // outer twiddles e^{2 pi i k1 (jlo + t)/Py} of the chunk, per distinct jlo, after the spectra
   cplx<double>* twc = stage + P.nplanes * per_plane;
 
@@ -352,7 +362,7 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
         const int pl = e / (nc * P2);
         const int o = e - pl * (nc * P2);
         const cplx<T> x = U[pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o];
-        stage[pl * per_plane + o] = mk((double)x.x, (double)x.y);
+        stage[pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1))] = mk((double)x.x, (double)x.y);
       }
       for (int e = tid; e < P.njlo * nc * JMAX; e += THREADS) {
         const int ji = e / (nc * JMAX);
@@ -367,8 +377,8 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
       if (!active) continue;
       for (int c = lane; c < nc; c += lanes) {
         const int k1 = k1c + c;
-        const cplx<double>* xa = stage + it.left * per_plane + c * P2;
-        const cplx<double>* xb = stage + it.right * per_plane + c * P2;
+        const cplx<double>* xa = stage + it.left * per_plane + c * CORR_RS;
+        const cplx<double>* xb = stage + it.right * per_plane + c * CORR_RS;
         cplx<double> z[P2];
 #pragma unroll
         for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(xa[k2], xb[k2]);
@@ -413,6 +423,125 @@ __global__ __launch_bounds__(THREADS) void corr_kernel(AsmParams P, const cplx<T
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// direct route: lag windows as plain sums over the frame (no transforms)
+// ---------------------------------------------------------------------------
+// win[out + (dx + hw)] = sum_y,x X_l(y, x) X_r(y + dy, x + dx) for one window
+// row (pair, dy), dx in [-hw, hw]; X_r is zero outside the frame.  Planes:
+// 0..nK-1 the template planes m_a G_R R, nK..nK+nB-1 the background planes
+// G m_b, nK+nB the masked science image G S, all evaluated on the fly in
+// FP64.  One block per (window row, band of DIR_BAND image rows); partial
+// sums per band, summed over the bands in a fixed order by dir_reduce_kernel.
+struct DirectRow {
+  int16_t left, right;   // planes
+  int16_t hw, dy;        // lag half-width along x, lag along y
+  int32_t out;           // offset of the window row in `win`
+};
+constexpr int DIR_XB = 4;       // consecutive x per thread (register reuse of the right row)
+constexpr int DIR_HWMAX = 18;   // lag half-widths up to 2w with w <= 9
+constexpr int DIR_BAND = 64;    // image rows per block
+constexpr int DIR_MAX_NX = 1024;
+constexpr int DIR_MIN_TPR = 4;
+
+template <typename T>
+__device__ __forceinline__ double plane_value(const AsmParams& P, int pl, int y, int x, const T* __restrict__ sci,
+                                              const T* __restrict__ tmpl, const uint8_t* __restrict__ mask) {
+  if (y < 0 || y >= P.ny || x < 0 || x >= P.nx) return 0.0;
+  const int64_t o = (int64_t)y * P.ld + x;
+  if (mask != nullptr && mask[o] != 0) return 0.0;
+  if (pl < P.nk) {
+    const int w = P.w;
+    if (y < w || y >= P.ny - w || x < w || x >= P.nx - w) return 0.0;
+    const double xh = (double)x * P.sx - 1.0, yh = (double)y * P.sy - 1.0;
+    return ipow(xh, P.kpoly.px[pl]) * ipow(yh, P.kpoly.qy[pl]) * (double)tmpl[o];
+  }
+  if (pl < P.nk + P.nb) {
+    const int b = pl - P.nk;
+    const double xh = (double)x * P.sx - 1.0, yh = (double)y * P.sy - 1.0;
+    return ipow(xh, P.bpoly.px[b]) * ipow(yh, P.bpoly.qy[b]);
+  }
+  return (double)sci[o];
+}
+
+template <typename T, int THREADS>
+__global__ __launch_bounds__(THREADS) void direct_win_kernel(AsmParams P, const T* __restrict__ sci,
+                                                             const T* __restrict__ tmpl,
+                                                             const uint8_t* __restrict__ mask,
+                                                             const DirectRow* __restrict__ rows,
+                                                             double* __restrict__ part, int nwin) {
+  constexpr int NACC = 2 * DIR_HWMAX + 1;
+  constexpr int MAXRPP = THREADS / DIR_MIN_TPR;
+  // rpp staged rows of tpr * DIR_XB + 2 hw values: at most THREADS * DIR_XB + MAXRPP * 2 DIR_HWMAX
+  __shared__ double rbuf[THREADS * DIR_XB + MAXRPP * 2 * DIR_HWMAX];
+  __shared__ double red[THREADS / 64][NACC];
+  const DirectRow R = rows[blockIdx.x];
+  const int hw = R.hw;
+  const int tpr = P.dir_tpr;
+  const int rpp = THREADS / tpr;
+  const int rstride = tpr * DIR_XB + 2 * hw;
+  const int tid = threadIdx.x;
+  const int sub = tid / tpr, tx = tid - sub * tpr;
+  const int y_begin = blockIdx.y * DIR_BAND;
+  const int y_end = min(P.ny, y_begin + DIR_BAND);
+  double acc[NACC];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+
+  for (int yb = y_begin; yb < y_end; yb += rpp) {
+    const int y = yb + sub;
+    __syncthreads();   // the previous rows have been read
+    double* rr = rbuf + sub * rstride;
+    for (int e = tx; e < rstride; e += tpr)
+      rr[e] = (y < y_end) ? plane_value<T>(P, R.right, y + R.dy, e - hw, sci, tmpl, mask) : 0.0;
+    __syncthreads();
+    if (y >= y_end) continue;
+    const int x0 = tx * DIR_XB;
+    double xl[DIR_XB];
+#pragma unroll
+    for (int k = 0; k < DIR_XB; ++k) xl[k] = plane_value<T>(P, R.left, y, x0 + k, sci, tmpl, mask);
+    // rr[x0 + j] = X_r(y + dy, x0 + j - hw); x = x0 + k pairs with lag dx = j - k - hw
+    const double* rx = rr + x0;
+#pragma unroll
+    for (int j = 0; j < NACC + DIR_XB - 1; ++j) {
+      if (j < 2 * hw + DIR_XB) {
+        const double v = rx[j];
+#pragma unroll
+        for (int k = 0; k < DIR_XB; ++k) {
+          const int d = j - k;
+          if (d >= 0 && d < NACC) {
+            if (d <= 2 * hw) acc[d] += xl[k] * v;
+          }
+        }
+      }
+    }
+  }
+  // block sum of every lag: waves by shuffles, then the waves in order
+  const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int d = 0; d < NACC; ++d) {
+    if (d <= 2 * hw) {
+      double v = acc[d];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) red[wave][d] = v;
+    }
+  }
+  __syncthreads();
+  if (tid <= 2 * hw) {
+    double v = 0.0;
+    for (int wv = 0; wv < THREADS / 64; ++wv) v += red[wv][tid];
+    part[(int64_t)blockIdx.y * nwin + R.out + tid] = v;
+  }
+}
+
+// win[i] = sum over bands of part[band][i], bands in order
+__global__ void dir_reduce_kernel(const double* __restrict__ part, int nband, int nwin, double* __restrict__ win) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nwin) return;
+  double v = 0.0;
+  for (int b = 0; b < nband; ++b) v += part[(int64_t)b * nwin + i];
+  win[i] = v;
 }
 
 // ---------------------------------------------------------------------------

@@ -35,11 +35,15 @@ struct SolveJob {
 };
 
 // Diagonal block: one wave of 64 lanes.
+//  A partial last block (nb < 64 rows) is padded with the identity, whose
+//  factor and inverse are the identity again, so every loop below runs over
+//  the full 64 with static bounds and no predicates.
 //  Factorisation: lane i holds row i of the block in registers.  At column j
 //  every lane publishes its A[i][j] in LDS; the pivot d = A[j][j] is read back
 //  by all lanes, lanes i > j scale their entry by 1/sqrt(d) and publish it
-//  again, then lane i applies A[i][l] -= L[i][j] L[l][j] for j < l <= i with
-//  L[l][j] read as an LDS broadcast (independent reads, pipelined).
+//  again, then every lane applies A[i][l] -= L[i][j] L[l][j] for l > j with
+//  L[l][j] read as an LDS broadcast.  L[i][j] is 0 on lanes i <= j, and the
+//  updates of a lane's upper part (l > i) are never read, so no lane is masked.
 //  Inverse X = L^{-1}: lane c holds column c, initialised to e_c, and the
 //  right-looking sweep X[j][c] /= L[j][j]; X[i][c] -= L[i][j] X[j][c] (i > j)
 //  reads L[i][j] as a broadcast from LDS.  Loops over the block are fully
@@ -56,14 +60,21 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restri
   int* __restrict__ info = J.info;
   const int lane = threadIdx.x;
   const int nb = min(NB, n - k0);
+  // coalesced load of the block through LDS (one row per step, lanes along it), identity padding
+  for (int r = 0; r < NB; ++r) {
+    double v = (lane == r) ? 1.0 : 0.0;
+    if (r < nb) v = (lane <= r) ? F[(int64_t)(k0 + r) * n + k0 + lane] : 0.0;
+    Ls[r][lane] = v;
+  }
+  __syncthreads();
   double row[NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c)
-    row[c] = (lane < nb && c < nb && c <= lane) ? F[(int64_t)(k0 + lane) * n + k0 + c] : 0.0;
+  for (int c = 0; c < NB; ++c) row[c] = Ls[lane][c];
+  __syncthreads();
   int fail = 0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (j < nb && fail == 0) {
+    if (fail == 0) {
       col[lane] = row[j];
       __syncthreads();
       const double d = col[j];
@@ -71,16 +82,15 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restri
         fail = j + 1;
       } else {
         const double sd = sqrt(d);
-        if (lane > j) row[j] *= 1.0 / sd;
+        const double rs = 1.0 / sd;
+        if (lane > j) row[j] *= rs;
         if (lane == j) row[j] = sd;
         __syncthreads();
         col[lane] = row[j];
         __syncthreads();
         const double lij = (lane > j) ? row[j] : 0.0;
 #pragma unroll
-        for (int l = j + 1; l < NB; ++l) {
-          if (l < nb && lane >= l) row[l] -= lij * col[l];
-        }
+        for (int l = j + 1; l < NB; ++l) row[l] -= lij * col[l];
       }
       __syncthreads();
     }
@@ -90,23 +100,19 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restri
     return;
   }
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    Ls[lane][c] = row[c];
-    if (lane < nb && c <= lane) F[(int64_t)(k0 + lane) * n + k0 + c] = row[c];
-  }
+  for (int c = 0; c < NB; ++c) Ls[lane][c] = row[c];
   __syncthreads();
+  // coalesced store of the factor's lower triangle
+  for (int r = 0; r < nb; ++r)
+    if (lane <= r) F[(int64_t)(k0 + r) * n + k0 + lane] = Ls[r][lane];
   double xc[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) xc[i] = (i == lane) ? 1.0 : 0.0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (j < nb) {
-      xc[j] *= 1.0 / Ls[j][j];
+    xc[j] *= 1.0 / Ls[j][j];
 #pragma unroll
-      for (int i = j + 1; i < NB; ++i) {
-        if (i < nb) xc[i] -= Ls[i][j] * xc[j];
-      }
-    }
+    for (int i = j + 1; i < NB; ++i) xc[i] -= Ls[i][j] * xc[j];
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) Linv[i * NB + lane] = (i < nb && lane < nb) ? xc[i] : 0.0;

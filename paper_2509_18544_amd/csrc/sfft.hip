@@ -34,9 +34,10 @@ constexpr int WIN_THREADS = 64;
 constexpr int WIN_IMAX = 64;
 constexpr int MAX_N = 8192;           // unknowns (the triangular solves keep x in LDS)
 constexpr int MAX_W = 15;
+constexpr double DIR_AUTO_FMA = 1.0e9;   // direct lag sums below this many multiply-adds (small frames)
 
 struct Layout {
-  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, kp, flags, tw32, tw64, items, wrows, job;
+  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, kp, flags, tw32, tw64, items, wrows, drows, job;
   size_t total;
 };
 
@@ -56,6 +57,9 @@ struct Derived {
   size_t csize;   // sizeof complex element of the transforms
   std::vector<CorrItem> items;
   std::vector<WinRow> wrows;
+  bool direct;                    // lag windows by direct sums instead of transforms
+  std::vector<DirectRow> drows;
+  int dir_tpr, dir_nband;
   GatherParams gp;
   PolyTab kpoly, bpoly;
 };
@@ -86,7 +90,8 @@ int validate(const sfft_desc* d) {
   if (d->ny > (1 << MAX_LOG_P) || d->nx > (1 << MAX_LOG_P)) return SFFT_EINVAL;
   if (d->mode != SFFT_MODE_F64 && d->mode != SFFT_MODE_F32C) return SFFT_EINVAL;
   if (d->refine_steps < -1 || d->refine_steps > 10) return SFFT_EINVAL;
-  if (d->flags != 0) return SFFT_EINVAL;
+  if ((d->flags & ~3) != 0 || (d->flags & 3) == 3) return SFFT_EINVAL;
+  if ((d->flags & 3) == SFFT_FLAG_ASSEMBLY_DIRECT && (d->nx > DIR_MAX_NX || 2 * d->w > DIR_HWMAX)) return SFFT_EINVAL;
   const int L = 2 * d->w + 1;
   const int nk = (d->dk + 1) * (d->dk + 2) / 2, nb = (d->db + 1) * (d->db + 2) / 2;
   const int64_t n = (int64_t)L * L * nk + nb;
@@ -165,6 +170,7 @@ int derive(const sfft_desc* d, Derived* D) {
   // correlation pairs -> items (lag rows in chunks of JMAX), window rows, gather offsets
   D->items.clear();
   D->wrows.clear();
+  D->drows.clear();
   int vrow = 0, wo = 0;
   auto add_pair = [&](int left, int right, int hw) {
     const int h = 2 * hw + 1;
@@ -185,6 +191,13 @@ int derive(const sfft_desc* d, Derived* D) {
       r.out = wo + j * h;
       r.hw = hw;
       D->wrows.push_back(r);
+      DirectRow q;
+      q.left = (int16_t)left;
+      q.right = (int16_t)right;
+      q.hw = (int16_t)hw;
+      q.dy = (int16_t)(j - hw);
+      q.out = wo + j * h;
+      D->drows.push_back(q);
     }
     const int off = wo;
     vrow += h;
@@ -267,6 +280,19 @@ int derive(const sfft_desc* d, Derived* D) {
   }
   D->vrows = vrow;
   D->nwin = wo;
+  // assembly route: forced by the descriptor, else direct sums when their
+  // multiply-adds stay below DIR_AUTO_FMA (small frames)
+  {
+    double fma = 0.0;
+    for (const DirectRow& q : D->drows) fma += (2.0 * q.hw + 1.0) * (double)d->ny * (double)d->nx;
+    const bool ok = d->nx <= DIR_MAX_NX && 2 * d->w <= DIR_HWMAX;
+    const int rf = d->flags & 3;
+    D->direct = rf == SFFT_FLAG_ASSEMBLY_DIRECT || (rf == SFFT_FLAG_ASSEMBLY_AUTO && ok && fma <= DIR_AUTO_FMA);
+    int tpr = DIR_MIN_TPR;
+    while (tpr * DIR_XB < d->nx) tpr *= 2;
+    D->dir_tpr = tpr;
+    D->dir_nband = (d->ny + DIR_BAND - 1) / DIR_BAND;
+  }
   if (D->nitems > MAX_ITEMS) return SFFT_EINVAL;
   D->gp.n = D->n;
   D->gp.nkk = D->nkk;
@@ -298,7 +324,8 @@ Layout layout_of(const Derived& D) {
     const size_t sub_bytes = align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>)) +
                              align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>)) +
                              align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>));
-    Lo.U = take(std::max(asm_bytes, sub_bytes));
+    const size_t dir_bytes = (size_t)D.dir_nband * D.nwin * sizeof(double);   // direct-route partial sums
+    Lo.U = take(std::max(std::max(asm_bytes, sub_bytes), dir_bytes));
   }
   Lo.V = take((size_t)(D.H + 1) * D.vrows * sizeof(cplx<double>));
   Lo.win = take((size_t)D.nwin * sizeof(double));
@@ -319,6 +346,7 @@ Layout layout_of(const Derived& D) {
   Lo.tw64 = take((size_t)TW_N * sizeof(cplx<double>));
   Lo.items = take((size_t)D.nitems * sizeof(CorrItem));
   Lo.wrows = take((size_t)D.wrows.size() * sizeof(WinRow));
+  Lo.drows = take((size_t)D.drows.size() * sizeof(DirectRow));
   Lo.job = take(sizeof(SolveJob));
   Lo.total = off;
   return Lo;
@@ -435,6 +463,10 @@ struct sfft_plan_s {
   SolveJob* jobs_dev = nullptr;
   std::vector<SolveJob> jobs_host;
   int max_n = 0, max_nblk = 0;
+  // graph of one captured batch run (sfft_batch_capture / sfft_batch_launch)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int corr_c1 = 0;   // residue chunk of the correlation kernel, 0 = default (sfft_autotune sets it)
   Derived D;
   Layout Lo;
   hipStream_t stream;
@@ -478,6 +510,7 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
   A.nitems = D.nitems;
   A.corr_lanes = D.corr_lanes;
   A.njlo = D.njlo;
+  A.dir_tpr = D.dir_tpr;
   for (int i = 0; i < MAX_JLO; ++i) A.jlo_list[i] = i < D.njlo ? D.jlo_list[i] : 0;
   A.vrows = D.vrows;
   A.kpoly = D.kpoly;
@@ -500,6 +533,61 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
   return A;
 }
 
+// Residue chunk of the correlation kernel: the spectra of C1 residues of every
+// plane (FP64, padded) and their outer twiddles are staged in LDS per chunk.
+size_t corr_lds_bytes(const Derived& D, int C1) {
+  const size_t stage =
+      ((size_t)D.nplanes * corr_plane_stride(C1) + (size_t)D.njlo * C1 * JMAX) * sizeof(cplx<double>);
+  const size_t red = (size_t)ASM_THREADS * ((JMAX + 1) / 2) * sizeof(cplx<double>);
+  return std::max(stage, red);
+}
+
+// Default chunk: the largest multiple of the item lanes whose stage fits 74 KB
+// (two blocks per CU); sfft_autotune may pick another.
+int corr_default_c1(const Derived& D) {
+  const int P1 = D.Py / P2;
+  const int lanes = D.corr_lanes;
+  const size_t per_res = (size_t)D.nplanes * CORR_RS * sizeof(cplx<double>) + (size_t)D.njlo * JMAX * sizeof(cplx<double>);
+  int C1 = (int)std::min<size_t>((size_t)P1, (74 * 1024) / per_res);
+  if (C1 >= lanes) C1 = (C1 / lanes) * lanes;   // whole rounds of the item lanes
+  return std::max(C1, 1);
+}
+
+template <typename T>
+int launch_corr(sfft_plan_s* p, const AsmParams& A, int C1, bool timed) {
+  const Derived& D = p->D;
+  const Layout& Lo = p->Lo;
+  hipStream_t s = p->stream;
+  const size_t lds = corr_lds_bytes(D, C1);
+  auto kfn = corr_kernel<T, ASM_THREADS>;
+  HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (timed) p->timer.begin(SFFT_STAGE_CORR, s);
+  kfn<<<D.H + 1, ASM_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.U), p->at<CorrItem>(Lo.items),
+                                        p->at<cplx<double>>(Lo.V), p->at<cplx<double>>(Lo.tw64), C1);
+  LAUNCH_CHECK();
+  if (timed) p->timer.end(s);
+  return SFFT_OK;
+}
+
+// moments reduction and the Omega/beta gather (both assembly routes)
+int gather_impl(sfft_plan_s* p, const AsmParams& A) {
+  const Derived& D = p->D;
+  const Layout& Lo = p->Lo;
+  hipStream_t s = p->stream;
+  p->timer.begin(SFFT_STAGE_GATHER, s);
+  moments_reduce_kernel<ASM_THREADS><<<D.nb * D.nb + D.nb, ASM_THREADS, 0, s>>>(A, p->at<double>(Lo.mom), p->at<double>(Lo.obb),
+                                                               p->at<double>(Lo.bb));
+  LAUNCH_CHECK();
+  {
+    dim3 grid((D.n + 255) / 256, D.n);
+    gather_kernel<<<grid, 256, 0, s>>>(D.gp, p->at<double>(Lo.win), p->at<double>(Lo.obb), p->at<double>(Lo.bb),
+                                       p->at<double>(Lo.omega), p->at<double>(Lo.beta));
+    LAUNCH_CHECK();
+  }
+  p->timer.end(s);
+  return SFFT_OK;
+}
+
 template <typename T>
 int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask, int64_t ld) {
   const Derived& D = p->D;
@@ -520,6 +608,19 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
   p->timer.end(s);
 
   constexpr int RN = std::is_same<T, float>::value ? ROW_NMAX_F32 : ROW_NMAX_F64;
+  if (D.direct) {
+    double* part = p->at<double>(Lo.U);
+    p->timer.begin(SFFT_STAGE_CORR, s);
+    direct_win_kernel<T, ASM_THREADS><<<dim3((unsigned)D.drows.size(), (unsigned)D.dir_nband), ASM_THREADS, 0, s>>>(
+        A, sci, tmpl, mask, p->at<DirectRow>(Lo.drows), part, D.nwin);
+    LAUNCH_CHECK();
+    p->timer.end(s);
+    p->timer.begin(SFFT_STAGE_ROW_WIN, s);
+    dir_reduce_kernel<<<(D.nwin + 255) / 256, 256, 0, s>>>(part, D.dir_nband, D.nwin, p->at<double>(Lo.win));
+    LAUNCH_CHECK();
+    p->timer.end(s);
+    return gather_impl(p, A);
+  }
   {
     const size_t lds = (size_t)lds_padded_size(D.rows_per_block * D.H) * sizeof(cplx<T>);
     const int grid = ((D.nrowblk + 7) / 8) * 8;   // whole XCD rounds for the remap
@@ -561,39 +662,15 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     p->timer.end(s);
   }
   {
-    const int P1 = D.Py / P2;
-    const int lanes = D.corr_lanes;
-    const size_t per_res = (size_t)D.nplanes * P2 * sizeof(cplx<double>) + (size_t)D.njlo * JMAX * sizeof(cplx<double>);
-    int C1 = (int)std::min<size_t>((size_t)P1, (76 * 1024) / per_res);
-    if (C1 >= lanes) C1 = (C1 / lanes) * lanes;   // whole rounds of the item lanes
-    C1 = std::max(C1, 1);
-    const size_t stage = (size_t)C1 * per_res;
-    const size_t red = (size_t)ASM_THREADS * ((JMAX + 1) / 2) * sizeof(cplx<double>);
-    const size_t lds = std::max(stage, red);
-    auto kfn = corr_kernel<T, ASM_THREADS>;
-    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    p->timer.begin(SFFT_STAGE_CORR, s);
-    kfn<<<D.H + 1, ASM_THREADS, lds, s>>>(A, U, p->at<CorrItem>(Lo.items), p->at<cplx<double>>(Lo.V), twd, C1);
-    LAUNCH_CHECK();
-    p->timer.end(s);
+    const int st = launch_corr<T>(p, A, p->corr_c1 > 0 ? p->corr_c1 : corr_default_c1(D), true);
+    if (st != SFFT_OK) return st;
   }
   p->timer.begin(SFFT_STAGE_ROW_WIN, s);
   row_win_kernel<WIN_THREADS, WIN_IMAX><<<(int)D.wrows.size(), WIN_THREADS, 0, s>>>(
       A, p->at<cplx<double>>(Lo.V), p->at<WinRow>(Lo.wrows), p->at<double>(Lo.win), twd);
   LAUNCH_CHECK();
   p->timer.end(s);
-  p->timer.begin(SFFT_STAGE_GATHER, s);
-  moments_reduce_kernel<ASM_THREADS><<<D.nb * D.nb + D.nb, ASM_THREADS, 0, s>>>(A, p->at<double>(Lo.mom), p->at<double>(Lo.obb),
-                                                               p->at<double>(Lo.bb));
-  LAUNCH_CHECK();
-  {
-    dim3 grid((D.n + 255) / 256, D.n);
-    gather_kernel<<<grid, 256, 0, s>>>(D.gp, p->at<double>(Lo.win), p->at<double>(Lo.obb), p->at<double>(Lo.bb),
-                                       p->at<double>(Lo.omega), p->at<double>(Lo.beta));
-    LAUNCH_CHECK();
-  }
-  p->timer.end(s);
-  return SFFT_OK;
+  return gather_impl(p, A);
 }
 
 // FP64 Cholesky, triangular solves and refinement for a table of jobs: one
@@ -718,12 +795,16 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
       LAUNCH_CHECK();
     }
     {
-      dim3 g((D.H + 1 + 255) / 256, (D.ny + SUBC_TY - 1) / SUBC_TY);
+      dim3 g((D.H + 1 + 63) / 64, (D.ny + SUBC_RB - 1) / SUBC_RB);
+      const size_t lds_c = sub_conv_lds_bytes(D.w);
       switch (D.w) {
-#define CONV_CASE(WV)                                     \
-  case WV:                                                \
-    sub_conv_kernel<WV><<<g, 256, 0, s>>>(S, Uq, K, Mh); \
-    break;
+#define CONV_CASE(WV)                                                                                          \
+  case WV: {                                                                                                   \
+    auto kc = sub_conv_kernel<WV>;                                                                             \
+    HIP_TRY(hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_c));   \
+    kc<<<g, 64 * SUBC_WAVES, lds_c, s>>>(S, Uq, K, Mh);                                                        \
+    break;                                                                                                     \
+  }
         CONV_CASE(0) CONV_CASE(1) CONV_CASE(2) CONV_CASE(3) CONV_CASE(4) CONV_CASE(5) CONV_CASE(6) CONV_CASE(7)
         CONV_CASE(8) CONV_CASE(9) CONV_CASE(10) CONV_CASE(11) CONV_CASE(12) CONV_CASE(13) CONV_CASE(14) CONV_CASE(15)
 #undef CONV_CASE
@@ -774,12 +855,12 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
       P.xend = bands[bnd][1];
       if (P.xend <= P.xbeg) continue;
       if (P.xend - P.xbeg < SUB_TX / 2) {
-        // narrow band: one thread per pixel
+        // narrow band: one wave per pixel
         const size_t lds_k = (size_t)D.nk * L2 * sizeof(double);
         HIP_TRY(hipFuncSetAttribute((const void*)subtract_band_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds_k));
         const int64_t npx = (int64_t)(P.xend - P.xbeg) * D.ny;
-        subtract_band_kernel<<<(int)((npx + 255) / 256), 256, lds_k, s>>>(
+        subtract_band_kernel<<<(int)((npx + BAND_WAVES - 1) / BAND_WAVES), 64 * BAND_WAVES, lds_k, s>>>(
             P, sci, tmpl, std::is_same<T, double>::value ? 1 : 0, kp, coeffs, diff);
         LAUNCH_CHECK();
         continue;
@@ -872,6 +953,8 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
   ok &= hipMemcpyAsync(p->at<void>(p->Lo.items), p->D.items.data(), p->D.items.size() * sizeof(CorrItem),
                        hipMemcpyHostToDevice, s) == hipSuccess;
   ok &= hipMemcpyAsync(p->at<void>(p->Lo.wrows), p->D.wrows.data(), p->D.wrows.size() * sizeof(WinRow),
+                       hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(p->at<void>(p->Lo.drows), p->D.drows.data(), p->D.drows.size() * sizeof(DirectRow),
                        hipMemcpyHostToDevice, s) == hipSuccess;
   p->jobs_host.assign(1, job_of(p));
   ok &= hipMemcpyAsync(p->at<void>(p->Lo.job), p->jobs_host.data(), sizeof(SolveJob), hipMemcpyHostToDevice, s) ==
@@ -1011,6 +1094,8 @@ void sfft_destroy(sfft_handle p) {
   if (p == nullptr) return;
   (void)hipStreamSynchronize(p->stream);
   p->timer.release();
+  if (p->gexec != nullptr) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph != nullptr) (void)hipGraphDestroy(p->graph);
   for (sfft_plan_s* m : p->members) sfft_destroy(m);
   p->members.clear();
   if (p->jobs_dev != nullptr) (void)hipFree(p->jobs_dev);
@@ -1105,6 +1190,118 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
     st = sfft_subtract(b->members[i], sci[i], tmpl[i], coeffs[i], diff[i], ld[i]);
     if (st != SFFT_OK) return st;
   }
+  return SFFT_OK;
+}
+
+int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld, int32_t* c1_out,
+                  float* ms_out, int32_t cap, int32_t* count_out) {
+  if (p == nullptr || sci == nullptr || tmpl == nullptr || cap < 0) return SFFT_EINVAL;
+  if (cap > 0 && (c1_out == nullptr || ms_out == nullptr)) return SFFT_EINVAL;
+  if (p->is_batch && p->members.empty()) return SFFT_EINVAL;
+  sfft_plan_s* t = p->is_batch ? p->members[0] : p;
+  if (ld < t->D.nx) return SFFT_EINVAL;
+  if (count_out) *count_out = 0;
+  if (t->D.direct) return SFFT_OK;   // the direct route has no correlation chunk to tune
+  int st = sfft_build_system(t, sci, tmpl, mask, ld);
+  if (st != SFFT_OK) return st;
+  const Derived& D = t->D;
+  const int P1 = D.Py / P2;
+  std::vector<int> cand;
+  for (int c = D.corr_lanes; c <= P1; c += D.corr_lanes)
+    if (corr_lds_bytes(D, c) <= 160 * 1024) cand.push_back(c);
+  if (cand.empty()) return SFFT_OK;
+  while (cand.size() > 12) {   // keep every other candidate, always the smallest and largest
+    std::vector<int> k;
+    for (size_t i = 0; i < cand.size(); i += 2) k.push_back(cand[i]);
+    if (k.back() != cand.back()) k.push_back(cand.back());
+    cand.swap(k);
+  }
+  const AsmParams A = asm_params(t, ld);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SFFT_EHIP;
+  }
+  int best = 0;
+  float best_ms = 0.0f;
+  int n = 0;
+  st = SFFT_OK;
+  for (int c : cand) {
+    constexpr int REPS = 3;
+    for (int r = 0; r <= REPS && st == SFFT_OK; ++r) {
+      if (r == 1) st = hipEventRecord(e0, t->stream) == hipSuccess ? SFFT_OK : SFFT_EHIP;
+      if (st == SFFT_OK)
+        st = D.mode == SFFT_MODE_F64 ? launch_corr<double>(t, A, c, false) : launch_corr<float>(t, A, c, false);
+    }
+    if (st == SFFT_OK) st = hipEventRecord(e1, t->stream) == hipSuccess ? SFFT_OK : SFFT_EHIP;
+    if (st == SFFT_OK) st = hipEventSynchronize(e1) == hipSuccess ? SFFT_OK : SFFT_EHIP;
+    float ms = 0.0f;
+    if (st == SFFT_OK) st = hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? SFFT_OK : SFFT_EHIP;
+    if (st != SFFT_OK) break;
+    ms /= (float)REPS;
+    if (n < cap) {
+      c1_out[n] = c;
+      ms_out[n] = ms;
+    }
+    ++n;
+    if (best == 0 || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SFFT_OK) return st;
+  t->corr_c1 = best;
+  if (p->is_batch)
+    for (sfft_plan_s* m : p->members)
+      if (std::memcmp(&m->desc, &t->desc, sizeof(sfft_desc)) == 0) m->corr_c1 = best;
+  if (count_out) *count_out = std::min(n, (int)cap);
+  return SFFT_OK;
+}
+
+int sfft_batch_capture(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
+                       const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info) {
+  if (b == nullptr || !b->is_batch || b->stream == nullptr) return SFFT_EINVAL;
+  if (b->gexec != nullptr) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph != nullptr) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  // event timing would put event records into the graph: off while capturing
+  std::vector<bool> timing;
+  timing.push_back(b->timer.on);
+  b->timer.on = false;
+  for (sfft_plan_s* m : b->members) {
+    timing.push_back(m->timer.on);
+    m->timer.on = false;
+  }
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  const int st = sfft_batch_run(b, sci, tmpl, mask, ld, coeffs, diff, info);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  b->timer.on = timing[0];
+  for (size_t i = 0; i < b->members.size(); ++i) b->members[i]->timer.on = timing[i + 1];
+  if (st != SFFT_OK || e != hipSuccess || g == nullptr) {
+    if (g != nullptr) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return st != SFFT_OK ? st : SFFT_EHIP;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return SFFT_EHIP;
+  }
+  b->graph = g;
+  b->gexec = x;
+  return SFFT_OK;
+}
+
+int sfft_batch_launch(sfft_handle b) {
+  if (b == nullptr || !b->is_batch) return SFFT_EINVAL;
+  if (b->gexec == nullptr) return SFFT_ESTATE;
+  HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
   return SFFT_OK;
 }
 

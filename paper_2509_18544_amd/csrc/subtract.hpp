@@ -60,51 +60,53 @@ __global__ void kprime_kernel(SubParams P, const double* __restrict__ theta, dou
 constexpr int SUB_TY = 16;
 constexpr int SUB_TX = 64;
 
-// Direct D on a narrow column band [P.xbeg, P.xend): one thread per pixel,
-// k' in LDS, template pixels through the cache.  Same arithmetic as below.
-__global__ __launch_bounds__(256) void subtract_band_kernel(SubParams P, const void* __restrict__ sci_v,
-                                                            const void* __restrict__ tmpl_v, int is_f64,
-                                                            const double* __restrict__ kp,
-                                                            const double* __restrict__ theta, void* __restrict__ diff_v) {
+// Direct D on a narrow column band [P.xbeg, P.xend): one wave per pixel, the
+// lanes split the nK L^2 kernel taps (k' in LDS) and sum by shuffles.  Same
+// arithmetic as subtract_kernel below, summed in a different order.
+constexpr int BAND_WAVES = 4;
+__global__ __launch_bounds__(64 * BAND_WAVES) void subtract_band_kernel(SubParams P, const void* __restrict__ sci_v,
+                                                                        const void* __restrict__ tmpl_v, int is_f64,
+                                                                        const double* __restrict__ kp,
+                                                                        const double* __restrict__ theta,
+                                                                        void* __restrict__ diff_v) {
   extern __shared__ double kps[];
   const int w = P.w;
   const int L = 2 * w + 1;
   const int L2 = L * L;
+  const int nkk = P.nk * L2;
   const int bw = P.xend - P.xbeg;
-  for (int e = threadIdx.x; e < P.nk * L2; e += 256) kps[e] = kp[e];
+  for (int e = threadIdx.x; e < nkk; e += 64 * BAND_WAVES) kps[e] = kp[e];
   __syncthreads();
-  const int id = blockIdx.x * 256 + threadIdx.x;
-  if (id >= bw * P.ny) return;
-  const int y = id / bw;
-  const int x = P.xbeg + (id - y * bw);
-  auto tv = [&](int yy, int xx) -> double {
-    const int64_t o = (int64_t)yy * P.ld + xx;
-    return is_f64 ? reinterpret_cast<const double*>(tmpl_v)[o] : (double)reinterpret_cast<const float*>(tmpl_v)[o];
-  };
+  const int lane = threadIdx.x & 63;
+  const int64_t id = (int64_t)blockIdx.x * BAND_WAVES + (threadIdx.x >> 6);
+  if (id >= (int64_t)bw * P.ny) return;
+  const int y = (int)(id / bw);
+  const int x = P.xbeg + (int)(id - (int64_t)y * bw);
   const double yh = 2.0 * (double)y / (double)(P.ny - 1) - 1.0;
   const double xh = 2.0 * (double)x / (double)(P.nx - 1) - 1.0;
-  double model = 0.0;
-  for (int a = 0; a < P.nk; ++a) {
-    double acc = 0.0;
-    for (int uy = -w; uy <= w; ++uy) {
-      const int sy = y - uy;
-      if (sy < 0 || sy >= P.ny) continue;
-      for (int ux = -w; ux <= w; ++ux) {
-        const int sx = x - ux;
-        if (sx < 0 || sx >= P.nx) continue;
-        acc += kps[a * L2 + (uy + w) * L + (ux + w)] * tv(sy, sx);
-      }
-    }
+  double acc = 0.0;
+  for (int t = lane; t < nkk; t += 64) {
+    const int a = t / L2;
+    const int r = t - a * L2;
+    const int uy = r / L - w;
+    const int ux = r - (uy + w) * L - w;
+    const int sy = y - uy, sx = x - ux;
+    if (sy < 0 || sy >= P.ny || sx < 0 || sx >= P.nx) continue;
+    const int64_t o = (int64_t)sy * P.ld + sx;
+    const double tv = is_f64 ? reinterpret_cast<const double*>(tmpl_v)[o]
+                             : (double)reinterpret_cast<const float*>(tmpl_v)[o];
     double m = 1.0;
-    for (int t = 0; t < P.kpx[a]; ++t) m *= xh;
-    for (int t = 0; t < P.kqy[a]; ++t) m *= yh;
-    model += m * acc;
+    for (int q = 0; q < P.kpx[a]; ++q) m *= xh;
+    for (int q = 0; q < P.kqy[a]; ++q) m *= yh;
+    acc += kps[t] * m * tv;
   }
-  const int nkk = P.nk * L2;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane != 0) return;
+  double model = acc;
   for (int b = 0; b < P.nb; ++b) {
     double m = 1.0;
-    for (int t = 0; t < P.bpx[b]; ++t) m *= xh;
-    for (int t = 0; t < P.bqy[b]; ++t) m *= yh;
+    for (int q = 0; q < P.bpx[b]; ++q) m *= xh;
+    for (int q = 0; q < P.bqy[b]; ++q) m *= yh;
     model += theta[nkk + b] * m;
   }
   const int64_t o = (int64_t)y * P.ld + x;
@@ -289,49 +291,68 @@ __global__ void sub_kspec_kernel(SpecParams P, const double* __restrict__ theta,
   K[(int64_t)row * (H + 1) + kx] = acc;
 }
 
-// M(y, kx) for a block of SUBC_TY rows; one thread per kx.  For each
-// monomial the SUBC_TY + 2W source rows (times yh^q) are loaded once into
-// registers and reused by every tap (W = w is a template parameter so that
-// every register index is static).
-constexpr int SUBC_TY = 8;   // output rows per thread
+// M(y, kx) = sum_a sum_{u_y} K[a][u_y][kx] yh(y - u_y)^q_a U_{p_a}(y - u_y, kx).
+// Block: 64 kx columns (the lanes) x SUBC_WAVES waves of SUBC_TY output rows.
+// For each monomial the block stages the SUBC_RB + 2W source rows it needs,
+// already weighted by yh^q, in LDS (HBM traffic ~ (1 + 2W / SUBC_RB) x the
+// source; the re-reads of a power p for its other monomials hit L2), and each
+// thread sums its SUBC_TY x L products straight from LDS with one tap in
+// registers at a time, so registers do not grow with w.
+constexpr int SUBC_TY = 12;                       // output rows per wave
+constexpr int SUBC_WAVES = 4;
+constexpr int SUBC_RB = SUBC_TY * SUBC_WAVES;     // output rows per block
+
+__host__ __device__ constexpr size_t sub_conv_lds_bytes(int w) {
+  return (size_t)(SUBC_RB + 2 * w) * 64 * sizeof(cplx<double>);
+}
 
 template <int W>
-__global__ __launch_bounds__(256) void sub_conv_kernel(SpecParams P, const cplx<double>* __restrict__ Uq,
-                                                       const cplx<double>* __restrict__ K,
-                                                       cplx<double>* __restrict__ Mh) {
+__global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P, const cplx<double>* __restrict__ Uq,
+                                                                   const cplx<double>* __restrict__ K,
+                                                                   cplx<double>* __restrict__ Mh) {
   constexpr int L = 2 * W + 1;
-  constexpr int WIN = SUBC_TY + 2 * W;
+  constexpr int WINB = SUBC_RB + 2 * W;           // source rows of the block
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<double>* win = reinterpret_cast<cplx<double>*>(smem_raw);   // [WINB][64]
   const int H = P.H;
-  const int kx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y0 = blockIdx.y * SUBC_TY;
-  if (kx > H) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int kx0 = blockIdx.x * 64;
+  const int kx = kx0 + lane;
+  const int yb = blockIdx.y * SUBC_RB;            // first output row of the block
+  const int y0 = yb + wave * SUBC_TY;             // first output row of the wave
   cplx<double> acc[SUBC_TY];
 #pragma unroll
   for (int t = 0; t < SUBC_TY; ++t) acc[t] = mk(0.0, 0.0);
   for (int a = 0; a < P.nk; ++a) {
     const int p = P.kpx[a], q = P.kqy[a];
-    const cplx<double>* Up = Uq + (int64_t)p * P.ny * (H + 1) + kx;
-    const cplx<double>* Ka = K + (int64_t)a * L * (H + 1) + kx;
-    // win[i] = yh(ys)^q U_p(ys, kx), ys = y0 - W + i
-    cplx<double> win[WIN];
-#pragma unroll
-    for (int i = 0; i < WIN; ++i) {
-      const int ys = y0 - W + i;
+    const cplx<double>* Up = Uq + (int64_t)p * P.ny * (H + 1);
+    __syncthreads();   // the previous monomial's rows have been read
+    for (int e = tid; e < WINB * 64; e += 64 * SUBC_WAVES) {
+      const int r = e >> 6, c = e & 63;
+      const int ys = yb - W + r;
       cplx<double> u = mk(0.0, 0.0);
-      if (ys >= 0 && ys < P.ny) {
-        u = Up[(int64_t)ys * (H + 1)];
+      if (ys >= 0 && ys < P.ny && kx0 + c <= H) {
+        u = Up[(int64_t)ys * (H + 1) + kx0 + c];
         if (q > 0) u = scale(u, ipow((double)ys * P.sy - 1.0, q));
       }
-      win[i] = u;
+      win[e] = u;
     }
-#pragma unroll
+    __syncthreads();
+    if (kx > H) continue;
+    const cplx<double>* Ka = K + (int64_t)a * L * (H + 1) + kx;
+    // output row y0 + t takes source row y0 + t - u_y = window row wave * TY + t + 2W - uyi
+    const cplx<double>* wl = win + (wave * SUBC_TY + 2 * W) * 64 + lane;
+#pragma unroll 1
     for (int uyi = 0; uyi < L; ++uyi) {
       const cplx<double> kv = Ka[(int64_t)uyi * (H + 1)];
-      // output row y0 + t takes source row y0 + t - u_y = window index t + 2W - uyi
+      const cplx<double>* src = wl - uyi * 64;
 #pragma unroll
-      for (int t = 0; t < SUBC_TY; ++t) acc[t] = acc[t] + kv * win[t + 2 * W - uyi];
+      for (int t = 0; t < SUBC_TY; ++t) acc[t] = acc[t] + kv * src[t * 64];
     }
   }
+  if (kx > H) return;
 #pragma unroll
   for (int t = 0; t < SUBC_TY; ++t) {
     const int y = y0 + t;

@@ -111,7 +111,7 @@ def make_dataset(npairs, seed0, n=512, chunk=32, pool=None, log=None):
     info [npairs]).  `pool` (an executor created before the GPU was touched)
     renders in parallel; without it frames are rendered in this process.
     """
-    feats, thetas, infos = [], [], []
+    feats, thetas, infos, params = [], [], [], []
     seeds = [(seed0 + i, n) for i in range(npairs)]
     it = pool.map(_render, seeds, chunksize=4) if pool is not None else map(_render, seeds)
     buf = []
@@ -121,11 +121,13 @@ def make_dataset(npairs, seed0, n=512, chunk=32, pool=None, log=None):
         if len(buf) == chunk or (len(feats) + len(buf)) == npairs:
             th, info = solve_pairs(buf)
             feats.extend(pair_features(q) for q in buf)
+            params.extend([q.truth["X"], q.truth["Y"], q.truth["fwhm_s0"], q.truth["fwhm_t0"]] for q in buf)
             thetas.append(th)
             infos.append(info)
             buf = []
             if log:
                 log(f"[learned] solved {len(feats)}/{npairs} pairs ({time.perf_counter() - t0:.1f}s)")
+    make_dataset.last_params = np.asarray(params)     # (X, Y, FWHM_s0, FWHM_t0) per frame, for diagnostics
     return np.asarray(feats), np.concatenate(thetas), np.concatenate(infos)
 
 
@@ -162,8 +164,10 @@ class Net:
         self._scale = self._shift = None
 
     # ---- training (FP32 kernels)
-    def train(self, feats, targets, epochs=30, batch=128, lr=1e-3, lr_final=1e-5, seed=0, log=None):
-        """Adam on the MSE of standardised targets.  Returns the per-epoch mean losses."""
+    def train(self, feats, targets, epochs=30, batch=128, lr=1e-4, lr_final=1e-6, seed=0, log=None):
+        """Adam on the MSE of standardised targets (cosine-decayed step size).  Returns the per-epoch
+        mean losses.  The inputs are strongly collinear (stamp pixels), so steps much above 1e-4
+        drive the network to the constant mean prediction."""
         import torch
         if self.xs is None:
             self.xs = Standardizer.fit(feats)
@@ -308,11 +312,13 @@ def _cli(argv=None):
     ap.add_argument("--n", type=int, default=512, help="frame side of the training frames")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=1e-4)
     ap.add_argument("--seed0", type=int, default=500000)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--save", default=None, help="checkpoint path prefix (.bin + .json)")
     ap.add_argument("--report", default=None, help="write the evaluation as JSON here")
+    ap.add_argument("--dump", default=None, help="also save the dataset (.npz) here")
+    ap.add_argument("--dump-only", action="store_true", help="stop after building (and saving) the dataset")
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)  # noqa: E731
 
@@ -326,8 +332,16 @@ def _cli(argv=None):
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     Xtr, THtr, info = make_dataset(a.train_pairs, a.seed0, n=a.n, pool=pool, log=log)
+    Ptr = make_dataset.last_params
     Xva, THva, info_v = make_dataset(a.val_pairs, a.seed0 + 10 ** 6, n=a.n, pool=pool, log=log)
+    Pva = make_dataset.last_params
     pool.shutdown()
+    if a.dump:
+        np.savez_compressed(a.dump, Xtr=Xtr.astype(np.float32), THtr=THtr, Ptr=Ptr, info=info,
+                            Xva=Xva.astype(np.float32), THva=THva, Pva=Pva)
+        log(f"[learned] wrote {a.dump}")
+    if a.dump_only:
+        return
     ok = info == 0
     log(f"[learned] dataset: {ok.sum()} usable of {len(ok)} ({time.perf_counter() - t0:.1f}s)")
     nk = DIMS[-1]

@@ -18,7 +18,7 @@ def to_dev(a, dtype, pitch=None):
 
 
 def run_pair(sci, tmpl, mask, w, dk, db, mode=B.SFFT_MODE_F64, pitch=None, refine_steps=-1,
-             theta_in=None, want_system=True):
+             theta_in=None, want_system=True, flags=0):
     """Build, solve and subtract one pair on cuda:0.  Returns host numpy results."""
     import torch
     ny, nx = sci.shape
@@ -27,7 +27,7 @@ def run_pair(sci, tmpl, mask, w, dk, db, mode=B.SFFT_MODE_F64, pitch=None, refin
     R = to_dev(tmpl, dt, pitch)
     M = None if mask is None else to_dev(mask.astype(np.uint8), torch.uint8, pitch)
     ld = S.stride(0)
-    plan = B.Plan(ny, nx, w, dk, db, mode=mode, refine_steps=refine_steps)
+    plan = B.Plan(ny, nx, w, dk, db, mode=mode, refine_steps=refine_steps, flags=flags)
     try:
         plan.build(S, R, M)
         out = {}

@@ -39,7 +39,10 @@ def test_num_coeffs_and_workspace():
     dict(ny=64, nx=64, w=2, dk=1, db=-2),
     dict(ny=5000, nx=64, w=2, dk=1, db=1),        # larger than 4096
     dict(ny=64, nx=64, w=2, dk=1, db=1, mode=7),
-    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=1),
+    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=3),        # no such assembly route
+    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=4),        # unknown flag bit
+    dict(ny=64, nx=2048, w=2, dk=1, db=1, flags=2),      # direct sums limited to nx <= 1024
+    dict(ny=64, nx=64, w=10, dk=1, db=1, flags=2),       # ... and to w <= 9
     dict(ny=4096, nx=4096, w=15, dk=3, db=3),     # more unknowns than the solver holds
 ])
 def test_invalid_descriptors(bad):

@@ -84,3 +84,53 @@ def test_failed_pair_is_isolated():
             assert oracle.rel_err(C[i].cpu().numpy(), ref["theta"]) <= 1e-9
     finally:
         B.sfft_destroy(h)
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_captured_graph_replays_equal_eager(mode):
+    """One captured graph for the whole batch, replayed three times with eager
+    runs, fills and synchronisations in between; every replay equals the eager
+    result bitwise."""
+    pairs = _pairs()
+    dt = torch.float64 if mode == F64 else torch.float32
+    descs = [B.make_desc(p.sci.shape[0], p.sci.shape[1], p.w, p.dk, p.db, mode) for p in pairs]
+    stream = torch.cuda.Stream()
+    h = B.sfft_batch_plan(descs, stream)
+    try:
+        with torch.cuda.stream(stream):
+            S = [torch.from_numpy(p.sci).to("cuda", dt) for p in pairs]
+            R = [torch.from_numpy(p.tmpl).to("cuda", dt) for p in pairs]
+            M = [torch.from_numpy(p.mask).cuda() for p in pairs]
+            ld = [s.stride(0) for s in S]
+            new_c = lambda: [torch.zeros(B.sfft_num_coeffs(d), dtype=torch.float64, device="cuda")  # noqa: E731
+                             for d in descs]
+            Ce, Cg = new_c(), new_c()
+            De, Dg = [torch.empty_like(s) for s in S], [torch.empty_like(s) for s in S]
+            ie = torch.zeros(len(pairs), dtype=torch.int32, device="cuda")
+            ig = torch.full_like(ie, -7)
+        stream.synchronize()
+        B.sfft_batch_run(h, S, R, M, ld, Ce, De, ie)
+        stream.synchronize()
+        with pytest.raises(B.SfftError) as e:
+            B.sfft_batch_launch(h)                     # nothing captured yet
+        assert e.value.status == B.SFFT_ESTATE
+        B.sfft_batch_capture(h, S, R, M, ld, Cg, Dg, ig)
+        stream.synchronize()
+        assert ig.cpu().tolist() == [-7] * len(pairs)  # capture alone runs nothing
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                for t in Cg + Dg:
+                    t.fill_(float("nan"))
+                ig.fill_(-7)
+            B.sfft_batch_launch(h)
+            stream.synchronize()
+            assert ig.cpu().tolist() == [0] * len(pairs), rep
+            for i in range(len(pairs)):
+                np.testing.assert_array_equal(Cg[i].cpu().numpy(), Ce[i].cpu().numpy())
+                np.testing.assert_array_equal(Dg[i].cpu().numpy(), De[i].cpu().numpy())
+            # eager work of the program between replays, on the same plan
+            B.sfft_batch_run(h, S, R, M, ld, Ce, De, ie)
+            stream.synchronize()
+        assert B.sfft_status(h)[0] == B.SFFT_OK
+    finally:
+        B.sfft_destroy(h)

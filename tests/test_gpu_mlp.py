@@ -90,7 +90,9 @@ def test_adam_steps_against_oracle():
         for step in range(1, 4):
             g = rng.normal(0, 1, n).astype(np.float32).astype(np.float64)
             B.sfft_mlp_adam_step(h, P, _dev(g), M1, M2, step, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8)
-            pr, m, v = M.adam_step(pr, g, m, v, step, lr=1e-2)
+            # the ABI takes FP32 hyperparameters: the oracle gets the same rounded values
+            f = lambda v: float(np.float32(v))  # noqa: E731
+            pr, m, v = M.adam_step(pr, g, m, v, step, lr=f(1e-2), b1=f(0.9), b2=f(0.999), eps=f(1e-8))
         torch.cuda.synchronize()
         assert _maxrel(P.cpu().double().numpy() - p, pr - p) <= 1e-4
         assert _maxrel(M1.cpu().double().numpy(), m) <= 1e-5

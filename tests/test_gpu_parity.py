@@ -63,21 +63,36 @@ SMALL = [
 ]
 
 
+FFT_ROUTE, DIRECT_ROUTE = B.SFFT_FLAG_ASSEMBLY_FFT, B.SFFT_FLAG_ASSEMBLY_DIRECT
+
+
+@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE])
 @pytest.mark.parametrize("mode", [F64, F32C])
 @pytest.mark.parametrize("case", SMALL)
-def test_small_parity(case, mode):
+def test_small_parity(case, mode, route):
     ny, nx, w, dk, db, frac, seed = case
     p = synth.random_pair(seed, ny, nx, w, dk, db, mask_frac=frac, stars=True)
-    res = run_pair(p.sci, p.tmpl, p.mask, w, dk, db, mode=mode)
+    res = run_pair(p.sci, p.tmpl, p.mask, w, dk, db, mode=mode, flags=route)
     _check_against_oracle(p, mode, res)
 
 
+@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE])
 @pytest.mark.parametrize("mode", [F64, F32C])
-def test_c1_parity(mode):
+def test_c1_parity(mode, route):
     p = synth.pair_c1()
-    res = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=mode)
+    res = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=mode, flags=route)
     et, ed = _check_against_oracle(p, mode, res)
-    print(f"C1 mode={mode} e_theta={et:.3e} e_D={ed:.3e}")
+    print(f"C1 mode={mode} route={route} e_theta={et:.3e} e_D={ed:.3e}")
+
+
+def test_routes_agree_on_omega():
+    """The direct sums and the transforms give the same Omega up to rounding (FP64)."""
+    p = synth.random_pair(81, 150, 140, 4, 2, 1, mask_frac=0.1, stars=True)
+    a = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, flags=FFT_ROUTE)
+    b = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, flags=DIRECT_ROUTE)
+    scale = np.abs(a["omega"]).max()
+    assert np.abs(a["omega"] - b["omega"]).max() <= 1e-12 * scale
+    assert np.abs(a["beta"] - b["beta"]).max() <= 1e-12 * np.abs(a["beta"]).max()
 
 
 @pytest.fixture(scope="module")
@@ -210,3 +225,35 @@ def test_fit_background_and_residual_of_a_guess(mode):
         assert eb <= tol_b and er <= tol_r
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_autotune_keeps_results_within_rounding(mode):
+    """The tuned correlation chunk only regroups the residue sums: Omega, theta
+    and D stay within rounding of the default plan, and still meet the oracle bar."""
+    p = synth.random_pair(91, 200, 180, 4, 2, 2, mask_frac=0.1, stars=True)
+    s_in, r_in = inputs_as_seen(p, mode)
+    dt = torch.float64 if mode == F64 else torch.float32
+    S = torch.from_numpy(s_in).to("cuda", dt)
+    R = torch.from_numpy(r_in).to("cuda", dt)
+    Mk = torch.from_numpy(p.mask).cuda()
+    out = []
+    for tune in (False, True):
+        plan = B.Plan(*p.sci.shape, p.w, p.dk, p.db, mode=mode, flags=FFT_ROUTE)
+        try:
+            if tune:
+                rep = B.sfft_autotune(plan.handle, S, R, Mk, S.stride(0))
+                assert len(rep) >= 1 and all(ms > 0 for _, ms in rep)
+            plan.build(S, R, Mk)
+            om, be = plan.system()
+            c, info = plan.solve()
+            d = plan.subtract(S, R, c)
+            torch.cuda.synchronize()
+            out.append((om.cpu().numpy(), c.cpu().numpy(), d.cpu().numpy().astype(np.float64)))
+        finally:
+            plan.close()
+    (om0, c0, d0), (om1, c1, d1) = out
+    assert np.abs(om1 - om0).max() <= 1e-12 * np.abs(om0).max()
+    ref = oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db)
+    assert oracle.rel_err(c1, ref["theta"]) <= TOL[mode]["theta"]
+    assert oracle.rel_err(d1, ref["diff"]) <= TOL[mode]["diff"]
