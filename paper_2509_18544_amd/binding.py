@@ -14,7 +14,8 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libsfft.so")
+# SFFT_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SFFT_LIBRARY") or os.path.join(_HERE, "_lib", "libsfft.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sfft.h")
 
 SFFT_OK = 0

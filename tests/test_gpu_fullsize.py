@@ -82,3 +82,20 @@ def test_c3_full_size(c3, mode):
     ed = np.linalg.norm(d_got - d_ref) / np.linalg.norm(d_ref)
     assert ed <= tol, f"e_D (sampled) {ed:.3e}"
     print(f"C3 mode={mode} e_theta={et:.3e} e_D(sampled)={ed:.3e}")
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_largest_frame_4096(mode):
+    """The largest frame the plan takes (4096 x 4096, FFT size 4096 with no
+    padding margin beyond the w-strip) against the oracle, recomputed here:
+    small kernel (w = 2, DK = DB = 1) so the oracle finishes in seconds."""
+    p = synth.random_pair(4096, 4096, 4096, 2, 1, 1, mask_frac=0.05, stars=True)
+    cast = np.float64 if mode == F64 else np.float32
+    s_in, r_in = p.sci.astype(cast).astype(np.float64), p.tmpl.astype(cast).astype(np.float64)
+    res = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=mode, want_system=False)
+    ref = oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db, mode="fft")
+    et = oracle.rel_err(res["theta"], ref["theta"])
+    ed = oracle.rel_err(res["diff"], ref["diff"])
+    print(f"4096 mode={mode} e_theta={et:.3e} e_D={ed:.3e}")
+    tol = 1e-9 if mode == F64 else 1e-5
+    assert res["info"] == 0 and et <= tol and ed <= tol

@@ -257,3 +257,16 @@ def test_autotune_keeps_results_within_rounding(mode):
     ref = oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db)
     assert oracle.rel_err(c1, ref["theta"]) <= TOL[mode]["theta"]
     assert oracle.rel_err(d1, ref["diff"]) <= TOL[mode]["diff"]
+
+
+@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE])
+@pytest.mark.parametrize("shape", [(6, 6, 1, 0, 0), (10, 7, 1, 1, 1), (2, 2, 0, 0, 0), (3, 64, 0, 1, 0)])
+def test_smallest_frames(shape, route):
+    """Frames at the size limit N = 4w + 2 and degenerate thin frames (plain noise images)."""
+    ny, nx, w, dk, db = shape
+    p = synth.random_pair(100 + ny * nx, ny, nx, w, dk, db, mask_frac=0.0, stars=False)
+    res = run_pair(p.sci, p.tmpl, p.mask, w, dk, db, flags=route)
+    ref = oracle.fit(p.sci, p.tmpl, p.mask, w, dk, db, mode="direct")
+    assert res["info"] == 0
+    assert oracle.rel_err(res["theta"], ref["theta"]) <= 1e-9
+    assert oracle.rel_err(res["diff"], ref["diff"]) <= 1e-9
