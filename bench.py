@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=8, help="distinct pairs per step (one batched run)")
+    ap.add_argument("--batch", type=int, default=16, help="distinct pairs per step (one batched run)")
     ap.add_argument("--mode", choices=["f32c", "f64"], default="f32c")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -141,7 +141,7 @@ def main():
     # ---- synthetic inputs (CPU, before any GPU use) ----
     t0 = time.perf_counter()
     seeds = [wl["seed0"] + i for i in range(args.batch)]
-    workers = max(1, min(args.batch, 8, len(os.sched_getaffinity(0))))
+    workers = max(1, min(args.batch, 16, len(os.sched_getaffinity(0))))
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
         pairs = list(ex.map(_gen, [(args.workload, s) for s in seeds]))
     log(f"[bench] generated {len(pairs)} {args.workload} pairs in {time.perf_counter() - t0:.1f}s")

@@ -211,7 +211,7 @@ __device__ __forceinline__ cplx<T> col_load(const AsmParams& P, const cplx<T>* _
 }
 
 template <typename T, int THREADS, int NMAX, int LGR0>
-__global__ __launch_bounds__(THREADS, 4) void col_fwd_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
                                                           cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(THREADS, 4) void col_fwd_kernel(AsmParams P, const 
 // XN(ky) = (Z(ky) - conj Z(-ky))/(2i) go to columns 0 and H; column 1 is
 // written as usual.  One block per base.
 template <typename T, int THREADS, int NMAX, int LGR0>
-__global__ __launch_bounds__(THREADS, 4) void col_fwd_dc_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_dc_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
                                                              cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);

@@ -215,7 +215,7 @@ struct SpecParams {
 
 // R2C of the rows xh^p R (p = 0..DK) -> Uq[p][y][0..H]
 template <typename T, int THREADS, int NMAX, int LGR0>
-__global__ __launch_bounds__(THREADS) void sub_rowfwd_kernel(SpecParams P, const T* __restrict__ tmpl,
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_kernel(SpecParams P, const T* __restrict__ tmpl,
                                                              cplx<double>* __restrict__ Uq,
                                                              const cplx<double>* __restrict__ tw, int npow) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -298,8 +298,8 @@ __global__ void sub_kspec_kernel(SpecParams P, const double* __restrict__ theta,
 // source; the re-reads of a power p for its other monomials hit L2), and each
 // thread sums its SUBC_TY x L products straight from LDS with one tap in
 // registers at a time, so registers do not grow with w.
-constexpr int SUBC_TY = 12;                       // output rows per wave
-constexpr int SUBC_WAVES = 4;
+constexpr int SUBC_TY = 6;                        // output rows per wave
+constexpr int SUBC_WAVES = 8;
 constexpr int SUBC_RB = SUBC_TY * SUBC_WAVES;     // output rows per block
 
 __host__ __device__ constexpr size_t sub_conv_lds_bytes(int w) {
