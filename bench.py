@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default correlation chunk")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time K graph replays of the batch run (reported as graph_pairs_per_s)")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -174,6 +176,20 @@ def main():
 
     def step():
         B.sfft_batch_run(handle, S, R, M, lds, C, Dd, info)
+
+    graph_value = None
+    if args.graph:
+        # the same batch run captured once and replayed as one graph launch per step
+        B.sfft_batch_capture(handle, S, R, M, lds, C, Dd, info)
+        for _ in range(args.warmup):
+            B.sfft_batch_launch(handle)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            B.sfft_batch_launch(handle)
+        torch.cuda.synchronize()
+        graph_value = args.batch * args.steps / (time.perf_counter() - tg)
+        log(f"[bench] graph replay: {graph_value:.2f} pairs/s")
 
     for _ in range(args.warmup):
         step()
@@ -278,6 +294,7 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": acc,
         "stages_ms_per_pair": {k: round(v, 4) for k, v in per_pair.items()},
+        "graph_pairs_per_s": None if graph_value is None else round(graph_value, 3),
         "stage_rooflines": {k: {"bound": v["bound"], "frac": v["frac"], "achieved": v["achieved"],
                                 "unit": v["unit"]} for k, v in stage_roofs.items()},
     }

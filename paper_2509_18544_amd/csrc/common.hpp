@@ -47,6 +47,17 @@ __device__ __forceinline__ cplx<T> scale(cplx<T> a, T s) { return mk(a.x * s, a.
 template <typename T>
 __device__ __forceinline__ cplx<T> conjg(cplx<T> a) { return mk(a.x, -a.y); }
 // conj(a) * b
+// acc + a * b as four fused multiply-adds (the plain expression rounds the
+// product before the sum and costs two more instructions)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmac(cplx<T> acc, cplx<T> a, cplx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
   return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
@@ -56,11 +67,22 @@ template <typename T, bool INV>
 __device__ __forceinline__ cplx<T> rot90(cplx<T> a) {
   return INV ? mk(-a.y, a.x) : mk(a.y, -a.x);
 }
-// twiddle exp(-+2 pi i m / TW_N) from the forward table
+// Twiddle exp(-+2 pi i m / TW_N) from the forward table.  FP64 transforms read
+// the whole table; FP32 transforms read only its first half tw[0 .. TW_N/2)
+// (16 KB, friendlier to L1) and use exp(-2 pi i (m + TW_N/2) / TW_N) = -tw[m],
+// an exact sign flip.
 template <typename T, bool INV>
 __device__ __forceinline__ cplx<T> twid(const cplx<T>* __restrict__ tw, int m) {
-  cplx<T> t = tw[m & (TW_N - 1)];
-  return INV ? conjg(t) : t;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    const cplx<T> t = tw[m & (TW_N - 1)];
+    return INV ? conjg(t) : t;
+  } else {
+    const cplx<float> t = tw[m & (TW_N / 2 - 1)];
+    const uint32_t flip = ((uint32_t)m & (uint32_t)(TW_N / 2)) << (31 - (TW_LOG - 1));
+    const uint32_t xr = __float_as_uint(t.x) ^ flip;
+    const uint32_t yr = __float_as_uint(t.y) ^ flip ^ (INV ? 0x80000000u : 0u);
+    return cplx<T>{__uint_as_float(xr), __uint_as_float(yr)};
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -349,7 +349,7 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
       const cplx<double> kv = Ka[(int64_t)uyi * (H + 1)];
       const cplx<double>* src = wl - uyi * 64;
 #pragma unroll
-      for (int t = 0; t < SUBC_TY; ++t) acc[t] = acc[t] + kv * src[t * 64];
+      for (int t = 0; t < SUBC_TY; ++t) acc[t] = cmac(acc[t], kv, src[t * 64]);
     }
   }
   if (kx > H) return;
