@@ -210,7 +210,7 @@ __device__ __forceinline__ cplx<T> col_load(const AsmParams& P, const cplx<T>* _
   return v;
 }
 
-template <typename T, int THREADS, int NMAX, int LGR0>
+template <typename T, int THREADS, int NMAX, int LGR0, int LGM>
 __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
                                                           cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -237,7 +237,8 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kerne
       buf[lds_pad(kb * Py + ((ky & (P1 - 1)) << LG_P2) + (ky >> lgP1))] = v;
     };
     __syncthreads();   // the previous output's copy-out has read the buffer
-    fft_run<T, NMAX, THREADS, false, false, true, LGR0>(buf, lgPy, 2, Py, tw, load0, store_res);
+    fft_run<T, NMAX, THREADS, false, false, true, LGR0, decltype(load0), decltype(store_res), LGM>(
+        buf, lgPy, 2, Py, tw, load0, store_res);
     __syncthreads();
     // ... and the two columns leave as one contiguous, coalesced block
     for (int e = tid; e < 2 * Py; e += THREADS) Xc[e] = buf[lds_pad(e)];
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kerne
 // z = x0 + i xN; after the transform X0(ky) = (Z(ky) + conj Z(-ky))/2 and
 // XN(ky) = (Z(ky) - conj Z(-ky))/(2i) go to columns 0 and H; column 1 is
 // written as usual.  One block per base.
-template <typename T, int THREADS, int NMAX, int LGR0>
+template <typename T, int THREADS, int NMAX, int LGR0, int LGM>
 __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_dc_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
                                                              cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -267,7 +268,8 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_dc_ke
     auto load0 = [&](int kb, int y) -> cplx<T> { return col_load<T>(P, blk, kb, y, q); };
     auto lds_store = [&](int kb, int ky, cplx<T> v) { buf[lds_pad(kb * Py + ky)] = v; };
     __syncthreads();
-    fft_run<T, NMAX, THREADS, false, false, true, LGR0>(buf, lgPy, 2, Py, tw, load0, lds_store);
+    fft_run<T, NMAX, THREADS, false, false, true, LGR0, decltype(load0), decltype(lds_store), LGM>(
+        buf, lgPy, 2, Py, tw, load0, lds_store);
     __syncthreads();
     for (int e = tid; e < 2 * Py; e += THREADS) {
       const int kb = e >> lgPy;

@@ -345,53 +345,27 @@ __device__ __forceinline__ void fft_pass(int lgN, int batch, int lgNs, const cpl
   }
 }
 
-// Dispatch one pass of radix 2^lgR (runtime) to the compiled radix.  An
-// in-place pass holds N * batch / THREADS values per thread whatever the radix.
-template <typename T, int NMAX, int THREADS, bool INV, bool IN_PLACE, class Load, class Store>
-__device__ __forceinline__ void fft_pass_rt(int lgR, int lgN, int batch, int lgNs, const cplx<T>* __restrict__ tw,
-                                            Load load, Store store) {
-  const int tid = threadIdx.x;
-  if (lgR == 4) {
-    fft_pass<T, 16, (NMAX / 16 + THREADS - 1) / THREADS, INV, IN_PLACE>(lgN, batch, lgNs, tw, tid, THREADS, load,
-                                                                      store);
-  } else if (lgR == 3) {
-    fft_pass<T, 8, (NMAX / 8 + THREADS - 1) / THREADS, INV, IN_PLACE>(lgN, batch, lgNs, tw, tid, THREADS, load,
-                                                                    store);
-  } else if (lgR == 2) {
-    fft_pass<T, 4, (NMAX / 4 + THREADS - 1) / THREADS, INV, IN_PLACE>(lgN, batch, lgNs, tw, tid, THREADS, load,
-                                                                    store);
-  } else {
-    fft_pass<T, 2, (NMAX / 2 + THREADS - 1) / THREADS, INV, IN_PLACE>(lgN, batch, lgNs, tw, tid, THREADS, load,
-                                                                    store);
-  }
-}
-
-// Pass plan for a transform of 2^lgN points: the remainder radix first, then
-// radix-16 passes, so that the last pass is always radix 16 (lgN >= 4).
-__device__ __forceinline__ int fft_npasses(int lgN) { return (lgN + 3) >> 2; }
-__device__ __forceinline__ int fft_pass_lgR(int lgN, int pass) {
-  const int rem = lgN & 3;
-  if (rem != 0 && pass == 0) return rem;
-  return 4;
-}
-
 // Complete transform: the first pass reads through `load0`, the last pass
 // writes through `storeN`, the passes in between run in place in the padded
 // LDS buffer `buf` (index b * bstride + i).  FIRST_IN_LDS says that load0
 // reads `buf` and LAST_IN_LDS that storeN writes it (those passes then run
-// in place).  LGR0 must equal fft_pass_lgR(lgN, 0).  Barriers
-// separate the passes; there is none after the final stores.
+// in place).  All passes after the first have radix 2^LGM (16 or 8; radix 8
+// holds half the values per thread in registers for one more pass); the first
+// takes the remainder, LGR0 = lgN mod LGM (or LGM).  Barriers separate the
+// passes; there is none after the final stores.
 template <typename T, int NMAX, int THREADS, bool INV, bool FIRST_IN_LDS, bool LAST_IN_LDS, int LGR0, class Load0,
-          class StoreN>
+          class StoreN, int LGM = 4>
 __device__ void fft_run(cplx<T>* buf, int lgN, int batch, int bstride, const cplx<T>* __restrict__ tw, Load0 load0,
                         StoreN storeN) {
-  const int np = fft_npasses(lgN);
+  static_assert(LGM == 3 || LGM == 4, "middle radix 8 or 16");
+  const int np = (lgN + LGM - 1) / LGM;
   auto lds_load = [&](int b, int i) { return buf[lds_pad(b * bstride + i)]; };
   auto lds_store = [&](int b, int i, cplx<T> v) { buf[lds_pad(b * bstride + i)] = v; };
   int lgNs = 0;
-  constexpr int I16 = (NMAX / 16 + THREADS - 1) / THREADS;
+  constexpr int RM = 1 << LGM;
+  constexpr int IM = (NMAX / RM + THREADS - 1) / THREADS;
   const int tid = threadIdx.x;
-  // first pass: the only one whose radix (2^LGR0, LGR0 = lgN mod 4 or 4) can be below 16
+  // first pass: the only one whose radix (2^LGR0) can be below 2^LGM
   constexpr int R0 = 1 << LGR0;
   constexpr int I0 = (NMAX / R0 + THREADS - 1) / THREADS;
   const int lgR0 = LGR0;
@@ -403,11 +377,11 @@ __device__ void fft_run(cplx<T>* buf, int lgN, int batch, int bstride, const cpl
   __syncthreads();
   lgNs = lgR0;
   for (int ps = 1; ps < np - 1; ++ps) {
-    fft_pass<T, 16, I16, INV, true>(lgN, batch, lgNs, tw, tid, THREADS, lds_load, lds_store);
+    fft_pass<T, RM, IM, INV, true>(lgN, batch, lgNs, tw, tid, THREADS, lds_load, lds_store);
     __syncthreads();
-    lgNs += 4;
+    lgNs += LGM;
   }
-  fft_pass<T, 16, I16, INV, LAST_IN_LDS>(lgN, batch, lgNs, tw, tid, THREADS, lds_load, storeN);
+  fft_pass<T, RM, IM, INV, LAST_IN_LDS>(lgN, batch, lgNs, tw, tid, THREADS, lds_load, storeN);
 }
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }

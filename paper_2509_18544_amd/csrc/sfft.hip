@@ -29,6 +29,7 @@ constexpr int SUB_NMAX = 4096;       // complex FP64 elements per subtraction ro
 constexpr int ROW_NMAX_F32 = 8192;    // complex elements in the row-pass LDS buffer (64 KB)
 constexpr int ROW_NMAX_F64 = 4096;    // 64 KB
 constexpr int COL_NMAX = 8192;        // complex elements per column-pass block (two columns)
+constexpr int COL_LGM = 4;            // later passes of the column transform: radix 16 (radix 8 measured slower)
 constexpr int MAX_ROWS_PER_BLOCK = 64;
 constexpr int WIN_THREADS = 64;
 constexpr int WIN_IMAX = 64;
@@ -307,7 +308,8 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // radix (log2) of the first pass of a 2^lgN-point transform: the remainder of
 // lgN mod 4, or 4 (the later passes are all radix 16)
-int first_radix_log(int lgN) { return (lgN & 3) ? (lgN & 3) : 4; }
+// first pass radix of a plan whose later passes have radix 2^lgm
+int first_radix_log(int lgN, int lgm = 4) { return (lgN % lgm) ? (lgN % lgm) : lgm; }
 
 Layout layout_of(const Derived& D) {
   Layout Lo;
@@ -644,11 +646,11 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     const int nblk = (D.H / 2 - 1) * D.nbase;
     const int grid = ((nblk + 7) / 8) * 8;
     p->timer.begin(SFFT_STAGE_COL_FWD, s);
-    switch (first_radix_log(D.lgPy)) {
+    switch (first_radix_log(D.lgPy, COL_LGM)) {
 #define COL_CASE(LG)                                                                                        \
   case LG: {                                                                                                \
-    auto kfn = col_fwd_kernel<T, FFT_THREADS, COL_NMAX, LG>;                                                \
-    auto kdc = col_fwd_dc_kernel<T, FFT_THREADS, COL_NMAX, LG>;                                             \
+    auto kfn = col_fwd_kernel<T, FFT_THREADS, COL_NMAX, LG, COL_LGM>;                                       \
+    auto kdc = col_fwd_dc_kernel<T, FFT_THREADS, COL_NMAX, LG, COL_LGM>;                                    \
     HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
     HIP_TRY(hipFuncSetAttribute((const void*)kdc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
     kdc<<<D.nbase, FFT_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.Ub), U, tw);                               \
