@@ -18,6 +18,7 @@
 namespace sfft {
 
 constexpr int NB = 64;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // One pair's solve: every kernel below takes a device table of jobs and
 // finds its pair from the block index, so that one launch serves a batch.
@@ -33,6 +34,29 @@ struct SolveJob {
   int* info;
   int n, nblk;
 };
+
+// acc = A B^T (64 x 64 tiles in LDS, K = NB) for this wave's 32 x 32 quarter
+// (rows wm.., columns wn..), on the FP64 matrix cores as 2 x 2 MFMA 16x16x4
+// tiles.  Operand layout of the 16x16x4 f64 MFMA: lane l gives A[row l%16][k
+// l/16] and B^T[k l/16][col l%16]; result register r of lane l is
+// D[l/16 + 4 r][l%16] (lr = l%16, lk = l/16 below; checked on the device).
+__device__ __forceinline__ void tile_abt(const double (*A)[NB + 1], const double (*B)[NB + 1], int wm, int wn,
+                                         int lr, int lk, f64x4 (&acc)[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int m0 = 0; m0 < NB; m0 += 4) {
+    const int kk = m0 + lk;
+    const double a0 = A[wm + lr][kk], a1 = A[wm + 16 + lr][kk];
+    const double b0 = B[wn + lr][kk], b1 = B[wn + 16 + lr][kk];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
 
 // Diagonal block: one wave of 64 lanes.
 //  A partial last block (nb < 64 rows) is padded with the identity, whose
@@ -139,31 +163,21 @@ __global__ __launch_bounds__(256) void trsm_kernel(const SolveJob* __restrict__ 
     B[i][j] = Linv[e];
   }
   __syncthreads();
-  // each thread: rows 4*ty + {0..3}, columns tx + 16*{0..3}
-  const int ty = tid / 16, tx = tid % 16;
-  double acc[4][4];
+  // L = A Linv^T on the matrix cores (see tile_abt)
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  f64x4 acc[2][2];
+  tile_abt(A, B, wm, wn, lr, lk, acc);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int m = 0; m < NB; ++m) {
-    double av[4], bv[4];
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = A[4 * ty + a][m];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = B[tx + 16 * b][m];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = 4 * ty + a, j = tx + 16 * b;
-      if (i < nr && j < nb) F[(int64_t)(r0 + i) * n + k0 + j] = acc[a][b];
-    }
+      for (int r = 0; r < 4; ++r) {
+        const int i = wm + 16 * a + lk + 4 * r, j = wn + 16 * c + lr;
+        if (i < nr && j < nb) F[(int64_t)(r0 + i) * n + k0 + j] = acc[a][c][r];
+      }
 }
 
 // Lower tiles (I >= J) of the trailing matrix: A_IJ -= L_I L_J^T.
@@ -197,30 +211,20 @@ __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ 
     B[i][m] = (i < nj && m < nb) ? F[(int64_t)(rj + i) * n + k0 + m] : 0.0;
   }
   __syncthreads();
-  const int ty = tid / 16, tx = tid % 16;
-  double acc[4][4];
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  f64x4 acc[2][2];
+  tile_abt(A, B, wm, wn, lr, lk, acc);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-  for (int m = 0; m < NB; ++m) {
-    double av[4], bv[4];
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = A[4 * ty + a][m];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) bv[c] = B[tx + 16 * c][m];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = 4 * ty + a, j = tx + 16 * c;
-      if (i < ni && j < nj && (I != J || j <= i)) F[(int64_t)(ri + i) * n + rj + j] -= acc[a][c];
-    }
+      for (int r = 0; r < 4; ++r) {
+        const int i = wm + 16 * a + lk + 4 * r, j = wn + 16 * c + lr;
+        if (i < ni && j < nj && (I != J || j <= i)) F[(int64_t)(ri + i) * n + rj + j] -= acc[a][c][r];
+      }
 }
 
 // Forward substitution L y = b (single block, 1024 threads).  The solution
