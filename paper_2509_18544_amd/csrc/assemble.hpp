@@ -366,14 +366,15 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
         const cplx<T> x = U[pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o];
         stage[pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1))] = mk((double)x.x, (double)x.y);
       }
-      for (int e = tid; e < P.njlo * nc * JMAX; e += THREADS) {
-        const int ji = e / (nc * JMAX);
-        const int r = e - ji * (nc * JMAX);
-        const int c = r / JMAX;
-        const int t = r - c * JMAX;
-        const int j = (int)P.jlo_list[ji] + t;
-        const int m = (((k1c + c) * j) % Py + Py) % Py;
-        twc[e] = conjg(twd[m << (TW_LOG - lgPy)]);
+      // Py is a power of two: the twiddle index is the product masked to [0, Py)
+      for (int ji = 0; ji < P.njlo; ++ji) {
+        const int jlo = P.jlo_list[ji];
+        for (int r = tid; r < nc * JMAX; r += THREADS) {
+          const int c = r / JMAX;
+          const int t = r - c * JMAX;
+          const int m = ((k1c + c) * (jlo + t)) & (Py - 1);
+          twc[ji * nc * JMAX + r] = conjg(twd[m << (TW_LOG - lgPy)]);
+        }
       }
       __syncthreads();
       if (!active) continue;
