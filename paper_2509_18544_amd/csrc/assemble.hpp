@@ -337,7 +337,14 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
   const int64_t pstride = (int64_t)(H + 1) * Py;
   const int per_plane = corr_plane_stride(C1);
   // outer twiddles e^{2 pi i k1 (jlo + t)/Py} of the chunk, per distinct jlo, after the spectra
-  cplx<double>* twc = stage + P.nplanes * per_plane;
+  cplx<double>* twc = stage + P.nplanes * per_plane;       // [njlo][C1][JMAX]
+  cplx<double>* twstep = twc + P.njlo * C1 * JMAX;           // [njlo][JMAX]
+  // e^{2 pi i C1 j / Py}: advancing k1 by one chunk multiplies each outer twiddle by it
+  for (int e = tid; e < P.njlo * JMAX; e += THREADS) {
+    const int ji = e / JMAX, t = e - ji * JMAX;
+    const int m = (C1 * ((int)P.jlo_list[ji] + t)) & (Py - 1);
+    twstep[e] = conjg(twd[m << (TW_LOG - lgPy)]);
+  }
 
   for (int wbase = 0; wbase < nwaves; wbase += THREADS / 64) {
     const int wv = wbase + (tid >> 6);
@@ -360,20 +367,39 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
     for (int k1c = 0; k1c < P1; k1c += C1) {
       const int nc = min(C1, P1 - k1c);
       __syncthreads();
-      for (int e = tid; e < P.nplanes * nc * P2; e += THREADS) {
-        const int pl = e / (nc * P2);
-        const int o = e - pl * (nc * P2);
-        const cplx<T> x = U[pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o];
-        stage[pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1))] = mk((double)x.x, (double)x.y);
+      // spectra: two neighbouring values per load (16 bytes in FP32)
+      const int npr = nc * (P2 / 2);
+      for (int e = tid; e < P.nplanes * npr; e += THREADS) {
+        const int pl = e / npr;
+        const int o = 2 * (e - pl * npr);
+        const cplx<T>* src = U + pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o;
+        cplx<double> v0, v1;
+        if constexpr (sizeof(T) == sizeof(float)) {
+          const float4 q = *reinterpret_cast<const float4*>(src);
+          v0 = mk((double)q.x, (double)q.y);
+          v1 = mk((double)q.z, (double)q.w);
+        } else {
+          v0 = mk((double)src[0].x, (double)src[0].y);
+          v1 = mk((double)src[1].x, (double)src[1].y);
+        }
+        cplx<double>* dst = stage + pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1));
+        dst[0] = v0;
+        dst[1] = v1;
       }
-      // Py is a power of two: the twiddle index is the product masked to [0, Py)
+      // outer twiddles: from the table for the first chunk (Py is a power of two,
+      // so the index is the product masked to [0, Py)), then by the FP64 step
       for (int ji = 0; ji < P.njlo; ++ji) {
         const int jlo = P.jlo_list[ji];
-        for (int r = tid; r < nc * JMAX; r += THREADS) {
-          const int c = r / JMAX;
-          const int t = r - c * JMAX;
-          const int m = ((k1c + c) * (jlo + t)) & (Py - 1);
-          twc[ji * nc * JMAX + r] = conjg(twd[m << (TW_LOG - lgPy)]);
+        for (int r = tid; r < C1 * JMAX; r += THREADS) {
+          const int t = r % JMAX;
+          cplx<double>& w = twc[ji * C1 * JMAX + r];
+          if (k1c == 0) {
+            const int c = r / JMAX;
+            const int m = (c * (jlo + t)) & (Py - 1);
+            w = conjg(twd[m << (TW_LOG - lgPy)]);
+          } else {
+            w = w * twstep[ji * JMAX + t];
+          }
         }
       }
       __syncthreads();
@@ -386,7 +412,7 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
 #pragma unroll
         for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(xa[k2], xb[k2]);
         dft16<double, true>(z);
-        const cplx<double>* twt = twc + ((int)it.jidx * nc + c) * JMAX;
+        const cplx<double>* twt = twc + ((int)it.jidx * C1 + c) * JMAX;
         (void)k1;
         switch (srot) {
 #define CORR_CASE(SV) \

@@ -539,7 +539,7 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
 // plane (FP64, padded) and their outer twiddles are staged in LDS per chunk.
 size_t corr_lds_bytes(const Derived& D, int C1) {
   const size_t stage =
-      ((size_t)D.nplanes * corr_plane_stride(C1) + (size_t)D.njlo * C1 * JMAX) * sizeof(cplx<double>);
+      ((size_t)D.nplanes * corr_plane_stride(C1) + (size_t)D.njlo * (C1 + 1) * JMAX) * sizeof(cplx<double>);
   const size_t red = (size_t)ASM_THREADS * ((JMAX + 1) / 2) * sizeof(cplx<double>);
   return std::max(stage, red);
 }
