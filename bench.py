@@ -226,8 +226,9 @@ def main():
     ncoef = B.sfft_num_coeffs(descs[0])
     Dinfo = dict(N=n_px, P=P, nplanes=nk + nb + 1, vrows=vrows, nk=nk, nb=nb, w=w, ncoef=ncoef,
                  nbase=pairs[0].dk + pairs[0].db + 3)
-    # dominant single-pair kernel stage (the factor/solve stages are batched launches)
-    dom = max((k for k in stages_avg if k not in ("factor", "solve")), key=lambda k: per_pair[k])
+    # dominant kernel: among the stages that are one kernel per pair (the factor/solve
+    # stages are batched launches of many kernels, the subtraction is six kernels)
+    dom = max((k for k in stages_avg if k in STAGE_KERNEL and k != "subtract"), key=lambda k: per_pair[k])
     def roof_of(stage):
         bound, amount = stage_cost(stage, Dinfo, mode == B.SFFT_MODE_F64)
         # batched stages run once per step for all pairs: price them per pair

@@ -325,7 +325,7 @@ Layout layout_of(const Derived& D) {
     const size_t asm_bytes = (size_t)D.nplanes * (D.H + 1) * D.Py * D.csize;
     const size_t sub_bytes = align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>)) +
                              align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>)) +
-                             align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>));
+                             2 * align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>));   // K and G
     const size_t dir_bytes = (size_t)D.dir_nband * D.nwin * sizeof(double);   // direct-route partial sums
     Lo.U = take(std::max(std::max(asm_bytes, sub_bytes), dir_bytes));
   }
@@ -778,6 +778,8 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
         reinterpret_cast<cplx<double>*>(base + align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>)));
     cplx<double>* K = reinterpret_cast<cplx<double>*>(
         reinterpret_cast<unsigned char*>(Mh) + align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>)));
+    cplx<double>* G = reinterpret_cast<cplx<double>*>(
+        reinterpret_cast<unsigned char*>(K) + align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>)));
     const size_t lds = (size_t)lds_padded_size(S.rows_per_block * D.H) * sizeof(cplx<double>);
     switch (first_radix_log(D.lgPx - 1)) {
 #define SUBF_CASE(LG)                                                                                       \
@@ -795,6 +797,9 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
       dim3 g((D.H + 1 + 255) / 256, D.nk * D.L);
       sub_kspec_kernel<<<g, 256, 0, s>>>(S, coeffs, K, twd);
       LAUNCH_CHECK();
+      dim3 gg((D.H + 1 + 255) / 256, D.L);
+      sub_gspec_kernel<<<gg, 256, 0, s>>>(S, K, G);
+      LAUNCH_CHECK();
     }
     {
       dim3 g((D.H + 1 + 63) / 64, (D.ny + SUBC_RB - 1) / SUBC_RB);
@@ -804,7 +809,7 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
   case WV: {                                                                                                   \
     auto kc = sub_conv_kernel<WV>;                                                                             \
     HIP_TRY(hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_c));   \
-    kc<<<g, 64 * SUBC_WAVES, lds_c, s>>>(S, Uq, K, Mh);                                                        \
+    kc<<<g, 64 * SUBC_WAVES, lds_c, s>>>(S, Uq, G, Mh);                                                        \
     break;                                                                                                     \
   }
         CONV_CASE(0) CONV_CASE(1) CONV_CASE(2) CONV_CASE(3) CONV_CASE(4) CONV_CASE(5) CONV_CASE(6) CONV_CASE(7)

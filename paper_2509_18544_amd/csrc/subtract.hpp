@@ -291,13 +291,41 @@ __global__ void sub_kspec_kernel(SpecParams P, const double* __restrict__ theta,
   K[(int64_t)row * (H + 1) + kx] = acc;
 }
 
-// M(y, kx) = sum_a sum_{u_y} K[a][u_y][kx] yh(y - u_y)^q_a U_{p_a}(y - u_y, kx).
+// Filters with the y-weight moved to the output row.  With yh(y - u_y) =
+// yh(y) - u_y sy and the binomial expansion of its q-th power,
+//   sum_a K_a(u_y) yh(y - u_y)^q_a U_{p_a}(y - u_y)
+//     = sum_{p,e} yh(y)^e sum_{u_y} G_{p,e}(u_y) U_p(y - u_y),
+//   G_{p,e}(u_y) = sum_{q >= e} C(q, e) (-u_y sy)^(q-e) K_{(p,q)}(u_y).
+// The pairs (p, e) are the monomials themselves; G[(p,e)] takes the place of
+// K[(p,q)] in the same layout, one thread per (u_y, kx).
+__global__ void sub_gspec_kernel(SpecParams P, const cplx<double>* __restrict__ K, cplx<double>* __restrict__ G) {
+  const int L = 2 * P.w + 1;
+  const int H = P.H;
+  const int uyi = blockIdx.y;
+  const int kx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kx > H) return;
+  const double d = -(double)(uyi - P.w) * P.sy;   // -u_y sy
+  for (int g = 0; g < P.nk; ++g) {
+    const int p = P.kpx[g], e = P.kqy[g];
+    cplx<double> acc = mk(0.0, 0.0);
+    for (int a = 0; a < P.nk; ++a) {
+      if (P.kpx[a] != p || P.kqy[a] < e) continue;
+      const int q = P.kqy[a];
+      const double c = binom(q, e) * ipow(d, q - e);
+      acc = acc + scale(K[((int64_t)a * L + uyi) * (H + 1) + kx], c);
+    }
+    G[((int64_t)g * L + uyi) * (H + 1) + kx] = acc;
+  }
+}
+
+// M(y, kx) = sum_a sum_{u_y} K[a][u_y][kx] yh(y - u_y)^q_a U_{p_a}(y - u_y, kx)
+//          = sum_{p,e} yh(y)^e sum_{u_y} G[(p,e)][u_y][kx] U_p(y - u_y, kx)   (sub_gspec_kernel).
 // Block: 64 kx columns (the lanes) x SUBC_WAVES waves of SUBC_TY output rows.
-// For each monomial the block stages the SUBC_RB + 2W source rows it needs,
-// already weighted by yh^q, in LDS (HBM traffic ~ (1 + 2W / SUBC_RB) x the
-// source; the re-reads of a power p for its other monomials hit L2), and each
-// thread sums its SUBC_TY x L products straight from LDS with one tap in
-// registers at a time, so registers do not grow with w.
+// For each x power p the block stages the SUBC_RB + 2W source rows of U_p in
+// LDS once (HBM traffic ~ (1 + 2W / SUBC_RB) x the source), and for each
+// filter of that power each thread sums its SUBC_TY x L products straight
+// from LDS with one tap in registers at a time (registers do not grow with
+// w), then weights the output rows by yh(y)^e.
 constexpr int SUBC_TY = 6;                        // output rows per wave
 constexpr int SUBC_WAVES = 8;
 constexpr int SUBC_RB = SUBC_TY * SUBC_WAVES;     // output rows per block
@@ -308,7 +336,7 @@ __host__ __device__ constexpr size_t sub_conv_lds_bytes(int w) {
 
 template <int W>
 __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P, const cplx<double>* __restrict__ Uq,
-                                                                   const cplx<double>* __restrict__ K,
+                                                                   const cplx<double>* __restrict__ G,
                                                                    cplx<double>* __restrict__ Mh) {
   constexpr int L = 2 * W + 1;
   constexpr int WINB = SUBC_RB + 2 * W;           // source rows of the block
@@ -325,31 +353,41 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
   cplx<double> acc[SUBC_TY];
 #pragma unroll
   for (int t = 0; t < SUBC_TY; ++t) acc[t] = mk(0.0, 0.0);
-  for (int a = 0; a < P.nk; ++a) {
-    const int p = P.kpx[a], q = P.kqy[a];
+  int pmax = 0;
+  for (int a = 0; a < P.nk; ++a) pmax = max(pmax, (int)P.kpx[a]);
+  for (int p = 0; p <= pmax; ++p) {
     const cplx<double>* Up = Uq + (int64_t)p * P.ny * (H + 1);
-    __syncthreads();   // the previous monomial's rows have been read
+    __syncthreads();   // the previous power's rows have been read
     for (int e = tid; e < WINB * 64; e += 64 * SUBC_WAVES) {
       const int r = e >> 6, c = e & 63;
       const int ys = yb - W + r;
       cplx<double> u = mk(0.0, 0.0);
-      if (ys >= 0 && ys < P.ny && kx0 + c <= H) {
-        u = Up[(int64_t)ys * (H + 1) + kx0 + c];
-        if (q > 0) u = scale(u, ipow((double)ys * P.sy - 1.0, q));
-      }
+      if (ys >= 0 && ys < P.ny && kx0 + c <= H) u = Up[(int64_t)ys * (H + 1) + kx0 + c];
       win[e] = u;
     }
     __syncthreads();
     if (kx > H) continue;
-    const cplx<double>* Ka = K + (int64_t)a * L * (H + 1) + kx;
-    // output row y0 + t takes source row y0 + t - u_y = window row wave * TY + t + 2W - uyi
-    const cplx<double>* wl = win + (wave * SUBC_TY + 2 * W) * 64 + lane;
-#pragma unroll 1
-    for (int uyi = 0; uyi < L; ++uyi) {
-      const cplx<double> kv = Ka[(int64_t)uyi * (H + 1)];
-      const cplx<double>* src = wl - uyi * 64;
+    for (int g = 0; g < P.nk; ++g) {
+      if (P.kpx[g] != p) continue;
+      const int ex = P.kqy[g];
+      const cplx<double>* Ga = G + (int64_t)g * L * (H + 1) + kx;
+      // output row y0 + t takes source row y0 + t - u_y = window row wave * TY + t + 2W - uyi
+      const cplx<double>* wl = win + (wave * SUBC_TY + 2 * W) * 64 + lane;
+      cplx<double> part[SUBC_TY];
 #pragma unroll
-      for (int t = 0; t < SUBC_TY; ++t) acc[t] = cmac(acc[t], kv, src[t * 64]);
+      for (int t = 0; t < SUBC_TY; ++t) part[t] = mk(0.0, 0.0);
+#pragma unroll 1
+      for (int uyi = 0; uyi < L; ++uyi) {
+        const cplx<double> kv = Ga[(int64_t)uyi * (H + 1)];
+        const cplx<double>* src = wl - uyi * 64;
+#pragma unroll
+        for (int t = 0; t < SUBC_TY; ++t) part[t] = cmac(part[t], kv, src[t * 64]);
+      }
+#pragma unroll
+      for (int t = 0; t < SUBC_TY; ++t) {
+        const double wy = ex > 0 ? ipow((double)(y0 + t) * P.sy - 1.0, ex) : 1.0;
+        acc[t] = acc[t] + scale(part[t], wy);
+      }
     }
   }
   if (kx > H) return;
