@@ -128,7 +128,7 @@ __device__ __forceinline__ T base_value(const AsmParams& P, int b, int y, int x,
   return sci[o];
 }
 
-template <typename T, int THREADS, int NMAX, int LGR0>
+template <typename T, int THREADS, int NMAX, int LGH>
 __global__ __launch_bounds__(THREADS) void row_fwd_kernel(AsmParams P, const T* __restrict__ sci,
                                                           const T* __restrict__ tmpl,
                                                           const uint8_t* __restrict__ mask, cplx<T>* __restrict__ U,
@@ -139,14 +139,13 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(AsmParams P, const T* 
   if (rb >= P.nrowblk) return;
   const int RB = P.rows_per_block;
   const int y0 = rb * RB;
-  const int H = P.H;
-  const int lgH = P.lgPx - 1;
+  constexpr int lgH = LGH;               // H = Px / 2 = 2^LGH
+  constexpr int H = 1 << LGH;
   const int Py = 1 << P.lgPy;
   const int64_t pstride = (int64_t)H * Py;   // elements per base plane
   const int tid = threadIdx.x;
-  const int twsx = TW_LOG - P.lgPx;
-  auto lds_load = [&](int r, int i) { return buf[lds_pad(r * H + i)]; };
-  auto lds_store = [&](int r, int i, cplx<T> v) { buf[lds_pad(r * H + i)] = v; };
+  constexpr int twsx = TW_LOG - (LGH + 1);
+  const LdsRows<T, LGH> lds{buf};
   for (int b = 0; b < P.nbase; ++b) {
     __syncthreads();   // the previous base's split has read the buffer
     // packed base rows z(j) = x(2j) + i x(2j+1), coalesced over j
@@ -162,7 +161,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(AsmParams P, const T* 
       buf[lds_pad(e)] = z;
     }
     __syncthreads();
-    fft_run<T, NMAX, THREADS, false, true, true, LGR0>(buf, lgH, RB, H, tw, lds_load, lds_store);
+    fft_run<T, NMAX, THREADS, false, true, true, LGH, 4>(buf, RB, tw, lds, lds);
     __syncthreads();
     // split and write: consecutive threads fill one (column pair, row block) segment
     cplx<T>* Ub = U + (int64_t)b * pstride;
@@ -194,94 +193,102 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(AsmParams P, const T* 
 // ---------------------------------------------------------------------------
 // col_fwd: y-weight, FFT along y, residue-major write of every output plane
 // ---------------------------------------------------------------------------
-// Block = (column pair c >= 1, base b).  For each output plane o built from
-// base b (weight yh^q) the first FFT pass reads the pair block of Ub[b] times
-// yh^q (rows past ny are zero); the last pass (radix 16, so its output index
-// is ky = k1 + P1 k2 with k1 < P1 = Py/16) places X(ky) at slot k1*P2 + k2 in
-// LDS, and the two columns are copied out as one contiguous block of
-// X[o][kx][slot].  Pair 0 (which holds the packed DC/Nyquist column) is done
-// by col_fwd_dc_kernel.
-template <typename T>
-__device__ __forceinline__ cplx<T> col_load(const AsmParams& P, const cplx<T>* __restrict__ blk, int kb, int y,
-                                            int q) {
-  if (y >= P.ny) return mk((T)0, (T)0);
-  cplx<T> v = blk[2 * y + kb];
-  if (q > 0) v = scale(v, (T)ipow((double)y * P.sy - 1.0, q));
-  return v;
-}
-
-template <typename T, int THREADS, int NMAX, int LGR0, int LGM>
+// Block = (column pair c, base b).  The pair block of Ub[b] (two columns,
+// rows past ny zero) is read from HBM once, into the registers of the first
+// transform pass: thread j < 2 Py / R0 holds the R0 inputs y = jj + r Py/R0
+// of butterfly jj of column kb (j = kb Py/R0 + jj).  For each output plane o
+// built from base b (weight yh^q) the first pass weights those registers,
+// applies its radix-R0 DFT (no twiddles: Ns = 1) and writes LDS; the later
+// passes run in LDS, the last one (radix 16, so its output index is
+// ky = k1 + P1 k2 with k1 < P1 = Py/16) placing X(ky) at slot k1*P2 + k2; the
+// two columns then leave as one contiguous block of X[o][kx][slot].
+//   Pair 0 holds the packed real column pair z = x0 + i xH (DC and Nyquist
+// columns) in its column 0: X0(ky) = (Z(ky) + conj Z(-ky))/2 and
+// XH(ky) = (Z(ky) - conj Z(-ky))/(2i) go to columns 0 and H; its column 1 is
+// written as usual.
+template <typename T, int THREADS, int NMAX, int LGPY, int LGM>
 __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
                                                           cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int npairs = P.H / 2 - 1;       // pairs 1 .. H/2-1
+  const int npairs = P.H / 2;           // pairs 0 .. H/2-1
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   if (id >= npairs * P.nbase) return;
   const int b = id / npairs;
-  const int c = 1 + (id - b * npairs);
-  const int Py = 1 << P.lgPy;
-  const int lgPy = P.lgPy;
+  const int c = id - b * npairs;
+  constexpr int lgPy = LGPY;
+  constexpr int Py = 1 << LGPY;
   const int H = P.H;
   const cplx<T>* blk = Ub + (int64_t)b * H * Py + (int64_t)c * Py * 2;
-  const int lgP1 = lgPy - LG_P2;
-  const int P1 = 1 << lgP1;
+  constexpr int lgP1 = lgPy - LG_P2;
+  constexpr int P1 = 1 << lgP1;
   const int tid = threadIdx.x;
-  for (int oi = 0; oi < P.base_count[b]; ++oi) {
-    const int o = P.out_plane[P.base_first[b] + oi];
-    const int q = P.out_q[P.base_first[b] + oi];
-    cplx<T>* Xc = X + (int64_t)o * (H + 1) * Py + (int64_t)(2 * c) * Py;   // columns 2c, 2c+1: contiguous
-    auto load0 = [&](int kb, int y) -> cplx<T> { return col_load<T>(P, blk, kb, y, q); };
-    // the last pass puts ky = k1 + P1 k2 at slot k1*P2 + k2 of the LDS buffer ...
-    auto store_res = [&](int kb, int ky, cplx<T> v) {
-      buf[lds_pad(kb * Py + ((ky & (P1 - 1)) << LG_P2) + (ky >> lgP1))] = v;
-    };
-    __syncthreads();   // the previous output's copy-out has read the buffer
-    fft_run<T, NMAX, THREADS, false, false, true, LGR0, decltype(load0), decltype(store_res), LGM>(
-        buf, lgPy, 2, Py, tw, load0, store_res);
-    __syncthreads();
-    // ... and the two columns leave as one contiguous, coalesced block
-    for (int e = tid; e < 2 * Py; e += THREADS) Xc[e] = buf[lds_pad(e)];
+  // first pass: radix R0 = 2^LGR0 over M0 = Py/R0 butterflies per column,
+  // one butterfly per thread
+  static_assert(THREADS >= 512 && NMAX >= 2 * Py, "two columns per block");
+  constexpr int LGR0 = fft_first_lgr(LGPY, LGM);
+  constexpr int R0 = 1 << LGR0;
+  constexpr int lgM0 = lgPy - LGR0;
+  static_assert((2 << lgM0) <= THREADS, "one first-pass butterfly per thread");
+  const bool act = tid < (2 << lgM0);
+  const int kb = tid >> lgM0;
+  const int jj = tid & ((1 << lgM0) - 1);
+  // rows past ny are never written by the row pass: read a valid row and
+  // select zero, so that every load is unconditional
+  const int jb = act ? jj : 0;
+  cplx<T> raw[R0];
+#pragma unroll
+  for (int r = 0; r < R0; ++r) {
+    const int y = jb + (r << lgM0);
+    const cplx<T> t = blk[2 * min(y, P.ny - 1) + (kb & 1)];
+    raw[r] = (act && y < P.ny) ? t : mk((T)0, (T)0);
   }
-}
-
-// Pair 0: column 0 holds the packed (DC, Nyquist) real-column pair
-// z = x0 + i xN; after the transform X0(ky) = (Z(ky) + conj Z(-ky))/2 and
-// XN(ky) = (Z(ky) - conj Z(-ky))/(2i) go to columns 0 and H; column 1 is
-// written as usual.  One block per base.
-template <typename T, int THREADS, int NMAX, int LGR0, int LGM>
-__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_dc_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
-                                                             cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int b = blockIdx.x;
-  const int Py = 1 << P.lgPy;
-  const int lgPy = P.lgPy;
-  const int H = P.H;
-  const int tid = threadIdx.x;
-  const cplx<T>* blk = Ub + (int64_t)b * H * Py;
-  const int lgP1 = lgPy - LG_P2;
+  // The last pass (radix 16 = P2, span Ns = P1) hands over ky = i0 + c with
+  // i0 < P1 and c = r P1, r < 16, and puts X(ky) at slot k1*P2 + k2 =
+  // i0*P2 + r of the LDS buffer (k1 = ky mod P1, k2 = ky / P1).
+  static_assert(LGM == LG_P2, "the last column pass must have radix P2");
+  auto store_res = [&](int kbo, int i0, int c, cplx<T> v) {
+    buf[lds_pad(kbo * Py + (i0 << LG_P2)) + (c >> lgP1)] = v;
+  };
   for (int oi = 0; oi < P.base_count[b]; ++oi) {
     const int o = P.out_plane[P.base_first[b] + oi];
     const int q = P.out_q[P.base_first[b] + oi];
+    __syncthreads();   // the previous output's copy-out has read the buffer
+    if (act) {
+      cplx<T> v[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int y = jj + (r << lgM0);
+        const T yh = (T)((double)y * P.sy - 1.0);
+        T w = (T)1;
+        for (int i = 0; i < q; ++i) w *= yh;
+        v[r] = scale(raw[r], w);
+      }
+      dftR<T, R0, false>(v);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) buf[lds_pad(kb * Py + (jj << LGR0) + r)] = v[r];
+    }
+    __syncthreads();
+    fft_tail<T, NMAX, THREADS, false, true, LGPY, LGR0, LGM, decltype(store_res)>(buf, 2, tw, store_res);
+    __syncthreads();
     cplx<T>* Xo = X + (int64_t)o * (H + 1) * Py;
-    auto load0 = [&](int kb, int y) -> cplx<T> { return col_load<T>(P, blk, kb, y, q); };
-    auto lds_store = [&](int kb, int ky, cplx<T> v) { buf[lds_pad(kb * Py + ky)] = v; };
-    __syncthreads();
-    fft_run<T, NMAX, THREADS, false, false, true, LGR0, decltype(load0), decltype(lds_store), LGM>(
-        buf, lgPy, 2, Py, tw, load0, lds_store);
-    __syncthreads();
-    for (int e = tid; e < 2 * Py; e += THREADS) {
-      const int kb = e >> lgPy;
-      const int s = e & (Py - 1);           // output slot = k1 * P2 + k2
-      const int ky = (s >> LG_P2) + ((s & (P2 - 1)) << lgP1);
-      if (kb == 0) {
-        const cplx<T> z = buf[lds_pad(ky)];
-        const cplx<T> zm = conjg(buf[lds_pad((Py - ky) & (Py - 1))]);
-        Xo[s] = scale(z + zm, (T)0.5);
-        Xo[(int64_t)H * Py + s] = scale(rot90<T, false>(z - zm), (T)0.5);
-      } else {
-        Xo[(int64_t)Py + s] = buf[lds_pad(Py + ky)];
+    if (c > 0) {
+      // columns 2c, 2c+1 are contiguous: one coalesced block
+      cplx<T>* Xc = Xo + (int64_t)(2 * c) * Py;
+      for (int e = tid; e < 2 * Py; e += THREADS) Xc[e] = buf[lds_pad(e)];
+    } else {
+      for (int e = tid; e < 2 * Py; e += THREADS) {
+        if (e >= Py) {
+          Xo[e] = buf[lds_pad(e)];
+          continue;
+        }
+        // slot e holds ky = k1 + P1 k2 with k1 = e / P2, k2 = e mod P2; -ky sits at slot(-ky)
+        const int ky = (e >> LG_P2) + ((e & (P2 - 1)) << lgP1);
+        const int km = (Py - ky) & (Py - 1);
+        const cplx<T> z = buf[lds_pad(e)];
+        const cplx<T> zm = conjg(buf[lds_pad(((km & (P1 - 1)) << LG_P2) + (km >> lgP1))]);
+        Xo[e] = scale(z + zm, (T)0.5);
+        Xo[(int64_t)H * Py + e] = scale(rot90<T, false>(z - zm), (T)0.5);
       }
     }
   }

@@ -4,9 +4,10 @@
 //                   the transforms need.
 //  * dft2/4/8/16 -- in-register DFTs of size 2..16 (forward: exp(-2 pi i jk/R),
 //                   inverse: exp(+2 pi i jk/R), unnormalised).
-//  * stockham_pass -- one radix-R pass of a self-sorting (Stockham) FFT on a
-//                   batch of power-of-two transforms held in LDS, staged
-//                   through registers so that it runs in place.
+//  * fft_pass / fft_run / fft_rest -- radix-R passes of a self-sorting
+//                   (Stockham) FFT on a batch of power-of-two transforms, with
+//                   the first and last pass reading and writing through
+//                   accessors and the passes in between in place in LDS.
 //
 // Twiddle factors come from a table tw[m] = exp(-2 pi i m / TW_N) computed in
 // FP64 on the host and rounded once to T; the inverse direction conjugates.
@@ -74,10 +75,10 @@ __device__ __forceinline__ cplx<T> rot90(cplx<T> a) {
 template <typename T, bool INV>
 __device__ __forceinline__ cplx<T> twid(const cplx<T>* __restrict__ tw, int m) {
   if constexpr (sizeof(T) == sizeof(double)) {
-    const cplx<T> t = tw[m & (TW_N - 1)];
+    const cplx<T> t = tw[(uint32_t)m & (uint32_t)(TW_N - 1)];
     return INV ? conjg(t) : t;
   } else {
-    const cplx<float> t = tw[m & (TW_N / 2 - 1)];
+    const cplx<float> t = tw[(uint32_t)m & (uint32_t)(TW_N / 2 - 1)];
     const uint32_t flip = ((uint32_t)m & (uint32_t)(TW_N / 2)) << (31 - (TW_LOG - 1));
     const uint32_t xr = __float_as_uint(t.x) ^ flip;
     const uint32_t yr = __float_as_uint(t.y) ^ flip ^ (INV ? 0x80000000u : 0u);
@@ -188,200 +189,163 @@ __device__ __forceinline__ void dftR(cplx<T>* v) {
   else if constexpr (R == 8) dft8<T, INV>(v);
   else dft16<T, INV>(v);
 }
-
 // ---------------------------------------------------------------------------
-// Stockham pass in LDS
-// ---------------------------------------------------------------------------
-//
-// `batch` transforms of length N = 2^lgN start at buf + b * bstride.  Before
-// the pass the data is the result of the previous passes whose radices
-// multiply to Ns (Ns = 1 before the first pass).  Butterfly j (0 <= j < N/R)
-// reads x[j + r N/R], twiddles element r by w_{Ns R}^{r k} with k = j mod Ns,
-// applies the R-point DFT and writes element r to (j - k) R + k + r Ns.  After
-// the last pass the data is the DFT in natural order.  Every thread stages
-// its butterflies in registers, so the caller must guarantee
-// N/R * batch <= nthreads * ITEMS, and the pass ends with a barrier.
-template <typename T, int R, int ITEMS, bool INV>
-__device__ __forceinline__ void stockham_pass(cplx<T>* buf, int lgN, int batch, int bstride, int lgNs,
-                                              const cplx<T>* __restrict__ tw, int tid, int nthreads) {
-  const int lgR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
-  const int lgM = lgN - lgR;
-  const int M = 1 << lgM;
-  const int all = M * batch;
-  const int Ns = 1 << lgNs;
-  // twiddle stride in the 4096 table for w_{Ns R}: TW_N / (Ns R)
-  const int tws = TW_LOG - (lgNs + lgR);
-  cplx<T> v[ITEMS][R];
-#pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    const int j = tid + it * nthreads;
-    if (j < all) {
-      const int b = j >> lgM;
-      const int jj = j & (M - 1);
-      const int k = jj & (Ns - 1);
-      const cplx<T>* src = buf + (size_t)b * bstride + jj;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = src[r << lgM];
-      if (lgNs > 0) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[it][r] = v[it][r] * twid<T, INV>(tw, (r * k) << tws);
-      }
-      dftR<T, R, INV>(v[it]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    const int j = tid + it * nthreads;
-    if (j < all) {
-      const int b = j >> lgM;
-      const int jj = j & (M - 1);
-      const int k = jj & (Ns - 1);
-      cplx<T>* dst = buf + (size_t)b * bstride + ((jj - k) << lgR) + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst[r << lgNs] = v[it][r];
-    }
-  }
-  __syncthreads();
-}
-
-// Full FFT of `batch` transforms of length 2^lgN in LDS: radix-16 passes,
-// then one radix-8/4/2 pass for the remaining bits.  NMAX bounds N * batch,
-// THREADS is the block size (both compile-time, to size the register staging).
-template <typename T, int NMAX, int THREADS, bool INV>
-__device__ void fft_lds(cplx<T>* buf, int lgN, int batch, int bstride, const cplx<T>* __restrict__ tw) {
-  const int tid = threadIdx.x;
-  int lgNs = 0;
-  int rem = lgN;
-  while (rem >= 4) {
-    stockham_pass<T, 16, (NMAX / 16 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid,
-                                                                  THREADS);
-    lgNs += 4;
-    rem -= 4;
-  }
-  if (rem == 3)
-    stockham_pass<T, 8, (NMAX / 8 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid, THREADS);
-  else if (rem == 2)
-    stockham_pass<T, 4, (NMAX / 4 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid, THREADS);
-  else if (rem == 1)
-    stockham_pass<T, 2, (NMAX / 2 + THREADS - 1) / THREADS, INV>(buf, lgN, batch, bstride, lgNs, tw, tid, THREADS);
-}
-
-// ---------------------------------------------------------------------------
-// Flexible Stockham pass: operands come from / go to arbitrary accessors
+// Stockham passes with compile-time sizes
 // ---------------------------------------------------------------------------
 // LDS buffers used by these passes are padded by one element every 16
 // (lds_pad) so that the strided Stockham stores do not pile onto one bank.
+// Transform b of a batch starts at element b * N of the unpadded index space.
+// Every size (N = 2^LGN, the radix, the span Ns already transformed) is a
+// template parameter, so that the index arithmetic folds into constants and
+// the LDS offsets into the instructions' immediate fields.
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 4) + 1; }
 
-// One radix-R pass over `batch` transforms of length 2^lgN.  Butterfly j
-// (0 <= j < N/R) takes inputs x[j + r N/R] = load(b, j + r N/R), twiddles input r
-// by w_{Ns R}^{r k} (k = j mod Ns), applies the R-point DFT and hands output r
-// to store(b, (j - k) R + k + r Ns, value).
+// radix of the first pass when the later ones have radix 2^LGM
+__host__ __device__ constexpr int fft_first_lgr(int lgn, int lgm) { return (lgn % lgm) ? (lgn % lgm) : lgm; }
+
+// Offset of padded element i0 + c from padded element i0, where the
+// accessors below guarantee that adding c moves i0 across whole 16-element
+// groups only: lds_pad(x + c) = lds_pad(x) + c + (c >> 4).
+__host__ __device__ constexpr int pad_off(int c) { return c + (c >> 4); }
+
+// One radix-R pass over `batch` transforms of length 2^LGN.  Butterfly j
+// (0 <= j < N/R) takes inputs x[j + r N/R] = load(b, j, r N/R), twiddles input r
+// by w_{Ns R}^{r k} (Ns = 2^LGNS, k = j mod Ns), applies the R-point DFT and
+// hands output r to store(b, (j - k) R + k, r Ns, value).  Accessors get the
+// element index split as i0 + c with c a compile-time constant after
+// unrolling; in-LDS accessors place it at lds_pad(b N + i0) + pad_off(c).
+// That is exact here: for the loads i0 = j < M = N/R and c = r M; for the
+// stores i0 = (j - k) R + k and c = r Ns; N, M, Ns, R are powers of two with
+// N >= 16, so c either is a multiple of 16 or stays inside the 16-group of i0.
 //   IN_PLACE = false: each butterfly is loaded, computed and stored in turn
 //                     (source and destination are different buffers).
 //   IN_PLACE = true : every thread first loads all its butterflies (at most
 //                     ITEMS), then a barrier, then the stores.
 // No barrier after the stores.
-template <typename T, int R, bool INV>
-__device__ __forceinline__ void fft_butterfly(cplx<T>* v, int k, int lgNs, int tws, const cplx<T>* __restrict__ tw) {
-  if (lgNs > 0) {
+template <typename T, int R, int LGNS, bool INV>
+__device__ __forceinline__ void fft_butterfly(cplx<T>* v, int k, const cplx<T>* __restrict__ tw) {
+  constexpr int lgR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  constexpr int tws = TW_LOG - (LGNS + lgR);
+  if constexpr (LGNS > 0) {
 #pragma unroll
     for (int r = 1; r < R; ++r) v[r] = v[r] * twid<T, INV>(tw, (r * k) << tws);
   }
   dftR<T, R, INV>(v);
 }
 
-template <typename T, int R, int ITEMS, bool INV, bool IN_PLACE, class Load, class Store>
-__device__ __forceinline__ void fft_pass(int lgN, int batch, int lgNs, const cplx<T>* __restrict__ tw, int tid,
-                                         int nthreads, Load load, Store store) {
+template <typename T, int R, int LGN, int LGNS, int ITEMS, int THREADS, bool INV, bool IN_PLACE, class Load,
+          class Store>
+__device__ __forceinline__ void fft_pass(int batch, const cplx<T>* __restrict__ tw, Load load, Store store) {
   constexpr int lgR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
-  const int lgM = lgN - lgR;
-  const int M = 1 << lgM;
+  constexpr int lgM = LGN - lgR;
+  constexpr int M = 1 << lgM;
+  constexpr int Ns = 1 << LGNS;
+  static_assert(LGNS + lgR <= LGN && LGN >= 4, "pass exceeds the transform length");
   const int all = M * batch;
-  const int Ns = 1 << lgNs;
-  const int tws = TW_LOG - (lgNs + lgR);
-  if (!IN_PLACE) {
-    for (int j = tid; j < all; j += nthreads) {
+  // the lane index passes through an empty asm so that this pass's index and
+  // address arithmetic is redone here instead of being hoisted out of the
+  // caller's loops into registers held across them
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  if constexpr (!IN_PLACE) {
+    for (int j = tid; j < all; j += THREADS) {
       const int b = j >> lgM;
       const int jj = j & (M - 1);
       const int k = jj & (Ns - 1);
       cplx<T> v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = load(b, jj + (r << lgM));
-      fft_butterfly<T, R, INV>(v, k, lgNs, tws, tw);
+      for (int r = 0; r < R; ++r) v[r] = load(b, jj, r * M);
+      fft_butterfly<T, R, LGNS, INV>(v, k, tw);
       const int base = ((jj - k) << lgR) + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) store(b, base + (r << lgNs), v[r]);
+      for (int r = 0; r < R; ++r) store(b, base, r * Ns, v[r]);
     }
-    return;
-  }
-  cplx<T> v[ITEMS][R];
+  } else {
+    cplx<T> v[ITEMS][R];
 #pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    const int j = tid + it * nthreads;
-    if (j < all) {
-      const int b = j >> lgM;
-      const int jj = j & (M - 1);
-      const int k = jj & (Ns - 1);
+    for (int it = 0; it < ITEMS; ++it) {
+      const int j = tid + it * THREADS;
+      if (j < all) {
+        const int b = j >> lgM;
+        const int jj = j & (M - 1);
+        const int k = jj & (Ns - 1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = load(b, jj + (r << lgM));
-      fft_butterfly<T, R, INV>(v[it], k, lgNs, tws, tw);
+        for (int r = 0; r < R; ++r) v[it][r] = load(b, jj, r * M);
+        fft_butterfly<T, R, LGNS, INV>(v[it], k, tw);
+      }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    const int j = tid + it * nthreads;
-    if (j < all) {
-      const int b = j >> lgM;
-      const int jj = j & (M - 1);
-      const int k = jj & (Ns - 1);
-      const int base = ((jj - k) << lgR) + k;
+    for (int it = 0; it < ITEMS; ++it) {
+      const int j = tid + it * THREADS;
+      if (j < all) {
+        const int b = j >> lgM;
+        const int jj = j & (M - 1);
+        const int k = jj & (Ns - 1);
+        const int base = ((jj - k) << lgR) + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) store(b, base + (r << lgNs), v[it][r]);
+        for (int r = 0; r < R; ++r) store(b, base, r * Ns, v[it][r]);
+      }
     }
   }
 }
 
-// Complete transform: the first pass reads through `load0`, the last pass
-// writes through `storeN`, the passes in between run in place in the padded
-// LDS buffer `buf` (index b * bstride + i).  FIRST_IN_LDS says that load0
-// reads `buf` and LAST_IN_LDS that storeN writes it (those passes then run
-// in place).  All passes after the first have radix 2^LGM (16 or 8; radix 8
-// holds half the values per thread in registers for one more pass); the first
-// takes the remainder, LGR0 = lgN mod LGM (or LGM).  Barriers separate the
-// passes; there is none after the final stores.
-template <typename T, int NMAX, int THREADS, bool INV, bool FIRST_IN_LDS, bool LAST_IN_LDS, int LGR0, class Load0,
-          class StoreN, int LGM = 4>
-__device__ void fft_run(cplx<T>* buf, int lgN, int batch, int bstride, const cplx<T>* __restrict__ tw, Load0 load0,
-                        StoreN storeN) {
-  static_assert(LGM == 3 || LGM == 4, "middle radix 8 or 16");
-  const int np = (lgN + LGM - 1) / LGM;
-  auto lds_load = [&](int b, int i) { return buf[lds_pad(b * bstride + i)]; };
-  auto lds_store = [&](int b, int i, cplx<T> v) { buf[lds_pad(b * bstride + i)] = v; };
-  int lgNs = 0;
+// In-LDS accessors of the padded buffer holding `batch` rows of 2^LGN values.
+template <typename T, int LGN>
+struct LdsRows {
+  cplx<T>* buf;
+  __device__ __forceinline__ cplx<T> operator()(int b, int i0, int c) const {
+    return buf[lds_pad((b << LGN) + i0) + pad_off(c)];
+  }
+  __device__ __forceinline__ void operator()(int b, int i0, int c, cplx<T> v) const {
+    buf[lds_pad((b << LGN) + i0) + pad_off(c)] = v;
+  }
+};
+
+// Passes from span 2^LGNS to the end of a transform of length 2^LGN held in
+// the padded LDS buffer `buf` (the earlier passes have been written there and
+// followed by a barrier).  All have radix 2^LGM; the passes in between run in
+// place, the last one writes through `storeN` (in place when LAST_IN_LDS says
+// that storeN writes `buf`).  No barrier after the final stores.
+template <typename T, int NMAX, int THREADS, bool INV, bool LAST_IN_LDS, int LGN, int LGNS, int LGM, class StoreN>
+__device__ __forceinline__ void fft_tail(cplx<T>* buf, int batch, const cplx<T>* __restrict__ tw, StoreN storeN) {
+  static_assert(LGM == 3 || LGM == 4, "later radix 8 or 16");
+  static_assert((LGN - LGNS) % LGM == 0 && LGNS < LGN, "later passes must tile the remaining bits");
   constexpr int RM = 1 << LGM;
   constexpr int IM = (NMAX / RM + THREADS - 1) / THREADS;
-  const int tid = threadIdx.x;
-  // first pass: the only one whose radix (2^LGR0) can be below 2^LGM
+  const LdsRows<T, LGN> lds{buf};
+  if constexpr (LGNS + LGM < LGN) {
+    fft_pass<T, RM, LGN, LGNS, IM, THREADS, INV, true>(batch, tw, lds, lds);
+    __syncthreads();
+    fft_tail<T, NMAX, THREADS, INV, LAST_IN_LDS, LGN, LGNS + LGM, LGM, StoreN>(buf, batch, tw, storeN);
+  } else {
+    fft_pass<T, RM, LGN, LGNS, IM, THREADS, INV, LAST_IN_LDS>(batch, tw, lds, storeN);
+  }
+}
+
+// Complete transform of `batch` rows of length 2^LGN: the first pass (radix
+// 2^fft_first_lgr(LGN, LGM)) reads through `load0`, the last pass writes
+// through `storeN`, the passes in between run in place in `buf`.
+// FIRST_IN_LDS says that load0 reads `buf` and LAST_IN_LDS that storeN writes
+// it (those passes then run in place).  NMAX bounds N * batch, THREADS is the
+// block size.  Barriers separate the passes; there is none after the final
+// stores.
+template <typename T, int NMAX, int THREADS, bool INV, bool FIRST_IN_LDS, bool LAST_IN_LDS, int LGN, int LGM,
+          class Load0, class StoreN>
+__device__ __forceinline__ void fft_run(cplx<T>* buf, int batch, const cplx<T>* __restrict__ tw, Load0 load0,
+                                        StoreN storeN) {
+  constexpr int LGR0 = fft_first_lgr(LGN, LGM);
   constexpr int R0 = 1 << LGR0;
   constexpr int I0 = (NMAX / R0 + THREADS - 1) / THREADS;
-  const int lgR0 = LGR0;
-  if (np == 1) {
-    fft_pass<T, R0, I0, INV, FIRST_IN_LDS || LAST_IN_LDS>(lgN, batch, 0, tw, tid, THREADS, load0, storeN);
-    return;
-  }
-  fft_pass<T, R0, I0, INV, FIRST_IN_LDS>(lgN, batch, 0, tw, tid, THREADS, load0, lds_store);
-  __syncthreads();
-  lgNs = lgR0;
-  for (int ps = 1; ps < np - 1; ++ps) {
-    fft_pass<T, RM, IM, INV, true>(lgN, batch, lgNs, tw, tid, THREADS, lds_load, lds_store);
+  if constexpr (LGR0 == LGN) {
+    fft_pass<T, R0, LGN, 0, I0, THREADS, INV, FIRST_IN_LDS || LAST_IN_LDS>(batch, tw, load0, storeN);
+  } else {
+    const LdsRows<T, LGN> lds{buf};
+    fft_pass<T, R0, LGN, 0, I0, THREADS, INV, FIRST_IN_LDS>(batch, tw, load0, lds);
     __syncthreads();
-    lgNs += LGM;
+    fft_tail<T, NMAX, THREADS, INV, LAST_IN_LDS, LGN, LGR0, LGM, StoreN>(buf, batch, tw, storeN);
   }
-  fft_pass<T, RM, IM, INV, LAST_IN_LDS>(lgN, batch, lgNs, tw, tid, THREADS, lds_load, storeN);
 }
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }

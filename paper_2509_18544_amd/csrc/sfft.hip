@@ -309,7 +309,6 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // radix (log2) of the first pass of a 2^lgN-point transform: the remainder of
 // lgN mod 4, or 4 (the later passes are all radix 16)
 // first pass radix of a plan whose later passes have radix 2^lgm
-int first_radix_log(int lgN, int lgm = 4) { return (lgN % lgm) ? (lgN % lgm) : lgm; }
 
 Layout layout_of(const Derived& D) {
   Layout Lo;
@@ -627,7 +626,7 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     const size_t lds = (size_t)lds_padded_size(D.rows_per_block * D.H) * sizeof(cplx<T>);
     const int grid = ((D.nrowblk + 7) / 8) * 8;   // whole XCD rounds for the remap
     p->timer.begin(SFFT_STAGE_ROW_FWD, s);
-    switch (first_radix_log(D.lgPx - 1)) {
+    switch (D.lgPx - 1) {
 #define ROW_CASE(LG)                                                                                       \
   case LG: {                                                                                               \
     auto kfn = row_fwd_kernel<T, FFT_THREADS, RN, LG>;                                                     \
@@ -635,7 +634,9 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     kfn<<<grid, FFT_THREADS, lds, s>>>(A, sci, tmpl, mask, p->at<cplx<T>>(Lo.Ub), tw);                  \
     break;                                                                                                 \
   }
-      ROW_CASE(1) ROW_CASE(2) ROW_CASE(3) ROW_CASE(4)
+      ROW_CASE(5) ROW_CASE(6) ROW_CASE(7) ROW_CASE(8) ROW_CASE(9) ROW_CASE(10) ROW_CASE(11)
+      default:
+        return SFFT_EINVAL;
 #undef ROW_CASE
     }
     LAUNCH_CHECK();
@@ -643,21 +644,20 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
   }
   {
     const size_t lds = (size_t)lds_padded_size(2 * D.Py) * sizeof(cplx<T>);
-    const int nblk = (D.H / 2 - 1) * D.nbase;
+    const int nblk = (D.H / 2) * D.nbase;
     const int grid = ((nblk + 7) / 8) * 8;
     p->timer.begin(SFFT_STAGE_COL_FWD, s);
-    switch (first_radix_log(D.lgPy, COL_LGM)) {
+    switch (D.lgPy) {
 #define COL_CASE(LG)                                                                                        \
   case LG: {                                                                                                \
     auto kfn = col_fwd_kernel<T, FFT_THREADS, COL_NMAX, LG, COL_LGM>;                                       \
-    auto kdc = col_fwd_dc_kernel<T, FFT_THREADS, COL_NMAX, LG, COL_LGM>;                                    \
     HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
-    HIP_TRY(hipFuncSetAttribute((const void*)kdc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
-    kdc<<<D.nbase, FFT_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.Ub), U, tw);                               \
-    if (nblk > 0) kfn<<<grid, FFT_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.Ub), U, tw);                     \
+    kfn<<<grid, FFT_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.Ub), U, tw);                                   \
     break;                                                                                                  \
   }
-      COL_CASE(1) COL_CASE(2) COL_CASE(3) COL_CASE(4)
+      COL_CASE(6) COL_CASE(7) COL_CASE(8) COL_CASE(9) COL_CASE(10) COL_CASE(11) COL_CASE(12)
+      default:
+        return SFFT_EINVAL;
 #undef COL_CASE
     }
     LAUNCH_CHECK();
@@ -781,7 +781,7 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
     cplx<double>* G = reinterpret_cast<cplx<double>*>(
         reinterpret_cast<unsigned char*>(K) + align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>)));
     const size_t lds = (size_t)lds_padded_size(S.rows_per_block * D.H) * sizeof(cplx<double>);
-    switch (first_radix_log(D.lgPx - 1)) {
+    switch (D.lgPx - 1) {
 #define SUBF_CASE(LG)                                                                                       \
   case LG: {                                                                                                \
     auto kf = sub_rowfwd_kernel<T, FFT_THREADS, SUB_NMAX, LG>;                                              \
@@ -789,7 +789,9 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
     kf<<<S.nrowblk, FFT_THREADS, lds, s>>>(S, tmpl, Uq, twd, D.dk + 1);                                     \
     break;                                                                                                  \
   }
-      SUBF_CASE(1) SUBF_CASE(2) SUBF_CASE(3) SUBF_CASE(4)
+      SUBF_CASE(5) SUBF_CASE(6) SUBF_CASE(7) SUBF_CASE(8) SUBF_CASE(9) SUBF_CASE(10) SUBF_CASE(11)
+      default:
+        return SFFT_EINVAL;
 #undef SUBF_CASE
     }
     LAUNCH_CHECK();
@@ -820,7 +822,7 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
       }
       LAUNCH_CHECK();
     }
-    switch (first_radix_log(D.lgPx - 1)) {
+    switch (D.lgPx - 1) {
 #define SUBI_CASE(LG)                                                                                       \
   case LG: {                                                                                                \
     auto ki = sub_rowinv_kernel<T, FFT_THREADS, SUB_NMAX, LG>;                                              \
@@ -828,7 +830,9 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
     ki<<<S.nrowblk, FFT_THREADS, lds, s>>>(S, Mh, sci, coeffs, diff, twd, xl, xr);                          \
     break;                                                                                                  \
   }
-      SUBI_CASE(1) SUBI_CASE(2) SUBI_CASE(3) SUBI_CASE(4)
+      SUBI_CASE(5) SUBI_CASE(6) SUBI_CASE(7) SUBI_CASE(8) SUBI_CASE(9) SUBI_CASE(10) SUBI_CASE(11)
+      default:
+        return SFFT_EINVAL;
 #undef SUBI_CASE
     }
     LAUNCH_CHECK();

@@ -214,7 +214,7 @@ struct SpecParams {
 };
 
 // R2C of the rows xh^p R (p = 0..DK) -> Uq[p][y][0..H]
-template <typename T, int THREADS, int NMAX, int LGR0>
+template <typename T, int THREADS, int NMAX, int LGH>
 __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_kernel(SpecParams P, const T* __restrict__ tmpl,
                                                              cplx<double>* __restrict__ Uq,
                                                              const cplx<double>* __restrict__ tw, int npow) {
@@ -222,12 +222,11 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_ke
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
   const int RB = P.rows_per_block;
   const int y0 = blockIdx.x * RB;
-  const int H = P.H;
-  const int lgH = P.lgPx - 1;
+  constexpr int H = 1 << LGH;             // H = Px / 2
+  constexpr int lgH = LGH;
   const int tid = threadIdx.x;
-  const int twsx = TW_LOG - P.lgPx;
-  auto lds_load = [&](int r, int i) { return buf[lds_pad(r * H + i)]; };
-  auto lds_store = [&](int r, int i, cplx<double> v) { buf[lds_pad(r * H + i)] = v; };
+  constexpr int twsx = TW_LOG - (LGH + 1);
+  const LdsRows<double, LGH> lds{buf};
   for (int p = 0; p < npow; ++p) {
     __syncthreads();
     for (int e = tid; e < RB * H; e += THREADS) {
@@ -244,7 +243,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_ke
       buf[lds_pad(e)] = mk(v0, v1);
     }
     __syncthreads();
-    fft_run<double, NMAX, THREADS, false, true, true, LGR0>(buf, lgH, RB, H, tw, lds_load, lds_store);
+    fft_run<double, NMAX, THREADS, false, true, true, LGH, 4>(buf, RB, tw, lds, lds);
     __syncthreads();
     for (int e = tid; e < RB * (H + 1); e += THREADS) {
       const int r = e / (H + 1);
@@ -401,7 +400,7 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
 // C2R of M(y, .) and D = S - model - background on the columns [xlo, xhi).
 // E(k) = (X(k) + conj X(H-k))/2, O(k) = (X(k) - conj X(H-k)) e^{2 pi i k/Px}/2,
 // z = IDFT_H(E + i O)/H, model(2j) = Re z(j), model(2j+1) = Im z(j).
-template <typename T, int THREADS, int NMAX, int LGR0>
+template <typename T, int THREADS, int NMAX, int LGH>
 __global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const cplx<double>* __restrict__ Mh,
                                                              const T* __restrict__ sci,
                                                              const double* __restrict__ theta, T* __restrict__ diff,
@@ -410,10 +409,10 @@ __global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
   const int RB = P.rows_per_block;
   const int y0 = blockIdx.x * RB;
-  const int H = P.H;
-  const int lgH = P.lgPx - 1;
+  constexpr int H = 1 << LGH;             // H = Px / 2
+  constexpr int lgH = LGH;
   const int tid = threadIdx.x;
-  const int twsx = TW_LOG - P.lgPx;
+  constexpr int twsx = TW_LOG - (LGH + 1);
   for (int e = tid; e < RB * H; e += THREADS) {
     const int r = e >> lgH;
     const int k = e & (H - 1);
@@ -430,9 +429,8 @@ __global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const
     buf[lds_pad(e)] = z;
   }
   __syncthreads();
-  auto lds_load = [&](int r, int i) { return buf[lds_pad(r * H + i)]; };
-  auto lds_store = [&](int r, int i, cplx<double> v) { buf[lds_pad(r * H + i)] = v; };
-  fft_run<double, NMAX, THREADS, true, true, true, LGR0>(buf, lgH, RB, H, tw, lds_load, lds_store);
+  const LdsRows<double, LGH> lds{buf};
+  fft_run<double, NMAX, THREADS, true, true, true, LGH, 4>(buf, RB, tw, lds, lds);
   __syncthreads();
   const int L2 = (2 * P.w + 1) * (2 * P.w + 1);
   const int nkk = P.nk * L2;
