@@ -106,75 +106,116 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 // an H-point FFT and split:
 //   X(k) = E(k) + e^{-2 pi i k/Px} O(k),  E = (Z(k) + conj Z(H-k))/2,
 //   O = (Z(k) - conj Z(H-k))/(2i);   slot 0 holds (X(0), X(H)).
-// Output layout Ub[b][kx/2][y][kx%2]: a block of rows_per_block rows of one
-// column pair is one contiguous 128-byte segment.
-template <typename T>
-__device__ __forceinline__ T base_value(const AsmParams& P, int b, int y, int x, const T* __restrict__ sci,
-                                        const T* __restrict__ tmpl, const uint8_t* __restrict__ mask) {
-  if (x >= P.nx) return (T)0;
-  const int64_t o = (int64_t)y * P.ld + x;
-  const bool good = (mask == nullptr) || (mask[o] == 0);
-  if (!good) return (T)0;
-  if (b < P.nbk) {
-    const int w = P.w;
-    if (y < w || y >= P.ny - w || x < w || x >= P.nx - w) return (T)0;
-    const double xh = (double)x * P.sx - 1.0;
-    return (T)(ipow(xh, b) * (double)tmpl[o]);
-  }
-  if (b < P.nbk + P.nbb) {
-    const double xh = (double)x * P.sx - 1.0;
-    return (T)ipow(xh, b - P.nbk);
-  }
-  return sci[o];
+// Output layout Ub[b][kx/2][y][kx%2]: the rows of one block and one column
+// pair form one contiguous segment of 2 * rows * 8 bytes (FP32).
+//
+// Bases: b < nbk: xh^b G_R R (R zero outside the interior [w, n-w) of both
+// axes), b < nbk + nbb: xh^(b-nbk) G, last: G S, with G = 0 at masked pixels
+// and outside the frame.  A thread packs the same NPT pairs for every base, so
+// it reads the mask once and keeps the G and G_R flags of its pairs as bits;
+// every input load is unconditional (clamped into the frame, then selected),
+// so a thread's loads for one base are all in flight together.
+constexpr int ROW_RPAD = 16;   // LDS row padding of the row pass (rows 128 B apart in bank space)
+__host__ __device__ constexpr int row_pass_rows(int nmax, int lgh) { return (nmax >> lgh) < 64 ? (nmax >> lgh) : 64; }
+__host__ __device__ constexpr int row_pass_lds(int nmax, int lgh) {
+  return lds_rows_size(row_pass_rows(nmax, lgh), lgh, ROW_RPAD);
 }
 
 template <typename T, int THREADS, int NMAX, int LGH>
-__global__ __launch_bounds__(THREADS) void row_fwd_kernel(AsmParams P, const T* __restrict__ sci,
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kernel(AsmParams P, const T* __restrict__ sci,
                                                           const T* __restrict__ tmpl,
                                                           const uint8_t* __restrict__ mask, cplx<T>* __restrict__ U,
                                                           const cplx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int H = 1 << LGH;            // H = Px / 2
+  constexpr int RB = row_pass_rows(NMAX, LGH);
+  constexpr int NPT = (RB * H) / THREADS;
+  static_assert(NPT * THREADS == RB * H && NPT >= 1 && NPT <= 16, "whole pairs per thread, flags in 32 bits");
   const int rb = xcd_remap(blockIdx.x, gridDim.x);
   if (rb >= P.nrowblk) return;
-  const int RB = P.rows_per_block;
   const int y0 = rb * RB;
-  constexpr int lgH = LGH;               // H = Px / 2 = 2^LGH
-  constexpr int H = 1 << LGH;
   const int Py = 1 << P.lgPy;
   const int64_t pstride = (int64_t)H * Py;   // elements per base plane
   const int tid = threadIdx.x;
   constexpr int twsx = TW_LOG - (LGH + 1);
-  const LdsRows<T, LGH> lds{buf};
+  const LdsRows<T, LGH, ROW_RPAD> lds{buf};
+  const int nx = P.nx, ny = P.ny, w = P.w;
+  // input offset of pixel (y, x), clamped into the frame so that every load is valid
+  auto offs = [&](int y, int x) -> int64_t { return (int64_t)min(y, ny - 1) * P.ld + min(x, nx - 1); };
+  uint32_t good = 0;    // bit 2i (+1): G of pixel 2j (2j+1) of pair i
+  uint32_t gint = 0;    // the same, and inside the interior (G_R)
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    const int e = tid + i * THREADS;
+    const int y = y0 + (e >> LGH);
+    const int x0 = 2 * (e & (H - 1));
+    const bool in0 = y < ny && x0 < nx, in1 = y < ny && x0 + 1 < nx;
+    const bool g0 = in0 && (mask == nullptr || mask[offs(y, x0)] == 0);
+    const bool g1 = in1 && (mask == nullptr || mask[offs(y, x0 + 1)] == 0);
+    const bool iy = y >= w && y < ny - w;
+    const bool i0 = g0 && iy && x0 >= w && x0 < nx - w;
+    const bool i1 = g1 && iy && x0 + 1 >= w && x0 + 1 < nx - w;
+    good |= ((uint32_t)g0 << (2 * i)) | ((uint32_t)g1 << (2 * i + 1));
+    gint |= ((uint32_t)i0 << (2 * i)) | ((uint32_t)i1 << (2 * i + 1));
+  }
   for (int b = 0; b < P.nbase; ++b) {
     __syncthreads();   // the previous base's split has read the buffer
-    // packed base rows z(j) = x(2j) + i x(2j+1), coalesced over j
-    for (int e = tid; e < RB * H; e += THREADS) {
-      const int r = e >> lgH;
+    // packed base rows z(j) = x(2j) + i x(2j+1)
+    const int kind = b < P.nbk ? 0 : (b < P.nbk + P.nbb ? 1 : 2);
+    const int pw = kind == 0 ? b : b - P.nbk;
+    // the lane index passes through an empty asm so that the per-pair
+    // coordinates are recomputed per base instead of held in registers
+    int lane = tid;
+    asm volatile("" : "+v"(lane));
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int e = lane + i * THREADS;
+      const int r = e >> LGH;
       const int j = e & (H - 1);
-      const int y = y0 + r;
-      cplx<T> z = mk((T)0, (T)0);
-      if (y < P.ny) {
-        z.x = base_value<T>(P, b, y, 2 * j, sci, tmpl, mask);
-        z.y = base_value<T>(P, b, y, 2 * j + 1, sci, tmpl, mask);
+      const int x0 = 2 * j;
+      const uint32_t flags = kind == 0 ? gint : good;
+      const bool g0 = (flags >> (2 * i)) & 1u, g1 = (flags >> (2 * i + 1)) & 1u;
+      cplx<T> z;
+      if (kind == 2) {
+        const int y = y0 + r;
+        const T s0 = sci[offs(y, x0)], s1 = sci[offs(y, x0 + 1)];
+        z = mk(g0 ? s0 : (T)0, g1 ? s1 : (T)0);
+      } else {
+        const double xh0 = (double)x0 * P.sx - 1.0;
+        const double xh1 = (double)(x0 + 1) * P.sx - 1.0;
+        double p0 = 1.0, p1 = 1.0;
+        for (int q = 0; q < pw; ++q) {
+          p0 *= xh0;
+          p1 *= xh1;
+        }
+        if (kind == 0) {
+          const int y = y0 + r;
+          const T t0 = tmpl[offs(y, x0)], t1 = tmpl[offs(y, x0 + 1)];
+          z = mk(g0 ? (T)(p0 * (double)t0) : (T)0, g1 ? (T)(p1 * (double)t1) : (T)0);
+        } else
+          z = mk(g0 ? (T)p0 : (T)0, g1 ? (T)p1 : (T)0);
       }
-      buf[lds_pad(e)] = z;
+      buf[lds.at(r, j)] = z;
     }
     __syncthreads();
-    fft_run<T, NMAX, THREADS, false, true, true, LGH, 4>(buf, RB, tw, lds, lds);
+    fft_run<T, NMAX, THREADS, false, true, true, LGH, 4, decltype(lds), decltype(lds), ROW_RPAD>(buf, RB, tw, lds,
+                                                                                                 lds);
     __syncthreads();
     // split and write: consecutive threads fill one (column pair, row block) segment
     cplx<T>* Ub = U + (int64_t)b * pstride;
-    const int seg = 2 * RB;
-    for (int e = tid; e < RB * H; e += THREADS) {
+    constexpr int seg = 2 * RB;
+#pragma unroll 1
+    for (int i = 0; i < NPT; ++i) {
+      const int e = tid + i * THREADS;
       const int c = e / seg;
       const int rem = e - c * seg;
       const int r = rem >> 1;
       const int k = 2 * c + (rem & 1);
       const int y = y0 + r;
-      if (y >= P.ny) continue;
-      const cplx<T> zk = buf[lds_pad(r * H + k)];
-      const cplx<T> zm = conjg(buf[lds_pad(r * H + ((H - k) & (H - 1)))]);
+      if (y >= ny) continue;
+      const cplx<T> zk = buf[lds.at(r, k)];
+      const cplx<T> zm = conjg(buf[lds.at(r, (H - k) & (H - 1))]);
       cplx<T> out;
       if (k == 0) {
         // E(0) = Re Z0, O(0) = Im Z0; X(0) = E + O, X(H) = E - O

@@ -291,34 +291,38 @@ __device__ __forceinline__ void fft_pass(int batch, const cplx<T>* __restrict__ 
   }
 }
 
-// In-LDS accessors of the padded buffer holding `batch` rows of 2^LGN values.
-template <typename T, int LGN>
+// In-LDS accessors of the padded buffer holding `batch` rows of 2^LGN values;
+// row b starts RPAD extra elements further on (rows that are a multiple of
+// 256 bytes apart would otherwise share their LDS banks).
+template <typename T, int LGN, int RPAD = 0>
 struct LdsRows {
   cplx<T>* buf;
-  __device__ __forceinline__ cplx<T> operator()(int b, int i0, int c) const {
-    return buf[lds_pad((b << LGN) + i0) + pad_off(c)];
-  }
-  __device__ __forceinline__ void operator()(int b, int i0, int c, cplx<T> v) const {
-    buf[lds_pad((b << LGN) + i0) + pad_off(c)] = v;
-  }
+  __device__ __forceinline__ static int at(int b, int i) { return lds_pad((b << LGN) + i) + b * RPAD; }
+  __device__ __forceinline__ cplx<T> operator()(int b, int i0, int c) const { return buf[at(b, i0) + pad_off(c)]; }
+  __device__ __forceinline__ void operator()(int b, int i0, int c, cplx<T> v) const { buf[at(b, i0) + pad_off(c)] = v; }
 };
+// elements of such a buffer
+__host__ __device__ constexpr int lds_rows_size(int batch, int lgn, int rpad) {
+  return lds_padded_size(batch << lgn) + batch * rpad;
+}
 
 // Passes from span 2^LGNS to the end of a transform of length 2^LGN held in
 // the padded LDS buffer `buf` (the earlier passes have been written there and
 // followed by a barrier).  All have radix 2^LGM; the passes in between run in
 // place, the last one writes through `storeN` (in place when LAST_IN_LDS says
 // that storeN writes `buf`).  No barrier after the final stores.
-template <typename T, int NMAX, int THREADS, bool INV, bool LAST_IN_LDS, int LGN, int LGNS, int LGM, class StoreN>
+template <typename T, int NMAX, int THREADS, bool INV, bool LAST_IN_LDS, int LGN, int LGNS, int LGM, class StoreN,
+          int RPAD = 0>
 __device__ __forceinline__ void fft_tail(cplx<T>* buf, int batch, const cplx<T>* __restrict__ tw, StoreN storeN) {
   static_assert(LGM == 3 || LGM == 4, "later radix 8 or 16");
   static_assert((LGN - LGNS) % LGM == 0 && LGNS < LGN, "later passes must tile the remaining bits");
   constexpr int RM = 1 << LGM;
   constexpr int IM = (NMAX / RM + THREADS - 1) / THREADS;
-  const LdsRows<T, LGN> lds{buf};
+  const LdsRows<T, LGN, RPAD> lds{buf};
   if constexpr (LGNS + LGM < LGN) {
     fft_pass<T, RM, LGN, LGNS, IM, THREADS, INV, true>(batch, tw, lds, lds);
     __syncthreads();
-    fft_tail<T, NMAX, THREADS, INV, LAST_IN_LDS, LGN, LGNS + LGM, LGM, StoreN>(buf, batch, tw, storeN);
+    fft_tail<T, NMAX, THREADS, INV, LAST_IN_LDS, LGN, LGNS + LGM, LGM, StoreN, RPAD>(buf, batch, tw, storeN);
   } else {
     fft_pass<T, RM, LGN, LGNS, IM, THREADS, INV, LAST_IN_LDS>(batch, tw, lds, storeN);
   }
@@ -329,10 +333,10 @@ __device__ __forceinline__ void fft_tail(cplx<T>* buf, int batch, const cplx<T>*
 // through `storeN`, the passes in between run in place in `buf`.
 // FIRST_IN_LDS says that load0 reads `buf` and LAST_IN_LDS that storeN writes
 // it (those passes then run in place).  NMAX bounds N * batch, THREADS is the
-// block size.  Barriers separate the passes; there is none after the final
-// stores.
+// block size, RPAD the row padding of `buf` (LdsRows).  Barriers separate the
+// passes; there is none after the final stores.
 template <typename T, int NMAX, int THREADS, bool INV, bool FIRST_IN_LDS, bool LAST_IN_LDS, int LGN, int LGM,
-          class Load0, class StoreN>
+          class Load0, class StoreN, int RPAD = 0>
 __device__ __forceinline__ void fft_run(cplx<T>* buf, int batch, const cplx<T>* __restrict__ tw, Load0 load0,
                                         StoreN storeN) {
   constexpr int LGR0 = fft_first_lgr(LGN, LGM);
@@ -341,10 +345,10 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, int batch, const cplx<T>* 
   if constexpr (LGR0 == LGN) {
     fft_pass<T, R0, LGN, 0, I0, THREADS, INV, FIRST_IN_LDS || LAST_IN_LDS>(batch, tw, load0, storeN);
   } else {
-    const LdsRows<T, LGN> lds{buf};
+    const LdsRows<T, LGN, RPAD> lds{buf};
     fft_pass<T, R0, LGN, 0, I0, THREADS, INV, FIRST_IN_LDS>(batch, tw, load0, lds);
     __syncthreads();
-    fft_tail<T, NMAX, THREADS, INV, LAST_IN_LDS, LGN, LGR0, LGM, StoreN>(buf, batch, tw, storeN);
+    fft_tail<T, NMAX, THREADS, INV, LAST_IN_LDS, LGN, LGR0, LGM, StoreN, RPAD>(buf, batch, tw, storeN);
   }
 }
 

@@ -30,7 +30,6 @@ constexpr int ROW_NMAX_F32 = 8192;    // complex elements in the row-pass LDS bu
 constexpr int ROW_NMAX_F64 = 4096;    // 64 KB
 constexpr int COL_NMAX = 8192;        // complex elements per column-pass block (two columns)
 constexpr int COL_LGM = 4;            // later passes of the column transform: radix 16 (radix 8 measured slower)
-constexpr int MAX_ROWS_PER_BLOCK = 64;
 constexpr int WIN_THREADS = 64;
 constexpr int WIN_IMAX = 64;
 constexpr int MAX_N = 8192;           // unknowns (the triangular solves keep x in LDS)
@@ -161,7 +160,7 @@ int derive(const sfft_desc* d, Derived* D) {
   }
   D->csize = d->mode == SFFT_MODE_F64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
   const int rowmax = d->mode == SFFT_MODE_F64 ? ROW_NMAX_F64 : ROW_NMAX_F32;
-  D->rows_per_block = std::min(MAX_ROWS_PER_BLOCK, std::min(rowmax / D->H, d->ny));
+  D->rows_per_block = row_pass_rows(rowmax, D->lgPx - 1);   // fixed per transform size (the kernel's own constant)
   D->nrowblk = (d->ny + D->rows_per_block - 1) / D->rows_per_block;
   D->nmom = (2 * d->db + 1) + (d->db + 1);
   D->nblk = (D->n + NB - 1) / NB;
@@ -623,7 +622,7 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     return gather_impl(p, A);
   }
   {
-    const size_t lds = (size_t)lds_padded_size(D.rows_per_block * D.H) * sizeof(cplx<T>);
+    const size_t lds = (size_t)row_pass_lds(RN, D.lgPx - 1) * sizeof(cplx<T>);
     const int grid = ((D.nrowblk + 7) / 8) * 8;   // whole XCD rounds for the remap
     p->timer.begin(SFFT_STAGE_ROW_FWD, s);
     switch (D.lgPx - 1) {
