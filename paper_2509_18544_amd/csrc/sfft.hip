@@ -759,7 +759,7 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
     S.lgPx = D.lgPx;
     S.H = D.H;
     S.ld = ld;
-    S.rows_per_block = std::max(1, std::min(D.ny, SUB_NMAX / D.H));
+    S.rows_per_block = sub_row_rows(SUB_NMAX, D.lgPx - 1);   // the kernels' own constant
     S.nrowblk = (D.ny + S.rows_per_block - 1) / S.rows_per_block;
     S.sx = 2.0 / (double)(D.nx - 1);
     S.sy = 2.0 / (double)(D.ny - 1);

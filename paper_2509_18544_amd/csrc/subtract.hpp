@@ -213,6 +213,9 @@ struct SpecParams {
   int8_t bpx[15], bqy[15];
 };
 
+// rows per block of the subtraction's row transforms (a power of two)
+__host__ __device__ constexpr int sub_row_rows(int nmax, int lgh) { return (nmax >> lgh) < 64 ? (nmax >> lgh) : 64; }
+
 // R2C of the rows xh^p R (p = 0..DK) -> Uq[p][y][0..H]
 template <typename T, int THREADS, int NMAX, int LGH>
 __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_kernel(SpecParams P, const T* __restrict__ tmpl,
@@ -220,26 +223,45 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_ke
                                                              const cplx<double>* __restrict__ tw, int npow) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
-  const int RB = P.rows_per_block;
-  const int y0 = blockIdx.x * RB;
+  constexpr int RB = sub_row_rows(NMAX, LGH);
   constexpr int H = 1 << LGH;             // H = Px / 2
-  constexpr int lgH = LGH;
+  constexpr int NPT = (RB * H) / THREADS;
+  static_assert(NPT * THREADS == RB * H, "whole pairs per thread");
+  const int y0 = blockIdx.x * RB;
   const int tid = threadIdx.x;
   constexpr int twsx = TW_LOG - (LGH + 1);
   const LdsRows<double, LGH> lds{buf};
+  // the thread's pairs of R, read once (clamped into the frame, unconditional)
+  T r0[NPT], r1[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    const int e = tid + i * THREADS;
+    const int y = min(y0 + (e >> LGH), P.ny - 1);
+    const int x0 = 2 * (e & (H - 1));
+    const T* row = tmpl + (int64_t)y * P.ld;
+    r0[i] = row[min(x0, P.nx - 1)];
+    r1[i] = row[min(x0 + 1, P.nx - 1)];
+  }
   for (int p = 0; p < npow; ++p) {
     __syncthreads();
-    for (int e = tid; e < RB * H; e += THREADS) {
-      const int r = e >> lgH;
-      const int j = e & (H - 1);
-      const int y = y0 + r;
-      double v0 = 0.0, v1 = 0.0;
-      if (y < P.ny) {
-        const int x0 = 2 * j, x1 = 2 * j + 1;
-        const T* row = tmpl + (int64_t)y * P.ld;
-        if (x0 < P.nx) v0 = ipow((double)x0 * P.sx - 1.0, p) * (double)row[x0];
-        if (x1 < P.nx) v1 = ipow((double)x1 * P.sx - 1.0, p) * (double)row[x1];
+    // the lane index passes through an empty asm so that the per-pair
+    // coordinates are recomputed per power instead of held in registers
+    int lane = tid;
+    asm volatile("" : "+v"(lane));
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int e = lane + i * THREADS;
+      const int y = y0 + (e >> LGH);
+      const int x0 = 2 * (e & (H - 1)), x1 = x0 + 1;
+      const double xh0 = (double)x0 * P.sx - 1.0, xh1 = (double)x1 * P.sx - 1.0;
+      double p0 = 1.0, p1 = 1.0;
+      for (int q = 0; q < p; ++q) {
+        p0 *= xh0;
+        p1 *= xh1;
       }
+      const bool in = y < P.ny;
+      const double v0 = (in && x0 < P.nx) ? p0 * (double)r0[i] : 0.0;
+      const double v1 = (in && x1 < P.nx) ? p1 * (double)r1[i] : 0.0;
       buf[lds_pad(e)] = mk(v0, v1);
     }
     __syncthreads();
@@ -328,6 +350,7 @@ __global__ void sub_gspec_kernel(SpecParams P, const cplx<double>* __restrict__ 
 constexpr int SUBC_TY = 6;                        // output rows per wave
 constexpr int SUBC_WAVES = 8;
 constexpr int SUBC_RB = SUBC_TY * SUBC_WAVES;     // output rows per block
+constexpr int SUBC_PF = 4;                        // filter taps loaded ahead
 
 __host__ __device__ constexpr size_t sub_conv_lds_bytes(int w) {
   return (size_t)(SUBC_RB + 2 * w) * 64 * sizeof(cplx<double>);
@@ -375,9 +398,17 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
       cplx<double> part[SUBC_TY];
 #pragma unroll
       for (int t = 0; t < SUBC_TY; ++t) part[t] = mk(0.0, 0.0);
+      // taps come through a ring of SUBC_PF loads in flight, so that the
+      // global-load latency of a tap overlaps the products of the taps before it
+      cplx<double> ring[SUBC_PF];
+#pragma unroll
+      for (int i = 0; i < SUBC_PF; ++i) ring[i] = i < L ? Ga[(int64_t)i * (H + 1)] : mk(0.0, 0.0);
 #pragma unroll 1
       for (int uyi = 0; uyi < L; ++uyi) {
-        const cplx<double> kv = Ga[(int64_t)uyi * (H + 1)];
+        const cplx<double> kv = ring[0];
+#pragma unroll
+        for (int i = 0; i + 1 < SUBC_PF; ++i) ring[i] = ring[i + 1];
+        ring[SUBC_PF - 1] = Ga[(int64_t)min(uyi + SUBC_PF, L - 1) * (H + 1)];
         const cplx<double>* src = wl - uyi * 64;
 #pragma unroll
         for (int t = 0; t < SUBC_TY; ++t) part[t] = cmac(part[t], kv, src[t * 64]);
@@ -407,26 +438,27 @@ __global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const
                                                              const cplx<double>* __restrict__ tw, int xlo, int xhi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
-  const int RB = P.rows_per_block;
-  const int y0 = blockIdx.x * RB;
+  constexpr int RB = sub_row_rows(NMAX, LGH);
   constexpr int H = 1 << LGH;             // H = Px / 2
-  constexpr int lgH = LGH;
+  constexpr int NPT = (RB * H) / THREADS;
+  static_assert(NPT * THREADS == RB * H, "whole values per thread");
+  const int y0 = blockIdx.x * RB;
   const int tid = threadIdx.x;
   constexpr int twsx = TW_LOG - (LGH + 1);
-  for (int e = tid; e < RB * H; e += THREADS) {
-    const int r = e >> lgH;
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    const int e = tid + i * THREADS;
+    const int r = e >> LGH;
     const int k = e & (H - 1);
     const int y = y0 + r;
-    cplx<double> z = mk(0.0, 0.0);
-    if (y < P.ny) {
-      const cplx<double>* row = Mh + (int64_t)y * (H + 1);
-      const cplx<double> xk = row[k];
-      const cplx<double> xm = conjg(row[H - k]);
-      const cplx<double> e2 = xk + xm;                                       // 2 E
-      const cplx<double> o2 = twid<double, true>(tw, k << twsx) * (xk - xm);  // 2 O
-      z = scale(e2 + rot90<double, true>(o2), 0.5);                          // E + i O
-    }
-    buf[lds_pad(e)] = z;
+    // rows past ny read row ny - 1 and are dropped: every load is unconditional
+    const cplx<double>* row = Mh + (int64_t)min(y, P.ny - 1) * (H + 1);
+    const cplx<double> xk = row[k];
+    const cplx<double> xm = conjg(row[H - k]);
+    const cplx<double> e2 = xk + xm;                                       // 2 E
+    const cplx<double> o2 = twid<double, true>(tw, k << twsx) * (xk - xm);  // 2 O
+    const cplx<double> z = scale(e2 + rot90<double, true>(o2), 0.5);       // E + i O
+    buf[lds_pad(e)] = y < P.ny ? z : mk(0.0, 0.0);
   }
   __syncthreads();
   const LdsRows<double, LGH> lds{buf};
