@@ -83,17 +83,6 @@ struct AsmParams {
   int dir_tpr;           // direct route: threads per image row (power of two)
 };
 
-// XCD-aware block order: consecutive row blocks land on the same XCD (blocks
-// are dispatched round-robin over the 8 XCDs), so the transposed 64-byte
-// segments that neighbouring row blocks write into one line meet in one L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
-  const int per = (nblk + 7) >> 3;
-  const int xcd = bid & 7;
-  const int slot = bid >> 3;
-  const int r = xcd * per + slot;
-  return r;
-}
-
 // ---------------------------------------------------------------------------
 // row_fwd: R2C along x of the x-weighted base rows; column-pair tiled write
 // ---------------------------------------------------------------------------

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.hpp"
+
 namespace sfft {
 
 constexpr int NB = 64;
@@ -58,6 +60,11 @@ __device__ __forceinline__ void tile_abt(const double (*A)[NB + 1], const double
   }
 }
 
+// The diagonal-block kernel is a single wave: its LDS accesses execute in
+// program order, so lanes exchange values through LDS with no barrier; this
+// only stops the compiler from moving memory accesses across the point.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
 // Diagonal block: one wave of 64 lanes.
 //  A partial last block (nb < 64 rows) is padded with the identity, whose
 //  factor and inverse are the identity again, so every loop below runs over
@@ -90,17 +97,17 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restri
     if (r < nb) v = (lane <= r) ? F[(int64_t)(k0 + r) * n + k0 + lane] : 0.0;
     Ls[r][lane] = v;
   }
-  __syncthreads();
+  wave_sync();
   double row[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) row[c] = Ls[lane][c];
-  __syncthreads();
+  wave_sync();
   int fail = 0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     if (fail == 0) {
       col[lane] = row[j];
-      __syncthreads();
+      wave_sync();
       const double d = col[j];
       if (!(d > 0.0) || !isfinite(d)) {
         fail = j + 1;
@@ -109,14 +116,14 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restri
         const double rs = 1.0 / sd;
         if (lane > j) row[j] *= rs;
         if (lane == j) row[j] = sd;
-        __syncthreads();
+        wave_sync();
         col[lane] = row[j];
-        __syncthreads();
+        wave_sync();
         const double lij = (lane > j) ? row[j] : 0.0;
 #pragma unroll
         for (int l = j + 1; l < NB; ++l) row[l] -= lij * col[l];
       }
-      __syncthreads();
+      wave_sync();
     }
   }
   if (fail) {
@@ -125,7 +132,7 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restri
   }
 #pragma unroll
   for (int c = 0; c < NB; ++c) Ls[lane][c] = row[c];
-  __syncthreads();
+  wave_sync();
   // coalesced store of the factor's lower triangle
   for (int r = 0; r < nb; ++r)
     if (lane <= r) F[(int64_t)(k0 + r) * n + k0 + lane] = Ls[r][lane];
@@ -180,24 +187,30 @@ __global__ __launch_bounds__(256) void trsm_kernel(const SolveJob* __restrict__ 
       }
 }
 
-// Lower tiles (I >= J) of the trailing matrix: A_IJ -= L_I L_J^T.
-__global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ jobs, int k) {
+// Lower tiles (I >= J) of the trailing matrix: A_IJ -= L_I L_J^T.  One block
+// per (job, tile), ntile tiles per job, through xcd_remap: an XCD takes a
+// contiguous run of tiles, so tiles of one row I (sharing the panel L_I) and
+// of neighbouring rows find the panels in its L2.
+__global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ jobs, int k, int njobs, int ntile) {
   __shared__ double A[NB][NB + 1];
   __shared__ double B[NB][NB + 1];
-  const SolveJob job = jobs[blockIdx.y];
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  if (id >= njobs * ntile) return;
+  const int jb = id / ntile;
+  const int b = id - jb * ntile;
+  const SolveJob job = jobs[jb];
   if (k >= job.nblk - 1 || *job.info != 0) return;
   double* __restrict__ F = job.F;
   const int n = job.n;
   const int k0 = k * NB;
   {
     const int T = job.nblk - k - 1;
-    if ((int)blockIdx.x >= T * (T + 1) / 2) return;
+    if (b >= T * (T + 1) / 2) return;
   }
   const int tid = threadIdx.x;
   const int nb = min(NB, n - k0);
   const int t0 = k0 + NB;  // first trailing row
-  // triangular tile enumeration: blockIdx.x = I (I+1)/2 + J
-  const int b = blockIdx.x;
+  // triangular tile enumeration: b = I (I+1)/2 + J
   int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= b) ++I;
   while (I * (I + 1) / 2 > b) --I;

@@ -352,6 +352,16 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, int batch, const cplx<T>* 
   }
 }
 
+// XCD-aware block order: blocks are dispatched round-robin over the 8 XCDs,
+// each with its own L2, so block bid is given work item xcd_remap(bid): each
+// XCD then takes one contiguous eighth of the items (neighbouring items that
+// share input lines, or write into one line, meet in one L2).  nblk must be a
+// multiple of 8; the map is a permutation of [0, nblk).
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int per = nblk >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
 __device__ __forceinline__ double ipow(double x, int p) {

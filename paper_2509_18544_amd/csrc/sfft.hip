@@ -694,7 +694,9 @@ int solve_jobs(hipStream_t s, const SolveJob* jobs, int njobs, int max_n, int ma
     if (T > 0) {
       trsm_kernel<<<dim3(T, njobs), 256, 0, s>>>(jobs, k);
       LAUNCH_CHECK();
-      syrk_kernel<<<dim3(T * (T + 1) / 2, njobs), 256, 0, s>>>(jobs, k);
+      const int ntile = T * (T + 1) / 2;
+      const int grid = ((njobs * ntile + 7) / 8) * 8;   // whole XCD rounds for the remap
+      syrk_kernel<<<grid, 256, 0, s>>>(jobs, k, njobs, ntile);
       LAUNCH_CHECK();
     }
   }
