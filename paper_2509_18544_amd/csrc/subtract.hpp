@@ -342,18 +342,23 @@ __global__ void sub_gspec_kernel(SpecParams P, const cplx<double>* __restrict__ 
 // M(y, kx) = sum_a sum_{u_y} K[a][u_y][kx] yh(y - u_y)^q_a U_{p_a}(y - u_y, kx)
 //          = sum_{p,e} yh(y)^e sum_{u_y} G[(p,e)][u_y][kx] U_p(y - u_y, kx)   (sub_gspec_kernel).
 // Block: 64 kx columns (the lanes) x SUBC_WAVES waves of SUBC_TY output rows.
-// For each x power p the block stages the SUBC_RB + 2W source rows of U_p in
-// LDS once (HBM traffic ~ (1 + 2W / SUBC_RB) x the source), and for each
-// filter of that power each thread sums its SUBC_TY x L products straight
-// from LDS with one tap in registers at a time (registers do not grow with
-// w), then weights the output rows by yh(y)^e.
+// For each x power p the block stages the source rows of U_p it needs in LDS
+// once (HBM traffic ~ (1 + 2W / SUBC_RB) x the source).  For each filter of
+// that power a thread takes the taps in groups of SUBC_GT (the next group's
+// loads in flight meanwhile); within a group it sweeps the TY + GT - 1 source
+// rows the group reaches, reading each from LDS once and adding it to every
+// output row it feeds, so a source row is read (TY + GT - 1) / (GT TY) times per
+// output and tap instead of once.  The last group is padded with zero taps
+// (the window carries GT - 1 extra rows above for their reads).  The output
+// rows are finally weighted by yh(y)^e.
 constexpr int SUBC_TY = 6;                        // output rows per wave
 constexpr int SUBC_WAVES = 8;
 constexpr int SUBC_RB = SUBC_TY * SUBC_WAVES;     // output rows per block
-constexpr int SUBC_PF = 4;                        // filter taps loaded ahead
+constexpr int SUBC_GT = 4;                        // filter taps per group
+constexpr int SUBC_PADR = SUBC_GT - 1;            // window rows above for the padded taps
 
 __host__ __device__ constexpr size_t sub_conv_lds_bytes(int w) {
-  return (size_t)(SUBC_RB + 2 * w) * 64 * sizeof(cplx<double>);
+  return (size_t)(SUBC_RB + 2 * w + SUBC_PADR) * 64 * sizeof(cplx<double>);
 }
 
 template <int W>
@@ -361,7 +366,9 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
                                                                    const cplx<double>* __restrict__ G,
                                                                    cplx<double>* __restrict__ Mh) {
   constexpr int L = 2 * W + 1;
-  constexpr int WINB = SUBC_RB + 2 * W;           // source rows of the block
+  constexpr int GT = SUBC_GT;
+  constexpr int NG = (L + GT - 1) / GT;           // tap groups (the last one padded)
+  constexpr int WINB = SUBC_RB + 2 * W + SUBC_PADR;   // window rows: source rows yb - W - PADR ..
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<double>* win = reinterpret_cast<cplx<double>*>(smem_raw);   // [WINB][64]
   const int H = P.H;
@@ -382,7 +389,7 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
     __syncthreads();   // the previous power's rows have been read
     for (int e = tid; e < WINB * 64; e += 64 * SUBC_WAVES) {
       const int r = e >> 6, c = e & 63;
-      const int ys = yb - W + r;
+      const int ys = yb - W - SUBC_PADR + r;
       cplx<double> u = mk(0.0, 0.0);
       if (ys >= 0 && ys < P.ny && kx0 + c <= H) u = Up[(int64_t)ys * (H + 1) + kx0 + c];
       win[e] = u;
@@ -393,25 +400,40 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
       if (P.kpx[g] != p) continue;
       const int ex = P.kqy[g];
       const cplx<double>* Ga = G + (int64_t)g * L * (H + 1) + kx;
-      // output row y0 + t takes source row y0 + t - u_y = window row wave * TY + t + 2W - uyi
-      const cplx<double>* wl = win + (wave * SUBC_TY + 2 * W) * 64 + lane;
+      // output row y0 + t with tap u reads source row y0 + t + W - u, i.e.
+      // window offset d = t - u from wl
+      const cplx<double>* wl = win + (wave * SUBC_TY + 2 * W + SUBC_PADR) * 64 + lane;
       cplx<double> part[SUBC_TY];
 #pragma unroll
       for (int t = 0; t < SUBC_TY; ++t) part[t] = mk(0.0, 0.0);
-      // taps come through a ring of SUBC_PF loads in flight, so that the
-      // global-load latency of a tap overlaps the products of the taps before it
-      cplx<double> ring[SUBC_PF];
+      cplx<double> kn[GT];   // taps of the next group (zero past the filter)
 #pragma unroll
-      for (int i = 0; i < SUBC_PF; ++i) ring[i] = i < L ? Ga[(int64_t)i * (H + 1)] : mk(0.0, 0.0);
+      for (int i = 0; i < GT; ++i) {
+        const cplx<double> t = Ga[(int64_t)min(i, L - 1) * (H + 1)];
+        kn[i] = i < L ? t : mk(0.0, 0.0);
+      }
 #pragma unroll 1
-      for (int uyi = 0; uyi < L; ++uyi) {
-        const cplx<double> kv = ring[0];
+      for (int gi = 0; gi < NG; ++gi) {
+        const int u0 = gi * GT;
+        cplx<double> kv[GT];
 #pragma unroll
-        for (int i = 0; i + 1 < SUBC_PF; ++i) ring[i] = ring[i + 1];
-        ring[SUBC_PF - 1] = Ga[(int64_t)min(uyi + SUBC_PF, L - 1) * (H + 1)];
-        const cplx<double>* src = wl - uyi * 64;
+        for (int i = 0; i < GT; ++i) {
+          kv[i] = kn[i];
+          const int u = u0 + GT + i;
+          const cplx<double> t = Ga[(int64_t)min(u, L - 1) * (H + 1)];
+          kn[i] = u < L ? t : mk(0.0, 0.0);
+        }
+        // source offsets d = t - u for this group run over [-(u0 + GT - 1), TY - 1 - u0]
+        const cplx<double>* src = wl - (u0 + GT - 1) * 64;
 #pragma unroll
-        for (int t = 0; t < SUBC_TY; ++t) part[t] = cmac(part[t], kv, src[t * 64]);
+        for (int dr = 0; dr < SUBC_TY + GT - 1; ++dr) {
+          const cplx<double> v = src[dr * 64];
+#pragma unroll
+          for (int i = 0; i < GT; ++i) {
+            const int t = dr - (GT - 1) + i;   // output row fed by tap u0 + i
+            if (t >= 0 && t < SUBC_TY) part[t] = cmac(part[t], kv[i], v);
+          }
+        }
       }
 #pragma unroll
       for (int t = 0; t < SUBC_TY; ++t) {
