@@ -614,7 +614,7 @@ __global__ void dir_reduce_kernel(const double* __restrict__ part, int nband, in
 // row_win: inverse along x restricted to the lag columns, FP64
 // ---------------------------------------------------------------------------
 // C(j, i) = 1/(Py Px) [ V(j,0) + (-1)^i V(j,H) + 2 Re sum_{kx=1}^{H-1} V(j,kx) e^{2 pi i kx i / Px} ]
-// One block per V row; the window half-width of the row's pair is hw.
+// One wave per V row (nrows rows); the window half-width of the row's pair is hw.
 struct WinRow {
   int32_t vrow;     // row of V
   int32_t out;      // offset of the first window value of this row in `win`
@@ -623,39 +623,50 @@ struct WinRow {
 
 template <int THREADS, int IMAX>
 __global__ __launch_bounds__(THREADS) void row_win_kernel(AsmParams P, const cplx<double>* __restrict__ V,
-                                                          const WinRow* __restrict__ rows, double* __restrict__ win,
+                                                          const WinRow* __restrict__ rows, int nrows,
+                                                          double* __restrict__ win,
                                                           const cplx<double>* __restrict__ twd) {
   static_assert(THREADS == 64, "one wave per window row");
-  const WinRow R = rows[blockIdx.x];
+  constexpr int HMAX = (IMAX - 1) / 2;   // largest half-width
+  // V is stored [kx][vrow]: neighbouring rows share every cache line they
+  // read, so they run on one XCD at about the same time (xcd_remap)
+  const int rid = xcd_remap(blockIdx.x, gridDim.x);
+  if (rid >= nrows) return;
+  const WinRow R = rows[rid];
   const int H = P.H;
   const int lgPx = P.lgPx;
   const int tid = threadIdx.x;
-  const int ni = 2 * R.hw + 1;
-  double acc[IMAX];
+  const int hw = R.hw;
+  // With m = i - hw in [-hw, hw] and theta = 2 pi kx / Px:
+  //   sum_kx w_kx Re(V e^{i theta m}) = Cc(|m|) - sgn(m) Cs(|m|),
+  //   Cc(m) = sum w_kx Re V cos(theta m),  Cs(m) = sum w_kx Im V sin(theta m),
+  // (w = 1 at kx = 0 and H, 2 between), so only m = 0 .. hw are accumulated.
+  double cc[HMAX + 1], cs[HMAX + 1];
 #pragma unroll
-  for (int i = 0; i < IMAX; ++i) acc[i] = 0.0;
+  for (int m = 0; m <= HMAX; ++m) cc[m] = cs[m] = 0.0;
   for (int kx = tid; kx <= H; kx += THREADS) {
     const cplx<double> v = V[(int64_t)kx * P.vrows + R.vrow];
     if (kx == 0 || kx == H) {
-      // real values with weight 1; the Nyquist column alternates in sign, (-1)^(i - hw)
+      // real values with weight 1; at the Nyquist column cos(pi m) = (-1)^m
       const bool nyq = (kx == H);
-      double sg = (nyq && (R.hw & 1)) ? -1.0 : 1.0;
+      double sg = 1.0;
 #pragma unroll
-      for (int i = 0; i < IMAX; ++i) {
-        if (i < ni) {
-          acc[i] += sg * v.x;
+      for (int m = 0; m <= HMAX; ++m) {
+        if (m <= hw) {
+          cc[m] += sg * v.x;
           if (nyq) sg = -sg;
         }
       }
     } else {
-      // 2 Re(v e^{2 pi i kx (i - hw)/Px}) by FP64 recurrence
-      const int m0 = (int)(((int64_t)kx * (int64_t)(2 * H - R.hw)) & (int64_t)(2 * H - 1));
-      cplx<double> t = conjg(twd[m0 << (TW_LOG - lgPx)]);
+      // e^{i theta m} by FP64 recurrence from m = 0
       const cplx<double> st = conjg(twd[kx << (TW_LOG - lgPx)]);
+      const double vr = 2.0 * v.x, vi = 2.0 * v.y;
+      cplx<double> t = mk(1.0, 0.0);
 #pragma unroll
-      for (int i = 0; i < IMAX; ++i) {
-        if (i < ni) {
-          acc[i] += 2.0 * (v.x * t.x - v.y * t.y);
+      for (int m = 0; m <= HMAX; ++m) {
+        if (m <= hw) {
+          cc[m] += vr * t.x;
+          cs[m] += vi * t.y;
           t = t * st;
         }
       }
@@ -663,11 +674,17 @@ __global__ __launch_bounds__(THREADS) void row_win_kernel(AsmParams P, const cpl
   }
   const double norm = 1.0 / ((double)(1 << P.lgPy) * (double)(2 * H));
 #pragma unroll
-  for (int i = 0; i < IMAX; ++i) {
-    if (i < ni) {
-      double v = acc[i];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-      if (tid == 0) win[R.out + i] = v * norm;
+  for (int m = 0; m <= HMAX; ++m) {
+    if (m <= hw) {
+      double c = cc[m], d = cs[m];
+      for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, 64);
+        d += __shfl_down(d, off, 64);
+      }
+      if (tid == 0) {
+        win[R.out + hw + m] = (c - d) * norm;
+        if (m > 0) win[R.out + hw - m] = (c + d) * norm;
+      }
     }
   }
 }

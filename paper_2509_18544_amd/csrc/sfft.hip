@@ -667,8 +667,11 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     if (st != SFFT_OK) return st;
   }
   p->timer.begin(SFFT_STAGE_ROW_WIN, s);
-  row_win_kernel<WIN_THREADS, WIN_IMAX><<<(int)D.wrows.size(), WIN_THREADS, 0, s>>>(
-      A, p->at<cplx<double>>(Lo.V), p->at<WinRow>(Lo.wrows), p->at<double>(Lo.win), twd);
+  {
+    const int nrows = (int)D.wrows.size();
+    row_win_kernel<WIN_THREADS, WIN_IMAX><<<((nrows + 7) / 8) * 8, WIN_THREADS, 0, s>>>(
+        A, p->at<cplx<double>>(Lo.V), p->at<WinRow>(Lo.wrows), nrows, p->at<double>(Lo.win), twd);
+  }
   LAUNCH_CHECK();
   p->timer.end(s);
   return gather_impl(p, A);
@@ -805,7 +808,8 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
       LAUNCH_CHECK();
     }
     {
-      dim3 g((D.H + 1 + 63) / 64, (D.ny + SUBC_RB - 1) / SUBC_RB);
+      const int nconv = ((D.H + 1 + 63) / 64) * ((D.ny + SUBC_RB - 1) / SUBC_RB);
+      const int g = ((nconv + 7) / 8) * 8;   // whole XCD rounds for the remap
       const size_t lds_c = sub_conv_lds_bytes(D.w);
       switch (D.w) {
 #define CONV_CASE(WV)                                                                                          \

@@ -375,9 +375,15 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int kx0 = blockIdx.x * 64;
+  // blocks (column group bx, row band by) in y-major order through xcd_remap:
+  // bands that share halo rows run on one XCD at about the same time
+  const int nby = (P.ny + SUBC_RB - 1) / SUBC_RB;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = bid / nby, by = bid - bx * nby;
+  if (bx * 64 > P.H) return;
+  const int kx0 = bx * 64;
   const int kx = kx0 + lane;
-  const int yb = blockIdx.y * SUBC_RB;            // first output row of the block
+  const int yb = by * SUBC_RB;                    // first output row of the block
   const int y0 = yb + wave * SUBC_TY;             // first output row of the wave
   cplx<double> acc[SUBC_TY];
 #pragma unroll
