@@ -342,6 +342,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kerne
 // spread the 16-byte reads of a wave, whose lanes take different residues and
 // planes, over the LDS banks instead of piling them on one bank quad.
 constexpr int CORR_RS = P2 + 1;
+constexpr int CORR_LB = 8;   // staging loads in flight per thread
 __host__ __device__ constexpr int corr_plane_stride(int c1) {
   return ((c1 * CORR_RS + 12) & ~15) + 3;
 }
@@ -404,24 +405,39 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
     for (int k1c = 0; k1c < P1; k1c += C1) {
       const int nc = min(C1, P1 - k1c);
       __syncthreads();
-      // spectra: two neighbouring values per load (16 bytes in FP32)
+      // spectra: two neighbouring values per load (16 bytes in FP32).  The
+      // loads of a batch of CORR_LB per thread are all issued before any is
+      // converted and stored, so their latencies overlap.
       const int npr = nc * (P2 / 2);
-      for (int e = tid; e < P.nplanes * npr; e += THREADS) {
-        const int pl = e / npr;
-        const int o = 2 * (e - pl * npr);
-        const cplx<T>* src = U + pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o;
-        cplx<double> v0, v1;
-        if constexpr (sizeof(T) == sizeof(float)) {
-          const float4 q = *reinterpret_cast<const float4*>(src);
-          v0 = mk((double)q.x, (double)q.y);
-          v1 = mk((double)q.z, (double)q.w);
-        } else {
-          v0 = mk((double)src[0].x, (double)src[0].y);
-          v1 = mk((double)src[1].x, (double)src[1].y);
+      const int ntot = P.nplanes * npr;
+      for (int e0 = tid; e0 < ntot; e0 += CORR_LB * THREADS) {
+        cplx<T> q[CORR_LB][2];
+#pragma unroll
+        for (int b = 0; b < CORR_LB; ++b) {
+          const int e = min(e0 + b * THREADS, ntot - 1);   // a valid element; the copy is dropped below
+          const int pl = e / npr;
+          const int o = 2 * (e - pl * npr);
+          const cplx<T>* src = U + pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o;
+          if constexpr (sizeof(T) == sizeof(float)) {
+            const float4 f = *reinterpret_cast<const float4*>(src);
+            q[b][0] = mk(f.x, f.y);
+            q[b][1] = mk(f.z, f.w);
+          } else {
+            q[b][0] = src[0];
+            q[b][1] = src[1];
+          }
         }
-        cplx<double>* dst = stage + pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1));
-        dst[0] = v0;
-        dst[1] = v1;
+#pragma unroll
+        for (int b = 0; b < CORR_LB; ++b) {
+          const int e = e0 + b * THREADS;
+          if (e < ntot) {
+            const int pl = e / npr;
+            const int o = 2 * (e - pl * npr);
+            cplx<double>* dst = stage + pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1));
+            dst[0] = mk((double)q[b][0].x, (double)q[b][0].y);
+            dst[1] = mk((double)q[b][1].x, (double)q[b][1].y);
+          }
+        }
       }
       // outer twiddles: from the table for the first chunk (Py is a power of two,
       // so the index is the product masked to [0, Py)), then by the FP64 step
