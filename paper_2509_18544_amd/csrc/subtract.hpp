@@ -213,6 +213,8 @@ struct SpecParams {
   int8_t bpx[15], bqy[15];
 };
 
+constexpr int SUB_MAXP = 5;   // x powers of the background polynomial (degree <= 4)
+
 // rows per block of the subtraction's row transforms (a power of two)
 __host__ __device__ constexpr int sub_row_rows(int nmax, int lgh) { return (nmax >> lgh) < 64 ? (nmax >> lgh) : 64; }
 
@@ -490,25 +492,52 @@ __global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const
   }
   __syncthreads();
   const LdsRows<double, LGH> lds{buf};
-  fft_run<double, NMAX, THREADS, true, true, true, LGH, 4>(buf, RB, tw, lds, lds);
-  __syncthreads();
+  // background along each of the block's rows as a polynomial in xh:
+  // bg(x, y) = sum_p c_p(y) xh^p with c_p(y) = sum over terms b with x power p
+  // of theta_b yh^(q_b), evaluated by Horner's rule per pixel
+  __shared__ double bcoef[RB][SUB_MAXP];
   const int L2 = (2 * P.w + 1) * (2 * P.w + 1);
   const int nkk = P.nk * L2;
+  if (tid < RB * SUB_MAXP) {
+    const int r = tid / SUB_MAXP, pw = tid - r * SUB_MAXP;
+    const double yh = (double)(y0 + r) * P.sy - 1.0;
+    double c = 0.0;
+    for (int b = 0; b < P.nb; ++b)
+      if (P.bpx[b] == pw) c += theta[nkk + b] * ipow(yh, P.bqy[b]);
+    bcoef[r][pw] = c;
+  }
+  int pdeg = 0;
+  for (int b = 0; b < P.nb; ++b) pdeg = max(pdeg, (int)P.bpx[b]);
+  fft_run<double, NMAX, THREADS, true, true, true, LGH, 4>(buf, RB, tw, lds, lds);
+  __syncthreads();
   const double invH = 1.0 / (double)H;
-  const int span = xhi - xlo;
-  for (int e = tid; e < RB * span; e += THREADS) {
-    const int r = e / span;
-    const int x = xlo + (e - r * span);
+  // pixels x = xlo + tid + i THREADS of every row; the science values of the
+  // thread are all loaded (clamped into the frame) before any is used
+  constexpr int XPT = (2 * H + THREADS - 1) / THREADS;
+  T sv[RB][XPT];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int y = min(y0 + r, P.ny - 1);
+      const int x = min(xlo + tid + i * THREADS, xhi - 1);
+      sv[r][i] = sci[(int64_t)y * P.ld + x];
+    }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
     const int y = y0 + r;
     if (y >= P.ny) continue;
-    const cplx<double> z = buf[lds_pad(r * H + (x >> 1))];
-    const double model = ((x & 1) ? z.y : z.x) * invH;
-    const double xh = (double)x * P.sx - 1.0;
-    const double yh = (double)y * P.sy - 1.0;
-    double bg = 0.0;
-    for (int b = 0; b < P.nb; ++b) bg += theta[nkk + b] * ipow(xh, P.bpx[b]) * ipow(yh, P.bqy[b]);
-    const int64_t o = (int64_t)y * P.ld + x;
-    diff[o] = (T)((double)sci[o] - model - bg);
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int x = xlo + tid + i * THREADS;
+      if (x >= xhi) continue;
+      const cplx<double> z = buf[lds_pad(r * H + (x >> 1))];
+      const double model = ((x & 1) ? z.y : z.x) * invH;
+      const double xh = (double)x * P.sx - 1.0;
+      double bg = bcoef[r][pdeg];
+      for (int pw = pdeg - 1; pw >= 0; --pw) bg = bg * xh + bcoef[r][pw];
+      diff[(int64_t)y * P.ld + x] = (T)((double)sv[r][i] - model - bg);
+    }
   }
 }
 
