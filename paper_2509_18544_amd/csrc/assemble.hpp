@@ -194,7 +194,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kerne
     // split and write: consecutive threads fill one (column pair, row block) segment
     cplx<T>* Ub = U + (int64_t)b * pstride;
     constexpr int seg = 2 * RB;
-#pragma unroll 1
+#pragma unroll 4
     for (int i = 0; i < NPT; ++i) {
       const int e = tid + i * THREADS;
       const int c = e / seg;
@@ -731,6 +731,7 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, const T* 
   const T* srow = sci + (int64_t)y * P.ld;
   const T* rrow = tmpl + (int64_t)y * P.ld;
   const uint8_t* mrow = mask ? mask + (int64_t)y * P.ld : nullptr;
+#pragma unroll 4
   for (int x = tid; x < P.nx; x += THREADS) {
     const T sv = srow[x];
     const T rv = rrow[x];

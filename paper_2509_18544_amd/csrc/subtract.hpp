@@ -269,6 +269,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_ke
     __syncthreads();
     fft_run<double, NMAX, THREADS, false, true, true, LGH, 4>(buf, RB, tw, lds, lds);
     __syncthreads();
+#pragma unroll 3
     for (int e = tid; e < RB * (H + 1); e += THREADS) {
       const int r = e / (H + 1);
       const int k = e - r * (H + 1);
