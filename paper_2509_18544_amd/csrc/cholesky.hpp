@@ -91,7 +91,9 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restri
   int* __restrict__ info = J.info;
   const int lane = threadIdx.x;
   const int nb = min(NB, n - k0);
-  // coalesced load of the block through LDS (one row per step, lanes along it), identity padding
+  // coalesced load of the block through LDS (one row per step, lanes along it),
+  // identity padding; unrolled so that the row loads overlap
+#pragma unroll 16
   for (int r = 0; r < NB; ++r) {
     double v = (lane == r) ? 1.0 : 0.0;
     if (r < nb) v = (lane <= r) ? F[(int64_t)(k0 + r) * n + k0 + lane] : 0.0;
@@ -164,10 +166,24 @@ __global__ __launch_bounds__(256) void trsm_kernel(const SolveJob* __restrict__ 
   const int r0 = k0 + NB + blockIdx.x * NB;
   const int nr = min(NB, n - r0);
   if (nr <= 0) return;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    A[i][j] = (i < nr && j < nb) ? F[(int64_t)(r0 + i) * n + k0 + j] : 0.0;
-    B[i][j] = Linv[e];
+  {
+    // every load of the thread is issued (clamped into the block) before any is stored
+    constexpr int PER = NB * NB / 256;
+    double av[PER], bv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * 256;
+      const int i = e / NB, j = e % NB;
+      av[q] = F[(int64_t)(r0 + min(i, nr - 1)) * n + k0 + min(j, nb - 1)];
+      bv[q] = Linv[e];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * 256;
+      const int i = e / NB, j = e % NB;
+      A[i][j] = (i < nr && j < nb) ? av[q] : 0.0;
+      B[i][j] = bv[q];
+    }
   }
   __syncthreads();
   // L = A Linv^T on the matrix cores (see tile_abt)
@@ -218,10 +234,24 @@ __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ 
   const int ri = t0 + I * NB, rj = t0 + J * NB;
   const int ni = min(NB, n - ri), nj = min(NB, n - rj);
   if (ni <= 0 || nj <= 0) return;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, m = e % NB;
-    A[i][m] = (i < ni && m < nb) ? F[(int64_t)(ri + i) * n + k0 + m] : 0.0;
-    B[i][m] = (i < nj && m < nb) ? F[(int64_t)(rj + i) * n + k0 + m] : 0.0;
+  {
+    // every load of the thread is issued (clamped into the panels) before any is stored
+    constexpr int PER = NB * NB / 256;
+    double av[PER], bv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * 256;
+      const int i = e / NB, m = min(e % NB, nb - 1);
+      av[q] = F[(int64_t)(ri + min(i, ni - 1)) * n + k0 + m];
+      bv[q] = F[(int64_t)(rj + min(i, nj - 1)) * n + k0 + m];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * 256;
+      const int i = e / NB, m = e % NB;
+      A[i][m] = (i < ni && m < nb) ? av[q] : 0.0;
+      B[i][m] = (i < nj && m < nb) ? bv[q] : 0.0;
+    }
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
@@ -229,6 +259,18 @@ __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ 
   const int lr = lane & 15, lk = lane >> 4;
   f64x4 acc[2][2];
   tile_abt(A, B, wm, wn, lr, lk, acc);
+  // read-modify-write of the tile: the reads are unconditional (clamped) so
+  // that they are all in flight together; only the stores are predicated
+  double fv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = min(wm + 16 * a + lk + 4 * r, ni - 1), j = min(wn + 16 * c + lr, nj - 1);
+        fv[a][c][r] = F[(int64_t)(ri + i) * n + rj + j];
+      }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -236,7 +278,7 @@ __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = wm + 16 * a + lk + 4 * r, j = wn + 16 * c + lr;
-        if (i < ni && j < nj && (I != J || j <= i)) F[(int64_t)(ri + i) * n + rj + j] -= acc[a][c][r];
+        if (i < ni && j < nj && (I != J || j <= i)) F[(int64_t)(ri + i) * n + rj + j] = fv[a][c][r] - acc[a][c][r];
       }
 }
 
