@@ -33,6 +33,7 @@ struct SolveJob {
   double* y;
   double* r;
   double* d;
+  double* w;            // right-hand side being updated by the substitutions
   int* info;
   int n, nblk;
 };
@@ -282,133 +283,130 @@ __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ 
       }
 }
 
-// Forward substitution L y = b (single block, 1024 threads).  The solution
-// vector lives in LDS (dynamic, n doubles) so that values written by one
-// thread are read by the others without a trip through the caches.
-// which = 0: L y = beta; which = 1: L y = r
-__global__ __launch_bounds__(1024) void trsv_lower_kernel(const SolveJob* __restrict__ jobs, int which) {
-  extern __shared__ double ys[];
-  __shared__ double part[NB][17];
-  __shared__ double rhs[NB];
-  const SolveJob J = jobs[blockIdx.x];
-  if (*J.info != 0) return;
-  const double* __restrict__ F = J.F;
+// Blocked right-looking substitutions, one launch per block step k; block
+// (ib, job) of the launch owns one row block, the block of lanes l = 0..63 x
+// quarters q = 0..3 (the waves) of a 64 x 64 tile.
+//  Forward L y = b (which = 0: b = beta, 1: b = r), blocks i = k + ib:
+//    every block forms y_k = Linv_k w_k (w_k = b_k at k = 0); block i = k
+//    stores it, blocks i > k update w_i = (k == 0 ? b_i : w_i) - L_ik y_k.
+//  Back L^T x = y (which = 0: x = theta, 1: x = d), blocks j = ib <= k:
+//    every block forms x_k = Linv_k^T w_k (w_k = y_k at k = nblk - 1);
+//    block j = k stores it, blocks j < k update
+//    w_j = (k == nblk - 1 ? y_j : w_j) - L_kj^T x_k.
+// Row blocks of a launch only read w_k, which no block of it writes.
+// 64-element sums over the four quarters: partial of quarter q, lane l in part[q][l].
+__device__ __forceinline__ double trsv_quarter_sum(double (*part)[NB + 1], int lane) {
+  return (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+__global__ __launch_bounds__(256) void trsv_lower_step_kernel(const SolveJob* __restrict__ jobs, int k, int which) {
+  __shared__ double part[4][NB + 1];
+  __shared__ double yk[NB];
+  const SolveJob J = jobs[blockIdx.y];
+  if (k >= J.nblk || *J.info != 0) return;
+  const int i = k + (int)blockIdx.x;
+  if (i >= J.nblk) return;
   const int n = J.n;
-  const double* __restrict__ Linv = J.Linv;
+  const int k0 = k * NB, nb = min(NB, n - k0);
+  const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
   const double* __restrict__ b = which == 0 ? J.beta : J.r;
-  double* __restrict__ y = J.y;
-  const int tid = threadIdx.x;
-  const int r = tid >> 4;       // row within the block (0..63)
-  const int sl = tid & 15;      // slice of the columns
-  const int nblk = (n + NB - 1) / NB;
-  for (int k = 0; k < nblk; ++k) {
-    const int k0 = k * NB;
-    const int nb = min(NB, n - k0);
-    double acc = 0.0;
-    if (r < nb) {
-      const double* row = F + (int64_t)(k0 + r) * n;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int c = sl;
-      for (; c + 48 < k0; c += 64) {
-        a0 += row[c] * ys[c];
-        a1 += row[c + 16] * ys[c + 16];
-        a2 += row[c + 32] * ys[c + 32];
-        a3 += row[c + 48] * ys[c + 48];
-      }
-      for (; c < k0; c += 16) a0 += row[c] * ys[c];
-      acc = (a0 + a1) + (a2 + a3);
+  const double* __restrict__ wk = k == 0 ? b : J.w;
+  // y_k = Linv_k w_k (Linv_k is zero past row / column nb)
+  const double* __restrict__ Li = J.Linv + (size_t)k * NB * NB;
+  {
+    double lv[16], bv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int c = q * 16 + m;
+      lv[m] = Li[lane * NB + c];
+      bv[m] = wk[k0 + min(c, nb - 1)];
     }
-    part[r][sl] = acc;
-    __syncthreads();
-    if (tid < NB) {
-      double s = 0.0;
-      for (int q = 0; q < 16; ++q) s += part[tid][q];
-      rhs[tid] = (tid < nb) ? b[k0 + tid] - s : 0.0;
-    }
-    __syncthreads();
-    // y_k = Linv_k rhs   (Linv lower triangular)
-    {
-      const double* Li = Linv + (int64_t)k * NB * NB;
-      double a2 = 0.0;
-      if (r < nb) {
-        for (int m = sl; m <= r; m += 16) a2 += Li[r * NB + m] * rhs[m];
-      }
-      part[r][sl] = a2;
-    }
-    __syncthreads();
-    if (tid < nb) {
-      double s = 0.0;
-      for (int q = 0; q < 16; ++q) s += part[tid][q];
-      ys[k0 + tid] = s;
-    }
-    __syncthreads();
+    double a = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a += lv[m] * bv[m];
+    part[q][lane] = a;
   }
-  for (int i = tid; i < n; i += 1024) y[i] = ys[i];
+  __syncthreads();
+  if (q == 0) yk[lane] = trsv_quarter_sum(part, lane);
+  __syncthreads();
+  if (i == k) {
+    if (tid < nb) J.y[k0 + tid] = yk[tid];
+    return;
+  }
+  // w_i -= L_ik y_k: row i0 + lane, columns of quarter q
+  const int i0 = i * NB, ni = min(NB, n - i0);
+  const double* __restrict__ row = J.F + (int64_t)(i0 + min(lane, ni - 1)) * n + k0;
+  {
+    double fv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) fv[m] = row[min(q * 16 + m, nb - 1)];
+    double a = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a += fv[m] * yk[q * 16 + m];
+    __syncthreads();
+    part[q][lane] = a;
+  }
+  __syncthreads();
+  if (q == 0 && lane < ni) {
+    const double* __restrict__ wi = k == 0 ? b : J.w;
+    J.w[i0 + lane] = wi[i0 + lane] - trsv_quarter_sum(part, lane);
+  }
 }
 
-// Back substitution L^T x = y (single block, 1024 threads), x in LDS.
-// which = 0: L^T theta = y; which = 1: L^T d = y
-__global__ __launch_bounds__(1024) void trsv_upper_kernel(const SolveJob* __restrict__ jobs, int which) {
-  extern __shared__ double xs[];
-  __shared__ double part[16][NB + 1];
-  __shared__ double rhs[NB];
-  const SolveJob J = jobs[blockIdx.x];
-  if (*J.info != 0) return;
-  const double* __restrict__ F = J.F;
+__global__ __launch_bounds__(256) void trsv_upper_step_kernel(const SolveJob* __restrict__ jobs, int k, int which) {
+  __shared__ double part[4][NB + 1];
+  __shared__ double xk[NB];
+  const SolveJob J = jobs[blockIdx.y];
+  if (k >= J.nblk || *J.info != 0) return;
+  const int j = (int)blockIdx.x;
+  if (j > k) return;
   const int n = J.n;
-  const double* __restrict__ Linv = J.Linv;
-  const double* __restrict__ y = J.y;
-  double* __restrict__ x = which == 0 ? J.theta : J.d;
-  const int tid = threadIdx.x;
-  const int c = tid & (NB - 1);   // column within the block
-  const int rs = tid >> 6;        // row slice 0..15
-  const int nblk = (n + NB - 1) / NB;
-  for (int k = nblk - 1; k >= 0; --k) {
-    const int k0 = k * NB;
-    const int nb = min(NB, n - k0);
-    const int rstart = k0 + nb;
-    double acc = 0.0;
-    if (c < nb) {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int rr = rstart + rs;
-      for (; rr + 48 < n; rr += 64) {
-        a0 += F[(int64_t)rr * n + k0 + c] * xs[rr];
-        a1 += F[(int64_t)(rr + 16) * n + k0 + c] * xs[rr + 16];
-        a2 += F[(int64_t)(rr + 32) * n + k0 + c] * xs[rr + 32];
-        a3 += F[(int64_t)(rr + 48) * n + k0 + c] * xs[rr + 48];
-      }
-      for (; rr < n; rr += 16) a0 += F[(int64_t)rr * n + k0 + c] * xs[rr];
-      acc = (a0 + a1) + (a2 + a3);
+  const int k0 = k * NB, nb = min(NB, n - k0);
+  const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+  const bool first = (k == J.nblk - 1);
+  const double* __restrict__ wk = first ? J.y : J.w;
+  // x_k = Linv_k^T w_k: x[c] = sum_m Linv_k[m][c] w_k[m], c = lane
+  const double* __restrict__ Li = J.Linv + (size_t)k * NB * NB;
+  {
+    double lv[16], bv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int r = q * 16 + m;
+      lv[m] = Li[r * NB + lane];
+      bv[m] = wk[k0 + min(r, nb - 1)];
     }
-    part[rs][c] = acc;
-    __syncthreads();
-    if (tid < NB) {
-      double s = 0.0;
-      for (int q = 0; q < 16; ++q) s += part[q][tid];
-      rhs[tid] = (tid < nb) ? y[k0 + tid] - s : 0.0;
-    }
-    __syncthreads();
-    // x_k = Linv_k^T rhs: x[c] = sum_{m >= c} Linv[m][c] rhs[m]
-    {
-      const double* Li = Linv + (int64_t)k * NB * NB;
-      double a2 = 0.0;
-      if (c < nb) {
-        for (int m = c + rs; m < nb; m += 16) a2 += Li[m * NB + c] * rhs[m];
-      }
-      part[rs][c] = a2;
-    }
-    __syncthreads();
-    if (tid < nb) {
-      double s = 0.0;
-      for (int q = 0; q < 16; ++q) s += part[q][tid];
-      xs[k0 + tid] = s;
-    }
-    __syncthreads();
+    double a = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a += lv[m] * bv[m];
+    part[q][lane] = a;
   }
-  for (int i = tid; i < n; i += 1024) x[i] = xs[i];
+  __syncthreads();
+  if (q == 0) xk[lane] = trsv_quarter_sum(part, lane);
+  __syncthreads();
+  double* __restrict__ x = which == 0 ? J.theta : J.d;
+  if (j == k) {
+    if (tid < nb) x[k0 + tid] = xk[tid];
+    return;
+  }
+  // w_j -= L_kj^T x_k: column j0 + lane, rows k0 + (quarter q)
+  const int j0 = j * NB;   // j < k, so the block is full
+  {
+    double fv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) fv[m] = J.F[(int64_t)(k0 + min(q * 16 + m, nb - 1)) * n + j0 + lane];
+    double a = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a += (q * 16 + m < nb) ? fv[m] * xk[q * 16 + m] : 0.0;
+    __syncthreads();
+    part[q][lane] = a;
+  }
+  __syncthreads();
+  if (q == 0) {
+    const double* __restrict__ wj = first ? J.y : J.w;
+    J.w[j0 + lane] = wj[j0 + lane] - trsv_quarter_sum(part, lane);
+  }
 }
 
-// r = b - A x   (A row-major n x n; one wave per row)
 __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ A, int n,
                                                        const double* __restrict__ b, const double* __restrict__ x,
                                                        double* __restrict__ r) {

@@ -37,7 +37,7 @@ constexpr int MAX_W = 15;
 constexpr double DIR_AUTO_FMA = 1.0e9;   // direct lag sums below this many multiply-adds (small frames)
 
 struct Layout {
-  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, kp, flags, tw32, tw64, items, wrows, drows, job;
+  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, w, kp, flags, tw32, tw64, items, wrows, drows, job;
   size_t total;
 };
 
@@ -340,6 +340,7 @@ Layout layout_of(const Derived& D) {
   Lo.y = take((size_t)D.n * sizeof(double));
   Lo.r = take((size_t)D.n * sizeof(double));
   Lo.d = take((size_t)D.n * sizeof(double));
+  Lo.w = take((size_t)D.n * sizeof(double));
   Lo.kp = take((size_t)D.nk * D.L * D.L * sizeof(double));
   Lo.flags = take(2 * sizeof(int));
   Lo.tw32 = take((size_t)TW_N * sizeof(cplx<float>));
@@ -705,20 +706,31 @@ int solve_jobs(hipStream_t s, const SolveJob* jobs, int njobs, int max_n, int ma
   }
   tm->end(s);
   tm->begin(SFFT_STAGE_SOLVE, s);
-  const size_t lds = (size_t)max_n * sizeof(double);
-  HIP_TRY(hipFuncSetAttribute((const void*)trsv_lower_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  HIP_TRY(hipFuncSetAttribute((const void*)trsv_upper_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  trsv_lower_kernel<<<njobs, 1024, lds, s>>>(jobs, 0);
-  LAUNCH_CHECK();
-  trsv_upper_kernel<<<njobs, 1024, lds, s>>>(jobs, 0);
-  LAUNCH_CHECK();
+  // blocked right-looking substitutions: one launch per block step, one
+  // block per row block still to be updated
+  auto solve_lower = [&](int which) -> int {
+    for (int k = 0; k < max_nblk; ++k) {
+      trsv_lower_step_kernel<<<dim3(max_nblk - k, njobs), 256, 0, s>>>(jobs, k, which);
+      LAUNCH_CHECK();
+    }
+    return SFFT_OK;
+  };
+  auto solve_upper = [&](int which) -> int {
+    for (int k = max_nblk - 1; k >= 0; --k) {
+      trsv_upper_step_kernel<<<dim3(k + 1, njobs), 256, 0, s>>>(jobs, k, which);
+      LAUNCH_CHECK();
+    }
+    return SFFT_OK;
+  };
+  int st = solve_lower(0);
+  if (st == SFFT_OK) st = solve_upper(0);
+  if (st != SFFT_OK) return st;
   for (int it = 0; it < refine; ++it) {
     residual_jobs_kernel<<<dim3((max_n + 3) / 4, njobs), 256, 0, s>>>(jobs);
     LAUNCH_CHECK();
-    trsv_lower_kernel<<<njobs, 1024, lds, s>>>(jobs, 1);
-    LAUNCH_CHECK();
-    trsv_upper_kernel<<<njobs, 1024, lds, s>>>(jobs, 1);
-    LAUNCH_CHECK();
+    st = solve_lower(1);
+    if (st == SFFT_OK) st = solve_upper(1);
+    if (st != SFFT_OK) return st;
     axpy_jobs_kernel<<<dim3((max_n + 255) / 256, njobs), 256, 0, s>>>(jobs);
     LAUNCH_CHECK();
   }
@@ -737,6 +749,7 @@ SolveJob job_of(sfft_plan_s* p) {
   J.y = p->at<double>(Lo.y);
   J.r = p->at<double>(Lo.r);
   J.d = p->at<double>(Lo.d);
+  J.w = p->at<double>(Lo.w);
   J.info = p->at<int>(Lo.flags);
   J.n = p->D.n;
   J.nblk = p->D.nblk;
