@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=16, help="distinct pairs per step (one batched run)")
+    ap.add_argument("--batch", type=int, default=32, help="distinct pairs per step (one batched run)")
     ap.add_argument("--mode", choices=["f32c", "f64"], default="f32c")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
