@@ -879,10 +879,29 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
     LAUNCH_CHECK();
     const size_t lds = ((size_t)(SUB_TY + 2 * D.w) * (SUB_TX + 2 * D.w) + (size_t)D.nk * L2) * sizeof(double);
     const int bands[2][2] = {{0, xl}, {xr, D.nx}};
+    const bool narrow0 = xl <= 0 || xl < SUB_TX / 2, narrow1 = D.nx - xr <= 0 || D.nx - xr < SUB_TX / 2;
+    if (narrow0 && narrow1) {
+      // both bands narrow: one launch, one wave per pixel
+      P.xbeg = 0;
+      P.xend = std::max(0, xl);
+      P.xbeg2 = xr;
+      P.xend2 = D.nx;
+      const size_t lds_k = (size_t)D.nk * L2 * sizeof(double);
+      HIP_TRY(hipFuncSetAttribute((const void*)subtract_band_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_k));
+      const int64_t npx = (int64_t)(P.xend - P.xbeg + std::max(0, P.xend2 - P.xbeg2)) * D.ny;
+      if (npx > 0) {
+        subtract_band_kernel<<<(int)((npx + BAND_WAVES - 1) / BAND_WAVES), 64 * BAND_WAVES, lds_k, s>>>(
+            P, sci, tmpl, std::is_same<T, double>::value ? 1 : 0, kp, coeffs, diff);
+        LAUNCH_CHECK();
+      }
+    }
     for (int bnd = 0; bnd < 2; ++bnd) {
       P.xbeg = bands[bnd][0];
       P.xend = bands[bnd][1];
+      P.xbeg2 = P.xend2 = 0;
       if (P.xend <= P.xbeg) continue;
+      if (narrow0 && narrow1) continue;   // done above
       if (P.xend - P.xbeg < SUB_TX / 2) {
         // narrow band: one wave per pixel
         const size_t lds_k = (size_t)D.nk * L2 * sizeof(double);

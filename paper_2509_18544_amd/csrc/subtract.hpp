@@ -23,6 +23,7 @@ namespace sfft {
 struct SubParams {
   int ny, nx, w, nk, nb;
   int xbeg, xend;        // the direct kernel writes columns [xbeg, xend) only
+  int xbeg2, xend2;      // narrow-band kernel: a second band (empty when xend2 <= xbeg2)
   int64_t ld;
   int8_t kpx[15], kqy[15];
   int8_t bpx[15], bqy[15];
@@ -60,10 +61,12 @@ __global__ void kprime_kernel(SubParams P, const double* __restrict__ theta, dou
 constexpr int SUB_TY = 16;
 constexpr int SUB_TX = 64;
 
-// Direct D on a narrow column band [P.xbeg, P.xend): one wave per pixel, the
-// lanes split the nK L^2 kernel taps (k' in LDS) and sum by shuffles.  Same
+// Direct D on the narrow column bands [P.xbeg, P.xend) and [P.xbeg2, P.xend2):
+// one wave per pixel, the lanes split the nK L^2 kernel taps (k' in LDS) and
+// sum by shuffles.  The template loads of a lane are unconditional (clamped
+// into the frame, then selected) so that several are in flight.  Same
 // arithmetic as subtract_kernel below, summed in a different order.
-constexpr int BAND_WAVES = 4;
+constexpr int BAND_WAVES = 8;
 __global__ __launch_bounds__(64 * BAND_WAVES) void subtract_band_kernel(SubParams P, const void* __restrict__ sci_v,
                                                                         const void* __restrict__ tmpl_v, int is_f64,
                                                                         const double* __restrict__ kp,
@@ -74,31 +77,40 @@ __global__ __launch_bounds__(64 * BAND_WAVES) void subtract_band_kernel(SubParam
   const int L = 2 * w + 1;
   const int L2 = L * L;
   const int nkk = P.nk * L2;
-  const int bw = P.xend - P.xbeg;
+  const int bw0 = P.xend - P.xbeg;
+  const int bw1 = max(0, P.xend2 - P.xbeg2);
   for (int e = threadIdx.x; e < nkk; e += 64 * BAND_WAVES) kps[e] = kp[e];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t id = (int64_t)blockIdx.x * BAND_WAVES + (threadIdx.x >> 6);
-  if (id >= (int64_t)bw * P.ny) return;
-  const int y = (int)(id / bw);
-  const int x = P.xbeg + (int)(id - (int64_t)y * bw);
+  int64_t id = (int64_t)blockIdx.x * BAND_WAVES + (threadIdx.x >> 6);
+  int y, x;
+  if (id < (int64_t)bw0 * P.ny) {
+    y = (int)(id / bw0);
+    x = P.xbeg + (int)(id - (int64_t)y * bw0);
+  } else {
+    id -= (int64_t)bw0 * P.ny;
+    if (id >= (int64_t)bw1 * P.ny) return;
+    y = (int)(id / bw1);
+    x = P.xbeg2 + (int)(id - (int64_t)y * bw1);
+  }
   const double yh = 2.0 * (double)y / (double)(P.ny - 1) - 1.0;
   const double xh = 2.0 * (double)x / (double)(P.nx - 1) - 1.0;
   double acc = 0.0;
+#pragma unroll 4
   for (int t = lane; t < nkk; t += 64) {
     const int a = t / L2;
     const int r = t - a * L2;
     const int uy = r / L - w;
     const int ux = r - (uy + w) * L - w;
     const int sy = y - uy, sx = x - ux;
-    if (sy < 0 || sy >= P.ny || sx < 0 || sx >= P.nx) continue;
-    const int64_t o = (int64_t)sy * P.ld + sx;
+    const bool in = sy >= 0 && sy < P.ny && sx >= 0 && sx < P.nx;
+    const int64_t o = (int64_t)min(max(sy, 0), P.ny - 1) * P.ld + min(max(sx, 0), P.nx - 1);
     const double tv = is_f64 ? reinterpret_cast<const double*>(tmpl_v)[o]
                              : (double)reinterpret_cast<const float*>(tmpl_v)[o];
     double m = 1.0;
     for (int q = 0; q < P.kpx[a]; ++q) m *= xh;
     for (int q = 0; q < P.kqy[a]; ++q) m *= yh;
-    acc += kps[t] * m * tv;
+    acc += in ? kps[t] * m * tv : 0.0;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane != 0) return;
