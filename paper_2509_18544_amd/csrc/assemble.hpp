@@ -790,6 +790,7 @@ __global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, co
     col = nG + P.bpoly.px[b];
     e = P.bpoly.qy[b];
   }
+#pragma unroll 4
   for (int y = tid; y < P.ny; y += THREADS) {
     const double yh = (double)y * P.sy - 1.0;
     acc += ipow(yh, e) * mom[(int64_t)y * P.nmom + col];

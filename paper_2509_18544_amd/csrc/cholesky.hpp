@@ -422,11 +422,26 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
 }
 
 // F <- Omega for every job (grid: chunks x jobs)
+// F = Omega on and below the diagonal (no kernel reads F above it: the
+// diagonal factor loads only its lower part, the panel and trailing loads are
+// strictly below, and the upper part of a diagonal trailing tile is read but
+// never stored).  One wave per row, 16-byte copies where the row is aligned.
 __global__ __launch_bounds__(256) void copy_omega_kernel(const SolveJob* __restrict__ jobs) {
   const SolveJob J = jobs[blockIdx.y];
-  const int64_t total = (int64_t)J.n * J.n;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
-    J.F[i] = J.omega[i];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= J.n) return;
+  const int lane = threadIdx.x & 63;
+  const double* __restrict__ src = J.omega + (int64_t)i * J.n;
+  double* __restrict__ dst = J.F + (int64_t)i * J.n;
+  if ((J.n & 1) == 0) {
+    // pairs (c, c+1) with c even <= i; c + 1 <= n - 1 as n is even
+#pragma unroll 4
+    for (int c = 2 * lane; c <= i; c += 128)
+      *reinterpret_cast<double2*>(dst + c) = *reinterpret_cast<const double2*>(src + c);
+  } else {
+#pragma unroll 4
+    for (int c = lane; c <= i; c += 64) dst[c] = src[c];
+  }
 }
 
 // r = beta - Omega theta for every job (one wave per row)

@@ -686,8 +686,7 @@ int solve_jobs(hipStream_t s, const SolveJob* jobs, int njobs, int max_n, int ma
   reset_info_kernel<<<(njobs + 63) / 64, 64, 0, s>>>(jobs, njobs);
   LAUNCH_CHECK();
   {
-    const int chunks = std::min(1024, (int)(((int64_t)max_n * max_n + 255) / 256));
-    dim3 g(chunks, njobs);
+    dim3 g((max_n + 3) / 4, njobs);   // one wave per row
     copy_omega_kernel<<<g, 256, 0, s>>>(jobs);
     LAUNCH_CHECK();
   }
