@@ -416,6 +416,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
   if (row >= n) return;
   const double* a = A + (int64_t)row * n;
   double acc = 0.0;
+#pragma unroll 8
   for (int c = lane; c < n; c += 64) acc += a[c] * x[c];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) r[row] = b[row] - acc;
@@ -453,6 +454,8 @@ __global__ __launch_bounds__(256) void residual_jobs_kernel(const SolveJob* __re
   if (row >= J.n || *J.info != 0) return;
   const double* a = J.omega + (int64_t)row * J.n;
   double acc = 0.0;
+  // unrolled so that a lane keeps several row loads in flight
+#pragma unroll 8
   for (int c = lane; c < J.n; c += 64) acc += a[c] * J.theta[c];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) J.r[row] = J.beta[row] - acc;
