@@ -874,7 +874,7 @@ int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coe
     }
     const int L2 = D.L * D.L;
     double* kp = p->at<double>(Lo.kp);
-    kprime_kernel<<<(L2 + 255) / 256, 256, 0, s>>>(P, coeffs, kp);
+    kprime_kernel<<<(D.nk * L2 + 255) / 256, 256, 0, s>>>(P, coeffs, kp);
     LAUNCH_CHECK();
     const size_t lds = ((size_t)(SUB_TY + 2 * D.w) * (SUB_TX + 2 * D.w) + (size_t)D.nk * L2) * sizeof(double);
     const int bands[2][2] = {{0, xl}, {xr, D.nx}};

@@ -35,15 +35,18 @@ __device__ __forceinline__ double binom(int n, int k) {
   return r;
 }
 
+// one thread per (a', u): the nK x L^2 outputs in parallel
 __global__ void kprime_kernel(SubParams P, const double* __restrict__ theta, double* __restrict__ kp) {
   const int L = 2 * P.w + 1;
   const int L2 = L * L;
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= L2) return;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= P.nk * L2) return;
+  const int ap = id / L2;
+  const int u = id - ap * L2;
   const int uy = u / L - P.w, ux = u % L - P.w;
   const double dx = 2.0 * (double)ux / (double)(P.nx - 1);
   const double dy = 2.0 * (double)uy / (double)(P.ny - 1);
-  for (int ap = 0; ap < P.nk; ++ap) {
+  {
     const int i = P.kpx[ap], j = P.kqy[ap];
     double s = 0.0;
     for (int a = 0; a < P.nk; ++a) {
@@ -318,6 +321,7 @@ __global__ void sub_kspec_kernel(SpecParams P, const double* __restrict__ theta,
   const int twsx = TW_LOG - P.lgPx;
   const int Px = 2 * H;
   cplx<double> acc = mk(0.0, 0.0);
+#pragma unroll 4
   for (int uxi = 0; uxi < L; ++uxi) {
     const int ux = uxi - P.w;
     const double k = theta[a * L * L + uyi * L + uxi];
