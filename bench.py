@@ -3,18 +3,31 @@
 
 One step = the whole subtraction (build the normal system from FFT
 correlations, FP64 Cholesky solve with refinement, convolve-and-subtract) of
-a batch of B distinct synthetic 4088x4088 Roman-detector-like pairs in one
-batched run (the factorisation launches serve all pairs at once).  Inputs are resident in device memory before the
-timed region; the value is pairs per second over the K timed steps.
+a batch of B distinct synthetic pairs in one batched run (the factorisation
+launches serve all pairs at once).  Inputs are resident in device memory
+before the timed region; `value` is pairs per second over the K timed steps
+of the headline form (FP32C: FP32 transforms, FP64 products, lag sums,
+Cholesky and refinement), with per-stage event timing off except around the
+dominant kernel.
 
-Also reported, on the same JSON line:
-  * roofline   -- the dominant stage's algorithmic bytes (or flops) per
-                  launch over its average device time, taken live from HIP
-                  events recorded on the stream that launches it;
-  * cpu_baseline -- the CPU FP64 oracle (scipy FFTs + LAPACK Cholesky) timed
-                  on this host on one pair of the same workload;
-  * accuracy   -- relative errors of pair 0's coefficients and difference
-                  image against that oracle.
+The same JSON line also carries:
+  * step_ms        -- median, p10 and p90 of the per-step device times;
+  * graph          -- the same batch captured once and replayed as one graph
+                      launch per step;
+  * fp64           -- the plain FP64 GPU form on the same pairs;
+  * roofline       -- the dominant kernel's algorithmic flops per launch over
+                      its average device time (HIP events on the stream that
+                      launches it, over the timed region), plus the whole
+                      path against the HBM roofline and against the
+                      bandwidth a plain device copy attains on this GPU;
+  * cpu_baseline   -- the CPU FP64 oracle timed on this host (median of 3) on
+                      one pair of the workload, and on the 256^2 and 1024^2
+                      pairs, with the core count and CPU model;
+  * accuracy       -- e_theta and e_D of EVERY timed pair against the oracle
+                      (theta* stored by tests/golden/make_golden.py or solved
+                      live, D* computed by the oracle from theta*), with the
+                      maximum over pairs; `value` is null unless every pair
+                      meets the bar (1e-5 FP32C, 1e-9 FP64).
 """
 from __future__ import annotations
 
@@ -32,29 +45,150 @@ sys.path.insert(0, ROOT)
 METRIC = "4088^2 image pairs/sec subtracted at <=1e-5 rel err vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+BAR = {"f32c": 1e-5, "f64": 1e-9}
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 WORKLOADS = {
-    "c3": dict(n=4088, w=9, dk=2, db=2, seed0=3000,
-               label="4088x4088 Roman-detector pair, 19x19 delta kernel (w=9), DK=2, DB=2, "
-                     "~40000 stars, bright-star + transient masks"),
-    "c2": dict(n=1024, w=9, dk=2, db=2, seed0=1002,
-               label="1024x1024 pair, 19x19 delta kernel, DK=2, DB=2, 3000 stars, 5% saturation mask"),
-    "c1": dict(n=256, w=5, dk=1, db=1, seed0=1001,
-               label="256x256 pair, 11x11 delta kernel, DK=1, DB=1, ~400 stars"),
+    "c3": dict(seed0=3000, label="4088x4088 Roman-detector pairs, 19x19 delta kernel (w=9), DK=2, DB=2, "
+                                 "~40000 stars, bright-star + transient masks"),
+    "c2": dict(seed0=1002, label="1024x1024 pairs, 19x19 delta kernel, DK=2, DB=2, 3000 stars, 5% saturation mask"),
+    "c1": dict(seed0=1001, label="256x256 pairs, 11x11 delta kernel, DK=1, DB=1, ~400 stars"),
+    "c4": dict(seed0=4000, label="S x T = 8 x 16 uneven cutouts, N in {512,1024,2048}, w in 5..9, DK in {1,2}, DB=DK"),
 }
 
 
-def _gen(args):
-    name, seed = args
-    import synth
-    if name == "c3":
-        p = synth.pair_c3(seed=seed)
-    elif name == "c2":
-        p = synth.pair_c2(seed=seed)
-    else:
-        p = synth.pair_c1(seed=seed)
-    return p
+# ---------------------------------------------------------------------------
+# synthetic inputs (CPU worker processes, created before the GPU is touched)
+# ---------------------------------------------------------------------------
 
+def _generate(workload, i):
+    import synth
+    seed0 = WORKLOADS[workload]["seed0"]
+    if workload == "c3":
+        return synth.pair_c3(seed=seed0 + i)
+    if workload == "c2":
+        return synth.pair_c2(seed=seed0 + i)
+    if workload == "c1":
+        return synth.pair_c1(seed=seed0 + i)
+    return synth.pair_c4(synth.batch_c4_descriptors()[i])
+
+
+
+def _pin_worker(cores, counter):
+    """Pool initializer: one host core per worker process (the oracle then uses one thread)."""
+    with counter.get_lock():
+        k = counter.value
+        counter.value += 1
+    os.sched_setaffinity(0, {cores[k % len(cores)]})
+
+
+# ---------------------------------------------------------------------------
+# CPU-baseline leg: everything that runs the oracle (timing and references)
+# ---------------------------------------------------------------------------
+
+def _oracle_reference(workload, i, pair, tags):
+    """theta* and D* of one pair for each input precision in `tags` (f32in / f64),
+    from the oracle: theta* stored by the golden script (4088^2 benchmark pairs)
+    or solved live, D* = the oracle's difference image from theta*."""
+    import numpy as np
+    import oracle
+    out = {}
+    for tag in tags:
+        cast = np.float32 if tag == "f32in" else np.float64
+        s_in = pair.sci.astype(cast).astype(np.float64)
+        r_in = pair.tmpl.astype(cast).astype(np.float64)
+        theta = None
+        gpath = os.path.join(GOLDEN, f"bench_c3_theta_{tag}.npy")
+        if workload == "c3" and WORKLOADS["c3"]["seed0"] == 3000 and os.path.exists(gpath):
+            g = np.load(gpath)
+            if i < g.shape[0]:
+                theta = g[i]
+        if theta is None:
+            theta = oracle.fit(s_in, r_in, pair.mask, pair.w, pair.dk, pair.db, mode="fft")["theta"]
+        dstar = oracle.difference(s_in, r_in, theta, pair.w, pair.dk, pair.db, mode="fft")
+        out[tag] = (theta, dstar)
+    return out
+
+
+def _prepare(job):
+    workload, i, tags = job
+    p = _generate(workload, i)
+    ref = _oracle_reference(workload, i, p, tags) if tags else None
+    return p, ref
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_leg(pairs, workload, log):
+    """The oracle as it stands, timed on this host's cores: median of 3 runs
+    on pair 0 of the workload, on the 256^2 pair (FFT and direct routes) and
+    on the 1024^2 pair; plus cond(Omega) of pair 0."""
+    import numpy as np
+    import scipy
+    import oracle
+    import synth
+
+    cores = len(os.sched_getaffinity(0))
+
+    def med3(fn):
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            r = fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)), ts, r
+
+    p = pairs[0]
+    s_in = p.sci.astype(np.float32).astype(np.float64)
+    r_in = p.tmpl.astype(np.float32).astype(np.float64)
+    t_med, ts, ref = med3(lambda: oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db, mode="fft"))
+    log(f"[bench] oracle on pair 0: median {t_med:.2f}s of {[round(x, 2) for x in ts]} on {cores} cores")
+    t = time.perf_counter()
+    cond = oracle.cond_number(ref["omega"])
+    log(f"[bench] cond(Omega) of pair 0 = {cond:.3e} ({time.perf_counter() - t:.1f}s)")
+    by = {}
+    for name, gen, mode in (("256x256 (fft route)", synth.pair_c1, "fft"), ("256x256 (direct route)", synth.pair_c1, "direct"),
+                            ("1024x1024 (fft route)", synth.pair_c2, "fft")):
+        q = gen()
+        tm, tq, _ = med3(lambda: oracle.fit(q.sci, q.tmpl, q.mask, q.w, q.dk, q.db, mode=mode))
+        by[name] = dict(value=round(1.0 / tm, 4), unit="pairs/s", median_s=round(tm, 4),
+                        runs_s=[round(x, 4) for x in tq])
+        log(f"[bench] oracle {name}: median {tm:.3f}s")
+    n = p.sci.shape[0]
+    cpu = dict(value=round(1.0 / t_med, 5), unit="pairs/s", cores=cores, kind="oracle",
+               sample=f"1 pair of the workload ({n}x{n}, seed {WORKLOADS[workload]['seed0']}, float32-rounded inputs): "
+                      f"FP64 scipy.fft correlations + LAPACK Cholesky + FFT difference image; median of 3 runs",
+               median_of=3, runs_s=[round(x, 3) for x in ts], cpu_model=cpu_model(),
+               versions=dict(numpy=np.__version__, scipy=scipy.__version__), by_config=by)
+    return cpu, ref, cond
+
+
+def accuracy_of(outputs, refs, tag, bar):
+    """Relative errors of every pair's theta and D against the oracle's."""
+    import numpy as np
+    et, ed, eb = [], [], []
+    for (theta, diff), ref in zip(outputs, refs):
+        th_ref, d_ref = ref[tag]
+        et.append(float(np.linalg.norm(theta - th_ref) / np.linalg.norm(th_ref)))
+        dd = diff.astype(np.float64)
+        ed.append(float(np.linalg.norm(dd - d_ref) / np.linalg.norm(d_ref)))
+        eb.append(float(np.abs(dd - d_ref).max() / np.abs(d_ref).max()))
+    return dict(pairs=len(et), e_theta_max=max(et), e_diff_max=max(ed), e_diff_inf_max=max(eb),
+                e_theta_median=float(np.median(et)), e_diff_median=float(np.median(ed)),
+                bar=bar, all_within=bool(max(et) <= bar and max(ed) <= bar))
+
+
+# ---------------------------------------------------------------------------
+# the GPU legs
+# ---------------------------------------------------------------------------
 
 def kernel_source_hash():
     h = hashlib.sha256()
@@ -66,7 +200,7 @@ def kernel_source_hash():
 
 
 STAGE_KERNEL = {"corr": "corr_kernel", "col_fwd": "col_fwd_kernel", "row_fwd": "row_fwd_kernel",
-                "subtract": "sub_conv_kernel", "moments": "moments_kernel", "row_win": "row_win_kernel"}
+                "moments": "moments_kernel", "row_win": "row_win_kernel"}
 
 
 def measured_traffic(stage, mode, src):
@@ -84,6 +218,16 @@ def measured_traffic(stage, mode, src):
     return None
 
 
+def shape_info(p):
+    n = p.sci.shape[0]
+    P = 1 << max(6, (n - 1).bit_length())
+    nk = (p.dk + 1) * (p.dk + 2) // 2
+    nb = (p.db + 1) * (p.db + 2) // 2
+    L = 2 * p.w + 1
+    return dict(N=n, P=P, nk=nk, nb=nb, w=p.w, ncoef=L * L * nk + nb, nbase=p.dk + p.db + 3,
+                nplanes=nk + nb + 1)
+
+
 def stage_cost(stage, D, mode_f64):
     """Algorithmic amount of one launch of a stage for one pair: ("hbm", bytes) or ("alu", FP64 flops).
 
@@ -92,10 +236,10 @@ def stage_cost(stage, D, mode_f64):
     spectral products (6 flops each), one 16-point inverse DFT (168 flops) and
     8 flops per lag row kept; the pair count and lag rows follow the fit.
     """
-    n, P, H, planes, vrows = D["N"], D["P"], D["P"] // 2, D["nplanes"], D["vrows"]
+    n, P, H, planes = D["N"], D["P"], D["P"] // 2, D["nplanes"]
     s = 8 if mode_f64 else 4
     cs = 2 * s
-    nk, nb, w, L = D["nk"], D["nb"], D["w"], 2 * D["w"] + 1
+    nk, nb, w = D["nk"], D["nb"], D["w"]
     nbase = D["nbase"]
     if stage == "row_fwd":
         return "hbm", n * n * (2 * s + 1) + nbase * n * H * cs
@@ -116,18 +260,157 @@ def stage_cost(stage, D, mode_f64):
     return None, None
 
 
+def path_bytes(D, mode_f64):
+    """Algorithmic HBM bytes of one whole pair: inputs read once and D written once,
+    every spectrum (the forward planes plus the apply's one) written and read once,
+    Omega gathered, factored and read."""
+    n, P = D["N"], D["P"]
+    s = 8 if mode_f64 else 4
+    nplanes = 2 * D["nk"] + D["nb"] + 2
+    return 3 * n * n * s + n * n + 2 * nplanes * P * (P // 2 + 1) * 2 * s + 4 * D["ncoef"] ** 2 * 8
+
+
+def copy_bandwidth(torch, dev, log, gib=2, reps=10):
+    """HBM bandwidth a plain device copy attains: (read + write bytes) / time."""
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    log(f"[bench] device copy of {gib} GiB: {ms:.3f} ms -> {gbs:.0f} GB/s (read + write)")
+    del a, b
+    return gbs
+
+
+def run_leg(B, torch, pairs, mode_name, args, log):
+    """Time one precision mode on the batch; returns figures and the host copies of the outputs."""
+    import numpy as np
+    mode = B.SFFT_MODE_F64 if mode_name == "f64" else B.SFFT_MODE_F32C
+    dt = torch.float64 if mode == B.SFFT_MODE_F64 else torch.float32
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    descs = [B.make_desc(p.sci.shape[0], p.sci.shape[1], p.w, p.dk, p.db, mode) for p in pairs]
+    handle = B.sfft_batch_plan(descs, stream)
+    with torch.cuda.stream(stream):
+        S = [torch.from_numpy(p.sci).to(dev, dt) for p in pairs]
+        R = [torch.from_numpy(p.tmpl).to(dev, dt) for p in pairs]
+        M = [torch.from_numpy(p.mask).to(dev) for p in pairs]
+        Dd = [torch.empty_like(x) for x in S]
+        C = [torch.zeros(B.sfft_num_coeffs(d), dtype=torch.float64, device=dev) for d in descs]
+        info = torch.zeros(len(pairs), dtype=torch.int32, device=dev)
+    lds = [x.stride(0) for x in S]
+    stream.synchronize()
+    out = dict(mode=mode_name)
+    tuned = None
+    if not args.no_autotune:
+        tuned = B.sfft_autotune(handle, S[0], R[0], M[0], lds[0])     # plan time, outside the timed region
+        log(f"[bench] {mode_name} autotune (chunk, ms): " + ", ".join(f"({c}, {t:.3f})" for c, t in tuned))
+    out["corr_chunk_autotune"] = tuned
+
+    def step():
+        B.sfft_batch_run(handle, S, R, M, lds, C, Dd, info)
+
+    # timed region: events around the correlation kernel only, the event pool made before
+    B.sfft_timing_enable(handle, ["corr"])
+    for _ in range(args.warmup):
+        step()
+    B.sfft_timing_read(handle)                          # synchronises; drops the warm-up counts
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k].record(stream)
+        step()
+    ev[args.steps].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    corr_tot = B.sfft_timing_read(handle)["corr"]
+    B.sfft_timing_enable(handle, False)
+    st, inf, nf = B.sfft_status(handle)
+    if st != B.SFFT_OK:
+        raise RuntimeError(f"device status {B.strerror(st)} (info={inf}, nonfinite={nf})")
+    steps_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    out["value"] = len(pairs) * args.steps / elapsed
+    out["ms_per_step"] = 1000.0 * elapsed / args.steps
+    out["step_ms"] = dict(median=float(np.median(steps_ms)), p10=float(np.percentile(steps_ms, 10)),
+                          p90=float(np.percentile(steps_ms, 90)), min=float(min(steps_ms)), max=float(max(steps_ms)))
+    out["corr_ms_per_launch"] = corr_tot[0] / corr_tot[1] if corr_tot[1] else None
+    out["corr_launches"] = corr_tot[1]
+    log(f"[bench] {mode_name}: {out['value']:.2f} pairs/s, {out['ms_per_step']:.2f} ms/step "
+        f"(median {out['step_ms']['median']:.2f}), corr {out['corr_ms_per_launch']:.4f} ms x {corr_tot[1]}")
+
+    # outputs of the last timed step, to the host for the accuracy check
+    out["outputs"] = [(c.cpu().numpy(), d.cpu().numpy()) for c, d in zip(C, Dd)]
+    out["info"] = info.cpu().tolist()
+
+    # the same batch as one captured graph, replayed once per step
+    out["graph"] = None
+    if not args.no_graph:
+        B.sfft_batch_capture(handle, S, R, M, lds, C, Dd, info)
+        for _ in range(max(1, args.warmup)):
+            B.sfft_batch_launch(handle)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            B.sfft_batch_launch(handle)
+        torch.cuda.synchronize()
+        gval = len(pairs) * args.steps / (time.perf_counter() - tg)
+        # the replays recompute the same outputs: they must equal the eager ones bitwise
+        same = all(np.array_equal(c.cpu().numpy(), o[0]) and np.array_equal(d.cpu().numpy(), o[1])
+                   for c, d, o in zip(C, Dd, out["outputs"]))
+        out["graph"] = dict(value=round(gval, 3), unit="pairs/s", outputs_equal_eager=bool(same))
+        log(f"[bench] {mode_name} graph replay: {gval:.2f} pairs/s (outputs equal eager: {same})")
+
+    # stage breakdown in a separate pass (every stage timed; not part of value)
+    B.sfft_timing_enable(handle, True)
+    for _ in range(2):
+        step()
+    tot = B.sfft_timing_read(handle)
+    B.sfft_timing_enable(handle, False)
+    out["stages_ms_per_pair"] = {k: (ms / (2 * len(pairs)) if c else 0.0) for k, (ms, c) in tot.items()}
+    out["stages_avg_ms"] = {k: (ms / c if c else 0.0) for k, (ms, c) in tot.items()}
+    B.sfft_destroy(handle)
+    del S, R, M, Dd, C
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline_of(stage, D, mode_f64, ms):
+    bound, amount = stage_cost(stage, D, mode_f64)
+    if bound is None or not ms:
+        return None
+    sec = ms / 1000.0
+    if bound == "hbm":
+        ach = amount / sec / 1e9
+        return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), per_launch=amount, avg_ms=round(ms, 4))
+    ach = amount / sec / 1e12
+    return dict(bound="alu", achieved=round(ach, 2), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / FP64_VECTOR_PEAK_TFLOPS, 4), per_launch=amount, avg_ms=round(ms, 4))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32, help="distinct pairs per step (one batched run)")
-    ap.add_argument("--mode", choices=["f32c", "f64"], default="f32c")
+    ap.add_argument("--mode", choices=["f32c", "f64"], default="f32c", help="the headline form")
+    ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 comparison form")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (its timing and the accuracy check): value is then null")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default correlation chunk")
-    ap.add_argument("--graph", action="store_true",
-                    help="also time K graph replays of the batch run (reported as graph_pairs_per_s)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -136,171 +419,125 @@ def main():
               "(pairs are independent; see the sharding notes in the design document). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-
-    wl = WORKLOADS[args.workload]
+    if args.workload == "c4":
+        args.batch = min(args.batch, 128) if args.batch != 32 else 128
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    wl = WORKLOADS[args.workload]
+    legs = [args.mode] + ([] if args.no_f64 or args.mode == "f64" else ["f64"])
+    tags = [] if args.no_cpu_baseline else [("f32in" if m == "f32c" else "f64") for m in legs]
 
-    # ---- synthetic inputs (CPU, before any GPU use) ----
+    # ---- synthetic inputs and the oracle's references, in CPU worker processes
+    # created before any GPU use (each worker pinned to one host core) ----
+    import multiprocessing as mp
     t0 = time.perf_counter()
-    seeds = [wl["seed0"] + i for i in range(args.batch)]
-    workers = max(1, min(args.batch, 16, len(os.sched_getaffinity(0))))
-    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        pairs = list(ex.map(_gen, [(args.workload, s) for s in seeds]))
-    log(f"[bench] generated {len(pairs)} {args.workload} pairs in {time.perf_counter() - t0:.1f}s")
+    cores = sorted(os.sched_getaffinity(0))
+    nwork = max(1, min(args.batch, 16, len(cores)))
+    ctx = mp.get_context("fork")
+    counter = ctx.Value("i", 0)
+    with cf.ProcessPoolExecutor(max_workers=nwork, mp_context=ctx, initializer=_pin_worker,
+                                initargs=(cores, counter)) as ex:
+        res = list(ex.map(_prepare, [(args.workload, i, tags) for i in range(args.batch)]))
+    pairs = [r[0] for r in res]
+    refs = [r[1] for r in res]
+    log(f"[bench] generated {len(pairs)} {args.workload} pairs"
+        + (" with oracle references" if tags else "") + f" in {time.perf_counter() - t0:.1f}s")
 
     import numpy as np
     import torch
     from paper_2509_18544_amd import binding as B
 
-    mode = B.SFFT_MODE_F64 if args.mode == "f64" else B.SFFT_MODE_F32C
-    dt = torch.float64 if mode == B.SFFT_MODE_F64 else torch.float32
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.Stream(device=dev)
-    descs = [B.make_desc(p.sci.shape[0], p.sci.shape[1], p.w, p.dk, p.db, mode) for p in pairs]
-    handle = B.sfft_batch_plan(descs, stream)
-    S = [torch.from_numpy(p.sci).to(dev, dt) for p in pairs]
-    R = [torch.from_numpy(p.tmpl).to(dev, dt) for p in pairs]
-    M = [torch.from_numpy(p.mask).to(dev) for p in pairs]
-    Dd = [torch.empty_like(x) for x in S]
-    C = [torch.zeros(B.sfft_num_coeffs(d), dtype=torch.float64, device=dev) for d in descs]
-    info = torch.zeros(len(pairs), dtype=torch.int32, device=dev)
-    lds = [x.stride(0) for x in S]
-    torch.cuda.synchronize()
+    copy_gbs = copy_bandwidth(torch, dev, log)
+    results = {m: run_leg(B, torch, pairs, m, args, log) for m in legs}
 
-    tuned = None
-    if not args.no_autotune:
-        # plan-time tuning on pair 0 (outside the timed region)
-        tuned = B.sfft_autotune(handle, S[0], R[0], M[0], lds[0])
-        log("[bench] autotune (chunk, ms): " + ", ".join(f"({c}, {t:.3f})" for c, t in tuned))
-
-    def step():
-        B.sfft_batch_run(handle, S, R, M, lds, C, Dd, info)
-
-    graph_value = None
-    if args.graph:
-        # the same batch run captured once and replayed as one graph launch per step
-        B.sfft_batch_capture(handle, S, R, M, lds, C, Dd, info)
-        for _ in range(args.warmup):
-            B.sfft_batch_launch(handle)
-        torch.cuda.synchronize()
-        tg = time.perf_counter()
-        for _ in range(args.steps):
-            B.sfft_batch_launch(handle)
-        torch.cuda.synchronize()
-        graph_value = args.batch * args.steps / (time.perf_counter() - tg)
-        log(f"[bench] graph replay: {graph_value:.2f} pairs/s")
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    B.sfft_timing_read(handle)          # drop warm-up counters
-    B.sfft_timing_enable(handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stage_tot = B.sfft_timing_read(handle)
-    B.sfft_timing_enable(handle, False)
-    st, inf, nf = B.sfft_status(handle)
-    if st != B.SFFT_OK:
-        raise RuntimeError(f"device status {B.strerror(st)} (info={inf}, nonfinite={nf})")
-    ms_per_step = 1000.0 * elapsed / args.steps
-    value = args.batch * args.steps / elapsed
-    # per pair: the batched factor/solve stages run once per step for all pairs
-    per_pair = {}
-    for k, (ms, c) in stage_tot.items():
-        per_pair[k] = ms / (args.steps * args.batch) if c else 0.0
-    stages_avg = {k: (ms / c if c else 0.0) for k, (ms, c) in stage_tot.items()}
-    log("[bench] stage device ms per pair: " + ", ".join(f"{k}={v:.3f}" for k, v in per_pair.items()))
-
-    # ---- roofline of the dominant stage ----
-    n_px = pairs[0].sci.shape[0]
-    P = 1 << max(6, (n_px - 1).bit_length())
-    nk = (pairs[0].dk + 1) * (pairs[0].dk + 2) // 2
-    nb = (pairs[0].db + 1) * (pairs[0].db + 2) // 2
-    w = pairs[0].w
-    vrows = (nk * (nk + 1) // 2) * (4 * w + 1) + (nk * nb + nk) * (2 * w + 1)
-    ncoef = B.sfft_num_coeffs(descs[0])
-    Dinfo = dict(N=n_px, P=P, nplanes=nk + nb + 1, vrows=vrows, nk=nk, nb=nb, w=w, ncoef=ncoef,
-                 nbase=pairs[0].dk + pairs[0].db + 3)
-    # dominant kernel: among the stages that are one kernel per pair (the factor/solve
-    # stages are batched launches of many kernels, the subtraction is six kernels)
-    dom = max((k for k in stages_avg if k in STAGE_KERNEL and k != "subtract"), key=lambda k: per_pair[k])
-    def roof_of(stage):
-        bound, amount = stage_cost(stage, Dinfo, mode == B.SFFT_MODE_F64)
-        # batched stages run once per step for all pairs: price them per pair
-        ms = per_pair.get(stage, 0.0) if stage in ("factor", "solve") else stages_avg.get(stage, 0.0)
-        if bound is None or ms <= 0:
-            return None
-        sec = ms / 1000.0
-        if bound == "hbm":
-            ach = amount / sec / 1e9
-            return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(ach / HBM_PEAK_GBS, 4), per_launch=amount, avg_ms=round(ms, 4))
-        ach = amount / sec / 1e12
-        return dict(bound="alu", achieved=round(ach, 2), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(ach / FP64_VECTOR_PEAK_TFLOPS, 4), per_launch=amount, avg_ms=round(ms, 4))
-
-    roof = roof_of(dom)
-    if roof is not None:
-        src = kernel_source_hash()
-        roof.update(kernel=dom, traffic=measured_traffic(dom, args.mode, src), src=src)
-    stage_roofs = {k: roof_of(k) for k in stages_avg if roof_of(k) is not None}
-
-    # ---- accuracy of pair 0 and the CPU baseline (the oracle itself) ----
-    theta_gpu = C[0].cpu().numpy()
-    diff_gpu = Dd[0].cpu().numpy().astype(np.float64)
-    cpu = None
-    acc = None
+    # ---- CPU baseline and accuracy (the oracle) ----
+    cpu = cond = None
+    acc = {}
     if not args.no_cpu_baseline:
-        import oracle
-        cores = len(os.sched_getaffinity(0))
-        p = pairs[0]
-        # the oracle sees exactly the values the GPU saw (float32 inputs upcast in FP32C mode)
-        s_in = S[0].cpu().numpy().astype(np.float64)
-        r_in = R[0].cpu().numpy().astype(np.float64)
-        t1 = time.perf_counter()
-        ref = oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db, mode="fft")
-        cpu_s = time.perf_counter() - t1
-        cpu = dict(value=round(1.0 / cpu_s, 5), unit="pairs/s", cores=cores, kind="oracle",
-                   sample=f"1 pair of the workload (seed {seeds[0]}): FP64 scipy.fft correlations + "
-                          f"LAPACK Cholesky + FFT difference image, {cpu_s:.1f} s")
-        acc = dict(e_theta=oracle.rel_err(theta_gpu, ref["theta"]),
-                   e_diff=oracle.rel_err(diff_gpu, ref["diff"]))
-        acc["within_1e-5"] = bool(acc["e_theta"] <= 1e-5 and acc["e_diff"] <= 1e-5)
-        log(f"[bench] oracle {cpu_s:.1f}s on {cores} cores; e_theta={acc['e_theta']:.2e} "
-            f"e_diff={acc['e_diff']:.2e}")
+        cpu, ref0, cond = cpu_baseline_leg(pairs, args.workload, log)
+        for m in legs:
+            tag = "f32in" if m == "f32c" else "f64"
+            acc[m] = accuracy_of(results[m]["outputs"], refs, tag, BAR[m])
+            acc[m]["failed_pairs"] = [i for i, v in enumerate(results[m]["info"]) if v != 0]
+            log(f"[bench] {m} accuracy over {acc[m]['pairs']} pairs: max e_theta={acc[m]['e_theta_max']:.2e} "
+                f"max e_D={acc[m]['e_diff_max']:.2e} (bar {BAR[m]:g})")
+        if "f32c" in legs and args.workload == "c3" and not args.no_cpu_baseline:
+            # the stored theta* of pair 0 must be what the oracle computes now
+            g = refs[0]["f32in"][0]
+            acc["f32c"]["golden_vs_live_theta"] = float(np.linalg.norm(g - ref0["theta"]) / np.linalg.norm(ref0["theta"]))
 
+    head = results[args.mode]
+    D = shape_info(pairs[0])
+    mode_f64 = args.mode == "f64"
+    uniform = len({(p.sci.shape, p.w, p.dk, p.db) for p in pairs}) == 1
+    # per-launch flops depend on the pair's shape: priced only for a uniform batch
+    roof = roofline_of("corr", D, mode_f64, head["corr_ms_per_launch"]) if uniform else None
+    src = kernel_source_hash()
+    if roof is not None:
+        roof.update(kernel="corr_kernel", traffic=measured_traffic("corr", args.mode, src), src=src,
+                    launches_timed=head["corr_launches"])
+    value = head["value"]
+    ok = (not args.no_cpu_baseline) and acc[args.mode]["all_within"] and not acc[args.mode]["failed_pairs"]
+    path = None
+    if uniform:
+        bpp = path_bytes(D, mode_f64)
+        path = dict(bytes_per_pair=bpp, roofline_pairs_per_s=round(HBM_PEAK_GBS * 1e9 / bpp, 1),
+                    frac=round(value / (HBM_PEAK_GBS * 1e9 / bpp), 4),
+                    attainable_gbs=round(copy_gbs, 1),
+                    frac_of_attainable=round(value / (copy_gbs * 1e9 / bpp), 4))
+    mpx = sum(p.sci.shape[0] * p.sci.shape[1] for p in pairs) / len(pairs) / 1e6
+    fp64 = None
+    if "f64" in results and args.mode != "f64":
+        r = results["f64"]
+        fp64 = dict(value=round(r["value"], 3) if (args.no_cpu_baseline or acc["f64"]["all_within"]) else None,
+                    measured=round(r["value"], 3), unit="pairs/s", ms_per_step=round(r["ms_per_step"], 3),
+                    step_ms={k: round(v, 3) for k, v in r["step_ms"].items()}, graph=r["graph"],
+                    corr_ms_per_launch=r["corr_ms_per_launch"], accuracy=acc.get("f64"),
+                    stages_ms_per_pair={k: round(v, 4) for k, v in r["stages_ms_per_pair"].items()})
+        if uniform:
+            bpp64 = path_bytes(D, True)
+            fp64["path_roofline"] = dict(bytes_per_pair=bpp64, frac=round(r["value"] / (HBM_PEAK_GBS * 1e9 / bpp64), 4))
+    stage_roofs = {}
+    for k, ms in head["stages_avg_ms"].items():
+        per = head["stages_ms_per_pair"].get(k, 0.0) if k in ("factor", "solve") else ms
+        rr = roofline_of(k, D, mode_f64, per) if uniform else None
+        if rr:
+            stage_roofs[k] = {kk: rr[kk] for kk in ("bound", "frac", "achieved", "unit")}
+    config = {"workload": wl["label"] + f"; {args.mode.upper()} mode; batch of {args.batch} distinct pairs per step "
+                                       f"(one batched run)",
+              "global_batch": args.batch, "frame": D["N"] if uniform else "mixed", "fft_size": D["P"] if uniform else "= N",
+              "coefficients": D["ncoef"] if uniform else "mixed",
+              "corr_chunk_autotune": head["corr_chunk_autotune"]}
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(value, 3) if ok else None,
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if mode == B.SFFT_MODE_F64 else "f32+f64",
+        "dtype": "f64" if mode_f64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wl["label"] + f"; {args.mode.upper()} mode; batch of {args.batch} "
-                                             f"distinct pairs per step (one batched run)",
-                   "global_batch": args.batch, "frame": n_px, "fft_size": P, "coefficients": ncoef,
-                   "corr_chunk_autotune": tuned},
+        "config": config,
         "roofline": roof,
         "cpu_baseline": cpu,
-        "accuracy": acc,
-        "stages_ms_per_pair": {k: round(v, 4) for k, v in per_pair.items()},
-        "graph_pairs_per_s": None if graph_value is None else round(graph_value, 3),
-        "stage_rooflines": {k: {"bound": v["bound"], "frac": v["frac"], "achieved": v["achieved"],
-                                "unit": v["unit"]} for k, v in stage_roofs.items()},
+        "measured_value": round(value, 3),
+        "accuracy": acc.get(args.mode),
+        "cond_omega_pair0": cond,
+        "step_ms": {k: round(v, 3) for k, v in head["step_ms"].items()},
+        "graph": head["graph"],
+        "megapixels_per_s": round(value * mpx, 2),
+        "path_roofline": path,
+        "attainable_hbm_gbs": round(copy_gbs, 1),
+        "fp64": fp64,
+        "stages_ms_per_pair": {k: round(v, 4) for k, v in head["stages_ms_per_pair"].items()},
+        "stage_rooflines": stage_roofs,
     }
     print(json.dumps(out), flush=True)
-    B.sfft_destroy(handle)
 
 
 if __name__ == "__main__":

@@ -97,8 +97,11 @@ int sfft_workspace_bytes(const sfft_desc* d, size_t* bytes);
 /* Create a plan bound to `hip_stream` (a hipStream_t, NULL = default stream).
  * `workspace` NULL: the plan allocates (and frees in sfft_destroy) its own
  * device memory; otherwise it borrows `workspace_bytes` bytes of caller
- * device memory, which must hold sfft_workspace_bytes() (else SFFT_ENOMEM).
- * Twiddle tables are computed in FP64 on the host and uploaded. */
+ * device memory, 256-byte aligned (else SFFT_EINVAL), which must hold
+ * sfft_workspace_bytes() (else SFFT_ENOMEM); its contents on entry do not
+ * matter and the plan writes nothing outside it.  Both checks happen before
+ * any device call.  Twiddle tables are computed in FP64 on the host and
+ * uploaded; the call synchronises the stream. */
 int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t workspace_bytes,
               sfft_handle* out);
 
@@ -162,10 +165,16 @@ enum {
   SFFT_NUM_STAGES = 9
 };
 
-/* Enable (1) or disable (0) HIP-event timing of every stage enqueued on the
- * plan's stream from now on.  Events are recorded on that stream around each
- * stage, so the numbers are device time of that stage alone. */
-int sfft_timing_enable(sfft_handle p, int enable);
+/* HIP-event timing of the stages in `stage_mask` (bit s = stage s; 0 turns
+ * timing off, SFFT_TIMING_ALL times every stage) enqueued on the plan's
+ * stream from now on.  Events are recorded on that stream around each timed
+ * stage, so the numbers are device time of that stage alone.  Enabling
+ * creates SFFT_TIMING_RESERVE event pairs per timed stage (per pair of a
+ * batch) up front, so that no event is created while the timed work runs
+ * as long as sfft_timing_read is called at least every SFFT_TIMING_RESERVE
+ * executions of a stage.  Bits past the last stage: SFFT_EINVAL. */
+enum { SFFT_TIMING_ALL = (1 << SFFT_NUM_STAGES) - 1, SFFT_TIMING_RESERVE = 32 };
+int sfft_timing_enable(sfft_handle p, int stage_mask);
 
 /* Synchronise the plan's stream and return, per stage, the total milliseconds
  * and the number of timed executions since the last read (host arrays of
@@ -183,16 +192,20 @@ int sfft_timing_read(sfft_handle p, double* ms, int64_t* count);
 /* Device bytes of a batch plan for `npairs` descriptors. Host only. */
 int sfft_batch_workspace_bytes(const sfft_desc* descs, int32_t npairs, size_t* bytes);
 
-/* Create a batch plan (allocates its workspace) bound to `hip_stream`.  Single-
- * pair calls on a batch handle return SFFT_EINVAL; sfft_status, sfft_timing_*
- * and sfft_destroy accept it. */
+/* Create a batch plan (allocates its workspace) bound to `hip_stream`.  Every
+ * descriptor must ask for the same number of refinement steps (one batched
+ * solve runs them for all pairs), else SFFT_EINVAL.  Single-pair calls on a
+ * batch handle return SFFT_EINVAL; sfft_status, sfft_timing_* and
+ * sfft_destroy accept it. */
 int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sfft_handle* out);
 
 /* Enqueue build + solve + subtract for every pair.  sci, tmpl, mask, ld,
  * coeffs, diff: HOST arrays of npairs entries holding DEVICE pointers (mask
  * array or entries may be NULL) and row pitches; info: device int32[npairs]
  * (may be NULL), LAPACK-style per pair, and a failed pair does not affect
- * the others. */
+ * the others.  A pair whose factorisation failed (info > 0) keeps its
+ * coeffs untouched, and its diff is then computed from those untouched
+ * coefficients: it is undefined as a result and must be discarded. */
 int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
                    const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info);
 

@@ -368,25 +368,35 @@ def beta_entries(sci, tmpl, mask, w, dk, db, rows):
 
 
 def difference_at(sci, tmpl, theta, w, dk, db, ys, xs):
-    """D at the pixels (ys[i], xs[i]) by the explicit sum over kernel taps and background terms."""
+    """D at the pixels (ys[i], xs[i]) by the explicit sum over kernel taps and background terms.
+
+    Per pixel z: D(z) = S(z) - sum_{a,u} k_{a,u} m_a(z - u) R(z - u) - sum_b c_b m_b(z), the sum
+    running over the taps whose source pixel z - u lies in the frame (the sum over taps of one
+    pixel is done with numpy on the L x L source window, flipped so that tap u meets z - u).
+    """
     sci = np.asarray(sci, dtype=np.float64)
     tmpl = np.asarray(tmpl, dtype=np.float64)
     ny, nx = sci.shape
     k, c = _split_theta(theta, w, dk, db)
     xh, yh = frame_coords(ny, nx)
+    kexp = monomial_exponents(dk)
+    bexp = monomial_exponents(db)
     out = []
     for y, x in zip(ys, xs):
+        y, x = int(y), int(x)
+        # taps u with 0 <= y - u_y < ny and 0 <= x - u_x < nx
+        uy_lo, uy_hi = max(-w, y - ny + 1), min(w, y)
+        ux_lo, ux_hi = max(-w, x - nx + 1), min(w, x)
         acc = 0.0
-        for a, (p, q) in enumerate(monomial_exponents(dk)):
-            for uy in range(-w, w + 1):
-                sy = y - uy
-                if not 0 <= sy < ny:
-                    continue
-                for ux in range(-w, w + 1):
-                    sx = x - ux
-                    if 0 <= sx < nx:
-                        acc += k[a, uy + w, ux + w] * xh[sx] ** p * yh[sy] ** q * tmpl[sy, sx]
-        for b, (p, q) in enumerate(monomial_exponents(db)):
+        if uy_lo <= uy_hi and ux_lo <= ux_hi:
+            sy = y - np.arange(uy_lo, uy_hi + 1)          # source rows, one per tap u_y
+            sx = x - np.arange(ux_lo, ux_hi + 1)
+            rwin = tmpl[np.ix_(sy, sx)]
+            for a, (p, q) in enumerate(kexp):
+                wgt = np.outer(yh[sy] ** q, xh[sx] ** p)
+                ka = k[a, uy_lo + w:uy_hi + w + 1, ux_lo + w:ux_hi + w + 1]
+                acc += float(np.sum(ka * wgt * rwin))
+        for b, (p, q) in enumerate(bexp):
             acc += c[b] * xh[x] ** p * yh[y] ** q
         out.append(sci[y, x] - acc)
     return np.array(out)

@@ -14,8 +14,8 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SFFT_LIBRARY may name another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("SFFT_LIBRARY") or os.path.join(_HERE, "_lib", "libsfft.so")
+# always the in-tree build (python -m paper_2509_18544_amd.build); no override
+LIB_PATH = os.path.join(_HERE, "_lib", "libsfft.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "sfft.h")
 
 SFFT_OK = 0
@@ -187,8 +187,20 @@ def sfft_status(handle):
 STAGES = ("moments", "row_fwd", "col_fwd", "corr", "row_win", "gather", "factor", "solve", "subtract")
 
 
-def sfft_timing_enable(handle, enable: bool = True):
-    _check(lib().sfft_timing_enable(handle, 1 if enable else 0), "sfft_timing_enable")
+SFFT_TIMING_ALL = (1 << 9) - 1
+
+
+def sfft_timing_enable(handle, stages=True):
+    """stages: True (every stage), False (off), or an iterable of stage names."""
+    if stages is True:
+        mask = SFFT_TIMING_ALL
+    elif stages is False or stages is None:
+        mask = 0
+    else:
+        mask = 0
+        for name in stages:
+            mask |= 1 << STAGES.index(name)
+    _check(lib().sfft_timing_enable(handle, int(mask)), "sfft_timing_enable")
 
 
 def sfft_timing_read(handle):

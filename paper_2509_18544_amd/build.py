@@ -25,6 +25,10 @@ FLAGS = [
 ]
 
 
+# roctx ranges around the ABI calls and stages (shown by rocprofv3 --marker-trace)
+LIBS = ["-lrocprofiler-sdk-roctx"]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -35,7 +39,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, *(os.path.join(CSRC, f) for f in SOURCES), "-o", tmp]
+    cmd = [hipcc(), *FLAGS, *(os.path.join(CSRC, f) for f in SOURCES), *LIBS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -346,6 +346,9 @@ constexpr int CORR_LB = 8;   // staging loads in flight per thread
 __host__ __device__ constexpr int corr_plane_stride(int c1) {
   return ((c1 * CORR_RS + 12) & ~15) + 3;
 }
+// complex elements reserved at the start of the correlation kernel's LDS for
+// the per-chunk twiddle steps (njlo x JMAX), rounded up to 256 bytes
+__host__ __device__ constexpr int corr_step_elems(int njlo) { return (njlo * JMAX + 15) & ~15; }
 
 template <int S>
 __device__ __forceinline__ void corr_accumulate(cplx<double>* acc, const cplx<double>* f,
@@ -361,7 +364,11 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
                                                        cplx<double>* __restrict__ V,
                                                        const cplx<double>* __restrict__ twd, int C1) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<double>* stage = reinterpret_cast<cplx<double>*>(smem_raw);
+  // LDS: [twstep: njlo x JMAX] [stage: spectra, then the chunk's outer twiddles].
+  // The lane reduction at the end of a pass of items overlays the stage only,
+  // so the steps survive into the next pass.
+  cplx<double>* twstep = reinterpret_cast<cplx<double>*>(smem_raw);   // [njlo][JMAX]
+  cplx<double>* stage = twstep + corr_step_elems(P.njlo);
   const int kx = blockIdx.x;
   const int H = P.H;
   const int Py = 1 << P.lgPy;
@@ -376,7 +383,6 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
   const int per_plane = corr_plane_stride(C1);
   // outer twiddles e^{2 pi i k1 (jlo + t)/Py} of the chunk, per distinct jlo, after the spectra
   cplx<double>* twc = stage + P.nplanes * per_plane;       // [njlo][C1][JMAX]
-  cplx<double>* twstep = twc + P.njlo * C1 * JMAX;           // [njlo][JMAX]
   // e^{2 pi i C1 j / Py}: advancing k1 by one chunk multiplies each outer twiddle by it
   for (int e = tid; e < P.njlo * JMAX; e += THREADS) {
     const int ji = e / JMAX, t = e - ji * JMAX;
@@ -480,7 +486,8 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
       }
     }
     // sum the lanes of each item through LDS, in two halves of the lag rows
-    cplx<double>* red = reinterpret_cast<cplx<double>*>(smem_raw);
+    // (over the staged spectra, which are dead until the next pass restages them)
+    cplx<double>* red = stage;
     constexpr int HALF = (JMAX + 1) / 2;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {

@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/sfft.h"
 #include "assemble.hpp"
 #include "cholesky.hpp"
@@ -391,15 +393,31 @@ void twiddle_tables(std::vector<cplx<double>>* t64, std::vector<cplx<float>>* t3
 
 }  // namespace
 
+// roctx range over a scope (host-side enqueue of an ABI call or a stage), so
+// that a marker trace shows which kernels each call and stage launched.
+struct RoctxScope {
+  explicit RoctxScope(const char* name) { roctxRangePushA(name); }
+  ~RoctxScope() { roctxRangePop(); }
+  RoctxScope(const RoctxScope&) = delete;
+  RoctxScope& operator=(const RoctxScope&) = delete;
+};
+
+namespace {
+const char* const kStageNames[SFFT_NUM_STAGES] = {"moments", "row_fwd", "col_fwd", "corr", "row_win",
+                                                  "gather", "factor", "solve", "subtract"};
+}
+
 // Optional per-stage device timing with events recorded on the plan's stream.
 struct StageTimer {
   bool on = false;
+  unsigned mask = 0;   // stages timed while on (bit s = stage s)
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[SFFT_NUM_STAGES];
   double ms[SFFT_NUM_STAGES] = {};
   int64_t cnt[SFFT_NUM_STAGES] = {};
   hipEvent_t open_ev = nullptr;
   int open_stage = -1;
+  bool ranged = false;   // a roctx range is open for the current stage
 
   hipEvent_t take() {
     if (!pool.empty()) {
@@ -411,13 +429,28 @@ struct StageTimer {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
   }
+  // keep at least n events ready so that timing does not create any while enabled
+  void reserve(size_t n) {
+    while (pool.size() < n) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      pool.push_back(e);
+    }
+  }
   void begin(int st, hipStream_t s) {
-    if (!on) return;
+    if (ranged) roctxRangePop();   // a stage left by an error return
+    roctxRangePushA(kStageNames[st]);
+    ranged = true;
+    if (!on || ((mask >> st) & 1u) == 0) return;
     open_ev = take();
     open_stage = st;
     if (open_ev) (void)hipEventRecord(open_ev, s);
   }
   void end(hipStream_t s) {
+    if (ranged) {
+      roctxRangePop();
+      ranged = false;
+    }
     if (!on || open_stage < 0) return;
     hipEvent_t e = take();
     if (open_ev && e) {
@@ -536,20 +569,23 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
 
 // Residue chunk of the correlation kernel: the spectra of C1 residues of every
 // plane (FP64, padded) and their outer twiddles are staged in LDS per chunk.
+// Layout: the twiddle steps, then the larger of the stage (spectra and the
+// chunk's outer twiddles) and the lane-reduction buffer that overlays it.
 size_t corr_lds_bytes(const Derived& D, int C1) {
-  const size_t stage =
-      ((size_t)D.nplanes * corr_plane_stride(C1) + (size_t)D.njlo * (C1 + 1) * JMAX) * sizeof(cplx<double>);
+  const size_t steps = (size_t)corr_step_elems(D.njlo) * sizeof(cplx<double>);
+  const size_t stage = ((size_t)D.nplanes * corr_plane_stride(C1) + (size_t)D.njlo * C1 * JMAX) * sizeof(cplx<double>);
   const size_t red = (size_t)ASM_THREADS * ((JMAX + 1) / 2) * sizeof(cplx<double>);
-  return std::max(stage, red);
+  return steps + std::max(stage, red);
 }
 
-// Default chunk: the largest multiple of the item lanes whose stage fits 74 KB
+// Default chunk: the largest multiple of the item lanes whose LDS fits 80 KB
 // (two blocks per CU); sfft_autotune may pick another.
 int corr_default_c1(const Derived& D) {
   const int P1 = D.Py / P2;
   const int lanes = D.corr_lanes;
-  const size_t per_res = (size_t)D.nplanes * CORR_RS * sizeof(cplx<double>) + (size_t)D.njlo * JMAX * sizeof(cplx<double>);
-  int C1 = (int)std::min<size_t>((size_t)P1, (74 * 1024) / per_res);
+  constexpr size_t budget = 80 * 1024;
+  int C1 = P1;
+  while (C1 > 1 && corr_lds_bytes(D, C1) > budget) --C1;
   if (C1 >= lanes) C1 = (C1 / lanes) * lanes;   // whole rounds of the item lanes
   return std::max(C1, 1);
 }
@@ -960,6 +996,7 @@ int sfft_workspace_bytes(const sfft_desc* d, size_t* bytes) {
 }
 
 int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t workspace_bytes, sfft_handle* out) {
+  RoctxScope range_("sfft_plan");
   if (out == nullptr) return SFFT_EINVAL;
   *out = nullptr;
   sfft_plan_s* p = new (std::nothrow) sfft_plan_s();
@@ -974,6 +1011,10 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
   p->stream = reinterpret_cast<hipStream_t>(hip_stream);
   p->built = false;
   if (workspace != nullptr) {
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {   // the carve-up keeps 256-byte alignment
+      delete p;
+      return SFFT_EINVAL;
+    }
     if (workspace_bytes < p->Lo.total) {
       delete p;
       return SFFT_ENOMEM;
@@ -1018,6 +1059,7 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
 }
 
 int sfft_build_system(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld) {
+  RoctxScope range_("sfft_build_system");
   if (p == nullptr || p->is_batch || sci == nullptr || tmpl == nullptr || ld < p->D.nx) return SFFT_EINVAL;
   int st;
   if (p->D.mode == SFFT_MODE_F64)
@@ -1041,6 +1083,7 @@ int sfft_get_system(sfft_handle p, double* omega, double* rhs) {
 }
 
 int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
+  RoctxScope range_("sfft_solve");
   if (p == nullptr || coeffs == nullptr || p->is_batch) return SFFT_EINVAL;
   if (!p->built) return SFFT_ESTATE;
   const Derived& D = p->D;
@@ -1054,6 +1097,7 @@ int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
 }
 
 int sfft_residual(sfft_handle p, const double* coeffs, double* rho) {
+  RoctxScope range_("sfft_residual");
   if (p == nullptr || p->is_batch || coeffs == nullptr || rho == nullptr) return SFFT_EINVAL;
   if (!p->built) return SFFT_ESTATE;
   const Derived& D = p->D;
@@ -1068,6 +1112,7 @@ int sfft_residual(sfft_handle p, const double* coeffs, double* rho) {
 }
 
 int sfft_fit_background(sfft_handle p, double* coeffs) {
+  RoctxScope range_("sfft_fit_background");
   if (p == nullptr || p->is_batch || coeffs == nullptr) return SFFT_EINVAL;
   if (!p->built) return SFFT_ESTATE;
   const Derived& D = p->D;
@@ -1079,6 +1124,7 @@ int sfft_fit_background(sfft_handle p, double* coeffs) {
 }
 
 int sfft_subtract(sfft_handle p, const void* sci, const void* tmpl, const double* coeffs, void* diff, int64_t ld) {
+  RoctxScope range_("sfft_subtract");
   if (p == nullptr || p->is_batch || sci == nullptr || tmpl == nullptr || coeffs == nullptr || diff == nullptr || ld < p->D.nx)
     return SFFT_EINVAL;
   if (p->D.mode == SFFT_MODE_F64)
@@ -1108,10 +1154,18 @@ int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out) {
   return SFFT_OK;
 }
 
-int sfft_timing_enable(sfft_handle p, int enable) {
-  if (p == nullptr) return SFFT_EINVAL;
-  p->timer.on = enable != 0;
-  for (sfft_plan_s* m : p->members) m->timer.on = enable != 0;
+int sfft_timing_enable(sfft_handle p, int stage_mask) {
+  if (p == nullptr || (stage_mask & ~SFFT_TIMING_ALL) != 0) return SFFT_EINVAL;
+  const unsigned m = (unsigned)stage_mask;
+  int timed = 0;
+  for (int st = 0; st < SFFT_NUM_STAGES; ++st) timed += (m >> st) & 1u;
+  auto setup = [&](StageTimer& t) {
+    t.on = m != 0;
+    t.mask = m;
+    if (m != 0) t.reserve((size_t)timed * 2 * SFFT_TIMING_RESERVE);
+  };
+  setup(p->timer);
+  for (sfft_plan_s* q : p->members) setup(q->timer);
   return SFFT_OK;
 }
 
@@ -1167,11 +1221,16 @@ int sfft_batch_workspace_bytes(const sfft_desc* descs, int32_t npairs, size_t* b
 }
 
 int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sfft_handle* out) {
+  RoctxScope range_("sfft_batch_plan");
   if (out == nullptr || descs == nullptr || npairs <= 0) return SFFT_EINVAL;
   *out = nullptr;
   for (int i = 0; i < npairs; ++i) {
     const int st = validate(&descs[i]);
     if (st != SFFT_OK) return st;
+    // the batched solve runs one refinement schedule for every pair
+    const int r0 = descs[0].refine_steps < 0 ? 1 : descs[0].refine_steps;
+    const int ri = descs[i].refine_steps < 0 ? 1 : descs[i].refine_steps;
+    if (ri != r0) return SFFT_EINVAL;
   }
   sfft_plan_s* b = new (std::nothrow) sfft_plan_s();
   if (b == nullptr) return SFFT_ENOMEM;
@@ -1210,6 +1269,7 @@ int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sf
 
 int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
                    const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info) {
+  RoctxScope range_("sfft_batch_run");
   if (b == nullptr || !b->is_batch || sci == nullptr || tmpl == nullptr || ld == nullptr || coeffs == nullptr ||
       diff == nullptr)
     return SFFT_EINVAL;
@@ -1242,6 +1302,7 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
 
 int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld, int32_t* c1_out,
                   float* ms_out, int32_t cap, int32_t* count_out) {
+  RoctxScope range_("sfft_autotune");
   if (p == nullptr || sci == nullptr || tmpl == nullptr || cap < 0) return SFFT_EINVAL;
   if (cap > 0 && (c1_out == nullptr || ms_out == nullptr)) return SFFT_EINVAL;
   if (p->is_batch && p->members.empty()) return SFFT_EINVAL;
@@ -1310,6 +1371,7 @@ int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_
 
 int sfft_batch_capture(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
                        const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info) {
+  RoctxScope range_("sfft_batch_capture");
   if (b == nullptr || !b->is_batch || b->stream == nullptr) return SFFT_EINVAL;
   if (b->gexec != nullptr) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph != nullptr) (void)hipGraphDestroy(b->graph);
@@ -1346,6 +1408,7 @@ int sfft_batch_capture(sfft_handle b, const void* const* sci, const void* const*
 }
 
 int sfft_batch_launch(sfft_handle b) {
+  RoctxScope range_("sfft_batch_launch");
   if (b == nullptr || !b->is_batch) return SFFT_EINVAL;
   if (b->gexec == nullptr) return SFFT_ESTATE;
   HIP_TRY(hipGraphLaunch(b->gexec, b->stream));

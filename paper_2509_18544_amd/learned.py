@@ -286,7 +286,11 @@ class WarmStart:
         return coeffs
 
     def subtract(self, plan, sci, tmpl, mask, feats, diff=None):
-        """Returns (coeffs, diff, rho, used_guess)."""
+        """Returns (coeffs, diff, rho, used_guess).
+
+        Raises SfftError (SFFT_ENOTSPD / SFFT_ENONFINITE) when the guess is
+        rejected and the fallback solve fails too: the rejected guess is never
+        used for the difference image."""
         plan.build(sci, tmpl, mask)
         coeffs = self.coefficients(plan, feats)
         rho = float(plan.residual(coeffs).item())        # synchronises
@@ -295,6 +299,9 @@ class WarmStart:
         if not used:
             self.fallbacks += 1
             plan.solve(coeffs)
+            st, info, nonfinite = plan.status()          # synchronises
+            if st != B.SFFT_OK:
+                raise B.SfftError(st, f"fallback solve (info={info}, nonfinite={nonfinite})")
         diff = plan.subtract(sci, tmpl, coeffs, diff)
         return coeffs, diff, rho, used
 

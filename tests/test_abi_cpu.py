@@ -82,3 +82,19 @@ def test_mlp_create_rejects_bad_shapes(dims, nl, max_batch):
     h = ctypes.c_void_p(0)
     st = B.lib().sfft_mlp_create(arr, nl, max_batch, None, ctypes.byref(h))
     assert st == B.SFFT_EINVAL and not h.value
+
+
+def test_caller_workspace_too_small_is_enomem():
+    """sfft_plan with a caller workspace smaller than sfft_workspace_bytes returns
+    SFFT_ENOMEM before touching the device (the pointer is never dereferenced)."""
+    d = B.make_desc(256, 256, 5, 1, 1, B.SFFT_MODE_F32C)
+    need = B.sfft_workspace_bytes(d)
+    h = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x100000)
+    for have in (0, 1, need - 1):
+        st = B.lib().sfft_plan(ctypes.byref(d), None, fake, have, ctypes.byref(h))
+        assert st == B.SFFT_ENOMEM and not h.value
+
+    # a misaligned workspace is rejected first
+    st = B.lib().sfft_plan(ctypes.byref(d), None, ctypes.c_void_p(0x100010), need, ctypes.byref(h))
+    assert st == B.SFFT_EINVAL and not h.value

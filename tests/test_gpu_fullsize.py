@@ -6,8 +6,12 @@ The oracle cannot rebuild the whole 2172 x 2172 system here in seconds, so:
     calls only the oracle);
   * Omega and beta are compared on sampled entries computed one by one from
     the definition (full-frame dot products of two design-matrix columns);
-  * D is compared on sampled pixels (interior, frame borders, corners, masked
-    pixels) computed one by one from theta* by the explicit sum.
+  * D is compared over the whole frame with D* = the oracle's FFT difference
+    image from theta*, both as the relative 2-norm error (the target's metric)
+    and restricted to the w-wide border band (whose columns next to the frame
+    edge a separate kernel writes), with a per-pixel max error there; and on
+    sampled pixels (interior, frame borders, corners, masked pixels) computed
+    one by one from theta* by the explicit sum.
 """
 import os
 
@@ -81,7 +85,33 @@ def test_c3_full_size(c3, mode):
     d_got = res["diff"][ys, xs]
     ed = np.linalg.norm(d_got - d_ref) / np.linalg.norm(d_ref)
     assert ed <= tol, f"e_D (sampled) {ed:.3e}"
-    print(f"C3 mode={mode} e_theta={et:.3e} e_D(sampled)={ed:.3e}")
+
+    # whole frame against the oracle's difference image from theta*
+    d_full = oracle.difference(s_in, r_in, theta_ref, p.w, p.dk, p.db, mode="fft")
+    ed_full = oracle.rel_err(res["diff"], d_full)
+    assert ed_full <= tol, f"e_D (whole frame) {ed_full:.3e}"
+    # the w-wide border band on all four sides
+    ny, nx = p.sci.shape
+    band = np.zeros((ny, nx), dtype=bool)
+    band[:p.w, :] = band[ny - p.w:, :] = band[:, :p.w] = band[:, nx - p.w:] = True
+    ed_band = oracle.rel_err(res["diff"][band], d_full[band])
+    assert ed_band <= tol, f"e_D (border band) {ed_band:.3e}"
+    # per pixel: |D - D*| against the local scale |S| + rms(D*) (bright stars carry
+    # proportionally larger absolute errors); the band must be no worse than the frame
+    scale = np.abs(s_in) + np.sqrt(np.mean(d_full ** 2))
+    pix = np.abs(res["diff"] - d_full) / scale
+    pix_band, pix_all = pix[band].max(), pix.max()
+    assert pix_band <= tol, f"per-pixel error in the band {pix_band:.3e}"
+    assert pix_all <= tol, f"per-pixel error in the frame {pix_all:.3e}"
+    # the pixels next to the left and right edges, one by one from the definition
+    rows = rng.integers(0, ny, 400)
+    for x in (0, 1, p.w - 1, p.w, nx - p.w - 1, nx - p.w, nx - 2, nx - 1):
+        got = res["diff"][rows, x]
+        ref1 = oracle.difference_at(s_in, r_in, theta_ref, p.w, p.dk, p.db, rows, np.full(rows.size, x))
+        e1 = (np.abs(got - ref1) / scale[rows, x]).max()
+        assert e1 <= tol, f"column {x}: {e1:.3e}"
+    print(f"C3 mode={mode} e_theta={et:.3e} e_D(sampled)={ed:.3e} e_D(frame)={ed_full:.3e} "
+          f"e_D(band)={ed_band:.3e} max pixel err band={pix_band:.3e} frame={pix_all:.3e}")
 
 
 @pytest.mark.parametrize("mode", [F64, F32C])

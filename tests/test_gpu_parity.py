@@ -186,9 +186,14 @@ def test_solve_before_build_and_bad_args():
 
 
 def test_native_library_is_loaded():
+    """The HIP library the tests call is the in-tree build, and it is mapped."""
+    import os
+    in_tree = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                           "paper_2509_18544_amd", "_lib", "libsfft.so")
+    assert os.path.realpath(B.LIB_PATH) == os.path.realpath(in_tree)
     B.lib()
     maps = open("/proc/self/maps").read()
-    assert B.LIB_PATH in maps
+    assert os.path.realpath(in_tree) in maps
 
 
 @pytest.mark.parametrize("mode", [F64, F32C])
@@ -270,3 +275,95 @@ def test_smallest_frames(shape, route):
     assert res["info"] == 0
     assert oracle.rel_err(res["theta"], ref["theta"]) <= 1e-9
     assert oracle.rel_err(res["diff"], ref["diff"]) <= 1e-9
+
+
+# Kernel half-widths above 9 (lag windows of 41..61 rows, several passes of
+# correlation items, the y-convolution instantiations for 10..15) and the
+# polynomial degrees 3 and 4 (10 and 15 monomials, up to 31 planes) that the
+# descriptor accepts.  The direct route takes w <= 9 only.
+WIDE = [
+    # ny, nx, w, dk, db, mask_frac, seed, routes
+    (96, 96, 10, 1, 1, 0.05, 301, (FFT_ROUTE,)),
+    (72, 80, 15, 0, 0, 0.05, 302, (FFT_ROUTE,)),
+    (100, 92, 12, 0, 2, 0.10, 303, (FFT_ROUTE,)),
+    (64, 64, 2, 4, 4, 0.10, 304, (FFT_ROUTE, DIRECT_ROUTE)),
+    (80, 76, 3, 3, 3, 0.10, 305, (FFT_ROUTE, DIRECT_ROUTE)),
+    (64, 80, 3, 4, 0, 0.05, 306, (FFT_ROUTE, DIRECT_ROUTE)),
+    (70, 70, 1, 0, 4, 0.05, 307, (FFT_ROUTE, DIRECT_ROUTE)),
+]
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+@pytest.mark.parametrize("case", WIDE)
+def test_wide_kernels_and_high_degrees(case, mode):
+    ny, nx, w, dk, db, frac, seed, routes = case
+    p = synth.random_pair(seed, ny, nx, w, dk, db, mask_frac=frac, stars=True)
+    s_in, r_in = inputs_as_seen(p, mode)
+    ref = oracle.fit(s_in, r_in, p.mask, w, dk, db, mode="direct")
+    for route in routes:
+        res = run_pair(p.sci, p.tmpl, p.mask, w, dk, db, mode=mode, flags=route)
+        et, ed = _check_against_oracle(p, mode, res, ref=ref)
+        print(f"{case[:5]} mode={mode} route={route}: e_theta={et:.2e} e_D={ed:.2e}")
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_autotune_wide_kernel_against_oracle(mode):
+    """Autotuning a w >= 10 plan (several passes of correlation items, every
+    chunk size the LDS allows) keeps Omega and theta at the oracle bar."""
+    p = synth.random_pair(311, 128, 120, 10, 1, 1, mask_frac=0.05, stars=True)
+    s_in, r_in = inputs_as_seen(p, mode)
+    dt = torch.float64 if mode == F64 else torch.float32
+    S = torch.from_numpy(s_in).to("cuda", dt)
+    R = torch.from_numpy(r_in).to("cuda", dt)
+    Mk = torch.from_numpy(p.mask).cuda()
+    ref = oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db, mode="direct")
+    plan = B.Plan(*p.sci.shape, p.w, p.dk, p.db, mode=mode, flags=FFT_ROUTE)
+    try:
+        rep = B.sfft_autotune(plan.handle, S, R, Mk, S.stride(0))
+        assert len(rep) >= 2
+        chosen = min(rep, key=lambda cm: cm[1])[0]
+        print(f"mode={mode}: candidates {rep}, chosen {chosen}")
+        plan.build(S, R, Mk)
+        om, be = plan.system()
+        c, info = plan.solve()
+        d = plan.subtract(S, R, c)
+        st, inf, nf = plan.status()
+        res = dict(omega=om.cpu().numpy(), beta=be.cpu().numpy(), theta=c.cpu().numpy(),
+                   diff=d.cpu().numpy().astype(np.float64), info=int(info.item()), status=st)
+    finally:
+        plan.close()
+    _check_against_oracle(p, mode, res, ref=ref)
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_caller_workspace(mode):
+    """A plan on a caller-owned workspace gives the same results, bit for bit,
+    as a plan that allocates its own."""
+    p = synth.random_pair(321, 96, 88, 3, 2, 2, mask_frac=0.1, stars=True)
+    a = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, mode=mode)
+    dt = torch.float64 if mode == F64 else torch.float32
+    d = B.make_desc(96, 88, p.w, p.dk, p.db, mode)
+    need = B.sfft_workspace_bytes(d)
+    ws = torch.full((need + 512,), 0xA5, dtype=torch.uint8, device="cuda")   # not zeroed: nothing may rely on it
+    S = torch.from_numpy(p.sci).to("cuda", dt)
+    R = torch.from_numpy(p.tmpl).to("cuda", dt)
+    Mk = torch.from_numpy(p.mask).cuda()
+    h = B.sfft_plan(d, None, ws[256:], need)
+    try:
+        B.sfft_build_system(h, S, R, Mk, S.stride(0))
+        om = torch.empty((a["omega"].shape[0],) * 2, dtype=torch.float64, device="cuda")
+        be = torch.empty((a["omega"].shape[0],), dtype=torch.float64, device="cuda")
+        B.sfft_get_system(h, om, be)
+        c = torch.zeros_like(be)
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        B.sfft_solve(h, c, info)
+        D = torch.empty_like(S)
+        B.sfft_subtract(h, S, R, c, D, S.stride(0))
+        assert B.sfft_status(h)[0] == B.SFFT_OK
+        np.testing.assert_array_equal(om.cpu().numpy(), a["omega"])
+        np.testing.assert_array_equal(c.cpu().numpy(), a["theta"])
+        np.testing.assert_array_equal(D.cpu().numpy().astype(np.float64), a["diff"])
+    finally:
+        B.sfft_destroy(h)
+    # the bytes outside the borrowed range are untouched
+    assert torch.all(ws[:256] == 0xA5).item() and torch.all(ws[256 + need:] == 0xA5).item()

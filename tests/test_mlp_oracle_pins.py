@@ -2,6 +2,7 @@
 (gradients), a linear network against its closed form, and Adam's first
 steps written out."""
 import numpy as np
+import pytest
 
 from oracle import mlp_oracle as M
 
@@ -77,3 +78,15 @@ def test_adam_first_steps():
     np.testing.assert_allclose(p1, p - 0.1 * np.sign(g), rtol=0, atol=1e-7)
     np.testing.assert_allclose(m1, 0.1 * g)
     np.testing.assert_allclose(v1, 0.001 * g * g)
+
+
+def test_mse_mean_normalisation_by_hand():
+    """mse = mean over every element of (y - t)^2, gradient 2 (y - t) / (number of elements)."""
+    y = np.array([[1.0, 2.0], [3.0, 4.0]])
+    t = np.array([[0.0, 2.0], [1.0, 1.0]])
+    loss, g = M.mse(y, t)
+    assert loss == 3.5                                      # (1 + 0 + 4 + 9) / 4
+    np.testing.assert_array_equal(g, np.array([[0.5, 0.0], [1.0, 1.5]]))
+    loss1, g1 = M.mse(np.array([[2.0, -1.0, 0.0]]), np.zeros((1, 3)))
+    assert loss1 == pytest.approx(5.0 / 3.0, rel=1e-15)
+    np.testing.assert_allclose(g1, np.array([[4.0 / 3.0, -2.0 / 3.0, 0.0]]), rtol=1e-15)

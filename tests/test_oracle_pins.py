@@ -333,8 +333,8 @@ def test_single_entry_and_pixel_functions_agree_with_full_system():
                                rtol=0, atol=1e-12 * np.abs(be).max())
     th = oracle.solve(om, be)
     D = oracle.difference(p.sci, p.tmpl, th, p.w, p.dk, p.db, mode="direct")
-    ys = [0, 0, 29, 15, 3, 29]
-    xs = [0, 33, 33, 17, 1, 0]
+    ys, xs = np.meshgrid(np.arange(30), np.arange(34), indexing="ij")   # every pixel, borders included
+    ys, xs = ys.ravel(), xs.ravel()
     np.testing.assert_allclose(oracle.difference_at(p.sci, p.tmpl, th, p.w, p.dk, p.db, ys, xs),
                                D[ys, xs], rtol=0, atol=1e-12 * np.abs(p.sci).max())
 
@@ -375,3 +375,50 @@ def test_fit_background_keeps_the_full_solution_and_rho_vanishes():
     guess = th + np.random.default_rng(1).normal(0.0, 0.01, th.size)
     ref = np.linalg.norm(phi.T @ (tgt - phi @ guess)) / np.linalg.norm(phi.T @ tgt)
     assert abs(oracle.residual_ratio(om, be, guess) - ref) <= 1e-9 * ref
+
+
+# ---------------------------------------------------------------------------
+# the error metric and the condition number reported with every result
+# ---------------------------------------------------------------------------
+
+def test_rel_err_closed_forms():
+    """rel_err is the whole-array 2-norm ratio ||x - ref|| / ||ref|| (A11 reading):
+    pinned by offsets whose norms are fixed by geometry, not by retyping the formula."""
+    ref = np.array([0.0, 0.0, 12.0, 5.0])                 # ||ref|| = 13
+    assert oracle.rel_err(ref, ref) == 0.0
+    # an offset of 2-norm 5 (3-4-5 triangle) gives 5/13; a max-norm reading would give 4/12,
+    # a 1-norm reading 7/17
+    assert oracle.rel_err(ref + np.array([3.0, 4.0, 0.0, 0.0]), ref) == pytest.approx(5.0 / 13.0, rel=1e-15)
+    # scaling: x = c ref -> |c - 1|
+    for cfac, want in ((3.0, 2.0), (-1.0, 2.0), (0.0, 1.0), (1.5, 0.5)):
+        assert oracle.rel_err(cfac * ref, ref) == pytest.approx(want, rel=1e-15)
+    # 2-D arrays: the Frobenius norm over the whole array (equal to the flattened vector)
+    r2 = np.arange(1.0, 13.0).reshape(3, 4)
+    x2 = r2.copy()
+    x2[1, 2] += 2.0
+    x2[2, 0] -= 1.0
+    assert oracle.rel_err(x2, r2) == pytest.approx(np.sqrt(5.0) / np.sqrt(650.0), rel=1e-14)
+    # an orthogonal offset of relative size t: rel_err = t whatever the direction
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=50)
+    e = rng.normal(size=50)
+    e -= (e @ v) / (v @ v) * v
+    e *= 0.25 * np.linalg.norm(v) / np.linalg.norm(e)
+    assert oracle.rel_err(v + e, v) == pytest.approx(0.25, rel=1e-13)
+    # a zero reference: the absolute norm (denominator 1)
+    assert oracle.rel_err(np.array([3.0, 4.0]), np.zeros(2)) == 5.0
+
+
+def test_cond_number_closed_forms():
+    """cond_number is the 2-norm condition number lambda_max / lambda_min of an SPD matrix."""
+    assert oracle.cond_number(np.diag([1.0, 10.0, 1000.0])) == pytest.approx(1000.0, rel=1e-14)
+    # invariant under an orthogonal change of basis
+    q, _ = np.linalg.qr(np.random.default_rng(1).normal(size=(6, 6)))
+    a = q @ np.diag([2.0, 3.0, 5.0, 7.0, 11.0, 0.5]) @ q.T
+    assert oracle.cond_number(a) == pytest.approx(22.0, rel=1e-12)
+    # the 4 x 4 Hilbert matrix, cond_2 = 1.5514e4 (a textbook value)
+    h4 = 1.0 / (np.arange(4)[:, None] + np.arange(4)[None, :] + 1.0)
+    assert oracle.cond_number(h4) == pytest.approx(15513.74, rel=1e-6)
+    # singular or indefinite: infinite
+    assert oracle.cond_number(np.array([[1.0, 1.0], [1.0, 1.0]])) == float("inf")
+    assert oracle.cond_number(np.diag([1.0, -2.0])) == float("inf")
