@@ -52,7 +52,8 @@ enum {
   SFFT_EHIP = -3,       /* a HIP runtime call failed                                          */
   SFFT_ENOTSPD = -4,    /* Omega is not positive definite (sfft_status only)                   */
   SFFT_ESTATE = -5,     /* call out of order (e.g. solve before build)                         */
-  SFFT_ENONFINITE = -6  /* NaN/Inf in the science or template image (sfft_status only)          */
+  SFFT_ENONFINITE = -6, /* NaN/Inf in the science or template image (sfft_status only)          */
+  SFFT_ETOOBIG = -7     /* larger than the static scratch of sfft_subtract_pair_noalloc           */
 };
 
 enum {
@@ -232,6 +233,32 @@ int sfft_batch_capture(sfft_handle b, const void* const* sci, const void* const*
 /* Replay the captured batch run on the batch stream: one graph launch for all
  * pairs.  SFFT_ESTATE without a capture. */
 int sfft_batch_launch(sfft_handle b);
+
+/* ---- one pair with no allocation ----
+ * For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc, code that must not call an allocator).
+ * Same result as sfft_plan (its own workspace) + sfft_build_system +
+ * sfft_solve + sfft_subtract on one pair, bit for bit, with the same
+ * arguments as those calls (info: device int32, may be NULL).  The
+ * workspace is a static device array of SFFT_NOALLOC_SCRATCH_BYTES bytes,
+ * one per GPU, that the library holds from its load until the process ends;
+ * the call never allocates (no hipMalloc/hipFree, no host heap).  A pair
+ * whose workspace would exceed it (sfft_workspace_bytes plus 96 KiB of
+ * twiddle tables: frames up to 1024 x 1024 at w = 9, DK = DB = 2 fit in
+ * both modes, 2048 x 2048 at those settings does not) returns SFFT_ETOOBIG
+ * before anything is enqueued.
+ *   - The first call on a GPU, and the first call after a descriptor
+ *     change on that GPU, upload the plan's tables and synchronise the
+ *     stream; later calls with the same descriptor only enqueue kernels.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents: calls that overlap on one GPU (other streams, other
+ *     threads before the previous call's work has drained) race, and the
+ *     caller must order them.  Host-side state is guarded per GPU.
+ *   - Device outcomes go to `info` as in sfft_solve; the non-finite flag of
+ *     this path is not reported (use a plan for sfft_status). */
+#define SFFT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int sfft_subtract_pair_noalloc(const sfft_desc* d, void* hip_stream, const void* sci, const void* tmpl,
+                               const uint8_t* mask, int64_t ld, double* coeffs, void* diff, int32_t* info);
 
 /* Release the plan (and its workspace if the plan allocated it). */
 void sfft_destroy(sfft_handle p);

@@ -25,6 +25,7 @@ SFFT_EHIP = -3
 SFFT_ENOTSPD = -4
 SFFT_ESTATE = -5
 SFFT_ENONFINITE = -6
+SFFT_ETOOBIG = -7
 
 SFFT_MODE_F64 = 0
 SFFT_MODE_F32C = 1
@@ -81,6 +82,7 @@ def lib():
         "sfft_batch_launch": (ctypes.c_int, [vp]),
         "sfft_autotune": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float),
                                          i32, ctypes.POINTER(i32)]),
+        "sfft_subtract_pair_noalloc": (ctypes.c_int, [D, vp, vp, vp, vp, i64, vp, vp, vp]),
         "sfft_destroy": (None, [vp]),
         "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sfft_mlp_create": (ctypes.c_int, [ctypes.POINTER(i32), i32, i32, vp, ctypes.POINTER(vp)]),
@@ -265,6 +267,17 @@ def sfft_autotune(handle, sci, tmpl, mask, ld: int, cap: int = 16):
 
 def sfft_batch_launch(handle):
     _check(lib().sfft_batch_launch(handle), "sfft_batch_launch")
+
+
+def sfft_subtract_pair_noalloc(desc: sfft_desc, sci, tmpl, mask, ld: int, coeffs, diff, info=None, stream=None):
+    """One pair (build + solve + subtract) on the library's static scratch: no allocation."""
+    _check(lib().sfft_subtract_pair_noalloc(ctypes.byref(desc), _stream_handle(stream), _ptr(sci), _ptr(tmpl),
+                                            _ptr(mask), int(ld), _ptr(coeffs), _ptr(diff), _ptr(info)),
+           "sfft_subtract_pair_noalloc")
+
+
+# bytes of the static scratch (SFFT_NOALLOC_SCRATCH_BYTES in include/sfft.h)
+SFFT_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 def sfft_destroy(handle):

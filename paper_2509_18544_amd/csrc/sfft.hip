@@ -11,6 +11,7 @@
 #include <new>
 #include <type_traits>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -38,6 +39,33 @@ constexpr int MAX_N = 8192;           // unknowns (the triangular solves keep x 
 constexpr int MAX_W = 15;
 constexpr double DIR_AUTO_FMA = 1.0e9;   // direct lag sums below this many multiply-adds (small frames)
 
+// A vector of fixed capacity held inline: filling it never allocates, so a
+// plan can be derived into static storage (the no-allocation entry point).
+template <typename T, int CAP>
+struct FixedVec {
+  T v[CAP];
+  int n = 0;
+  void clear() { n = 0; }
+  bool push_back(const T& x) {
+    if (n >= CAP) return false;
+    v[n++] = x;
+    return true;
+  }
+  int size() const { return n; }
+  T* data() { return v; }
+  const T* data() const { return v; }
+  T& operator[](int i) { return v[i]; }
+  const T& operator[](int i) const { return v[i]; }
+  T& back() { return v[n - 1]; }
+  T* begin() { return v; }
+  T* end() { return v + n; }
+  const T* begin() const { return v; }
+  const T* end() const { return v + n; }
+};
+
+// lag rows of all windows: every item covers at most JMAX of them
+constexpr int MAX_VROWS = JMAX * MAX_ITEMS;
+
 struct Layout {
   size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, w, kp, flags, tw32, tw64, items, wrows, drows, job;
   size_t total;
@@ -57,10 +85,10 @@ struct Derived {
   int njlo;
   int16_t jlo_list[MAX_JLO];
   size_t csize;   // sizeof complex element of the transforms
-  std::vector<CorrItem> items;
-  std::vector<WinRow> wrows;
+  FixedVec<CorrItem, MAX_ITEMS> items;
+  FixedVec<WinRow, MAX_VROWS> wrows;
   bool direct;                    // lag windows by direct sums instead of transforms
-  std::vector<DirectRow> drows;
+  FixedVec<DirectRow, MAX_VROWS> drows;
   int dir_tpr, dir_nband;
   GatherParams gp;
   PolyTab kpoly, bpoly;
@@ -174,6 +202,7 @@ int derive(const sfft_desc* d, Derived* D) {
   D->wrows.clear();
   D->drows.clear();
   int vrow = 0, wo = 0;
+  bool fits = true;   // every table stayed within its capacity
   auto add_pair = [&](int left, int right, int hw) {
     const int h = 2 * hw + 1;
     for (int j = -hw; j <= hw; j += JMAX) {
@@ -185,21 +214,21 @@ int derive(const sfft_desc* d, Derived* D) {
       it.vrow = vrow + (j + hw);
       it.jidx = 0;
       it.pad_ = 0;
-      D->items.push_back(it);
+      fits &= D->items.push_back(it);
     }
     for (int j = 0; j < h; ++j) {
       WinRow r;
       r.vrow = vrow + j;
       r.out = wo + j * h;
       r.hw = hw;
-      D->wrows.push_back(r);
+      fits &= D->wrows.push_back(r);
       DirectRow q;
       q.left = (int16_t)left;
       q.right = (int16_t)right;
       q.hw = (int16_t)hw;
       q.dy = (int16_t)(j - hw);
       q.out = wo + j * h;
-      D->drows.push_back(q);
+      fits &= D->drows.push_back(q);
     }
     const int off = wo;
     vrow += h;
@@ -212,11 +241,22 @@ int derive(const sfft_desc* d, Derived* D) {
   for (int a = 0; a < D->nk; ++a)
     for (int b = 0; b < D->nb; ++b) D->gp.kb_off[a * D->nb + b] = add_pair(a, D->nk + b, w);
   for (int a = 0; a < D->nk; ++a) D->gp.ks_off[a] = add_pair(a, D->nk + D->nb, w);
+  if (!fits) return SFFT_EINVAL;   // more correlation items than the kernels take
   // items sorted by their residue rotation (jlo mod P2) so that a wave of the
   // correlation kernel normally takes a single case of its rotation switch
-  std::stable_sort(D->items.begin(), D->items.end(), [](const CorrItem& x, const CorrItem& y) {
-    return ((x.jlo % P2) + P2) % P2 < ((y.jlo % P2) + P2) % P2;
-  });
+  // (a stable insertion sort: no allocation, at most MAX_ITEMS items)
+  {
+    auto rot_of = [](const CorrItem& x) { return ((x.jlo % P2) + P2) % P2; };
+    for (int i = 1; i < D->items.size(); ++i) {
+      const CorrItem x = D->items[i];
+      int j = i - 1;
+      while (j >= 0 && rot_of(D->items[j]) > rot_of(x)) {
+        D->items[j + 1] = D->items[j];
+        --j;
+      }
+      D->items[j + 1] = x;
+    }
+  }
   // threads per item: the largest count (<= 64) that keeps all real items in
   // one pass of the block; each rotation group is padded with empty items
   // (nj = 0) to a whole number of waves so that a wave takes one switch case.
@@ -227,7 +267,7 @@ int derive(const sfft_desc* d, Derived* D) {
       const int ipw = 64 / l;
       // waves needed with group padding
       int waves = 0;
-      size_t i = 0;
+      int i = 0;
       while (i < D->items.size()) {
         const int rot = ((D->items[i].jlo % P2) + P2) % P2;
         int cnt = 0;
@@ -247,24 +287,25 @@ int derive(const sfft_desc* d, Derived* D) {
     }
     D->corr_lanes = lanes;
     const int ipw = 64 / lanes;
-    std::vector<CorrItem> padded;
-    size_t i = 0;
+    FixedVec<CorrItem, MAX_ITEMS> padded;
+    int i = 0;
     while (i < D->items.size()) {
       const int rot = ((D->items[i].jlo % P2) + P2) % P2;
       int cnt = 0;
       while (i < D->items.size() && ((D->items[i].jlo % P2) + P2) % P2 == rot) {
-        padded.push_back(D->items[i]);
+        fits &= padded.push_back(D->items[i]);
         ++cnt;
         ++i;
       }
       while (cnt % ipw != 0) {
         CorrItem e = padded.back();
         e.nj = 0;
-        padded.push_back(e);
+        fits &= padded.push_back(e);
         ++cnt;
       }
     }
-    D->items.swap(padded);
+    if (!fits) return SFFT_EINVAL;
+    D->items = padded;
   }
   D->nitems = (int)D->items.size();
   // distinct first lag rows (the correlation kernel tabulates their twiddles per chunk)
@@ -357,9 +398,7 @@ Layout layout_of(const Derived& D) {
 
 // exp(-2 pi i m / TW_N) in FP64, from long-double sin/cos on the first octant
 // and exact symmetries elsewhere.
-void twiddle_tables(std::vector<cplx<double>>* t64, std::vector<cplx<float>>* t32) {
-  t64->resize(TW_N);
-  t32->resize(TW_N);
+void twiddle_tables(cplx<double>* t64, cplx<float>* t32) {
   const long double pi = 3.141592653589793238462643383279502884L;
   for (int m = 0; m < TW_N; ++m) {
     // angle = 2 pi m / N; reduce to [0, pi/4] by octant symmetry
@@ -384,10 +423,10 @@ void twiddle_tables(std::vector<cplx<double>>* t64, std::vector<cplx<float>>* t3
       case 6: c = s0; s = -c0; break;                      // 3pi/2 + r
       default: c = c1; s = -s1; break;                     // 2pi - (pi/4 - r)
     }
-    (*t64)[m].x = (double)c;
-    (*t64)[m].y = -(double)s;   // forward sign
-    (*t32)[m].x = (float)(*t64)[m].x;
-    (*t32)[m].y = (float)(*t64)[m].y;
+    t64[m].x = (double)c;
+    t64[m].y = -(double)s;   // forward sign
+    t32[m].x = (float)t64[m].x;
+    t32[m].y = (float)t64[m].y;
   }
 }
 
@@ -410,6 +449,7 @@ const char* const kStageNames[SFFT_NUM_STAGES] = {"moments", "row_fwd", "col_fwd
 // Optional per-stage device timing with events recorded on the plan's stream.
 struct StageTimer {
   bool on = false;
+  bool silent = false;   // no roctx ranges either (the no-allocation path calls nothing that may allocate)
   unsigned mask = 0;   // stages timed while on (bit s = stage s)
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[SFFT_NUM_STAGES];
@@ -438,6 +478,7 @@ struct StageTimer {
     }
   }
   void begin(int st, hipStream_t s) {
+    if (silent) return;
     if (ranged) roctxRangePop();   // a stage left by an error return
     roctxRangePushA(kStageNames[st]);
     ranged = true;
@@ -447,6 +488,7 @@ struct StageTimer {
     if (open_ev) (void)hipEventRecord(open_ev, s);
   }
   void end(hipStream_t s) {
+    if (silent) return;
     if (ranged) {
       roctxRangePop();
       ranged = false;
@@ -988,11 +1030,12 @@ int sfft_num_coeffs(const sfft_desc* d, int64_t* n) {
 
 int sfft_workspace_bytes(const sfft_desc* d, size_t* bytes) {
   if (bytes == nullptr) return SFFT_EINVAL;
-  Derived D;
-  const int st = derive(d, &D);
-  if (st != SFFT_OK) return st;
-  *bytes = layout_of(D).total;
-  return SFFT_OK;
+  Derived* D = new (std::nothrow) Derived();   // its tables are held inline: too large for the stack
+  if (D == nullptr) return SFFT_ENOMEM;
+  const int st = derive(d, D);
+  if (st == SFFT_OK) *bytes = layout_of(*D).total;
+  delete D;
+  return st;
 }
 
 int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t workspace_bytes, sfft_handle* out) {
@@ -1031,7 +1074,9 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
     p->ws = reinterpret_cast<unsigned char*>(m);
     p->owns_ws = true;
   }
-  twiddle_tables(&p->tw64h, &p->tw32h);
+  p->tw64h.resize(TW_N);
+  p->tw32h.resize(TW_N);
+  twiddle_tables(p->tw64h.data(), p->tw32h.data());
   hipStream_t s = p->stream;
   bool ok = true;
   ok &= hipMemcpyAsync(p->at<void>(p->Lo.tw64), p->tw64h.data(), TW_N * sizeof(cplx<double>), hipMemcpyHostToDevice,
@@ -1415,6 +1460,130 @@ int sfft_batch_launch(sfft_handle b) {
   return SFFT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The no-allocation entry point
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+// Device memory of sfft_subtract_pair_noalloc: one copy per GPU, set aside when
+// the library's code object is loaded on that GPU and held until the process
+// ends.  In host code this name is only a stand-in for the symbol: the address
+// of a GPU's copy comes from hipGetSymbolAddress at set-up and is the only one
+// ever passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[SFFT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 16;
+// the twiddle tables sit at the end of the scratch (uploaded once per GPU);
+// a plan's workspace takes the bytes before them
+constexpr size_t SCR_TW32 = SFFT_NOALLOC_SCRATCH_BYTES - (size_t)TW_N * sizeof(cplx<float>);
+constexpr size_t SCR_TW64 = SCR_TW32 - (size_t)TW_N * sizeof(cplx<double>);
+static_assert(SCR_TW64 % 256 == 0, "256-byte aligned carve-up");
+
+struct NoAllocDevice {
+  std::mutex mu;
+  bool ready = false;               // set-up done on this GPU
+  unsigned char* ptr = nullptr;     // this GPU's address of `scratch`
+  bool have_desc = false;           // the scratch holds the tables of `desc`
+  sfft_desc desc;
+  sfft_plan_s plan;                 // host state of the single-pair plan (tables held inline)
+};
+NoAllocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+std::mutex g_tw_mu;
+bool g_tw_ready = false;
+cplx<double> g_tw64[TW_N];
+cplx<float> g_tw32[TW_N];
+
+template <typename T>
+int noalloc_run(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask, int64_t ld, double* coeffs,
+                T* diff, int32_t* info) {
+  int st = build_impl<T>(p, sci, tmpl, mask, ld);
+  if (st != SFFT_OK) return st;
+  const Derived& D = p->D;
+  hipStream_t s = p->stream;
+  st = solve_jobs(s, p->at<SolveJob>(p->Lo.job), 1, D.n, D.nblk, D.refine, &p->timer);
+  if (st != SFFT_OK) return st;
+  copy_out_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(p->at<double>(p->Lo.theta), coeffs, D.n, p->at<int>(p->Lo.flags),
+                                                    info);
+  LAUNCH_CHECK();
+  return subtract_impl<T>(p, sci, tmpl, coeffs, diff, ld);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfft_subtract_pair_noalloc(const sfft_desc* d, void* hip_stream, const void* sci, const void* tmpl,
+                               const uint8_t* mask, int64_t ld, double* coeffs, void* diff, int32_t* info) {
+  if (d == nullptr || sci == nullptr || tmpl == nullptr || coeffs == nullptr || diff == nullptr) return SFFT_EINVAL;
+  int st = validate(d);
+  if (st != SFFT_OK) return st;
+  if (ld < d->nx) return SFFT_EINVAL;
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return SFFT_EINVAL;
+  NoAllocDevice& g = g_noalloc[dev];
+  std::lock_guard<std::mutex> lock(g.mu);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  sfft_plan_s* p = &g.plan;
+  if (!g.ready) {
+    // set-up, once per GPU with that GPU current: its address of the array,
+    // and the FP64/FP32 twiddle tables at the end of it
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (ptr == nullptr) return SFFT_EHIP;
+    {
+      std::lock_guard<std::mutex> tl(g_tw_mu);
+      if (!g_tw_ready) {
+        twiddle_tables(g_tw64, g_tw32);
+        g_tw_ready = true;
+      }
+    }
+    unsigned char* base = static_cast<unsigned char*>(ptr);
+    HIP_TRY(hipMemcpyAsync(base + SCR_TW64, g_tw64, sizeof(g_tw64), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(base + SCR_TW32, g_tw32, sizeof(g_tw32), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g.ptr = base;
+    p->timer.silent = true;
+    g.ready = true;
+  }
+  if (!g.have_desc || std::memcmp(&g.desc, d, sizeof(sfft_desc)) != 0) {
+    // a new descriptor: derive the plan into the static host state, check the
+    // size, upload its tables (the previous call's kernels on this stream
+    // read the old ones first)
+    g.have_desc = false;
+    st = derive(d, &p->D);
+    if (st != SFFT_OK) return st;
+    p->Lo = layout_of(p->D);
+    if (p->Lo.total > SCR_TW64) return SFFT_ETOOBIG;
+    p->Lo.tw64 = SCR_TW64;
+    p->Lo.tw32 = SCR_TW32;
+    p->desc = *d;
+    p->ws = g.ptr;
+    p->owns_ws = false;
+    p->stream = s;
+    const Derived& D = p->D;
+    HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.items), D.items.data(), (size_t)D.items.size() * sizeof(CorrItem),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.wrows), D.wrows.data(), (size_t)D.wrows.size() * sizeof(WinRow),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.drows), D.drows.data(), (size_t)D.drows.size() * sizeof(DirectRow),
+                           hipMemcpyHostToDevice, s));
+    const SolveJob job = job_of(p);
+    HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.job), &job, sizeof(job), hipMemcpyHostToDevice, s));
+    // the host tables (and `job`) may change once the copies have been made
+    HIP_TRY(hipStreamSynchronize(s));
+    g.desc = *d;
+    g.have_desc = true;
+  }
+  p->stream = s;
+  p->built = true;
+  if (p->D.mode == SFFT_MODE_F64)
+    return noalloc_run<double>(p, (const double*)sci, (const double*)tmpl, mask, ld, coeffs, (double*)diff, info);
+  return noalloc_run<float>(p, (const float*)sci, (const float*)tmpl, mask, ld, coeffs, (float*)diff, info);
+}
+
 const char* sfft_strerror(int status) {
   switch (status) {
     case SFFT_OK: return "success";
@@ -1424,6 +1593,8 @@ const char* sfft_strerror(int status) {
     case SFFT_ENOTSPD: return "normal matrix is not positive definite";
     case SFFT_ESTATE: return "call out of order (build the system first)";
     case SFFT_ENONFINITE: return "non-finite value in the science or template image";
+    case SFFT_ETOOBIG:
+      return "the pair needs more device memory than the no-allocation entry point's static scratch holds";
     default: return "unknown status";
   }
 }

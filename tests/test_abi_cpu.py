@@ -57,7 +57,7 @@ def test_invalid_descriptors(bad):
 
 
 def test_strerror_covers_codes():
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert B.strerror(code) and B.strerror(code) != "unknown status"
     assert B.strerror(123) == "unknown status"
 
@@ -69,6 +69,27 @@ def test_null_arguments():
     assert lib.sfft_solve(None, None, None) == B.SFFT_EINVAL
     assert lib.sfft_subtract(None, None, None, None, None, 0) == B.SFFT_EINVAL
     lib.sfft_destroy(None)
+
+
+def test_noalloc_rejects_bad_arguments_before_any_device_call():
+    """The no-allocation entry point checks its descriptor and pointers on the
+    host first: these return SFFT_EINVAL with no GPU present (the fake
+    pointers are never dereferenced)."""
+    lib = B.lib()
+    fake = ctypes.c_void_p(0x100000)
+    good = B.make_desc(64, 64, 2, 1, 1, B.SFFT_MODE_F64)
+    bad = B.make_desc(64, 64, -1, 1, 1, B.SFFT_MODE_F64)
+    assert lib.sfft_subtract_pair_noalloc(None, None, fake, fake, None, 64, fake, fake, None) == B.SFFT_EINVAL
+    assert lib.sfft_subtract_pair_noalloc(ctypes.byref(bad), None, fake, fake, None, 64, fake, fake,
+                                          None) == B.SFFT_EINVAL
+    for args in ((None, fake, fake, fake), (fake, None, fake, fake), (fake, fake, None, fake),
+                 (fake, fake, fake, None)):
+        sci, tmpl, coeffs, diff = args
+        assert lib.sfft_subtract_pair_noalloc(ctypes.byref(good), None, sci, tmpl, None, 64, coeffs, diff,
+                                              None) == B.SFFT_EINVAL
+    # a row pitch shorter than the frame
+    assert lib.sfft_subtract_pair_noalloc(ctypes.byref(good), None, fake, fake, None, 63, fake, fake,
+                                          None) == B.SFFT_EINVAL
 
 
 @pytest.mark.parametrize("dims,nl,max_batch", [
