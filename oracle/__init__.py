@@ -7,4 +7,5 @@ from the product path.
 """
 from .sfft_oracle import *  # noqa: F401,F403
 from . import mlp_oracle  # noqa: F401,E402
-from .kernel_oracle import convolve, apply_kernel  # noqa: F401,E402
+from .kernel_oracle import (apply_kernel, centre_kernel, convolve, decorrelation_kernel,  # noqa: F401,E402
+                            decorrelation_spectrum, DECORR_GRID)
