@@ -23,6 +23,11 @@ The same JSON line also carries:
   * cpu_baseline   -- the CPU FP64 oracle timed on this host (median of 3) on
                       one pair of the workload, and on the 256^2 and 1024^2
                       pairs, with the core count and CPU model;
+  * assembly_routes -- pair 0 assembled by each route (FFT transforms, direct
+                      lag sums where allowed, FP64 matrix-core products):
+                      sfft_autotune_route's build times and the route it keeps,
+                      and the matrix-core kernel's executed FP64 TFLOP/s
+                      against the 78.6 TFLOP/s peak;
   * accuracy       -- e_theta and e_D of EVERY timed pair against the oracle
                       (theta* stored by tests/golden/make_golden.py or solved
                       live, D* computed by the oracle from theta*), with the
@@ -190,11 +195,17 @@ def accuracy_of(outputs, refs, tag, bar):
 # the GPU legs
 # ---------------------------------------------------------------------------
 
+# what the correlation kernel is compiled from: its header, the shared
+# device helpers and the build flags (the committed traffic figures are valid
+# while these are unchanged)
+CORR_SOURCES = ("paper_2509_18544_amd/csrc/assemble.hpp", "paper_2509_18544_amd/csrc/common.hpp",
+                "paper_2509_18544_amd/build.py")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    cdir = os.path.join(ROOT, "paper_2509_18544_amd", "csrc")
-    for f in sorted(os.listdir(cdir)):
-        with open(os.path.join(cdir, f), "rb") as fh:
+    for f in CORR_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -344,6 +355,8 @@ def run_leg(B, torch, pairs, mode_name, args, log):
                           p90=float(np.percentile(steps_ms, 90)), min=float(min(steps_ms)), max=float(max(steps_ms)))
     out["corr_ms_per_launch"] = corr_tot[0] / corr_tot[1] if corr_tot[1] else None
     out["corr_launches"] = corr_tot[1]
+    # a launch serves every pair of a group (same descriptor): pairs per launch
+    out["corr_pairs_per_launch"] = len(pairs) * args.steps / corr_tot[1] if corr_tot[1] else None
     log(f"[bench] {mode_name}: {out['value']:.2f} pairs/s, {out['ms_per_step']:.2f} ms/step "
         f"(median {out['step_ms']['median']:.2f}), corr {out['corr_ms_per_launch']:.4f} ms x {corr_tot[1]}")
 
@@ -384,10 +397,72 @@ def run_leg(B, torch, pairs, mode_name, args, log):
     return out
 
 
-def roofline_of(stage, D, mode_f64, ms):
+MFMA_F64_PEAK_TFLOPS = 78.6
+MFMA_XC = 256          # columns per block of the MFMA route's kernel
+
+
+def mfma_flops(D):
+    """(executed, useful) FP64 flops of one MFMA-route assembly: per (pair, 16-lag
+    dy tile) block row, every source row of the frame runs 16 x 4 instructions
+    of 16x16x4 (2048 flops) per dx tile over each 256-column chunk; the useful
+    part is one multiply-add per pixel and window entry."""
+    n, w, nk, nb = D["N"], D["w"], D["nk"], D["nb"]
+    pairs = [2 * w] * (nk * (nk + 1) // 2) + [w] * (nk * nb + nk)   # lag half-widths: 2w (kernel x kernel), w
+    nxc = -(-n // MFMA_XC)
+    executed = useful = 0
+    for hw in pairs:
+        h = 2 * hw + 1
+        tiles = -(-h // 16)
+        executed += tiles * tiles * nxc * n * 64 * 2048
+        useful += 2 * h * h * n * n
+    return executed, useful
+
+
+def route_leg(B, torch, p, mode_name, log):
+    """Assembly routes on pair 0: sfft_autotune_route's build times (FFT, direct,
+    MFMA) and the MFMA kernel's own device time with its matrix-core rate."""
+    mode = B.SFFT_MODE_F64 if mode_name == "f64" else B.SFFT_MODE_F32C
+    dt = torch.float64 if mode == B.SFFT_MODE_F64 else torch.float32
+    S = torch.from_numpy(p.sci).to("cuda", dt)
+    R = torch.from_numpy(p.tmpl).to("cuda", dt)
+    M = torch.from_numpy(p.mask).cuda()
+    n = p.sci.shape[0]
+    out = {}
+    plan = B.Plan(n, n, p.w, p.dk, p.db, mode=mode)
+    try:
+        ms, route = B.sfft_autotune_route(plan.handle, S, R, M, S.stride(0))
+        out["build_ms"] = {k: (round(v, 3) if v is not None else None) for k, v in ms.items()}
+        out["auto_route"] = route
+    finally:
+        plan.close()
+    plan = B.Plan(n, n, p.w, p.dk, p.db, mode=mode, flags=B.SFFT_FLAG_ASSEMBLY_MFMA)
+    try:
+        plan.build(S, R, M)
+        B.sfft_timing_enable(plan.handle, ["corr"])
+        for _ in range(2):
+            plan.build(S, R, M)
+        t = B.sfft_timing_read(plan.handle)["corr"]
+        B.sfft_timing_enable(plan.handle, False)
+        kms = t[0] / t[1]
+        ex, us = mfma_flops(shape_info(p))
+        out["mfma_kernel"] = dict(avg_ms=round(kms, 3), executed_tflop=round(ex / 1e12, 3),
+                                  useful_tflop=round(us / 1e12, 3),
+                                  achieved_tflops=round(ex / (kms * 1e-3) / 1e12, 2), peak=MFMA_F64_PEAK_TFLOPS,
+                                  utilisation=round(ex / (kms * 1e-3) / 1e12 / MFMA_F64_PEAK_TFLOPS, 4))
+    finally:
+        plan.close()
+    log(f"[bench] assembly routes on pair 0 ({mode_name}): {out}")
+    del S, R, M
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline_of(stage, D, mode_f64, ms, pairs=1.0):
+    """Algorithmic amount of `pairs` pairs over `ms` milliseconds against the peak."""
     bound, amount = stage_cost(stage, D, mode_f64)
     if bound is None or not ms:
         return None
+    amount = amount * pairs
     sec = ms / 1000.0
     if bound == "hbm":
         ach = amount / sec / 1e9
@@ -411,6 +486,7 @@ def main():
                     help="skip the oracle (its timing and the accuracy check): value is then null")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default correlation chunk")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--no-routes", action="store_true", help="skip the assembly-route timings")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -450,6 +526,9 @@ def main():
     torch.cuda.set_device(dev)
     copy_gbs = copy_bandwidth(torch, dev, log)
     results = {m: run_leg(B, torch, pairs, m, args, log) for m in legs}
+    routes = None
+    if not args.no_routes and len({(p.sci.shape, p.w, p.dk, p.db) for p in pairs}) == 1:
+        routes = route_leg(B, torch, pairs[0], args.mode, log)
 
     # ---- CPU baseline and accuracy (the oracle) ----
     cpu = cond = None
@@ -472,11 +551,12 @@ def main():
     mode_f64 = args.mode == "f64"
     uniform = len({(p.sci.shape, p.w, p.dk, p.db) for p in pairs}) == 1
     # per-launch flops depend on the pair's shape: priced only for a uniform batch
-    roof = roofline_of("corr", D, mode_f64, head["corr_ms_per_launch"]) if uniform else None
+    ppl = head["corr_pairs_per_launch"]
+    roof = roofline_of("corr", D, mode_f64, head["corr_ms_per_launch"], ppl) if uniform else None
     src = kernel_source_hash()
     if roof is not None:
         roof.update(kernel="corr_kernel", traffic=measured_traffic("corr", args.mode, src), src=src,
-                    launches_timed=head["corr_launches"])
+                    launches_timed=head["corr_launches"], pairs_per_launch=ppl)
     value = head["value"]
     ok = (not args.no_cpu_baseline) and acc[args.mode]["all_within"] and not acc[args.mode]["failed_pairs"]
     path = None
@@ -499,9 +579,8 @@ def main():
             bpp64 = path_bytes(D, True)
             fp64["path_roofline"] = dict(bytes_per_pair=bpp64, frac=round(r["value"] / (HBM_PEAK_GBS * 1e9 / bpp64), 4))
     stage_roofs = {}
-    for k, ms in head["stages_avg_ms"].items():
-        per = head["stages_ms_per_pair"].get(k, 0.0) if k in ("factor", "solve") else ms
-        rr = roofline_of(k, D, mode_f64, per) if uniform else None
+    for k, per in head["stages_ms_per_pair"].items():
+        rr = roofline_of(k, D, mode_f64, per) if uniform else None   # the per-pair share of device time
         if rr:
             stage_roofs[k] = {kk: rr[kk] for kk in ("bound", "frac", "achieved", "unit")}
     config = {"workload": wl["label"] + f"; {args.mode.upper()} mode; batch of {args.batch} distinct pairs per step "
@@ -536,6 +615,7 @@ def main():
         "fp64": fp64,
         "stages_ms_per_pair": {k: round(v, 4) for k, v in head["stages_ms_per_pair"].items()},
         "stage_rooflines": stage_roofs,
+        "assembly_routes": routes,
     }
     print(json.dumps(out), flush=True)
 

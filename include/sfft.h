@@ -72,18 +72,25 @@ typedef struct {
 } sfft_desc;
 
 /* How the lag windows of Omega and beta are computed (sfft_desc.flags).
- * Both routes give the same sums up to rounding:
+ * All routes give the same sums up to rounding:
  *   FFT    -- zero-padded transforms, spectral products, pruned inverses
  *             (cost ~ P^2 log P per plane; the route for large frames);
  *   DIRECT -- plain FP64 sums over the frame, sum_z X_l(z) X_r(z + d), for
  *             every lag d of every window (cost ~ lags * N^2; wins for small
  *             frames; needs nx <= 1024 and w <= 9, else SFFT_EINVAL);
+ *   MFMA   -- the same FP64 sums as matrix-core products: for each source
+ *             row y' of the right plane, C(dy, dx) += sum_x X_l(y' - dy, x)
+ *             X_r(y', x + dx) is a (16 lags dy) x K x (16 lags dx) product
+ *             on v_mfma_f64_16x16x4f64 (cost ~ lags^2 * N^2, on the FP64
+ *             matrix cores; any w);
  *   AUTO   -- DIRECT when it is allowed and needs at most 1e9 multiply-adds,
- *             else FFT. */
+ *             else FFT, until sfft_autotune_route has timed the routes on
+ *             real inputs and kept the fastest. */
 enum {
   SFFT_FLAG_ASSEMBLY_AUTO = 0,
   SFFT_FLAG_ASSEMBLY_FFT = 1,
-  SFFT_FLAG_ASSEMBLY_DIRECT = 2
+  SFFT_FLAG_ASSEMBLY_DIRECT = 2,
+  SFFT_FLAG_ASSEMBLY_MFMA = 3
 };
 
 typedef struct sfft_plan_s* sfft_handle;
@@ -144,6 +151,40 @@ int sfft_fit_background(sfft_handle p, double* coeffs);
  * float* (F32C), pitch ld; coeffs: device double[n]. */
 int sfft_subtract(sfft_handle p, const void* sci, const void* tmpl, const double* coeffs,
                   void* diff, int64_t ld);
+
+/* Enqueue out = K * img, the plan's kernel applied to one image:
+ *   out(y, x) = sum_{a < nK} sum_{|u| <= w} k_{a,u} (m_a img)(y - u_y, x - u_x),
+ * zero outside the frame, k_{a,u} = kcoef[a L^2 + (u_y+w) L + (u_x+w)] (the
+ * kernel part of the coefficient layout, nK L^2 device doubles; any
+ * background part is ignored).  This is the model the subtraction removes,
+ * computed the same way (FFTs along x, the y-convolution in the row-spectral
+ * domain, direct sums on the border columns).  With DK = 0 and a (2w+1)^2
+ * stamp it is the plain linear convolution of pipeline step 5 of the paper
+ * ("Pipeline steps": cross-convolve the template PSF with the science image
+ * and the science PSF with the template), stamps up to 31 x 31 (w <= 15).
+ * img/out: double* (F64) or float* (F32C), pitch ld, distinct buffers; the
+ * arithmetic is FP64 in both modes.  Needs no build. */
+int sfft_apply_kernel(sfft_handle p, const void* img, const double* kcoef, void* out, int64_t ld);
+
+/* Enqueue the decorrelation kernel of pipeline step 7 of the paper
+ * ("Pipeline steps": fit the decorrelation kernel and apply it to the
+ * difference image, the science PSF and the cross-convolved science image;
+ * the paper gives no formula, this is the project's reading).  With the
+ * images cross-convolved as in step 5 (S' = P_R * S, R' = P_S * R) and
+ * independent white noise sigma_sci, sigma_tmpl on the science and template
+ * images, the difference image's noise has the spectrum
+ *   N(f) = sigma_sci^2 |P_R^(f)|^2 + sigma_tmpl^2 |K_c^(f)|^2 |P_S^(f)|^2,
+ * K_c the plan's matching kernel (coeffs, the fitted theta) at the frame
+ * centre, K_c(u) = sum_a k_{a,u} (-2u_x/(nx-1))^p_a (-2u_y/(ny-1))^q_a.
+ * The kernel with spectrum sqrt((sigma_sci^2 + sigma_tmpl^2) / N(f)) makes it
+ * white; spectra are DFTs on a 64 x 64 grid of the stamps centred on tap
+ * (0, 0), and psi is that kernel's (2t+1)^2 central taps:
+ * psi[(u_y+t)(2t+1) + (u_x+t)], device doubles.  psf_sci (P_S) and psf_tmpl
+ * (P_R): (2s+1)^2 device doubles, row-major, centred.  0 <= s, t <= 15 and
+ * finite sigmas > 0, else SFFT_EINVAL.  Apply psi with sfft_apply_kernel on a
+ * plan with w = t, DK = 0.  FP64; one block; needs no build. */
+int sfft_decorrelation_kernel(sfft_handle p, const double* coeffs, const double* psf_sci, const double* psf_tmpl,
+                              int32_t s, double sigma_sci, double sigma_tmpl, int32_t t, double* psi);
 
 /* Synchronise the plan's stream and report device-side outcomes of the
  * last build/solve: SFFT_ENONFINITE if a non-finite science/template value
@@ -222,6 +263,18 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
  * on the direct route has nothing to tune (count 0). */
 int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld, int32_t* c1_out,
                   float* ms_out, int32_t cap, int32_t* count_out);
+
+/* Time the assembly (sfft_build_system) of this plan on real inputs with each
+ * route -- FFT, DIRECT (where allowed) and MFMA, one warm-up and three timed
+ * builds each -- and, if the descriptor asks for SFFT_FLAG_ASSEMBLY_AUTO,
+ * keep the fastest in the plan (and in every batch member with pair 0's
+ * descriptor; for a batch handle the inputs are pair 0's).  A forced route is
+ * kept.  ms_out (host, may be NULL): 3 entries, the average build time of the
+ * FFT, DIRECT and MFMA routes in ms (-1 = not allowed); route_out (host, may
+ * be NULL): the flag value of the route in use afterwards.  Results of the
+ * routes agree up to rounding.  Synchronises the stream. */
+int sfft_autotune_route(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld,
+                        float* ms_out, int32_t* route_out);
 
 /* Capture one sfft_batch_run with these buffers into a HIP graph held by the
  * batch handle (replacing an earlier capture); nothing runs yet.  The batch

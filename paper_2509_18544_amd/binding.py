@@ -33,6 +33,8 @@ SFFT_MODE_F32C = 1
 SFFT_FLAG_ASSEMBLY_AUTO = 0
 SFFT_FLAG_ASSEMBLY_FFT = 1
 SFFT_FLAG_ASSEMBLY_DIRECT = 2
+SFFT_FLAG_ASSEMBLY_MFMA = 3
+ROUTES = ("fft", "direct", "mfma")
 
 
 class SfftError(RuntimeError):
@@ -83,6 +85,11 @@ def lib():
         "sfft_autotune": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float),
                                          i32, ctypes.POINTER(i32)]),
         "sfft_subtract_pair_noalloc": (ctypes.c_int, [D, vp, vp, vp, vp, i64, vp, vp, vp]),
+        "sfft_apply_kernel": (ctypes.c_int, [vp, vp, vp, vp, i64]),
+        "sfft_decorrelation_kernel": (ctypes.c_int, [vp, vp, vp, vp, i32, ctypes.c_double, ctypes.c_double, i32,
+                                                     vp]),
+        "sfft_autotune_route": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_float),
+                                               ctypes.POINTER(i32)]),
         "sfft_destroy": (None, [vp]),
         "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sfft_mlp_create": (ctypes.c_int, [ctypes.POINTER(i32), i32, i32, vp, ctypes.POINTER(vp)]),
@@ -178,6 +185,17 @@ def sfft_subtract(handle, sci, tmpl, coeffs, diff, ld: int):
            "sfft_subtract")
 
 
+def sfft_apply_kernel(handle, img, kcoef, out, ld: int):
+    _check(lib().sfft_apply_kernel(handle, _ptr(img), _ptr(kcoef), _ptr(out), int(ld)), "sfft_apply_kernel")
+
+
+def sfft_decorrelation_kernel(handle, coeffs, psf_sci, psf_tmpl, s: int, sigma_sci: float, sigma_tmpl: float,
+                              t: int, psi):
+    _check(lib().sfft_decorrelation_kernel(handle, _ptr(coeffs), _ptr(psf_sci), _ptr(psf_tmpl), int(s),
+                                           float(sigma_sci), float(sigma_tmpl), int(t), _ptr(psi)),
+           "sfft_decorrelation_kernel")
+
+
 def sfft_status(handle):
     """(status, info, nonfinite) after synchronising the plan's stream."""
     info = ctypes.c_int32(0)
@@ -265,6 +283,15 @@ def sfft_autotune(handle, sci, tmpl, mask, ld: int, cap: int = 16):
     return [(int(c1[i]), float(ms[i])) for i in range(cnt.value)]
 
 
+def sfft_autotune_route(handle, sci, tmpl, mask, ld: int):
+    """Time the assembly with each route; returns ({route: ms or None}, route in use)."""
+    ms = (ctypes.c_float * 3)()
+    r = ctypes.c_int32(0)
+    _check(lib().sfft_autotune_route(handle, _ptr(sci), _ptr(tmpl), _ptr(mask), int(ld), ms, ctypes.byref(r)),
+           "sfft_autotune_route")
+    return {ROUTES[i]: (None if ms[i] < 0 else float(ms[i])) for i in range(3)}, ROUTES[r.value - 1]
+
+
 def sfft_batch_launch(handle):
     _check(lib().sfft_batch_launch(handle), "sfft_batch_launch")
 
@@ -346,6 +373,14 @@ class Plan:
             diff = torch.empty_like(sci)
         sfft_subtract(self.handle, sci, tmpl, coeffs, diff, sci.stride(0))
         return diff
+
+    def apply_kernel(self, img, kcoef, out=None):
+        """out = K * img with the plan's w and DK (kcoef: nK (2w+1)^2 device doubles)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(img)
+        sfft_apply_kernel(self.handle, img, kcoef, out, img.stride(0))
+        return out
 
     def status(self):
         return sfft_status(self.handle)

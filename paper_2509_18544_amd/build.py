@@ -22,6 +22,10 @@ FLAGS = [
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
+    # keep the correlation kernel's per-rotation accumulate blocks apart: sunk
+    # into one block they need a register rotation per residue (more VALU
+    # instructions and 256 instead of 205 VGPRs)
+    "-mllvm", "-simplifycfg-sink-common=false",
 ]
 
 

@@ -111,10 +111,13 @@ __host__ __device__ constexpr int row_pass_lds(int nmax, int lgh) {
 }
 
 template <typename T, int THREADS, int NMAX, int LGH>
-__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kernel(AsmParams P, const T* __restrict__ sci,
-                                                          const T* __restrict__ tmpl,
-                                                          const uint8_t* __restrict__ mask, cplx<T>* __restrict__ U,
-                                                          const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kernel(AsmParams P, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const T* __restrict__ sci = static_cast<const T*>(PS.sci[pr]);
+  const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
+  const uint8_t* __restrict__ mask = PS.mask[pr];
+  cplx<T>* __restrict__ U = ws_at<cplx<T>>(PS, pr, O.Ub);
+  const cplx<T>* __restrict__ tw = ws_at<const cplx<T>>(PS, pr, sizeof(T) == 4 ? O.tw32 : O.tw64);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   constexpr int H = 1 << LGH;            // H = Px / 2
@@ -237,8 +240,11 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kerne
 // XH(ky) = (Z(ky) - conj Z(-ky))/(2i) go to columns 0 and H; its column 1 is
 // written as usual.
 template <typename T, int THREADS, int NMAX, int LGPY, int LGM>
-__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kernel(AsmParams P, const cplx<T>* __restrict__ Ub,
-                                                          cplx<T>* __restrict__ X, const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kernel(AsmParams P, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const cplx<T>* __restrict__ Ub = ws_at<const cplx<T>>(PS, pr, O.Ub);
+  cplx<T>* __restrict__ X = ws_at<cplx<T>>(PS, pr, O.U);
+  const cplx<T>* __restrict__ tw = ws_at<const cplx<T>>(PS, pr, sizeof(T) == 4 ? O.tw32 : O.tw64);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int npairs = P.H / 2;           // pairs 0 .. H/2-1
@@ -327,9 +333,15 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kerne
 // ---------------------------------------------------------------------------
 // corr: spectral products and pruned inverse along y on the lag rows
 // ---------------------------------------------------------------------------
-// One block per column kx in [0, H].  Residues k1 are processed in chunks of
-// C1; for each chunk every plane's P2 values X(k1 + P1 k2) are staged in LDS
-// in FP64.  With Z(k2) = conj(X_left(k2)) X_right(k2) and the inner inverse
+// One block per column kx in [0, H), with the Nyquist column H packed into
+// block 0: the columns kx = 0 and kx = H of a real image's 2-D transform are
+// conjugate-symmetric in ky, so their lag correlations V_0(j) and V_H(j) are
+// real and block 0 forms the single inverse of Z_0 + i Z_H, whose real and
+// imaginary parts are V_0 and V_H (row_win_kernel reads them so).  That makes
+// the grid H uniform blocks instead of H + 1, with no lone block in a last
+// round.  Block 0 stages both columns with half the residue chunk.
+// Residues k1 are processed in chunks of C1 (block 0: C1dc); for each chunk
+// every staged plane's P2 values X(k1 + P1 k2) are staged in LDS in FP64.  With Z(k2) = conj(X_left(k2)) X_right(k2) and the inner inverse
 // DFT F(r) = sum_k2 Z(k2) e^{2 pi i k2 r/P2}, lag row j = jlo + t accumulates
 //   V(j) += e^{2 pi i k1 j/Py} F((jlo + t) mod P2).
 // The rotation s = jlo mod P2 is a compile-time case of a switch (items are
@@ -353,16 +365,19 @@ __host__ __device__ constexpr int corr_step_elems(int njlo) { return (njlo * JMA
 template <int S>
 __device__ __forceinline__ void corr_accumulate(cplx<double>* acc, const cplx<double>* f,
                                                 const cplx<double>* __restrict__ tw) {
-  // all JMAX rows are accumulated (rows past the item's count are never written out)
+  // all JMAX rows are accumulated (rows past the item's count are never written out);
+  // four FMAs per complex multiply-add
 #pragma unroll
-  for (int t = 0; t < JMAX; ++t) acc[t] = acc[t] + tw[t] * f[(S + t) & (P2 - 1)];
+  for (int t = 0; t < JMAX; ++t) acc[t] = cmac(acc[t], tw[t], f[(S + t) & (P2 - 1)]);
 }
 
 template <typename T, int THREADS>
-__global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cplx<T>* __restrict__ U,
-                                                       const CorrItem* __restrict__ items,
-                                                       cplx<double>* __restrict__ V,
-                                                       const cplx<double>* __restrict__ twd, int C1) {
+__global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet PS, WsOff O, int C1, int C1dc) {
+  const int pr = blockIdx.z;
+  const cplx<T>* __restrict__ U = ws_at<const cplx<T>>(PS, pr, O.U);
+  const CorrItem* __restrict__ items = ws_at<const CorrItem>(PS, pr, O.items);
+  cplx<double>* __restrict__ V = ws_at<cplx<double>>(PS, pr, O.V);
+  const cplx<double>* __restrict__ twd = ws_at<const cplx<double>>(PS, pr, O.tw64);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // LDS: [twstep: njlo x JMAX] [stage: spectra, then the chunk's outer twiddles].
   // The lane reduction at the end of a pass of items overlays the stage only,
@@ -370,6 +385,7 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
   cplx<double>* twstep = reinterpret_cast<cplx<double>*>(smem_raw);   // [njlo][JMAX]
   cplx<double>* stage = twstep + corr_step_elems(P.njlo);
   const int kx = blockIdx.x;
+  const bool pk = kx == 0;                     // the DC and Nyquist columns, packed
   const int H = P.H;
   const int Py = 1 << P.lgPy;
   const int lgPy = P.lgPy;
@@ -380,13 +396,15 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
   const int ipw = 64 / lanes;            // items per wave
   const int nwaves = (nitems + ipw - 1) / ipw;
   const int64_t pstride = (int64_t)(H + 1) * Py;
-  const int per_plane = corr_plane_stride(C1);
+  const int C = pk ? C1dc : C1;                // residues per chunk of this block
+  const int nst = pk ? 2 * P.nplanes : P.nplanes;   // staged planes (block 0: column 0, then column H)
+  const int per_plane = corr_plane_stride(C);
   // outer twiddles e^{2 pi i k1 (jlo + t)/Py} of the chunk, per distinct jlo, after the spectra
-  cplx<double>* twc = stage + P.nplanes * per_plane;       // [njlo][C1][JMAX]
-  // e^{2 pi i C1 j / Py}: advancing k1 by one chunk multiplies each outer twiddle by it
+  cplx<double>* twc = stage + nst * per_plane;              // [njlo][C][JMAX]
+  // e^{2 pi i C j / Py}: advancing k1 by one chunk multiplies each outer twiddle by it
   for (int e = tid; e < P.njlo * JMAX; e += THREADS) {
     const int ji = e / JMAX, t = e - ji * JMAX;
-    const int m = (C1 * ((int)P.jlo_list[ji] + t)) & (Py - 1);
+    const int m = (C * ((int)P.jlo_list[ji] + t)) & (Py - 1);
     twstep[e] = conjg(twd[m << (TW_LOG - lgPy)]);
   }
 
@@ -408,14 +426,14 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
 #pragma unroll
     for (int t = 0; t < JMAX; ++t) acc[t] = mk(0.0, 0.0);
 
-    for (int k1c = 0; k1c < P1; k1c += C1) {
-      const int nc = min(C1, P1 - k1c);
+    for (int k1c = 0; k1c < P1; k1c += C) {
+      const int nc = min(C, P1 - k1c);
       __syncthreads();
       // spectra: two neighbouring values per load (16 bytes in FP32).  The
       // loads of a batch of CORR_LB per thread are all issued before any is
       // converted and stored, so their latencies overlap.
       const int npr = nc * (P2 / 2);
-      const int ntot = P.nplanes * npr;
+      const int ntot = nst * npr;
       for (int e0 = tid; e0 < ntot; e0 += CORR_LB * THREADS) {
         cplx<T> q[CORR_LB][2];
 #pragma unroll
@@ -423,7 +441,9 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
           const int e = min(e0 + b * THREADS, ntot - 1);   // a valid element; the copy is dropped below
           const int pl = e / npr;
           const int o = 2 * (e - pl * npr);
-          const cplx<T>* src = U + pl * pstride + (int64_t)kx * Py + (int64_t)k1c * P2 + o;
+          const bool hi = pl >= P.nplanes;                 // block 0: the Nyquist column's planes
+          const int col = hi ? H : kx;
+          const cplx<T>* src = U + (pl - (hi ? P.nplanes : 0)) * pstride + (int64_t)col * Py + (int64_t)k1c * P2 + o;
           if constexpr (sizeof(T) == sizeof(float)) {
             const float4 f = *reinterpret_cast<const float4*>(src);
             q[b][0] = mk(f.x, f.y);
@@ -449,9 +469,9 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
       // so the index is the product masked to [0, Py)), then by the FP64 step
       for (int ji = 0; ji < P.njlo; ++ji) {
         const int jlo = P.jlo_list[ji];
-        for (int r = tid; r < C1 * JMAX; r += THREADS) {
+        for (int r = tid; r < C * JMAX; r += THREADS) {
           const int t = r % JMAX;
-          cplx<double>& w = twc[ji * C1 * JMAX + r];
+          cplx<double>& w = twc[ji * C * JMAX + r];
           if (k1c == 0) {
             const int c = r / JMAX;
             const int m = (c * (jlo + t)) & (Py - 1);
@@ -470,8 +490,15 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, const cpl
         cplx<double> z[P2];
 #pragma unroll
         for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(xa[k2], xb[k2]);
+        if (pk) {
+          // + i Z_H: the Nyquist column's product on the imaginary axis
+          const cplx<double>* ya = xa + P.nplanes * per_plane;
+          const cplx<double>* yb = xb + P.nplanes * per_plane;
+#pragma unroll
+          for (int k2 = 0; k2 < P2; ++k2) z[k2] = z[k2] + rot90<double, true>(cmulc(ya[k2], yb[k2]));
+        }
         dft16<double, true>(z);
-        const cplx<double>* twt = twc + ((int)it.jidx * C1 + c) * JMAX;
+        const cplx<double>* twt = twc + ((int)it.jidx * C + c) * JMAX;
         (void)k1;
         switch (srot) {
 #define CORR_CASE(SV) \
@@ -555,11 +582,13 @@ __device__ __forceinline__ double plane_value(const AsmParams& P, int pl, int y,
 }
 
 template <typename T, int THREADS>
-__global__ __launch_bounds__(THREADS) void direct_win_kernel(AsmParams P, const T* __restrict__ sci,
-                                                             const T* __restrict__ tmpl,
-                                                             const uint8_t* __restrict__ mask,
-                                                             const DirectRow* __restrict__ rows,
-                                                             double* __restrict__ part, int nwin) {
+__global__ __launch_bounds__(THREADS) void direct_win_kernel(AsmParams P, PairSet PS, WsOff O, int nwin) {
+  const int pr = blockIdx.z;
+  const T* __restrict__ sci = static_cast<const T*>(PS.sci[pr]);
+  const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
+  const uint8_t* __restrict__ mask = PS.mask[pr];
+  const DirectRow* __restrict__ rows = ws_at<const DirectRow>(PS, pr, O.drows);
+  double* __restrict__ part = ws_at<double>(PS, pr, O.U);   // per-band partial sums
   constexpr int NACC = 2 * DIR_HWMAX + 1;
   constexpr int MAXRPP = THREADS / DIR_MIN_TPR;
   // rpp staged rows of tpr * DIR_XB + 2 hw values: at most THREADS * DIR_XB + MAXRPP * 2 DIR_HWMAX
@@ -625,12 +654,132 @@ __global__ __launch_bounds__(THREADS) void direct_win_kernel(AsmParams P, const 
 }
 
 // win[i] = sum over bands of part[band][i], bands in order
-__global__ void dir_reduce_kernel(const double* __restrict__ part, int nband, int nwin, double* __restrict__ win) {
+__global__ void dir_reduce_kernel(PairSet PS, WsOff O, int nband, int nwin) {
+  const int pr = blockIdx.z;
+  const double* __restrict__ part = ws_at<const double>(PS, pr, O.U);
+  double* __restrict__ win = ws_at<double>(PS, pr, O.win);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nwin) return;
   double v = 0.0;
   for (int b = 0; b < nband; ++b) v += part[(int64_t)b * nwin + i];
   win[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// MFMA route: lag windows as FP64 matrix-core products (no transforms)
+// ---------------------------------------------------------------------------
+// For a source row y' of the right plane X_r and the 16 lags dy of a tile,
+//   C(dy, dx) += sum_x X_l(y' - dy, x) X_r(y', x + dx)
+// is the product of the 16 x K matrix A[dy][x] = X_l(y' - dy, x) (rows of the
+// left plane) and the K x 16 Hankel matrix B[x][dx] = X_r(y', x + dx), run on
+// v_mfma_f64_16x16x4f64 with K = 4 pixels per instruction and every dx tile
+// of the window sharing the A operand.  Summing over y' and x gives the lag
+// window itself (z = (y' - dy, x) runs over the frame).
+// A block owns one (pair, dy tile), one chunk of MFMA_XC columns x and one
+// band of source rows y'.  It sweeps the band row by row: the 16 left-plane
+// rows of the tile sit in an LDS ring (one new row enters per step, the row
+// of the largest y), the right-plane row with its +-hw margin beside it, and
+// the next step's values are loaded into registers while the matrix cores
+// run.  The four waves split the chunk's columns, each accumulating every dx
+// tile; at the end the waves' tiles are summed through LDS and the block
+// writes one partial window per (chunk, band), summed over chunks and bands
+// in a fixed order by dir_reduce_kernel.  Operand layout of the MFMA: lane l
+// gives A[l%16][l/16] and B[l/16][l%16]; register r of lane l holds
+// D[l/16 + 4r][l%16].
+struct MfmaTile {
+  int16_t left, right;   // planes
+  int16_t hw, dy0;       // lag half-width; the tile's lags are dy0 .. dy0 + 15
+  int32_t out;           // offset of the pair's window ((2hw+1) x (2hw+1), dy-major) in `win`
+};
+constexpr int MFMA_XC = 256;                    // columns per block, 64 per wave
+constexpr int MFMA_MAXT = 4;                    // dx tiles: 2 hw + 1 <= 64
+constexpr int MFMA_RS = MFMA_XC + 4;            // ring row stride (doubles): spreads the 16 rows over the banks
+constexpr int MFMA_XR = MFMA_XC + 2 * 32;       // right-plane row with its margin (hw <= 31)
+constexpr int MFMA_THREADS = 256;
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(MFMA_THREADS) void mfma_win_kernel(AsmParams P, PairSet PS, WsOff O, int nwin,
+                                                                int nxc, int band) {
+  const int pr = blockIdx.z;
+  const T* __restrict__ sci = static_cast<const T*>(PS.sci[pr]);
+  const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
+  const uint8_t* __restrict__ mask = PS.mask[pr];
+  const MfmaTile Tl = ws_at<const MfmaTile>(PS, pr, O.mtiles)[blockIdx.x];
+  double* __restrict__ part = ws_at<double>(PS, pr, O.U);   // [chunk, band] partial windows
+  __shared__ double ring[16 * MFMA_RS];
+  __shared__ double xr[MFMA_XR];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int xc = (int)blockIdx.y % nxc, yb = (int)blockIdx.y / nxc;
+  const int x0 = xc * MFMA_XC;
+  const int ylo = yb * band, yhi = min(P.ny, ylo + band);
+  const int hw = Tl.hw, dy0 = Tl.dy0;
+  const int ndx = (2 * hw + 1 + 15) / 16;
+  const int nxr = MFMA_XC + 2 * hw;               // right-plane values per step
+  // prologue: the 15 older rows of the first step's tile (rows ylo - dy0 - 15 .. ylo - dy0 - 1)
+  for (int e = tid; e < 15 * MFMA_XC; e += MFMA_THREADS) {
+    const int m = e / MFMA_XC + 1, j = e - (m - 1) * MFMA_XC;
+    const int row = ylo - dy0 - m;
+    ring[(row & 15) * MFMA_RS + j] = plane_value<T>(P, Tl.left, row, x0 + j, sci, tmpl, mask);
+  }
+  // the values entering at step y: ring row y - dy0 and the right-plane row y
+  double av = 0.0, xv0 = 0.0, xv1 = 0.0;
+  auto fetch = [&](int y) {
+    av = plane_value<T>(P, Tl.left, y - dy0, x0 + tid, sci, tmpl, mask);
+    xv0 = plane_value<T>(P, Tl.right, y, x0 - hw + tid, sci, tmpl, mask);
+    xv1 = tid + MFMA_THREADS < nxr ? plane_value<T>(P, Tl.right, y, x0 - hw + tid + MFMA_THREADS, sci, tmpl, mask)
+                                   : 0.0;
+  };
+  auto store = [&](int y) {
+    ring[((y - dy0) & 15) * MFMA_RS + tid] = av;
+    xr[tid] = xv0;
+    if (tid + MFMA_THREADS < nxr) xr[tid + MFMA_THREADS] = xv1;
+  };
+  for (int e = tid; e < MFMA_XR; e += MFMA_THREADS) xr[e] = 0.0;   // the margin past nxr stays zero
+  __syncthreads();
+  if (ylo < yhi) {
+    fetch(ylo);
+    store(ylo);
+  }
+  mf64x4 acc[MFMA_MAXT];
+#pragma unroll
+  for (int t = 0; t < MFMA_MAXT; ++t) acc[t] = mf64x4{0.0, 0.0, 0.0, 0.0};
+  const int xw = wave * (MFMA_XC / 4);            // this wave's first column in the chunk
+  for (int y = ylo; y < yhi; ++y) {
+    __syncthreads();
+    if (y + 1 < yhi) fetch(y + 1);                // in flight while the matrix cores run
+    const double* arow = ring + ((y - dy0 - lr) & 15) * MFMA_RS + xw + lk;
+    const double* brow = xr + xw + lk + lr;
+#pragma unroll 4
+    for (int ks = 0; ks < MFMA_XC / 16; ++ks) {
+      const double a = arow[4 * ks];
+#pragma unroll
+      for (int t = 0; t < MFMA_MAXT; ++t)
+        if (t < ndx) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[4 * ks + 16 * t], acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+    if (y + 1 < yhi) store(y + 1);
+  }
+  // sum the four waves' tiles through LDS (over the ring), then write the partial window
+  __syncthreads();
+  double* red = ring;   // [wave][t][16 x 16]
+#pragma unroll
+  for (int t = 0; t < MFMA_MAXT; ++t)
+    if (t < ndx)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(wave * MFMA_MAXT + t) * 256 + (lk + 4 * r) * 16 + lr] = acc[t][r];
+  __syncthreads();
+  const int h = 2 * hw + 1;
+  double* dst = part + (int64_t)blockIdx.y * nwin + Tl.out;
+  for (int t = 0; t < ndx; ++t) {
+    const int m = tid >> 4, n = tid & 15;
+    const int dy = dy0 + m, dx = -hw + 16 * t + n;
+    const double v = (red[(0 * MFMA_MAXT + t) * 256 + tid] + red[(1 * MFMA_MAXT + t) * 256 + tid]) +
+                     (red[(2 * MFMA_MAXT + t) * 256 + tid] + red[(3 * MFMA_MAXT + t) * 256 + tid]);
+    if (dy <= hw && dx <= hw) dst[(dy + hw) * h + (dx + hw)] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -645,10 +794,12 @@ struct WinRow {
 };
 
 template <int THREADS, int IMAX>
-__global__ __launch_bounds__(THREADS) void row_win_kernel(AsmParams P, const cplx<double>* __restrict__ V,
-                                                          const WinRow* __restrict__ rows, int nrows,
-                                                          double* __restrict__ win,
-                                                          const cplx<double>* __restrict__ twd) {
+__global__ __launch_bounds__(THREADS) void row_win_kernel(AsmParams P, PairSet PS, WsOff O, int nrows) {
+  const int pr = blockIdx.z;
+  const cplx<double>* __restrict__ V = ws_at<const cplx<double>>(PS, pr, O.V);
+  const WinRow* __restrict__ rows = ws_at<const WinRow>(PS, pr, O.wrows);
+  double* __restrict__ win = ws_at<double>(PS, pr, O.win);
+  const cplx<double>* __restrict__ twd = ws_at<const cplx<double>>(PS, pr, O.tw64);
   static_assert(THREADS == 64, "one wave per window row");
   constexpr int HMAX = (IMAX - 1) / 2;   // largest half-width
   // V is stored [kx][vrow]: neighbouring rows share every cache line they
@@ -667,17 +818,17 @@ __global__ __launch_bounds__(THREADS) void row_win_kernel(AsmParams P, const cpl
   double cc[HMAX + 1], cs[HMAX + 1];
 #pragma unroll
   for (int m = 0; m <= HMAX; ++m) cc[m] = cs[m] = 0.0;
-  for (int kx = tid; kx <= H; kx += THREADS) {
+  for (int kx = tid; kx < H; kx += THREADS) {
     const cplx<double> v = V[(int64_t)kx * P.vrows + R.vrow];
-    if (kx == 0 || kx == H) {
-      // real values with weight 1; at the Nyquist column cos(pi m) = (-1)^m
-      const bool nyq = (kx == H);
+    if (kx == 0) {
+      // the packed DC (real part) and Nyquist (imaginary part) columns: real
+      // values with weight 1; at the Nyquist column cos(pi m) = (-1)^m
       double sg = 1.0;
 #pragma unroll
       for (int m = 0; m <= HMAX; ++m) {
         if (m <= hw) {
-          cc[m] += sg * v.x;
-          if (nyq) sg = -sg;
+          cc[m] += v.x + sg * v.y;
+          sg = -sg;
         }
       }
     } else {
@@ -718,10 +869,13 @@ __global__ __launch_bounds__(THREADS) void row_win_kernel(AsmParams P, const cpl
 // mom[y][p]          = sum_x G xh^p,      p in [0, 2DB]
 // mom[y][2DB+1+p]    = sum_x G S xh^p,    p in [0, DB]
 template <typename T, int THREADS>
-__global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, const T* __restrict__ sci,
-                                                          const T* __restrict__ tmpl,
-                                                          const uint8_t* __restrict__ mask,
-                                                          double* __restrict__ mom, int* __restrict__ nonfinite) {
+__global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const T* __restrict__ sci = static_cast<const T*>(PS.sci[pr]);
+  const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
+  const uint8_t* __restrict__ mask = PS.mask[pr];
+  double* __restrict__ mom = ws_at<double>(PS, pr, O.mom);
+  int* __restrict__ nonfinite = ws_at<int>(PS, pr, O.flags) + 1;
   constexpr int NG_MAX = 2 * MAX_DEG + 1;
   constexpr int NS_MAX = MAX_DEG + 1;
   constexpr int NM = NG_MAX + NS_MAX;
@@ -779,8 +933,11 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, const T* 
 // Omega_BB and beta_B from the per-row moments: one block per output, fixed
 // summation order (deterministic).
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, const double* __restrict__ mom,
-                                                                 double* __restrict__ obb, double* __restrict__ bb) {
+__global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const double* __restrict__ mom = ws_at<const double>(PS, pr, O.mom);
+  double* __restrict__ obb = ws_at<double>(PS, pr, O.obb);
+  double* __restrict__ bb = ws_at<double>(PS, pr, O.bb);
   __shared__ double red[THREADS / 64];
   const int tid = threadIdx.x;
   const int nb = P.nb;
@@ -823,9 +980,13 @@ struct GatherParams {
   int ks_off[MAX_NB];           // window offset of corr(A_a, S_m)
 };
 
-__global__ void gather_kernel(GatherParams G, const double* __restrict__ win, const double* __restrict__ obb,
-                              const double* __restrict__ bb, double* __restrict__ omega,
-                              double* __restrict__ beta) {
+__global__ void gather_kernel(GatherParams G, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const double* __restrict__ win = ws_at<const double>(PS, pr, O.win);
+  const double* __restrict__ obb = ws_at<const double>(PS, pr, O.obb);
+  const double* __restrict__ bb = ws_at<const double>(PS, pr, O.bb);
+  double* __restrict__ omega = ws_at<double>(PS, pr, O.omega);
+  double* __restrict__ beta = ws_at<double>(PS, pr, O.beta);
   const int r = blockIdx.y;
   const int L = G.L, w = G.w;
   const int L2 = L * L;
@@ -863,6 +1024,11 @@ __global__ void gather_kernel(GatherParams G, const double* __restrict__ win, co
       beta[r] = bb[r - G.nkk];
     }
   }
+}
+
+// The non-finite flag of every pair of the group, cleared before a build.
+__global__ void clear_nonfinite_kernel(PairSet PS, WsOff O) {
+  if (threadIdx.x == 0) ws_at<int>(PS, blockIdx.z, O.flags)[1] = 0;
 }
 
 }  // namespace sfft

@@ -491,6 +491,17 @@ __global__ void copy_out_kernel(const double* __restrict__ src, double* __restri
   if (i < n) dst[i] = src[i];
 }
 
+// theta -> the caller's coefficients and the solve outcome -> info, for every
+// pair of a group (pair blockIdx.z); coefficients untouched if info != 0
+__global__ void copy_out_group_kernel(PairSet PS, WsOff O, int n) {
+  const int pr = blockIdx.z;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int inf = ws_at<const int>(PS, pr, O.flags)[0];
+  if (i == 0 && PS.info[pr] != nullptr) *PS.info[pr] = inf;
+  if (inf != 0) return;
+  if (i < n) PS.coeffs[pr][i] = ws_at<const double>(PS, pr, O.theta)[i];
+}
+
 __global__ void set_int_kernel(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }

@@ -364,6 +364,33 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
+// ---------------------------------------------------------------------------
+// batched launches
+// ---------------------------------------------------------------------------
+// A launch serves a group of up to MAX_GROUP pairs that share a descriptor and
+// a row pitch, so that every size, table and workspace offset is the same for
+// all of them: pair blockIdx.z reads its own images and workspace through a
+// PairSet passed by value (a captured graph holds the pointers themselves).
+constexpr int MAX_GROUP = 32;
+struct PairSet {
+  const void* sci[MAX_GROUP];
+  const void* tmpl[MAX_GROUP];
+  const uint8_t* mask[MAX_GROUP];   // entries may be null (no mask)
+  unsigned char* ws[MAX_GROUP];     // the pair's workspace
+  double* coeffs[MAX_GROUP];        // theta: read by the subtraction, written by the solve's copy-out
+  void* diff[MAX_GROUP];
+  int32_t* info[MAX_GROUP];         // per-pair solve outcome (entries may be null)
+};
+// Byte offsets of the workspace buffers (the same for every pair of a group).
+struct WsOff {
+  size_t Ub, U, V, win, mom, obb, bb, omega, beta, kp, flags, tw32, tw64, items, wrows, drows, mtiles, theta;
+  size_t Uq, Mh, G;   // the subtraction's buffers (inside the U region)
+};
+template <typename X>
+__device__ __forceinline__ X* ws_at(const PairSet& S, int pr, size_t off) {
+  return reinterpret_cast<X*>(S.ws[pr] + off);
+}
+
 __device__ __forceinline__ double ipow(double x, int p) {
   double r = 1.0;
   for (int i = 0; i < p; ++i) r *= x;

@@ -20,6 +20,7 @@
 #include "assemble.hpp"
 #include "cholesky.hpp"
 #include "common.hpp"
+#include "decorr.hpp"
 #include "subtract.hpp"
 
 using namespace sfft;
@@ -38,6 +39,11 @@ constexpr int WIN_IMAX = 64;
 constexpr int MAX_N = 8192;           // unknowns (the triangular solves keep x in LDS)
 constexpr int MAX_W = 15;
 constexpr double DIR_AUTO_FMA = 1.0e9;   // direct lag sums below this many multiply-adds (small frames)
+constexpr int MFMA_TARGET_BLOCKS = 2048;  // the MFMA route splits the rows into bands up to about this many blocks
+constexpr int MAX_MTILES = MFMA_MAXT * MAX_ITEMS;   // (pair, dy tile) units of the MFMA route
+
+// how the lag windows are computed
+enum Route { ROUTE_FFT = 0, ROUTE_DIRECT = 1, ROUTE_MFMA = 2 };
 
 // A vector of fixed capacity held inline: filling it never allocates, so a
 // plan can be derived into static storage (the no-allocation entry point).
@@ -67,7 +73,8 @@ struct FixedVec {
 constexpr int MAX_VROWS = JMAX * MAX_ITEMS;
 
 struct Layout {
-  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, w, kp, flags, tw32, tw64, items, wrows, drows, job;
+  size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, w, kp, flags, tw32, tw64, items, wrows, drows,
+      mtiles, job;
   size_t total;
 };
 
@@ -87,8 +94,10 @@ struct Derived {
   size_t csize;   // sizeof complex element of the transforms
   FixedVec<CorrItem, MAX_ITEMS> items;
   FixedVec<WinRow, MAX_VROWS> wrows;
-  bool direct;                    // lag windows by direct sums instead of transforms
+  int route;                      // Route: transforms, direct sums or matrix-core products
   FixedVec<DirectRow, MAX_VROWS> drows;
+  FixedVec<MfmaTile, MAX_MTILES> mtiles;
+  int mfma_nxc, mfma_band, mfma_nband;   // MFMA route: column chunks, rows per band, bands
   int dir_tpr, dir_nband;
   GatherParams gp;
   PolyTab kpoly, bpoly;
@@ -120,7 +129,7 @@ int validate(const sfft_desc* d) {
   if (d->ny > (1 << MAX_LOG_P) || d->nx > (1 << MAX_LOG_P)) return SFFT_EINVAL;
   if (d->mode != SFFT_MODE_F64 && d->mode != SFFT_MODE_F32C) return SFFT_EINVAL;
   if (d->refine_steps < -1 || d->refine_steps > 10) return SFFT_EINVAL;
-  if ((d->flags & ~3) != 0 || (d->flags & 3) == 3) return SFFT_EINVAL;
+  if ((d->flags & ~3) != 0) return SFFT_EINVAL;
   if ((d->flags & 3) == SFFT_FLAG_ASSEMBLY_DIRECT && (d->nx > DIR_MAX_NX || 2 * d->w > DIR_HWMAX)) return SFFT_EINVAL;
   const int L = 2 * d->w + 1;
   const int nk = (d->dk + 1) * (d->dk + 2) / 2, nb = (d->db + 1) * (d->db + 2) / 2;
@@ -201,6 +210,7 @@ int derive(const sfft_desc* d, Derived* D) {
   D->items.clear();
   D->wrows.clear();
   D->drows.clear();
+  D->mtiles.clear();
   int vrow = 0, wo = 0;
   bool fits = true;   // every table stayed within its capacity
   auto add_pair = [&](int left, int right, int hw) {
@@ -229,6 +239,15 @@ int derive(const sfft_desc* d, Derived* D) {
       q.dy = (int16_t)(j - hw);
       q.out = wo + j * h;
       fits &= D->drows.push_back(q);
+    }
+    for (int dy0 = -hw; dy0 <= hw; dy0 += 16) {
+      MfmaTile t;
+      t.left = (int16_t)left;
+      t.right = (int16_t)right;
+      t.hw = (int16_t)hw;
+      t.dy0 = (int16_t)dy0;
+      t.out = wo;
+      fits &= D->mtiles.push_back(t);
     }
     const int off = wo;
     vrow += h;
@@ -330,7 +349,16 @@ int derive(const sfft_desc* d, Derived* D) {
     for (const DirectRow& q : D->drows) fma += (2.0 * q.hw + 1.0) * (double)d->ny * (double)d->nx;
     const bool ok = d->nx <= DIR_MAX_NX && 2 * d->w <= DIR_HWMAX;
     const int rf = d->flags & 3;
-    D->direct = rf == SFFT_FLAG_ASSEMBLY_DIRECT || (rf == SFFT_FLAG_ASSEMBLY_AUTO && ok && fma <= DIR_AUTO_FMA);
+    const bool direct = rf == SFFT_FLAG_ASSEMBLY_DIRECT || (rf == SFFT_FLAG_ASSEMBLY_AUTO && ok && fma <= DIR_AUTO_FMA);
+    D->route = rf == SFFT_FLAG_ASSEMBLY_MFMA ? ROUTE_MFMA : (direct ? ROUTE_DIRECT : ROUTE_FFT);
+    // MFMA route: column chunks, then row bands until the grid has about
+    // MFMA_TARGET_BLOCKS blocks (bands of at least 16 rows)
+    D->mfma_nxc = (d->nx + MFMA_XC - 1) / MFMA_XC;
+    const int base = std::max(1, D->mtiles.size() * D->mfma_nxc);
+    const int nb_max = std::max(1, d->ny / 16);
+    const int nband = std::min(nb_max, std::max(1, (MFMA_TARGET_BLOCKS + base - 1) / base));
+    D->mfma_band = (d->ny + nband - 1) / nband;
+    D->mfma_nband = (d->ny + D->mfma_band - 1) / D->mfma_band;
     int tpr = DIR_MIN_TPR;
     while (tpr * DIR_XB < d->nx) tpr *= 2;
     D->dir_tpr = tpr;
@@ -364,11 +392,14 @@ Layout layout_of(const Derived& D) {
   {
     // the subtraction's spectra reuse the assembly's spectra region (not live at the same time)
     const size_t asm_bytes = (size_t)D.nplanes * (D.H + 1) * D.Py * D.csize;
+    // x-power spectra, model spectrum and filters G (FP64)
     const size_t sub_bytes = align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>)) +
                              align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>)) +
-                             2 * align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>));   // K and G
-    const size_t dir_bytes = (size_t)D.dir_nband * D.nwin * sizeof(double);   // direct-route partial sums
-    Lo.U = take(std::max(std::max(asm_bytes, sub_bytes), dir_bytes));
+                             align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>));
+    // direct and MFMA route partial sums (per band, per chunk and band)
+    const size_t dir_bytes = (size_t)D.dir_nband * D.nwin * sizeof(double);
+    const size_t mfma_bytes = (size_t)D.mfma_nxc * D.mfma_nband * D.nwin * sizeof(double);
+    Lo.U = take(std::max(std::max(asm_bytes, sub_bytes), std::max(dir_bytes, mfma_bytes)));
   }
   Lo.V = take((size_t)(D.H + 1) * D.vrows * sizeof(cplx<double>));
   Lo.win = take((size_t)D.nwin * sizeof(double));
@@ -391,6 +422,7 @@ Layout layout_of(const Derived& D) {
   Lo.items = take((size_t)D.nitems * sizeof(CorrItem));
   Lo.wrows = take((size_t)D.wrows.size() * sizeof(WinRow));
   Lo.drows = take((size_t)D.drows.size() * sizeof(DirectRow));
+  Lo.mtiles = take((size_t)D.mtiles.size() * sizeof(MfmaTile));
   Lo.job = take(sizeof(SolveJob));
   Lo.total = off;
   return Lo;
@@ -609,15 +641,53 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
   return A;
 }
 
+// Byte offsets of the workspace buffers handed to the kernels.
+WsOff ws_offsets(const Derived& D, const Layout& Lo) {
+  WsOff O;
+  O.Ub = Lo.Ub;
+  O.U = Lo.U;
+  O.V = Lo.V;
+  O.win = Lo.win;
+  O.mom = Lo.mom;
+  O.obb = Lo.obb;
+  O.bb = Lo.bb;
+  O.omega = Lo.omega;
+  O.beta = Lo.beta;
+  O.kp = Lo.kp;
+  O.flags = Lo.flags;
+  O.tw32 = Lo.tw32;
+  O.tw64 = Lo.tw64;
+  O.items = Lo.items;
+  O.wrows = Lo.wrows;
+  O.drows = Lo.drows;
+  O.mtiles = Lo.mtiles;
+  O.theta = Lo.theta;
+  // the subtraction's x-power spectra, model spectrum and filters reuse the U region
+  O.Uq = Lo.U;
+  O.Mh = O.Uq + align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>));
+  O.G = O.Mh + align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>));
+  return O;
+}
+
+// The buffers of one pair on its plan's workspace, as a group of one.
+PairSet pair_set_one(const sfft_plan_s* p, const void* sci, const void* tmpl, const uint8_t* mask,
+                     const double* coeffs, void* diff, int32_t* info);
+
 // Residue chunk of the correlation kernel: the spectra of C1 residues of every
-// plane (FP64, padded) and their outer twiddles are staged in LDS per chunk.
-// Layout: the twiddle steps, then the larger of the stage (spectra and the
-// chunk's outer twiddles) and the lane-reduction buffer that overlays it.
+// plane (FP64, padded) and their outer twiddles are staged in LDS per chunk;
+// block 0, which carries the DC and Nyquist columns, stages both with the
+// chunk corr_dc_chunk(C1).  Layout: the twiddle steps, then the largest of
+// the two stages (spectra and the chunk's outer twiddles) and the
+// lane-reduction buffer that overlays them.
+int corr_dc_chunk(int C1) { return std::max(1, C1 / 2); }
 size_t corr_lds_bytes(const Derived& D, int C1) {
   const size_t steps = (size_t)corr_step_elems(D.njlo) * sizeof(cplx<double>);
+  const int cd = corr_dc_chunk(C1);
   const size_t stage = ((size_t)D.nplanes * corr_plane_stride(C1) + (size_t)D.njlo * C1 * JMAX) * sizeof(cplx<double>);
+  const size_t stage_dc =
+      ((size_t)2 * D.nplanes * corr_plane_stride(cd) + (size_t)D.njlo * cd * JMAX) * sizeof(cplx<double>);
   const size_t red = (size_t)ASM_THREADS * ((JMAX + 1) / 2) * sizeof(cplx<double>);
-  return steps + std::max(stage, red);
+  return steps + std::max(std::max(stage, stage_dc), red);
 }
 
 // Default chunk: the largest multiple of the item lanes whose LDS fits 80 KB
@@ -633,72 +703,76 @@ int corr_default_c1(const Derived& D) {
 }
 
 template <typename T>
-int launch_corr(sfft_plan_s* p, const AsmParams& A, int C1, bool timed) {
+int launch_corr(sfft_plan_s* p, const AsmParams& A, const PairSet& PS, int np, int C1, bool timed) {
   const Derived& D = p->D;
-  const Layout& Lo = p->Lo;
   hipStream_t s = p->stream;
   const size_t lds = corr_lds_bytes(D, C1);
   auto kfn = corr_kernel<T, ASM_THREADS>;
   HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (timed) p->timer.begin(SFFT_STAGE_CORR, s);
-  kfn<<<D.H + 1, ASM_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.U), p->at<CorrItem>(Lo.items),
-                                        p->at<cplx<double>>(Lo.V), p->at<cplx<double>>(Lo.tw64), C1);
+  kfn<<<dim3(D.H, 1, np), ASM_THREADS, lds, s>>>(A, PS, ws_offsets(D, p->Lo), C1, corr_dc_chunk(C1));
   LAUNCH_CHECK();
   if (timed) p->timer.end(s);
   return SFFT_OK;
 }
 
 // moments reduction and the Omega/beta gather (both assembly routes)
-int gather_impl(sfft_plan_s* p, const AsmParams& A) {
+int gather_impl(sfft_plan_s* p, const AsmParams& A, const PairSet& PS, int np) {
   const Derived& D = p->D;
-  const Layout& Lo = p->Lo;
+  const WsOff O = ws_offsets(D, p->Lo);
   hipStream_t s = p->stream;
   p->timer.begin(SFFT_STAGE_GATHER, s);
-  moments_reduce_kernel<ASM_THREADS><<<D.nb * D.nb + D.nb, ASM_THREADS, 0, s>>>(A, p->at<double>(Lo.mom), p->at<double>(Lo.obb),
-                                                               p->at<double>(Lo.bb));
+  moments_reduce_kernel<ASM_THREADS><<<dim3(D.nb * D.nb + D.nb, 1, np), ASM_THREADS, 0, s>>>(A, PS, O);
   LAUNCH_CHECK();
-  {
-    dim3 grid((D.n + 255) / 256, D.n);
-    gather_kernel<<<grid, 256, 0, s>>>(D.gp, p->at<double>(Lo.win), p->at<double>(Lo.obb), p->at<double>(Lo.bb),
-                                       p->at<double>(Lo.omega), p->at<double>(Lo.beta));
-    LAUNCH_CHECK();
-  }
+  gather_kernel<<<dim3((D.n + 255) / 256, D.n, np), 256, 0, s>>>(D.gp, PS, O);
+  LAUNCH_CHECK();
   p->timer.end(s);
   return SFFT_OK;
 }
 
+// Assembly of Omega and beta for the np pairs of PS, which share the plan
+// p's descriptor and row pitch (p is one of them: its sizes, tables and
+// workspace offsets are every pair's).
 template <typename T>
-int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask, int64_t ld) {
+int build_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   const Derived& D = p->D;
-  const Layout& Lo = p->Lo;
   hipStream_t s = p->stream;
   const AsmParams A = asm_params(p, ld);
-  cplx<T>* U = p->at<cplx<T>>(Lo.U);
-  const cplx<T>* tw = std::is_same<T, float>::value ? reinterpret_cast<const cplx<T>*>(p->at<cplx<float>>(Lo.tw32))
-                                                     : reinterpret_cast<const cplx<T>*>(p->at<cplx<double>>(Lo.tw64));
-  const cplx<double>* twd = p->at<cplx<double>>(Lo.tw64);
-  int* flags = p->at<int>(Lo.flags);
+  const WsOff O = ws_offsets(D, p->Lo);
 
-  set_int_kernel<<<1, 64, 0, s>>>(flags + 1, 0);
+  clear_nonfinite_kernel<<<dim3(1, 1, np), 64, 0, s>>>(PS, O);
   LAUNCH_CHECK();
   p->timer.begin(SFFT_STAGE_MOMENTS, s);
-  moments_kernel<T, ASM_THREADS><<<D.ny, ASM_THREADS, 0, s>>>(A, sci, tmpl, mask, p->at<double>(Lo.mom), flags + 1);
+  moments_kernel<T, ASM_THREADS><<<dim3(D.ny, 1, np), ASM_THREADS, 0, s>>>(A, PS, O);
   LAUNCH_CHECK();
   p->timer.end(s);
 
   constexpr int RN = std::is_same<T, float>::value ? ROW_NMAX_F32 : ROW_NMAX_F64;
-  if (D.direct) {
-    double* part = p->at<double>(Lo.U);
+  if (D.route == ROUTE_MFMA) {
+    // lag windows as FP64 matrix-core products, partial per (column chunk, row band)
+    const int nparts = D.mfma_nxc * D.mfma_nband;
     p->timer.begin(SFFT_STAGE_CORR, s);
-    direct_win_kernel<T, ASM_THREADS><<<dim3((unsigned)D.drows.size(), (unsigned)D.dir_nband), ASM_THREADS, 0, s>>>(
-        A, sci, tmpl, mask, p->at<DirectRow>(Lo.drows), part, D.nwin);
+    mfma_win_kernel<T><<<dim3((unsigned)D.mtiles.size(), (unsigned)nparts, np), MFMA_THREADS, 0, s>>>(
+        A, PS, O, D.nwin, D.mfma_nxc, D.mfma_band);
     LAUNCH_CHECK();
     p->timer.end(s);
     p->timer.begin(SFFT_STAGE_ROW_WIN, s);
-    dir_reduce_kernel<<<(D.nwin + 255) / 256, 256, 0, s>>>(part, D.dir_nband, D.nwin, p->at<double>(Lo.win));
+    dir_reduce_kernel<<<dim3((D.nwin + 255) / 256, 1, np), 256, 0, s>>>(PS, O, nparts, D.nwin);
     LAUNCH_CHECK();
     p->timer.end(s);
-    return gather_impl(p, A);
+    return gather_impl(p, A, PS, np);
+  }
+  if (D.route == ROUTE_DIRECT) {
+    p->timer.begin(SFFT_STAGE_CORR, s);
+    direct_win_kernel<T, ASM_THREADS><<<dim3((unsigned)D.drows.size(), (unsigned)D.dir_nband, np), ASM_THREADS, 0, s>>>(
+        A, PS, O, D.nwin);
+    LAUNCH_CHECK();
+    p->timer.end(s);
+    p->timer.begin(SFFT_STAGE_ROW_WIN, s);
+    dir_reduce_kernel<<<dim3((D.nwin + 255) / 256, 1, np), 256, 0, s>>>(PS, O, D.dir_nband, D.nwin);
+    LAUNCH_CHECK();
+    p->timer.end(s);
+    return gather_impl(p, A, PS, np);
   }
   {
     const size_t lds = (size_t)row_pass_lds(RN, D.lgPx - 1) * sizeof(cplx<T>);
@@ -709,7 +783,7 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
   case LG: {                                                                                               \
     auto kfn = row_fwd_kernel<T, FFT_THREADS, RN, LG>;                                                     \
     HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-    kfn<<<grid, FFT_THREADS, lds, s>>>(A, sci, tmpl, mask, p->at<cplx<T>>(Lo.Ub), tw);                  \
+    kfn<<<dim3(grid, 1, np), FFT_THREADS, lds, s>>>(A, PS, O);                                             \
     break;                                                                                                 \
   }
       ROW_CASE(5) ROW_CASE(6) ROW_CASE(7) ROW_CASE(8) ROW_CASE(9) ROW_CASE(10) ROW_CASE(11)
@@ -730,7 +804,7 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
   case LG: {                                                                                                \
     auto kfn = col_fwd_kernel<T, FFT_THREADS, COL_NMAX, LG, COL_LGM>;                                       \
     HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
-    kfn<<<grid, FFT_THREADS, lds, s>>>(A, p->at<cplx<T>>(Lo.Ub), U, tw);                                   \
+    kfn<<<dim3(grid, 1, np), FFT_THREADS, lds, s>>>(A, PS, O);                                              \
     break;                                                                                                  \
   }
       COL_CASE(6) COL_CASE(7) COL_CASE(8) COL_CASE(9) COL_CASE(10) COL_CASE(11) COL_CASE(12)
@@ -742,18 +816,17 @@ int build_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask,
     p->timer.end(s);
   }
   {
-    const int st = launch_corr<T>(p, A, p->corr_c1 > 0 ? p->corr_c1 : corr_default_c1(D), true);
+    const int st = launch_corr<T>(p, A, PS, np, p->corr_c1 > 0 ? p->corr_c1 : corr_default_c1(D), true);
     if (st != SFFT_OK) return st;
   }
   p->timer.begin(SFFT_STAGE_ROW_WIN, s);
   {
     const int nrows = (int)D.wrows.size();
-    row_win_kernel<WIN_THREADS, WIN_IMAX><<<((nrows + 7) / 8) * 8, WIN_THREADS, 0, s>>>(
-        A, p->at<cplx<double>>(Lo.V), p->at<WinRow>(Lo.wrows), nrows, p->at<double>(Lo.win), twd);
+    row_win_kernel<WIN_THREADS, WIN_IMAX><<<dim3(((nrows + 7) / 8) * 8, 1, np), WIN_THREADS, 0, s>>>(A, PS, O, nrows);
   }
   LAUNCH_CHECK();
   p->timer.end(s);
-  return gather_impl(p, A);
+  return gather_impl(p, A, PS, np);
 }
 
 // FP64 Cholesky, triangular solves and refinement for a table of jobs: one
@@ -833,186 +906,119 @@ SolveJob job_of(sfft_plan_s* p) {
   return J;
 }
 
+// Convolve-and-subtract for the np pairs of PS (same descriptor and row pitch
+// as the plan p): D = S - model - background with theta from PS.coeffs; with
+// apply_only, the model K * R alone (PS.tmpl = the image, PS.coeffs = the
+// kernel coefficients, no science image).
 template <typename T>
-int subtract_impl(sfft_plan_s* p, const T* sci, const T* tmpl, const double* coeffs, T* diff, int64_t ld) {
+int subtract_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld, bool apply_only = false) {
   const Derived& D = p->D;
-  const Layout& Lo = p->Lo;
+  const WsOff O = ws_offsets(D, p->Lo);
   hipStream_t s = p->stream;
-  const cplx<double>* twd = p->at<cplx<double>>(Lo.tw64);
   p->timer.begin(SFFT_STAGE_SUBTRACT, s);
-  // columns the circular x-convolution cannot produce exactly: [0, xl) and [xr, nx)
+  // columns the circular x-convolution cannot produce exactly: [0, xl) and
+  // [xr, nx), at most w on each side (xr - xl >= nx - 2w > 0 for every valid plan)
   const int xl = std::max(0, std::min(D.nx, D.w - (D.Px - D.nx)));
   const int xr = std::max(xl, std::min(D.nx, D.Px - D.w));
-  if (xr > xl) {
-    SpecParams S;
-    std::memset(&S, 0, sizeof(S));
-    S.ny = D.ny;
-    S.nx = D.nx;
-    S.w = D.w;
-    S.nk = D.nk;
-    S.nb = D.nb;
-    S.lgPx = D.lgPx;
-    S.H = D.H;
-    S.ld = ld;
-    S.rows_per_block = sub_row_rows(SUB_NMAX, D.lgPx - 1);   // the kernels' own constant
-    S.nrowblk = (D.ny + S.rows_per_block - 1) / S.rows_per_block;
-    S.sx = 2.0 / (double)(D.nx - 1);
-    S.sy = 2.0 / (double)(D.ny - 1);
-    for (int i = 0; i < D.nk; ++i) {
-      S.kpx[i] = D.kpoly.px[i];
-      S.kqy[i] = D.kpoly.qy[i];
-    }
-    for (int i = 0; i < D.nb; ++i) {
-      S.bpx[i] = D.bpoly.px[i];
-      S.bqy[i] = D.bpoly.qy[i];
-    }
-    unsigned char* base = p->ws + Lo.U;
-    cplx<double>* Uq = reinterpret_cast<cplx<double>*>(base);
-    cplx<double>* Mh =
-        reinterpret_cast<cplx<double>*>(base + align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>)));
-    cplx<double>* K = reinterpret_cast<cplx<double>*>(
-        reinterpret_cast<unsigned char*>(Mh) + align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>)));
-    cplx<double>* G = reinterpret_cast<cplx<double>*>(
-        reinterpret_cast<unsigned char*>(K) + align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>)));
-    const size_t lds = (size_t)lds_padded_size(S.rows_per_block * D.H) * sizeof(cplx<double>);
-    switch (D.lgPx - 1) {
+  SpecParams S;
+  std::memset(&S, 0, sizeof(S));
+  S.ny = D.ny;
+  S.nx = D.nx;
+  S.w = D.w;
+  S.nk = D.nk;
+  S.nb = D.nb;
+  S.lgPx = D.lgPx;
+  S.H = D.H;
+  S.ld = ld;
+  S.rows_per_block = sub_row_rows(SUB_NMAX, D.lgPx - 1);   // the kernels' own constant
+  S.nrowblk = (D.ny + S.rows_per_block - 1) / S.rows_per_block;
+  S.sx = 2.0 / (double)(D.nx - 1);
+  S.sy = 2.0 / (double)(D.ny - 1);
+  for (int i = 0; i < D.nk; ++i) {
+    S.kpx[i] = D.kpoly.px[i];
+    S.kqy[i] = D.kpoly.qy[i];
+  }
+  for (int i = 0; i < D.nb; ++i) {
+    S.bpx[i] = D.bpoly.px[i];
+    S.bqy[i] = D.bpoly.qy[i];
+  }
+  {
+    // filters G and the border kernel k' in one launch
+    const int L2 = D.L * D.L;
+    const int ngb = ((D.H + 1 + PREP_THREADS - 1) / PREP_THREADS) * D.L;
+    const int nkb = (D.nk * L2 + PREP_THREADS - 1) / PREP_THREADS;
+    sub_prep_kernel<<<dim3(ngb + nkb, 1, np), PREP_THREADS, 0, s>>>(S, PS, O, ngb);
+    LAUNCH_CHECK();
+  }
+  const size_t lds = (size_t)lds_padded_size(S.rows_per_block * D.H) * sizeof(cplx<double>);
+  switch (D.lgPx - 1) {
 #define SUBF_CASE(LG)                                                                                       \
   case LG: {                                                                                                \
     auto kf = sub_rowfwd_kernel<T, FFT_THREADS, SUB_NMAX, LG>;                                              \
     HIP_TRY(hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
-    kf<<<S.nrowblk, FFT_THREADS, lds, s>>>(S, tmpl, Uq, twd, D.dk + 1);                                     \
+    kf<<<dim3(S.nrowblk, 1, np), FFT_THREADS, lds, s>>>(S, PS, O, D.dk + 1);                                \
     break;                                                                                                  \
   }
-      SUBF_CASE(5) SUBF_CASE(6) SUBF_CASE(7) SUBF_CASE(8) SUBF_CASE(9) SUBF_CASE(10) SUBF_CASE(11)
-      default:
-        return SFFT_EINVAL;
+    SUBF_CASE(5) SUBF_CASE(6) SUBF_CASE(7) SUBF_CASE(8) SUBF_CASE(9) SUBF_CASE(10) SUBF_CASE(11)
+    default:
+      return SFFT_EINVAL;
 #undef SUBF_CASE
-    }
-    LAUNCH_CHECK();
-    {
-      dim3 g((D.H + 1 + 255) / 256, D.nk * D.L);
-      sub_kspec_kernel<<<g, 256, 0, s>>>(S, coeffs, K, twd);
-      LAUNCH_CHECK();
-      dim3 gg((D.H + 1 + 255) / 256, D.L);
-      sub_gspec_kernel<<<gg, 256, 0, s>>>(S, K, G);
-      LAUNCH_CHECK();
-    }
-    {
-      const int nconv = ((D.H + 1 + 63) / 64) * ((D.ny + SUBC_RB - 1) / SUBC_RB);
-      const int g = ((nconv + 7) / 8) * 8;   // whole XCD rounds for the remap
-      const size_t lds_c = sub_conv_lds_bytes(D.w);
-      switch (D.w) {
+  }
+  LAUNCH_CHECK();
+  {
+    const int nconv = ((D.H + 1 + 63) / 64) * ((D.ny + SUBC_RB - 1) / SUBC_RB);
+    const int g = ((nconv + 7) / 8) * 8;   // whole XCD rounds for the remap
+    const size_t lds_c = sub_conv_lds_bytes(D.w);
+    switch (D.w) {
 #define CONV_CASE(WV)                                                                                          \
   case WV: {                                                                                                   \
     auto kc = sub_conv_kernel<WV>;                                                                             \
     HIP_TRY(hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_c));   \
-    kc<<<g, 64 * SUBC_WAVES, lds_c, s>>>(S, Uq, G, Mh);                                                        \
+    kc<<<dim3(g, 1, np), 64 * SUBC_WAVES, lds_c, s>>>(S, PS, O);                                               \
     break;                                                                                                     \
   }
-        CONV_CASE(0) CONV_CASE(1) CONV_CASE(2) CONV_CASE(3) CONV_CASE(4) CONV_CASE(5) CONV_CASE(6) CONV_CASE(7)
-        CONV_CASE(8) CONV_CASE(9) CONV_CASE(10) CONV_CASE(11) CONV_CASE(12) CONV_CASE(13) CONV_CASE(14) CONV_CASE(15)
+      CONV_CASE(0) CONV_CASE(1) CONV_CASE(2) CONV_CASE(3) CONV_CASE(4) CONV_CASE(5) CONV_CASE(6) CONV_CASE(7)
+      CONV_CASE(8) CONV_CASE(9) CONV_CASE(10) CONV_CASE(11) CONV_CASE(12) CONV_CASE(13) CONV_CASE(14) CONV_CASE(15)
 #undef CONV_CASE
-        default:
-          return SFFT_EINVAL;
-      }
-      LAUNCH_CHECK();
+      default:
+        return SFFT_EINVAL;
     }
-    switch (D.lgPx - 1) {
+    LAUNCH_CHECK();
+  }
+  // border pixels, one wave each, in the leading blocks of the inverse pass
+  const int64_t nbandpx = (int64_t)(xl + (D.nx - xr)) * D.ny;
+  const int nbandblk = (int)((nbandpx + FFT_THREADS / 64 - 1) / (FFT_THREADS / 64));
+  switch (D.lgPx - 1) {
 #define SUBI_CASE(LG)                                                                                       \
   case LG: {                                                                                                \
     auto ki = sub_rowinv_kernel<T, FFT_THREADS, SUB_NMAX, LG>;                                              \
     HIP_TRY(hipFuncSetAttribute((const void*)ki, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
-    ki<<<S.nrowblk, FFT_THREADS, lds, s>>>(S, Mh, sci, coeffs, diff, twd, xl, xr);                          \
+    ki<<<dim3(nbandblk + S.nrowblk, 1, np), FFT_THREADS, lds, s>>>(S, PS, O, xl, xr, nbandblk,              \
+                                                                   apply_only ? 1 : 0);                     \
     break;                                                                                                  \
   }
-      SUBI_CASE(5) SUBI_CASE(6) SUBI_CASE(7) SUBI_CASE(8) SUBI_CASE(9) SUBI_CASE(10) SUBI_CASE(11)
-      default:
-        return SFFT_EINVAL;
+    SUBI_CASE(5) SUBI_CASE(6) SUBI_CASE(7) SUBI_CASE(8) SUBI_CASE(9) SUBI_CASE(10) SUBI_CASE(11)
+    default:
+      return SFFT_EINVAL;
 #undef SUBI_CASE
-    }
-    LAUNCH_CHECK();
   }
-  // border columns (or the whole frame when the spectral route has no exact interior)
-  if (xl > 0 || xr < D.nx) {
-    SubParams P;
-    std::memset(&P, 0, sizeof(P));
-    P.ny = D.ny;
-    P.nx = D.nx;
-    P.w = D.w;
-    P.nk = D.nk;
-    P.nb = D.nb;
-    P.ld = ld;
-    for (int i = 0; i < D.nk; ++i) {
-      P.kpx[i] = D.kpoly.px[i];
-      P.kqy[i] = D.kpoly.qy[i];
-    }
-    for (int i = 0; i < D.nb; ++i) {
-      P.bpx[i] = D.bpoly.px[i];
-      P.bqy[i] = D.bpoly.qy[i];
-    }
-    const int L2 = D.L * D.L;
-    double* kp = p->at<double>(Lo.kp);
-    kprime_kernel<<<(D.nk * L2 + 255) / 256, 256, 0, s>>>(P, coeffs, kp);
-    LAUNCH_CHECK();
-    const size_t lds = ((size_t)(SUB_TY + 2 * D.w) * (SUB_TX + 2 * D.w) + (size_t)D.nk * L2) * sizeof(double);
-    const int bands[2][2] = {{0, xl}, {xr, D.nx}};
-    const bool narrow0 = xl <= 0 || xl < SUB_TX / 2, narrow1 = D.nx - xr <= 0 || D.nx - xr < SUB_TX / 2;
-    if (narrow0 && narrow1) {
-      // both bands narrow: one launch, one wave per pixel
-      P.xbeg = 0;
-      P.xend = std::max(0, xl);
-      P.xbeg2 = xr;
-      P.xend2 = D.nx;
-      const size_t lds_k = (size_t)D.nk * L2 * sizeof(double);
-      HIP_TRY(hipFuncSetAttribute((const void*)subtract_band_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds_k));
-      const int64_t npx = (int64_t)(P.xend - P.xbeg + std::max(0, P.xend2 - P.xbeg2)) * D.ny;
-      if (npx > 0) {
-        subtract_band_kernel<<<(int)((npx + BAND_WAVES - 1) / BAND_WAVES), 64 * BAND_WAVES, lds_k, s>>>(
-            P, sci, tmpl, std::is_same<T, double>::value ? 1 : 0, kp, coeffs, diff);
-        LAUNCH_CHECK();
-      }
-    }
-    for (int bnd = 0; bnd < 2; ++bnd) {
-      P.xbeg = bands[bnd][0];
-      P.xend = bands[bnd][1];
-      P.xbeg2 = P.xend2 = 0;
-      if (P.xend <= P.xbeg) continue;
-      if (narrow0 && narrow1) continue;   // done above
-      if (P.xend - P.xbeg < SUB_TX / 2) {
-        // narrow band: one wave per pixel
-        const size_t lds_k = (size_t)D.nk * L2 * sizeof(double);
-        HIP_TRY(hipFuncSetAttribute((const void*)subtract_band_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds_k));
-        const int64_t npx = (int64_t)(P.xend - P.xbeg) * D.ny;
-        subtract_band_kernel<<<(int)((npx + BAND_WAVES - 1) / BAND_WAVES), 64 * BAND_WAVES, lds_k, s>>>(
-            P, sci, tmpl, std::is_same<T, double>::value ? 1 : 0, kp, coeffs, diff);
-        LAUNCH_CHECK();
-        continue;
-      }
-      dim3 grid((P.xend - P.xbeg + SUB_TX - 1) / SUB_TX, (D.ny + SUB_TY - 1) / SUB_TY);
-#define SUB_CASE(NKV)                                                                                      \
-  case NKV: {                                                                                              \
-    auto kfn = subtract_kernel<T, NKV>;                                                                    \
-    HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-    kfn<<<grid, 256, lds, s>>>(P, sci, tmpl, kp, coeffs, diff);                                            \
-    break;                                                                                                 \
-  }
-      switch (D.nk) {
-        SUB_CASE(1)
-        SUB_CASE(3)
-        SUB_CASE(6)
-        SUB_CASE(10)
-        SUB_CASE(15)
-        default:
-          return SFFT_EINVAL;
-      }
-#undef SUB_CASE
-      LAUNCH_CHECK();
-    }
-  }
+  LAUNCH_CHECK();
   p->timer.end(s);
   return SFFT_OK;
+}
+
+PairSet pair_set_one(const sfft_plan_s* p, const void* sci, const void* tmpl, const uint8_t* mask,
+                     const double* coeffs, void* diff, int32_t* info) {
+  PairSet S;
+  std::memset(&S, 0, sizeof(S));
+  S.sci[0] = sci;
+  S.tmpl[0] = tmpl;
+  S.mask[0] = mask;
+  S.ws[0] = p->ws;
+  S.coeffs[0] = const_cast<double*>(coeffs);
+  S.diff[0] = diff;
+  S.info[0] = info;
+  return S;
 }
 
 }  // namespace
@@ -1089,6 +1095,8 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
                        hipMemcpyHostToDevice, s) == hipSuccess;
   ok &= hipMemcpyAsync(p->at<void>(p->Lo.drows), p->D.drows.data(), p->D.drows.size() * sizeof(DirectRow),
                        hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(p->at<void>(p->Lo.mtiles), p->D.mtiles.data(), p->D.mtiles.size() * sizeof(MfmaTile),
+                       hipMemcpyHostToDevice, s) == hipSuccess;
   p->jobs_host.assign(1, job_of(p));
   ok &= hipMemcpyAsync(p->at<void>(p->Lo.job), p->jobs_host.data(), sizeof(SolveJob), hipMemcpyHostToDevice, s) ==
         hipSuccess;
@@ -1106,11 +1114,8 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
 int sfft_build_system(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld) {
   RoctxScope range_("sfft_build_system");
   if (p == nullptr || p->is_batch || sci == nullptr || tmpl == nullptr || ld < p->D.nx) return SFFT_EINVAL;
-  int st;
-  if (p->D.mode == SFFT_MODE_F64)
-    st = build_impl<double>(p, (const double*)sci, (const double*)tmpl, mask, ld);
-  else
-    st = build_impl<float>(p, (const float*)sci, (const float*)tmpl, mask, ld);
+  const PairSet PS = pair_set_one(p, sci, tmpl, mask, nullptr, nullptr, nullptr);
+  const int st = p->D.mode == SFFT_MODE_F64 ? build_impl<double>(p, PS, 1, ld) : build_impl<float>(p, PS, 1, ld);
   if (st == SFFT_OK) p->built = true;
   return st;
 }
@@ -1172,9 +1177,46 @@ int sfft_subtract(sfft_handle p, const void* sci, const void* tmpl, const double
   RoctxScope range_("sfft_subtract");
   if (p == nullptr || p->is_batch || sci == nullptr || tmpl == nullptr || coeffs == nullptr || diff == nullptr || ld < p->D.nx)
     return SFFT_EINVAL;
-  if (p->D.mode == SFFT_MODE_F64)
-    return subtract_impl<double>(p, (const double*)sci, (const double*)tmpl, coeffs, (double*)diff, ld);
-  return subtract_impl<float>(p, (const float*)sci, (const float*)tmpl, coeffs, (float*)diff, ld);
+  const PairSet PS = pair_set_one(p, sci, tmpl, nullptr, coeffs, diff, nullptr);
+  return p->D.mode == SFFT_MODE_F64 ? subtract_impl<double>(p, PS, 1, ld) : subtract_impl<float>(p, PS, 1, ld);
+}
+
+int sfft_apply_kernel(sfft_handle p, const void* img, const double* kcoef, void* out, int64_t ld) {
+  RoctxScope range_("sfft_apply_kernel");
+  if (p == nullptr || p->is_batch || img == nullptr || kcoef == nullptr || out == nullptr || ld < p->D.nx ||
+      img == out)
+    return SFFT_EINVAL;
+  const PairSet PS = pair_set_one(p, nullptr, img, nullptr, kcoef, out, nullptr);
+  return p->D.mode == SFFT_MODE_F64 ? subtract_impl<double>(p, PS, 1, ld, true)
+                                    : subtract_impl<float>(p, PS, 1, ld, true);
+}
+
+int sfft_decorrelation_kernel(sfft_handle p, const double* coeffs, const double* psf_sci, const double* psf_tmpl,
+                              int32_t s, double sigma_sci, double sigma_tmpl, int32_t t, double* psi) {
+  RoctxScope range_("sfft_decorrelation_kernel");
+  if (p == nullptr || p->is_batch || coeffs == nullptr || psf_sci == nullptr || psf_tmpl == nullptr || psi == nullptr)
+    return SFFT_EINVAL;
+  if (s < 0 || s > DEC_MAXS || t < 0 || t > DEC_MAXS) return SFFT_EINVAL;
+  if (!(sigma_sci > 0.0) || !(sigma_tmpl > 0.0) || !std::isfinite(sigma_sci) || !std::isfinite(sigma_tmpl))
+    return SFFT_EINVAL;
+  const Derived& D = p->D;
+  DecParams Q;
+  std::memset(&Q, 0, sizeof(Q));
+  Q.w = D.w;
+  Q.nk = D.nk;
+  Q.s = s;
+  Q.t = t;
+  Q.sx = 2.0 / (double)(D.nx - 1);
+  Q.sy = 2.0 / (double)(D.ny - 1);
+  Q.var_s = sigma_sci * sigma_sci;
+  Q.var_r = sigma_tmpl * sigma_tmpl;
+  for (int i = 0; i < D.nk; ++i) {
+    Q.kpx[i] = D.kpoly.px[i];
+    Q.kqy[i] = D.kpoly.qy[i];
+  }
+  decorr_kernel<<<1, DEC_THREADS, 0, p->stream>>>(Q, coeffs, psf_sci, psf_tmpl, p->at<cplx<double>>(p->Lo.tw64), psi);
+  LAUNCH_CHECK();
+  return SFFT_OK;
 }
 
 int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out) {
@@ -1324,22 +1366,66 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
         ld[i] < b->members[i]->D.nx)
       return SFFT_EINVAL;
   hipStream_t s = b->stream;
-  // assembly of every pair (each launch fills the device)
+  // groups of pairs with the same descriptor, row pitch and correlation
+  // chunk, at most MAX_GROUP each: every launch of a group serves all of its
+  // pairs (pair = blockIdx.z), so small cutouts fill the device together and
+  // large ones share one launch tail
+  std::vector<std::vector<int>> groups;
   for (int i = 0; i < np; ++i) {
-    const int st = sfft_build_system(b->members[i], sci[i], tmpl[i], mask ? mask[i] : nullptr, ld[i]);
+    const sfft_plan_s* mi = b->members[i];
+    bool placed = false;
+    for (auto& g : groups) {
+      const sfft_plan_s* mj = b->members[g[0]];
+      if ((int)g.size() < MAX_GROUP && ld[g[0]] == ld[i] && mj->corr_c1 == mi->corr_c1 &&
+          std::memcmp(&mj->desc, &mi->desc, sizeof(sfft_desc)) == 0) {
+        g.push_back(i);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) groups.push_back(std::vector<int>(1, i));
+  }
+  auto set_of = [&](const std::vector<int>& g) {
+    PairSet S;
+    std::memset(&S, 0, sizeof(S));
+    for (size_t k = 0; k < g.size(); ++k) {
+      const int i = g[k];
+      S.sci[k] = sci[i];
+      S.tmpl[k] = tmpl[i];
+      S.mask[k] = mask ? mask[i] : nullptr;
+      S.ws[k] = b->members[i]->ws;
+      S.coeffs[k] = coeffs[i];
+      S.diff[k] = diff[i];
+      S.info[k] = info ? info + i : nullptr;
+    }
+    return S;
+  };
+  // assembly, one group at a time
+  for (const auto& g : groups) {
+    sfft_plan_s* lead = b->members[g[0]];
+    const PairSet PS = set_of(g);
+    const int n = (int)g.size();
+    const int st = lead->D.mode == SFFT_MODE_F64 ? build_impl<double>(lead, PS, n, ld[g[0]])
+                                                 : build_impl<float>(lead, PS, n, ld[g[0]]);
     if (st != SFFT_OK) return st;
+    for (int i : g) b->members[i]->built = true;
   }
   // one batched factorisation and solve for all pairs
   int st = solve_jobs(s, b->jobs_dev, np, b->max_n, b->max_nblk, b->members[0]->D.refine, &b->timer);
   if (st != SFFT_OK) return st;
-  for (int i = 0; i < np; ++i) {
-    sfft_plan_s* m = b->members[i];
-    copy_out_kernel<<<(m->D.n + 255) / 256, 256, 0, s>>>(m->at<double>(m->Lo.theta), coeffs[i], m->D.n,
-                                                       m->at<int>(m->Lo.flags), info ? info + i : nullptr);
+  for (const auto& g : groups) {
+    const sfft_plan_s* lead = b->members[g[0]];
+    copy_out_group_kernel<<<dim3((lead->D.n + 255) / 256, 1, (int)g.size()), 256, 0, s>>>(
+        set_of(g), ws_offsets(lead->D, lead->Lo), lead->D.n);
     LAUNCH_CHECK();
   }
-  for (int i = 0; i < np; ++i) {
-    st = sfft_subtract(b->members[i], sci[i], tmpl[i], coeffs[i], diff[i], ld[i]);
+  // convolve-and-subtract, one group at a time
+  for (const auto& g : groups) {
+    sfft_plan_s* lead = b->members[g[0]];
+    const PairSet PS = set_of(g);
+    const int n = (int)g.size();
+    st = lead->D.mode == SFFT_MODE_F64 ? subtract_impl<double>(lead, PS, n, ld[g[0]])
+                                       : subtract_impl<float>(lead, PS, n, ld[g[0]]);
     if (st != SFFT_OK) return st;
   }
   return SFFT_OK;
@@ -1354,7 +1440,7 @@ int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_
   sfft_plan_s* t = p->is_batch ? p->members[0] : p;
   if (ld < t->D.nx) return SFFT_EINVAL;
   if (count_out) *count_out = 0;
-  if (t->D.direct) return SFFT_OK;   // the direct route has no correlation chunk to tune
+  if (t->D.route != ROUTE_FFT) return SFFT_OK;   // only the transform route has a correlation chunk
   int st = sfft_build_system(t, sci, tmpl, mask, ld);
   if (st != SFFT_OK) return st;
   const Derived& D = t->D;
@@ -1370,6 +1456,7 @@ int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_
     cand.swap(k);
   }
   const AsmParams A = asm_params(t, ld);
+  const PairSet PS = pair_set_one(t, sci, tmpl, mask, nullptr, nullptr, nullptr);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1385,7 +1472,8 @@ int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_
     for (int r = 0; r <= REPS && st == SFFT_OK; ++r) {
       if (r == 1) st = hipEventRecord(e0, t->stream) == hipSuccess ? SFFT_OK : SFFT_EHIP;
       if (st == SFFT_OK)
-        st = D.mode == SFFT_MODE_F64 ? launch_corr<double>(t, A, c, false) : launch_corr<float>(t, A, c, false);
+        st = D.mode == SFFT_MODE_F64 ? launch_corr<double>(t, A, PS, 1, c, false)
+                                     : launch_corr<float>(t, A, PS, 1, c, false);
     }
     if (st == SFFT_OK) st = hipEventRecord(e1, t->stream) == hipSuccess ? SFFT_OK : SFFT_EHIP;
     if (st == SFFT_OK) st = hipEventSynchronize(e1) == hipSuccess ? SFFT_OK : SFFT_EHIP;
@@ -1412,6 +1500,56 @@ int sfft_autotune(sfft_handle p, const void* sci, const void* tmpl, const uint8_
       if (std::memcmp(&m->desc, &t->desc, sizeof(sfft_desc)) == 0) m->corr_c1 = best;
   if (count_out) *count_out = std::min(n, (int)cap);
   return SFFT_OK;
+}
+
+int sfft_autotune_route(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld,
+                        float* ms_out, int32_t* route_out) {
+  RoctxScope range_("sfft_autotune_route");
+  if (p == nullptr || sci == nullptr || tmpl == nullptr) return SFFT_EINVAL;
+  if (p->is_batch && p->members.empty()) return SFFT_EINVAL;
+  sfft_plan_s* t = p->is_batch ? p->members[0] : p;
+  if (ld < t->D.nx) return SFFT_EINVAL;
+  const Derived& D = t->D;
+  const int r0 = D.route;
+  const bool direct_ok = D.nx <= DIR_MAX_NX && 2 * D.w <= DIR_HWMAX;
+  const bool tunable = (t->desc.flags & 3) == SFFT_FLAG_ASSEMBLY_AUTO;
+  const PairSet PS = pair_set_one(t, sci, tmpl, mask, nullptr, nullptr, nullptr);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SFFT_EHIP;
+  }
+  float ms[3] = {-1.0f, -1.0f, -1.0f};
+  int st = SFFT_OK;
+  int best = r0;
+  for (int r = ROUTE_FFT; r <= ROUTE_MFMA && st == SFFT_OK; ++r) {
+    if (r == ROUTE_DIRECT && !direct_ok) continue;
+    t->D.route = r;
+    constexpr int REPS = 3;
+    for (int k = 0; k <= REPS && st == SFFT_OK; ++k) {   // one warm-up build, then REPS timed
+      if (k == 1) st = hipEventRecord(e0, t->stream) == hipSuccess ? SFFT_OK : SFFT_EHIP;
+      if (st == SFFT_OK)
+        st = D.mode == SFFT_MODE_F64 ? build_impl<double>(t, PS, 1, ld) : build_impl<float>(t, PS, 1, ld);
+    }
+    if (st == SFFT_OK) st = hipEventRecord(e1, t->stream) == hipSuccess ? SFFT_OK : SFFT_EHIP;
+    if (st == SFFT_OK) st = hipEventSynchronize(e1) == hipSuccess ? SFFT_OK : SFFT_EHIP;
+    float v = 0.0f;
+    if (st == SFFT_OK) st = hipEventElapsedTime(&v, e0, e1) == hipSuccess ? SFFT_OK : SFFT_EHIP;
+    if (st != SFFT_OK) break;
+    ms[r] = v / (float)REPS;
+    if (tunable && (r == ROUTE_FFT || ms[r] < ms[best])) best = r;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  t->D.route = st == SFFT_OK ? best : r0;
+  if (st == SFFT_OK && p->is_batch)
+    for (sfft_plan_s* m : p->members)
+      if (std::memcmp(&m->desc, &t->desc, sizeof(sfft_desc)) == 0) m->D.route = best;
+  if (ms_out)
+    for (int r = 0; r < 3; ++r) ms_out[r] = ms[r];
+  if (route_out) *route_out = t->D.route + 1;   // the descriptor's flag value of the route
+  return st;
 }
 
 int sfft_batch_capture(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
@@ -1496,18 +1634,18 @@ cplx<double> g_tw64[TW_N];
 cplx<float> g_tw32[TW_N];
 
 template <typename T>
-int noalloc_run(sfft_plan_s* p, const T* sci, const T* tmpl, const uint8_t* mask, int64_t ld, double* coeffs,
-                T* diff, int32_t* info) {
-  int st = build_impl<T>(p, sci, tmpl, mask, ld);
+int noalloc_run(sfft_plan_s* p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld, double* coeffs,
+                void* diff, int32_t* info) {
+  const PairSet PS = pair_set_one(p, sci, tmpl, mask, coeffs, diff, info);
+  int st = build_impl<T>(p, PS, 1, ld);
   if (st != SFFT_OK) return st;
   const Derived& D = p->D;
   hipStream_t s = p->stream;
   st = solve_jobs(s, p->at<SolveJob>(p->Lo.job), 1, D.n, D.nblk, D.refine, &p->timer);
   if (st != SFFT_OK) return st;
-  copy_out_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(p->at<double>(p->Lo.theta), coeffs, D.n, p->at<int>(p->Lo.flags),
-                                                    info);
+  copy_out_group_kernel<<<dim3((D.n + 255) / 256, 1, 1), 256, 0, s>>>(PS, ws_offsets(D, p->Lo), D.n);
   LAUNCH_CHECK();
-  return subtract_impl<T>(p, sci, tmpl, coeffs, diff, ld);
+  return subtract_impl<T>(p, PS, 1, ld);
 }
 
 }  // namespace
@@ -1570,6 +1708,8 @@ int sfft_subtract_pair_noalloc(const sfft_desc* d, void* hip_stream, const void*
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.drows), D.drows.data(), (size_t)D.drows.size() * sizeof(DirectRow),
                            hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.mtiles), D.mtiles.data(), (size_t)D.mtiles.size() * sizeof(MfmaTile),
+                           hipMemcpyHostToDevice, s));
     const SolveJob job = job_of(p);
     HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.job), &job, sizeof(job), hipMemcpyHostToDevice, s));
     // the host tables (and `job`) may change once the copies have been made
@@ -1579,9 +1719,8 @@ int sfft_subtract_pair_noalloc(const sfft_desc* d, void* hip_stream, const void*
   }
   p->stream = s;
   p->built = true;
-  if (p->D.mode == SFFT_MODE_F64)
-    return noalloc_run<double>(p, (const double*)sci, (const double*)tmpl, mask, ld, coeffs, (double*)diff, info);
-  return noalloc_run<float>(p, (const float*)sci, (const float*)tmpl, mask, ld, coeffs, (float*)diff, info);
+  return p->D.mode == SFFT_MODE_F64 ? noalloc_run<double>(p, sci, tmpl, mask, ld, coeffs, diff, info)
+                                    : noalloc_run<float>(p, sci, tmpl, mask, ld, coeffs, diff, info);
 }
 
 const char* sfft_strerror(int status) {

@@ -7,203 +7,14 @@
 // gives model(z) = sum_a' m_a'(z) sum_u k'_{a',u} R(z - u) with
 // k'_{a',u} = sum_a k_{a,u} e_{a,a'}(u): nK plain convolutions of the same
 // unmasked template, combined with the output-side monomials.  Pixels outside
-// the frame contribute zero (linear convolution, no wrap-around).
-//
-// kprime_kernel : k' from theta (FP64).
-// subtract_kernel: LDS-tiled direct convolution (16 x 64 output tile per block,
-//                  4 pixels x nK accumulators per thread, FP64 accumulation);
-//                  used for the border columns that the spectral route below
-//                  cannot produce exactly.
+// the frame contribute zero (linear convolution, no wrap-around).  The border
+// columns that the spectral route below cannot produce exactly are summed
+// this way, directly, with k' (band_model).
 #pragma once
 
 #include "common.hpp"
 
 namespace sfft {
-
-struct SubParams {
-  int ny, nx, w, nk, nb;
-  int xbeg, xend;        // the direct kernel writes columns [xbeg, xend) only
-  int xbeg2, xend2;      // narrow-band kernel: a second band (empty when xend2 <= xbeg2)
-  int64_t ld;
-  int8_t kpx[15], kqy[15];
-  int8_t bpx[15], bqy[15];
-};
-
-__device__ __forceinline__ double binom(int n, int k) {
-  double r = 1.0;
-  for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
-  return r;
-}
-
-// one thread per (a', u): the nK x L^2 outputs in parallel
-__global__ void kprime_kernel(SubParams P, const double* __restrict__ theta, double* __restrict__ kp) {
-  const int L = 2 * P.w + 1;
-  const int L2 = L * L;
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= P.nk * L2) return;
-  const int ap = id / L2;
-  const int u = id - ap * L2;
-  const int uy = u / L - P.w, ux = u % L - P.w;
-  const double dx = 2.0 * (double)ux / (double)(P.nx - 1);
-  const double dy = 2.0 * (double)uy / (double)(P.ny - 1);
-  {
-    const int i = P.kpx[ap], j = P.kqy[ap];
-    double s = 0.0;
-    for (int a = 0; a < P.nk; ++a) {
-      const int p = P.kpx[a], q = P.kqy[a];
-      if (i > p || j > q) continue;
-      double e = binom(p, i) * binom(q, j);
-      for (int t = 0; t < p - i; ++t) e *= -dx;
-      for (int t = 0; t < q - j; ++t) e *= -dy;
-      s += theta[a * L2 + u] * e;
-    }
-    kp[ap * L2 + u] = s;
-  }
-}
-
-constexpr int SUB_TY = 16;
-constexpr int SUB_TX = 64;
-
-// Direct D on the narrow column bands [P.xbeg, P.xend) and [P.xbeg2, P.xend2):
-// one wave per pixel, the lanes split the nK L^2 kernel taps (k' in LDS) and
-// sum by shuffles.  The template loads of a lane are unconditional (clamped
-// into the frame, then selected) so that several are in flight.  Same
-// arithmetic as subtract_kernel below, summed in a different order.
-constexpr int BAND_WAVES = 8;
-__global__ __launch_bounds__(64 * BAND_WAVES) void subtract_band_kernel(SubParams P, const void* __restrict__ sci_v,
-                                                                        const void* __restrict__ tmpl_v, int is_f64,
-                                                                        const double* __restrict__ kp,
-                                                                        const double* __restrict__ theta,
-                                                                        void* __restrict__ diff_v) {
-  extern __shared__ double kps[];
-  const int w = P.w;
-  const int L = 2 * w + 1;
-  const int L2 = L * L;
-  const int nkk = P.nk * L2;
-  const int bw0 = P.xend - P.xbeg;
-  const int bw1 = max(0, P.xend2 - P.xbeg2);
-  for (int e = threadIdx.x; e < nkk; e += 64 * BAND_WAVES) kps[e] = kp[e];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  int64_t id = (int64_t)blockIdx.x * BAND_WAVES + (threadIdx.x >> 6);
-  int y, x;
-  if (id < (int64_t)bw0 * P.ny) {
-    y = (int)(id / bw0);
-    x = P.xbeg + (int)(id - (int64_t)y * bw0);
-  } else {
-    id -= (int64_t)bw0 * P.ny;
-    if (id >= (int64_t)bw1 * P.ny) return;
-    y = (int)(id / bw1);
-    x = P.xbeg2 + (int)(id - (int64_t)y * bw1);
-  }
-  const double yh = 2.0 * (double)y / (double)(P.ny - 1) - 1.0;
-  const double xh = 2.0 * (double)x / (double)(P.nx - 1) - 1.0;
-  double acc = 0.0;
-#pragma unroll 4
-  for (int t = lane; t < nkk; t += 64) {
-    const int a = t / L2;
-    const int r = t - a * L2;
-    const int uy = r / L - w;
-    const int ux = r - (uy + w) * L - w;
-    const int sy = y - uy, sx = x - ux;
-    const bool in = sy >= 0 && sy < P.ny && sx >= 0 && sx < P.nx;
-    const int64_t o = (int64_t)min(max(sy, 0), P.ny - 1) * P.ld + min(max(sx, 0), P.nx - 1);
-    const double tv = is_f64 ? reinterpret_cast<const double*>(tmpl_v)[o]
-                             : (double)reinterpret_cast<const float*>(tmpl_v)[o];
-    double m = 1.0;
-    for (int q = 0; q < P.kpx[a]; ++q) m *= xh;
-    for (int q = 0; q < P.kqy[a]; ++q) m *= yh;
-    acc += in ? kps[t] * m * tv : 0.0;
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane != 0) return;
-  double model = acc;
-  for (int b = 0; b < P.nb; ++b) {
-    double m = 1.0;
-    for (int q = 0; q < P.bpx[b]; ++q) m *= xh;
-    for (int q = 0; q < P.bqy[b]; ++q) m *= yh;
-    model += theta[nkk + b] * m;
-  }
-  const int64_t o = (int64_t)y * P.ld + x;
-  if (is_f64) {
-    reinterpret_cast<double*>(diff_v)[o] = reinterpret_cast<const double*>(sci_v)[o] - model;
-  } else {
-    reinterpret_cast<float*>(diff_v)[o] = (float)((double)reinterpret_cast<const float*>(sci_v)[o] - model);
-  }
-}
-
-// Dynamic LDS: tile (SUB_TY + 2w) x (SUB_TX + 2w) doubles, then nK * L^2 doubles of k'.
-template <typename T, int NK>
-__global__ __launch_bounds__(256) void subtract_kernel(SubParams P, const T* __restrict__ sci,
-                                                       const T* __restrict__ tmpl, const double* __restrict__ kp,
-                                                       const double* __restrict__ theta, T* __restrict__ diff) {
-  extern __shared__ double sm[];
-  const int w = P.w;
-  const int L = 2 * w + 1;
-  const int L2 = L * L;
-  const int TW = SUB_TX + 2 * w;
-  const int TH = SUB_TY + 2 * w;
-  double* tile = sm;
-  double* kps = sm + TW * TH;
-  const int y0 = blockIdx.y * SUB_TY;
-  const int x0 = P.xbeg + blockIdx.x * SUB_TX;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < TW * TH; e += 256) {
-    const int r = e / TW, c = e % TW;
-    const int y = y0 - w + r, x = x0 - w + c;
-    tile[e] = (y >= 0 && y < P.ny && x >= 0 && x < P.nx) ? (double)tmpl[(int64_t)y * P.ld + x] : 0.0;
-  }
-  for (int e = tid; e < NK * L2; e += 256) kps[e] = kp[e];
-  __syncthreads();
-  const int ty = tid >> 4;          // 0..15
-  const int tx = (tid & 15) * 4;    // 0..60
-  double acc[NK][4];
-#pragma unroll
-  for (int a = 0; a < NK; ++a)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[a][i] = 0.0;
-  for (int uy = -w; uy <= w; ++uy) {
-    const double* trow = tile + (ty - uy + w) * TW + tx + w;
-    const double* krow = kps + (uy + w) * L + w;
-    for (int ux = -w; ux <= w; ++ux) {
-      double rv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) rv[i] = trow[i - ux];
-#pragma unroll
-      for (int a = 0; a < NK; ++a) {
-        const double k = krow[a * L2 + ux];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[a][i] += k * rv[i];
-      }
-    }
-  }
-  const int y = y0 + ty;
-  if (y >= P.ny) return;
-  const double yh = 2.0 * (double)y / (double)(P.ny - 1) - 1.0;
-  const int nkk = NK * L2;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int x = x0 + tx + i;
-    if (x >= P.xend) continue;
-    const double xh = 2.0 * (double)x / (double)(P.nx - 1) - 1.0;
-    double model = 0.0;
-#pragma unroll
-    for (int a = 0; a < NK; ++a) {
-      double m = 1.0;
-      for (int t = 0; t < P.kpx[a]; ++t) m *= xh;
-      for (int t = 0; t < P.kqy[a]; ++t) m *= yh;
-      model += m * acc[a][i];
-    }
-    for (int b = 0; b < P.nb; ++b) {
-      double m = 1.0;
-      for (int t = 0; t < P.bpx[b]; ++t) m *= xh;
-      for (int t = 0; t < P.bqy[b]; ++t) m *= yh;
-      model += theta[nkk + b] * m;
-    }
-    const int64_t o = (int64_t)y * P.ld + x;
-    diff[o] = (T)((double)sci[o] - model);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Spectral route for the interior (x-direction by FFT, y-direction direct)
@@ -215,8 +26,12 @@ __global__ __launch_bounds__(256) void subtract_kernel(SubParams P, const T* __r
 //   M(y, kx) = sum_a sum_{u_y} K_a(u_y, kx) yh(y-u_y)^q U_p(y-u_y, kx)   (0 <= y-u_y < ny)
 // is the row transform of the model; a C2R transform per row gives the model,
 // exact wherever the circular x-convolution does not wrap into the frame
-// (x >= w - (Px - nx) and x < Px - w); the remaining border columns are
-// recomputed by the direct kernel above.  All of it in FP64.
+// (x >= w - (Px - nx) and x < Px - w).  The remaining border columns (at most
+// w on each side) are summed directly in the inverse row pass.  All of it in
+// FP64, and the spectra U_p and M are stored as complex128 in both modes:
+// complex64 storage moves the FP32 rounding of every spectral value into
+// every pixel of the model (about 1e-6 of |D| over the frame at 4096^2, with
+// single faint pixels above 1e-5 of their local scale).
 struct SpecParams {
   int ny, nx, w, nk, nb;
   int lgPx, H;           // Px = 2^lgPx, H = Px / 2; spectra rows hold H + 1 values
@@ -235,9 +50,12 @@ __host__ __device__ constexpr int sub_row_rows(int nmax, int lgh) { return (nmax
 
 // R2C of the rows xh^p R (p = 0..DK) -> Uq[p][y][0..H]
 template <typename T, int THREADS, int NMAX, int LGH>
-__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_kernel(SpecParams P, const T* __restrict__ tmpl,
-                                                             cplx<double>* __restrict__ Uq,
-                                                             const cplx<double>* __restrict__ tw, int npow) {
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_kernel(SpecParams P, PairSet PS, WsOff O,
+                                                                                     int npow) {
+  const int pr = blockIdx.z;
+  const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
+  cplx<double>* __restrict__ Uq = ws_at<cplx<double>>(PS, pr, O.Uq);
+  const cplx<double>* __restrict__ tw = ws_at<const cplx<double>>(PS, pr, O.tw64);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
   constexpr int RB = sub_row_rows(NMAX, LGH);
@@ -308,68 +126,91 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_ke
   }
 }
 
-// K[a][u_y][kx] = sum_{u_x} k_{a,u} e^{-2 pi i kx u_x / Px}
-__global__ void sub_kspec_kernel(SpecParams P, const double* __restrict__ theta, cplx<double>* __restrict__ K,
-                                 const cplx<double>* __restrict__ tw) {
-  const int L = 2 * P.w + 1;
-  const int H = P.H;
-  const int row = blockIdx.y;            // a * L + (u_y + w)
-  const int kx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kx > H) return;
-  const int a = row / L;
-  const int uyi = row - a * L;
-  const int twsx = TW_LOG - P.lgPx;
-  const int Px = 2 * H;
-  cplx<double> acc = mk(0.0, 0.0);
-#pragma unroll 4
-  for (int uxi = 0; uxi < L; ++uxi) {
-    const int ux = uxi - P.w;
-    const double k = theta[a * L * L + uyi * L + uxi];
-    const int m = (int)(((int64_t)kx * (ux + Px)) & (Px - 1));
-    acc = acc + scale(twid<double, false>(tw, m << twsx), k);
-  }
-  K[(int64_t)row * (H + 1) + kx] = acc;
+// Binomial coefficients C(n, k) for n <= 4 (polynomial degrees are at most 4).
+__device__ __forceinline__ double binom4(int n, int k) {
+  constexpr double tab[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0}, {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+  return tab[n][k];
 }
 
-// Filters with the y-weight moved to the output row.  With yh(y - u_y) =
-// yh(y) - u_y sy and the binomial expansion of its q-th power,
+// Filters of the y-convolution and the output-side kernel k', in one launch.
+//
+// The y-weight moves to the output row: with yh(y - u_y) = yh(y) - u_y sy
+// and the binomial expansion of its q-th power,
 //   sum_a K_a(u_y) yh(y - u_y)^q_a U_{p_a}(y - u_y)
 //     = sum_{p,e} yh(y)^e sum_{u_y} G_{p,e}(u_y) U_p(y - u_y),
-//   G_{p,e}(u_y) = sum_{q >= e} C(q, e) (-u_y sy)^(q-e) K_{(p,q)}(u_y).
-// The pairs (p, e) are the monomials themselves; G[(p,e)] takes the place of
-// K[(p,q)] in the same layout, one thread per (u_y, kx).
-__global__ void sub_gspec_kernel(SpecParams P, const cplx<double>* __restrict__ K, cplx<double>* __restrict__ G) {
+//   G_{p,e}(u_y, kx) = sum_{u_x} e^{-2 pi i kx u_x / Px} gamma_{p,e}(u_y, u_x),
+//   gamma_{p,e}(u_y, u_x) = sum_{q >= e} C(q, e) (-u_y sy)^(q-e) k_{(p,q),u}.
+// The pairs (p, e) are the monomials themselves, so G[g] (g = (p, e)) has
+// the layout of the coefficients: G[(g L + u_y + w)(H + 1) + kx].
+// Blocks [0, ngb): a block takes one u_y and 256 kx; it forms gamma of its
+// u_y in LDS, then each thread sums every G_g of its kx.
+// Blocks [ngb, ..): one thread per (a', u) forming k'_{a',u} =
+//   sum_a k_{a,u} C(p_a, p') C(q_a, q') (-u_x sx)^(p_a - p') (-u_y sy)^(q_a - q')
+// for the border columns.
+constexpr int PREP_THREADS = 256;
+__global__ __launch_bounds__(PREP_THREADS) void sub_prep_kernel(SpecParams P, PairSet PS, WsOff O, int ngb) {
+  const int pr = blockIdx.z;
+  const double* __restrict__ theta = PS.coeffs[pr];
+  cplx<double>* __restrict__ G = ws_at<cplx<double>>(PS, pr, O.G);
+  double* __restrict__ kp = ws_at<double>(PS, pr, O.kp);
+  const cplx<double>* __restrict__ tw = ws_at<const cplx<double>>(PS, pr, O.tw64);
+  constexpr int LMAX = 2 * 15 + 1;
+  __shared__ double gam[15][LMAX];
   const int L = 2 * P.w + 1;
+  const int L2 = L * L;
   const int H = P.H;
-  const int uyi = blockIdx.y;
-  const int kx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kx > H) return;
-  const double d = -(double)(uyi - P.w) * P.sy;   // -u_y sy
-  for (int g = 0; g < P.nk; ++g) {
-    const int p = P.kpx[g], e = P.kqy[g];
-    cplx<double> acc = mk(0.0, 0.0);
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= ngb) {
+    const int id = ((int)blockIdx.x - ngb) * PREP_THREADS + tid;
+    if (id >= P.nk * L2) return;
+    const int ap = id / L2;
+    const int u = id - ap * L2;
+    const int uy = u / L - P.w, ux = u % L - P.w;
+    const double dx = (double)ux * P.sx, dy = (double)uy * P.sy;
+    const int i = P.kpx[ap], j = P.kqy[ap];
+    double acc = 0.0;
     for (int a = 0; a < P.nk; ++a) {
-      if (P.kpx[a] != p || P.kqy[a] < e) continue;
-      const int q = P.kqy[a];
-      const double c = binom(q, e) * ipow(d, q - e);
-      acc = acc + scale(K[((int64_t)a * L + uyi) * (H + 1) + kx], c);
+      const int pa = P.kpx[a], qa = P.kqy[a];
+      if (i > pa || j > qa) continue;
+      acc += theta[a * L2 + u] * binom4(pa, i) * binom4(qa, j) * ipow(-dx, pa - i) * ipow(-dy, qa - j);
     }
-    G[((int64_t)g * L + uyi) * (H + 1) + kx] = acc;
+    kp[ap * L2 + u] = acc;
+    return;
   }
+  const int nkb = (H + 1 + PREP_THREADS - 1) / PREP_THREADS;   // blocks per u_y row
+  const int uyi = (int)blockIdx.x / nkb;
+  const double d = -(double)(uyi - P.w) * P.sy;                // -u_y sy
+  for (int e = tid; e < P.nk * L; e += PREP_THREADS) {
+    const int g = e / L, uxi = e - g * L;
+    const int pg = P.kpx[g], eg = P.kqy[g];
+    double v = 0.0;
+    for (int a = 0; a < P.nk; ++a) {
+      if (P.kpx[a] != pg || P.kqy[a] < eg) continue;
+      const int q = P.kqy[a];
+      v += binom4(q, eg) * ipow(d, q - eg) * theta[a * L2 + uyi * L + uxi];
+    }
+    gam[g][uxi] = v;
+  }
+  __syncthreads();
+  const int kx = ((int)blockIdx.x - uyi * nkb) * PREP_THREADS + tid;
+  if (kx > H) return;
+  const int twsx = TW_LOG - P.lgPx;
+  const int Px = 2 * H;
+  cplx<double> acc[15];
+#pragma unroll
+  for (int g = 0; g < 15; ++g) acc[g] = mk(0.0, 0.0);
+  for (int uxi = 0; uxi < L; ++uxi) {
+    const int m = (int)(((int64_t)kx * (uxi - P.w + Px)) & (Px - 1));
+    const cplx<double> t = twid<double, false>(tw, m << twsx);
+#pragma unroll
+    for (int g = 0; g < 15; ++g)
+      if (g < P.nk) acc[g] = acc[g] + scale(t, gam[g][uxi]);
+  }
+#pragma unroll
+  for (int g = 0; g < 15; ++g)
+    if (g < P.nk) G[((int64_t)g * L + uyi) * (H + 1) + kx] = acc[g];
 }
 
-// M(y, kx) = sum_a sum_{u_y} K[a][u_y][kx] yh(y - u_y)^q_a U_{p_a}(y - u_y, kx)
-//          = sum_{p,e} yh(y)^e sum_{u_y} G[(p,e)][u_y][kx] U_p(y - u_y, kx)   (sub_gspec_kernel).
-// Block: 64 kx columns (the lanes) x SUBC_WAVES waves of SUBC_TY output rows.
-// For each x power p the block stages the source rows of U_p it needs in LDS
-// once (HBM traffic ~ (1 + 2W / SUBC_RB) x the source).  For each filter of
-// that power a thread takes the taps in groups of SUBC_GT (the next group's
-// loads in flight meanwhile); within a group it sweeps the TY + GT - 1 source
-// rows the group reaches, reading each from LDS once and adding it to every
-// output row it feeds, so a source row is read (TY + GT - 1) / (GT TY) times per
-// output and tap instead of once.  The last group is padded with zero taps
-// (the window carries GT - 1 extra rows above for their reads).  The output
-// rows are finally weighted by yh(y)^e.
 constexpr int SUBC_TY = 6;                        // output rows per wave
 constexpr int SUBC_WAVES = 8;
 constexpr int SUBC_RB = SUBC_TY * SUBC_WAVES;     // output rows per block
@@ -381,9 +222,11 @@ __host__ __device__ constexpr size_t sub_conv_lds_bytes(int w) {
 }
 
 template <int W>
-__global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P, const cplx<double>* __restrict__ Uq,
-                                                                   const cplx<double>* __restrict__ G,
-                                                                   cplx<double>* __restrict__ Mh) {
+__global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const cplx<double>* __restrict__ Uq = ws_at<const cplx<double>>(PS, pr, O.Uq);
+  const cplx<double>* __restrict__ G = ws_at<const cplx<double>>(PS, pr, O.G);
+  cplx<double>* __restrict__ Mh = ws_at<cplx<double>>(PS, pr, O.Mh);
   constexpr int L = 2 * W + 1;
   constexpr int GT = SUBC_GT;
   constexpr int NG = (L + GT - 1) / GT;           // tap groups (the last one padded)
@@ -475,22 +318,92 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
   }
 }
 
-// C2R of M(y, .) and D = S - model - background on the columns [xlo, xhi).
+// Direct model value at one border pixel (y, x), computed by one wave: the
+// lanes split the L^2 offsets u, load the template value R(y - u_y, x - u_x)
+// once per offset and sum sum_a k'_{a',u} m_a'(y, x) over the nK output-side
+// monomials (evaluated once per pixel), then reduce by shuffles (lane 0 holds
+// the total).  The template loads of a lane are unconditional (clamped into
+// the frame, then selected) so that several are in flight.
+template <typename T>
+__device__ __forceinline__ double band_model(const SpecParams& P, int y, int x, const T* __restrict__ tmpl,
+                                             const double* __restrict__ kp, int lane) {
+  const int w = P.w;
+  const int L = 2 * w + 1;
+  const int L2 = L * L;
+  const double yh = (double)y * P.sy - 1.0;
+  const double xh = (double)x * P.sx - 1.0;
+  double m[15];
+#pragma unroll
+  for (int a = 0; a < 15; ++a) m[a] = a < P.nk ? ipow(xh, P.kpx[a]) * ipow(yh, P.kqy[a]) : 0.0;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int r = lane; r < L2; r += 64) {
+    const int uy = r / L - w;
+    const int ux = r - (uy + w) * L - w;
+    const int sy = y - uy, sx = x - ux;
+    const bool in = sy >= 0 && sy < P.ny && sx >= 0 && sx < P.nx;
+    const int64_t o = (int64_t)min(max(sy, 0), P.ny - 1) * P.ld + min(max(sx, 0), P.nx - 1);
+    const double tv = (double)tmpl[o];
+    double k = 0.0;
+#pragma unroll
+    for (int a = 0; a < 15; ++a)
+      if (a < P.nk) k = fma(kp[a * L2 + r], m[a], k);
+    acc += in ? k * tv : 0.0;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  return acc;
+}
+
+// C2R of M(y, .) and D = S - model - background (apply_only: the model K * R
+// itself, with no science image or background) on the columns [xlo, xhi)
+// (blocks nbandblk.. , RB rows each); the border columns [0, xlo) and
+// [xhi, nx) by direct sums (band_model) in blocks 0 .. nbandblk - 1, one wave
+// per pixel.
 // E(k) = (X(k) + conj X(H-k))/2, O(k) = (X(k) - conj X(H-k)) e^{2 pi i k/Px}/2,
 // z = IDFT_H(E + i O)/H, model(2j) = Re z(j), model(2j+1) = Im z(j).
 template <typename T, int THREADS, int NMAX, int LGH>
-__global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const cplx<double>* __restrict__ Mh,
-                                                             const T* __restrict__ sci,
-                                                             const double* __restrict__ theta, T* __restrict__ diff,
-                                                             const cplx<double>* __restrict__ tw, int xlo, int xhi) {
+__global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, PairSet PS, WsOff O, int xlo, int xhi,
+                                                             int nbandblk, int apply_only) {
+  const int pr = blockIdx.z;
+  const cplx<double>* __restrict__ Mh = ws_at<const cplx<double>>(PS, pr, O.Mh);
+  const T* __restrict__ sci = static_cast<const T*>(PS.sci[pr]);
+  const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
+  const double* __restrict__ theta = PS.coeffs[pr];
+  const double* __restrict__ kp = ws_at<const double>(PS, pr, O.kp);
+  T* __restrict__ diff = static_cast<T*>(PS.diff[pr]);
+  const cplx<double>* __restrict__ tw = ws_at<const cplx<double>>(PS, pr, O.tw64);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
   constexpr int RB = sub_row_rows(NMAX, LGH);
   constexpr int H = 1 << LGH;             // H = Px / 2
   constexpr int NPT = (RB * H) / THREADS;
   static_assert(NPT * THREADS == RB * H, "whole values per thread");
-  const int y0 = blockIdx.x * RB;
   const int tid = threadIdx.x;
+  if ((int)blockIdx.x < nbandblk) {
+    // border columns [0, xlo) and [xhi, nx): one wave per pixel, direct sums.
+    // These blocks come first in the grid so that their load latencies
+    // overlap the transform blocks that follow.
+    const int nleft = xlo, nband = xlo + (P.nx - xhi);
+    const int lane = tid & 63;
+    const int64_t pix = (int64_t)blockIdx.x * (THREADS / 64) + (tid >> 6);
+    if (pix >= (int64_t)nband * P.ny) return;
+    const int y = (int)(pix / nband);
+    const int c = (int)(pix - (int64_t)y * nband);
+    const int x = c < nleft ? c : xhi + (c - nleft);
+    const double model = band_model<T>(P, y, x, tmpl, kp, lane);
+    if (lane == 0 && apply_only) {
+      diff[(int64_t)y * P.ld + x] = (T)model;
+    } else if (lane == 0) {
+      const int L2 = (2 * P.w + 1) * (2 * P.w + 1);
+      const double xh = (double)x * P.sx - 1.0, yh = (double)y * P.sy - 1.0;
+      double bg = 0.0;
+      for (int b = 0; b < P.nb; ++b) bg += theta[P.nk * L2 + b] * ipow(xh, P.bpx[b]) * ipow(yh, P.bqy[b]);
+      const int64_t o = (int64_t)y * P.ld + x;
+      diff[o] = (T)((double)sci[o] - model - bg);
+    }
+    return;
+  }
+  const int y0 = ((int)blockIdx.x - nbandblk) * RB;
   constexpr int twsx = TW_LOG - (LGH + 1);
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
@@ -519,7 +432,7 @@ __global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const
     const int r = tid / SUB_MAXP, pw = tid - r * SUB_MAXP;
     const double yh = (double)(y0 + r) * P.sy - 1.0;
     double c = 0.0;
-    for (int b = 0; b < P.nb; ++b)
+    for (int b = 0; b < (apply_only ? 0 : P.nb); ++b)
       if (P.bpx[b] == pw) c += theta[nkk + b] * ipow(yh, P.bqy[b]);
     bcoef[r][pw] = c;
   }
@@ -538,7 +451,7 @@ __global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const
     for (int i = 0; i < XPT; ++i) {
       const int y = min(y0 + r, P.ny - 1);
       const int x = min(xlo + tid + i * THREADS, xhi - 1);
-      sv[r][i] = sci[(int64_t)y * P.ld + x];
+      sv[r][i] = apply_only ? (T)0 : sci[(int64_t)y * P.ld + x];   // no science image when applying K
     }
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
@@ -553,7 +466,7 @@ __global__ __launch_bounds__(THREADS) void sub_rowinv_kernel(SpecParams P, const
       const double xh = (double)x * P.sx - 1.0;
       double bg = bcoef[r][pdeg];
       for (int pw = pdeg - 1; pw >= 0; --pw) bg = bg * xh + bcoef[r][pw];
-      diff[(int64_t)y * P.ld + x] = (T)((double)sv[r][i] - model - bg);
+      diff[(int64_t)y * P.ld + x] = apply_only ? (T)model : (T)((double)sv[r][i] - model - bg);
     }
   }
 }

@@ -92,7 +92,8 @@ def traffic(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv:
     for k in sorted(f):
         fb = f[k] * cf * 1024.0
         wb = w.get(k, 0.0) * cw * 1024.0
-        print(f"{k[:70]:70s} fetch {fb / 1e6:10.1f} MB  write {wb / 1e6:8.1f} MB  total {(fb + wb) / 1e6:10.1f} MB")
+        print(f"{k[:70]:70s} fetch {fb / 1e6:10.1f} MB  write {wb / 1e6:8.1f} MB  total {(fb + wb) / 1e6:10.1f} MB"
+              f"  ({int(round(fb + wb))} B)")
 
 
 def main(argv=None) -> None:

@@ -48,3 +48,24 @@ def run_pair(sci, tmpl, mask, w, dk, db, mode=B.SFFT_MODE_F64, pitch=None, refin
         return res
     finally:
         plan.close()
+
+
+def oracle_reference(args):
+    """(theta*, D*) of one pair from the CPU oracle, for a process pool:
+    args = (sci, tmpl, mask, w, dk, db, input dtype name)."""
+    import oracle
+    sci, tmpl, mask, w, dk, db, cast = args
+    s_in = sci.astype(cast).astype(np.float64)
+    r_in = tmpl.astype(cast).astype(np.float64)
+    ref = oracle.fit(s_in, r_in, mask, w, dk, db, mode="fft")
+    return ref["theta"], ref["diff"]
+
+
+def pin_worker(cores, counter):
+    """Pool initializer: one host core per worker process, so that the oracle
+    (whose FFT thread count follows the affinity mask) runs single-threaded."""
+    import os
+    with counter.get_lock():
+        k = counter.value
+        counter.value += 1
+    os.sched_setaffinity(0, {cores[k % len(cores)]})

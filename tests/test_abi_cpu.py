@@ -30,6 +30,11 @@ def test_num_coeffs_and_workspace():
     # spectra dominate: 13 planes of 4096 x 2049 complex
     assert 13 * 4096 * 2049 * 8 < ws32 < ws64
     assert B.sfft_num_coeffs(B.make_desc(256, 256, 5, 1, 1)) == 121 * 3 + 3
+    # every assembly route is a valid descriptor; the workspace holds all their buffers
+    sizes = {f: B.sfft_workspace_bytes(B.make_desc(1024, 1024, 9, 2, 2, B.SFFT_MODE_F32C, flags=f))
+             for f in (B.SFFT_FLAG_ASSEMBLY_AUTO, B.SFFT_FLAG_ASSEMBLY_FFT, B.SFFT_FLAG_ASSEMBLY_DIRECT,
+                       B.SFFT_FLAG_ASSEMBLY_MFMA)}
+    assert len(set(sizes.values())) == 1
 
 
 @pytest.mark.parametrize("bad", [
@@ -39,7 +44,7 @@ def test_num_coeffs_and_workspace():
     dict(ny=64, nx=64, w=2, dk=1, db=-2),
     dict(ny=5000, nx=64, w=2, dk=1, db=1),        # larger than 4096
     dict(ny=64, nx=64, w=2, dk=1, db=1, mode=7),
-    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=3),        # no such assembly route
+    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=7),        # route bits plus an unknown bit
     dict(ny=64, nx=64, w=2, dk=1, db=1, flags=4),        # unknown flag bit
     dict(ny=64, nx=2048, w=2, dk=1, db=1, flags=2),      # direct sums limited to nx <= 1024
     dict(ny=64, nx=64, w=10, dk=1, db=1, flags=2),       # ... and to w <= 9

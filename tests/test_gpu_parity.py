@@ -63,10 +63,10 @@ SMALL = [
 ]
 
 
-FFT_ROUTE, DIRECT_ROUTE = B.SFFT_FLAG_ASSEMBLY_FFT, B.SFFT_FLAG_ASSEMBLY_DIRECT
+FFT_ROUTE, DIRECT_ROUTE, MFMA_ROUTE = B.SFFT_FLAG_ASSEMBLY_FFT, B.SFFT_FLAG_ASSEMBLY_DIRECT, B.SFFT_FLAG_ASSEMBLY_MFMA
 
 
-@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE])
+@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE, MFMA_ROUTE])
 @pytest.mark.parametrize("mode", [F64, F32C])
 @pytest.mark.parametrize("case", SMALL)
 def test_small_parity(case, mode, route):
@@ -76,7 +76,7 @@ def test_small_parity(case, mode, route):
     _check_against_oracle(p, mode, res)
 
 
-@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE])
+@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE, MFMA_ROUTE])
 @pytest.mark.parametrize("mode", [F64, F32C])
 def test_c1_parity(mode, route):
     p = synth.pair_c1()
@@ -86,13 +86,40 @@ def test_c1_parity(mode, route):
 
 
 def test_routes_agree_on_omega():
-    """The direct sums and the transforms give the same Omega up to rounding (FP64)."""
+    """The direct sums, the matrix-core products and the transforms give the same
+    Omega up to rounding (FP64), entry by entry."""
     p = synth.random_pair(81, 150, 140, 4, 2, 1, mask_frac=0.1, stars=True)
     a = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, flags=FFT_ROUTE)
-    b = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, flags=DIRECT_ROUTE)
     scale = np.abs(a["omega"]).max()
-    assert np.abs(a["omega"] - b["omega"]).max() <= 1e-12 * scale
-    assert np.abs(a["beta"] - b["beta"]).max() <= 1e-12 * np.abs(a["beta"]).max()
+    for route in (DIRECT_ROUTE, MFMA_ROUTE):
+        b = run_pair(p.sci, p.tmpl, p.mask, p.w, p.dk, p.db, flags=route)
+        assert np.abs(a["omega"] - b["omega"]).max() <= 1e-12 * scale, route
+        assert np.abs(a["beta"] - b["beta"]).max() <= 1e-12 * np.abs(a["beta"]).max(), route
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_route_autotune_keeps_the_fastest_and_the_result(mode):
+    """sfft_autotune_route times every allowed route on the real pair and keeps
+    the fastest on an AUTO plan; the fit after it still matches the oracle."""
+    p = synth.random_pair(82, 192, 176, 5, 1, 1, mask_frac=0.05, stars=True)
+    dt = torch.float64 if mode == F64 else torch.float32
+    S, R = torch.from_numpy(p.sci).to("cuda", dt), torch.from_numpy(p.tmpl).to("cuda", dt)
+    M = torch.from_numpy(p.mask).cuda()
+    plan = B.Plan(*p.sci.shape, p.w, p.dk, p.db, mode=mode)
+    try:
+        ms, route = B.sfft_autotune_route(plan.handle, S, R, M, S.stride(0))
+        timed = {k: v for k, v in ms.items() if v is not None}
+        assert set(timed) == {"fft", "direct", "mfma"} and all(v > 0 for v in timed.values())
+        assert route == min(timed, key=timed.get)
+        plan.build(S, R, M)
+        coeffs, info = plan.solve()
+        diff = plan.subtract(S, R, coeffs)
+        res = dict(theta=coeffs.cpu().numpy(), diff=diff.cpu().numpy().astype(np.float64),
+                   info=int(info.item()), status=plan.status()[0])
+        _check_against_oracle(p, mode, res)
+        print(f"route timings {ms} -> {route}")
+    finally:
+        plan.close()
 
 
 @pytest.fixture(scope="module")
@@ -264,7 +291,7 @@ def test_autotune_keeps_results_within_rounding(mode):
     assert oracle.rel_err(d1, ref["diff"]) <= TOL[mode]["diff"]
 
 
-@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE])
+@pytest.mark.parametrize("route", [FFT_ROUTE, DIRECT_ROUTE, MFMA_ROUTE])
 @pytest.mark.parametrize("shape", [(6, 6, 1, 0, 0), (10, 7, 1, 1, 1), (2, 2, 0, 0, 0), (3, 64, 0, 1, 0)])
 def test_smallest_frames(shape, route):
     """Frames at the size limit N = 4w + 2 and degenerate thin frames (plain noise images)."""
@@ -283,13 +310,13 @@ def test_smallest_frames(shape, route):
 # descriptor accepts.  The direct route takes w <= 9 only.
 WIDE = [
     # ny, nx, w, dk, db, mask_frac, seed, routes
-    (96, 96, 10, 1, 1, 0.05, 301, (FFT_ROUTE,)),
-    (72, 80, 15, 0, 0, 0.05, 302, (FFT_ROUTE,)),
-    (100, 92, 12, 0, 2, 0.10, 303, (FFT_ROUTE,)),
-    (64, 64, 2, 4, 4, 0.10, 304, (FFT_ROUTE, DIRECT_ROUTE)),
-    (80, 76, 3, 3, 3, 0.10, 305, (FFT_ROUTE, DIRECT_ROUTE)),
-    (64, 80, 3, 4, 0, 0.05, 306, (FFT_ROUTE, DIRECT_ROUTE)),
-    (70, 70, 1, 0, 4, 0.05, 307, (FFT_ROUTE, DIRECT_ROUTE)),
+    (96, 96, 10, 1, 1, 0.05, 301, (FFT_ROUTE, MFMA_ROUTE)),
+    (72, 80, 15, 0, 0, 0.05, 302, (FFT_ROUTE, MFMA_ROUTE)),
+    (100, 92, 12, 0, 2, 0.10, 303, (FFT_ROUTE, MFMA_ROUTE)),
+    (64, 64, 2, 4, 4, 0.10, 304, (FFT_ROUTE, DIRECT_ROUTE, MFMA_ROUTE)),
+    (80, 76, 3, 3, 3, 0.10, 305, (FFT_ROUTE, DIRECT_ROUTE, MFMA_ROUTE)),
+    (64, 80, 3, 4, 0, 0.05, 306, (FFT_ROUTE, DIRECT_ROUTE, MFMA_ROUTE)),
+    (70, 70, 1, 0, 4, 0.05, 307, (FFT_ROUTE, DIRECT_ROUTE, MFMA_ROUTE)),
 ]
 
 
