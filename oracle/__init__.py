@@ -9,3 +9,5 @@ from .sfft_oracle import *  # noqa: F401,F403
 from . import mlp_oracle  # noqa: F401,E402
 from .kernel_oracle import (apply_kernel, centre_kernel, convolve, decorrelation_kernel,  # noqa: F401,E402
                             decorrelation_spectrum, DECORR_GRID)
+from . import ratio_oracle  # noqa: F401,E402
+from .ratio_oracle import kernel_sums, ratio_constraints, ratio_map, solve_const_ratio  # noqa: F401,E402
