@@ -11,3 +11,4 @@ from .kernel_oracle import (apply_kernel, centre_kernel, convolve, decorrelation
                             decorrelation_spectrum, DECORR_GRID)
 from . import ratio_oracle  # noqa: F401,E402
 from .ratio_oracle import kernel_sums, ratio_constraints, ratio_map, solve_const_ratio  # noqa: F401,E402
+from . import align_oracle  # noqa: F401,E402
