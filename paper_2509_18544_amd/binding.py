@@ -34,6 +34,7 @@ SFFT_FLAG_ASSEMBLY_AUTO = 0
 SFFT_FLAG_ASSEMBLY_FFT = 1
 SFFT_FLAG_ASSEMBLY_DIRECT = 2
 SFFT_FLAG_ASSEMBLY_MFMA = 3
+SFFT_FLAG_CONST_RATIO = 16   # constant photometric ratio (spatial kernel sums vanish)
 ROUTES = ("fft", "direct", "mfma")
 
 
@@ -46,6 +47,15 @@ class SfftError(RuntimeError):
 class sfft_desc(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("ny", "nx", "w", "dk", "db", "mode", "refine_steps", "flags")]
+
+
+class sfft_ws_frame(ctypes.Structure):
+    """One warm-start frame's catalogue (include/sfft_render.h); pointers are device addresses."""
+    _fields_ = [("n", ctypes.c_int32), ("nstar", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("bc", ctypes.c_double * 6), ("noise_seed", ctypes.c_uint64),
+                ("xs", ctypes.c_void_p), ("ys", ctypes.c_void_p), ("flux", ctypes.c_void_p),
+                ("fw_s", ctypes.c_void_p), ("fw_t", ctypes.c_void_p), ("mask_r", ctypes.c_void_p),
+                ("tile_start", ctypes.c_void_p)]
 
 
 _lib = None
@@ -90,6 +100,7 @@ def lib():
                                                      vp]),
         "sfft_autotune_route": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_float),
                                                ctypes.POINTER(i32)]),
+        "sfft_render_ws_frame": (ctypes.c_int, [ctypes.POINTER(sfft_ws_frame), vp, vp, vp, vp, i64, vp, vp]),
         "sfft_destroy": (None, [vp]),
         "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sfft_mlp_create": (ctypes.c_int, [ctypes.POINTER(i32), i32, i32, vp, ctypes.POINTER(vp)]),
@@ -290,6 +301,12 @@ def sfft_autotune_route(handle, sci, tmpl, mask, ld: int):
     _check(lib().sfft_autotune_route(handle, _ptr(sci), _ptr(tmpl), _ptr(mask), int(ld), ms, ctypes.byref(r)),
            "sfft_autotune_route")
     return {ROUTES[i]: (None if ms[i] < 0 else float(ms[i])) for i in range(3)}, ROUTES[r.value - 1]
+
+
+def sfft_render_ws_frame(frame: sfft_ws_frame, sci, tmpl, mask, ld: int, norm_scratch, overflow, stream=None):
+    _check(lib().sfft_render_ws_frame(ctypes.byref(frame), _stream_handle(stream), _ptr(sci), _ptr(tmpl),
+                                      _ptr(mask), int(ld), _ptr(norm_scratch), _ptr(overflow)),
+           "sfft_render_ws_frame")
 
 
 def sfft_batch_launch(handle):

@@ -131,6 +131,117 @@ def make_dataset(npairs, seed0, n=512, chunk=32, pool=None, log=None):
     return np.asarray(feats), np.concatenate(thetas), np.concatenate(infos)
 
 
+# ---------------------------------------------------------------- 4088^2 frames rendered on the GPU
+
+RT = 32   # catalogue tile side of the renderer (include/sfft_render.h)
+
+
+def ws_frame_host(args):
+    """Catalogue of one warm-start frame (synth.ws_catalog) in the renderer's tile
+    order, for a host worker pool: returns (seed, catalogue, sorted arrays, tile_start)."""
+    import synth
+    seed, n = args
+    cat = synth.ws_catalog(seed, n=n)
+    nt = -(-n // RT)
+    tx = np.clip(np.floor(cat["xs"] / RT), 0, nt - 1).astype(np.int64)
+    ty = np.clip(np.floor(cat["ys"] / RT), 0, nt - 1).astype(np.int64)
+    tile = ty * nt + tx
+    order = np.argsort(tile, kind="stable")
+    start = np.concatenate([[0], np.cumsum(np.bincount(tile, minlength=nt * nt))]).astype(np.int32)
+    arrays = np.stack([cat[k][order] for k in ("xs", "ys", "flux", "fw_s", "fw_t", "mask_r")])
+    small = {k: cat[k] for k in ("n", "X", "Y", "fwhm_s0", "fwhm_t0", "beta", "bc", "noise_seed", "stamp_s",
+                                 "stamp_t")}
+    return seed, small, arrays, start
+
+
+class FrameRenderer:
+    """Device buffers for `nbuf` frames of side n and the GPU rendering of catalogues into them."""
+
+    def __init__(self, nbuf, n, stream=None):
+        import torch
+        self.n = n
+        self.S = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+        self.R = [torch.empty_like(x) for x in self.S]
+        self.M = [torch.empty((n, n), dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+        self.overflow = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.keep = []
+        self.stream = stream
+
+    def render(self, k, small, arrays, start):
+        """Frame k <- the catalogue (host arrays from ws_frame_host)."""
+        import torch
+        A = torch.from_numpy(np.ascontiguousarray(arrays)).cuda()
+        T = torch.from_numpy(start).cuda()
+        norm = torch.empty(2 * max(1, arrays.shape[1]), dtype=torch.float64, device="cuda")
+        f = B.sfft_ws_frame()
+        f.n, f.nstar, f.beta = self.n, arrays.shape[1], small["beta"]
+        for i in range(6):
+            f.bc[i] = float(small["bc"][i])
+        f.noise_seed = int(small["noise_seed"])
+        f.xs, f.ys, f.flux, f.fw_s, f.fw_t, f.mask_r = (A[i].data_ptr() for i in range(6))
+        f.tile_start = T.data_ptr()
+        B.sfft_render_ws_frame(f, self.S[k], self.R[k], self.M[k], self.n, norm, self.overflow, self.stream)
+        self.keep.append((A, T, norm))           # alive until the stream has run the kernels
+
+    def settle(self):
+        import torch
+        torch.cuda.synchronize()
+        self.keep = []
+        if int(self.overflow.item()) != 0:
+            raise RuntimeError("a render neighbourhood held more stars than the renderer stages")
+
+
+def make_dataset_gpu(npairs, seed0, n=4088, chunk=32, pool=None, log=None):
+    """`npairs` frames of side n rendered on the GPU from host catalogues (seeds
+    seed0..) and solved in FP64 batches of `chunk` (one batch plan, reused).
+    Returns (features, theta, info) like make_dataset; make_dataset_gpu.last_params
+    holds (X, Y, FWHM_s0, FWHM_t0, beta) per frame."""
+    import torch
+    desc = B.make_desc(n, n, W, DK, DB, B.SFFT_MODE_F64)
+    ncoef = B.sfft_num_coeffs(desc)
+    rend = FrameRenderer(chunk, n)
+    h = B.sfft_batch_plan([desc] * chunk)
+    C = torch.zeros((chunk, ncoef), dtype=torch.float64, device="cuda")
+    Dd = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in range(chunk)]
+    info = torch.zeros(chunk, dtype=torch.int32, device="cuda")
+    feats, thetas, infos, params = [], [], [], []
+    seeds = [(seed0 + i, n) for i in range(npairs)]
+    chunks = [seeds[i:i + chunk] for i in range(0, npairs, chunk)]
+    t0 = time.perf_counter()
+    nxt = pool.map(ws_frame_host, chunks[0]) if pool is not None else map(ws_frame_host, chunks[0])
+    try:
+        for ci in range(len(chunks)):
+            cur = list(nxt)
+            if ci + 1 < len(chunks):   # the next catalogues are drawn while this batch runs
+                nxt = pool.map(ws_frame_host, chunks[ci + 1]) if pool is not None else map(ws_frame_host, chunks[ci + 1])
+            for k, (_, small, arrays, start) in enumerate(cur):
+                rend.render(k, small, arrays, start)
+            m = len(cur)
+            if m == chunk:
+                B.sfft_batch_run(h, rend.S, rend.R, rend.M, [n] * chunk, list(C), Dd, info)
+                th, inf = C.cpu().numpy().copy(), info.cpu().numpy().copy()
+            else:   # a short last batch: its own plan
+                h2 = B.sfft_batch_plan([desc] * m)
+                try:
+                    B.sfft_batch_run(h2, rend.S[:m], rend.R[:m], rend.M[:m], [n] * m, list(C[:m]), Dd[:m], info[:m])
+                    th, inf = C[:m].cpu().numpy().copy(), info[:m].cpu().numpy().copy()
+                finally:
+                    B.sfft_destroy(h2)
+            rend.settle()
+            for (_, small, _, _) in cur:
+                feats.append(features(small["stamp_s"], small["stamp_t"], small["X"], small["Y"]))
+                params.append([small["X"], small["Y"], small["fwhm_s0"], small["fwhm_t0"], small["beta"]])
+            thetas.append(th)
+            infos.append(inf)
+            if log and (ci % 10 == 9 or ci == len(chunks) - 1):
+                log(f"[learned] rendered and solved {len(feats)}/{npairs} frames of {n}^2 "
+                    f"({time.perf_counter() - t0:.1f}s)")
+    finally:
+        B.sfft_destroy(h)
+    make_dataset_gpu.last_params = np.asarray(params)
+    return np.asarray(feats), np.concatenate(thetas), np.concatenate(infos)
+
+
 # ---------------------------------------------------------------- the network
 
 def he_uniform(dims, seed):
@@ -316,7 +427,11 @@ def _cli(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--train-pairs", type=int, default=20000)
     ap.add_argument("--val-pairs", type=int, default=64)
-    ap.add_argument("--n", type=int, default=512, help="frame side of the training frames")
+    ap.add_argument("--frames", choices=["gpu", "host"], default="gpu",
+                    help="gpu: frames rendered by the library's renderer (synth.ws_catalog recipe, any n); "
+                         "host: synth.pair_ws rendered on the host (small n)")
+    ap.add_argument("--n", type=int, default=4088, help="frame side of the training frames")
+    ap.add_argument("--test-pairs", type=int, default=0, help="held-out frames for the evaluation (default val)")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-4)
@@ -331,18 +446,21 @@ def _cli(argv=None):
 
     import concurrent.futures as cf
     import multiprocessing as mp
-    # the render pool starts before anything touches the GPU
+    # the host pool starts before anything touches the GPU
     pool = cf.ProcessPoolExecutor(max_workers=max(1, a.workers), mp_context=mp.get_context("spawn"))
-    list(pool.map(_render, [(0, 64)] * max(1, a.workers)))
+    warm = ws_frame_host if a.frames == "gpu" else _render
+    list(pool.map(warm, [(0, 64)] * max(1, a.workers)))
 
     import torch
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    Xtr, THtr, info = make_dataset(a.train_pairs, a.seed0, n=a.n, pool=pool, log=log)
-    Ptr = make_dataset.last_params
-    Xva, THva, info_v = make_dataset(a.val_pairs, a.seed0 + 10 ** 6, n=a.n, pool=pool, log=log)
-    Pva = make_dataset.last_params
+    build = make_dataset_gpu if a.frames == "gpu" else make_dataset
+    Xtr, THtr, info = build(a.train_pairs, a.seed0, n=a.n, pool=pool, log=log)
+    Ptr = build.last_params
+    Xva, THva, info_v = build(a.val_pairs, a.seed0 + 10 ** 6, n=a.n, pool=pool, log=log)
+    Pva = build.last_params
     pool.shutdown()
+    t_data = time.perf_counter() - t0
     if a.dump:
         np.savez_compressed(a.dump, Xtr=Xtr.astype(np.float32), THtr=THtr, Ptr=Ptr, info=info,
                             Xva=Xva.astype(np.float32), THva=THva, Pva=Pva)
@@ -359,73 +477,119 @@ def _cli(argv=None):
     t_train = time.perf_counter() - t1
     if a.save:
         net.save(a.save)
-    rep = evaluate(net, a.val_pairs, a.seed0 + 10 ** 6, n=a.n, theta_ref=THva, base_mean=THtr[ok].mean(axis=0))
+    ntest = a.test_pairs or a.val_pairs
+    base = THtr[ok].mean(axis=0)
+    if a.frames == "gpu":
+        rep = evaluate_gpu(net, ntest, a.seed0 + 2 * 10 ** 6, n=a.n, base_mean=base, log=log)
+    else:
+        rep = evaluate(net, ntest, a.seed0 + 10 ** 6, n=a.n, theta_ref=THva, base_mean=base)
+    # validation loss of the trained network on the held-out validation frames
+    import torch as _t
+    nv = min(len(Xva), net.max_batch)
+    Yv = _t.empty((nv, net.dims[-1]), device="cuda")
+    B.sfft_mlp_forward(net.handle, net.params, _t.from_numpy(net.xs.apply(Xva[:nv]).astype(np.float32)).cuda(), nv, Yv)
+    resid = Yv.cpu().numpy() - net.ys.apply(THva[:nv, :nk])
     rep.update(train_pairs=int(ok.sum()), epochs=a.epochs, train_seconds=t_train, final_loss=hist[-1],
-               loss_first=hist[0])
+               loss_first=hist[0], frames=a.frames, data_seconds=t_data,
+               val_loss=float(np.mean(resid ** 2)), val_explained=float(1.0 - np.mean(resid ** 2)))
     print(json.dumps(rep))
     if a.report:
         with open(a.report, "w") as f:
             json.dump(rep, f, indent=1)
 
 
+def _eval_frame(plan, ws, S, R, M, f, base_mean, nk, ev):
+    """One held-out frame: the full solve path and the quick look (both timed
+    after a warm-up), rho of the guess, the policy, and the mean-kernel baseline.
+    Returns (e_kernel_net, e_kernel_mean, e_diff_net, e_diff_mean, rho, ms_full,
+    ms_quick, ms_policy)."""
+    import torch
+    for _ in range(2):                     # first pass warms up, second is timed
+        ev[0].record()
+        plan.build(S, R, M)
+        c_full, _ = plan.solve()
+        d_full = plan.subtract(S, R, c_full)
+        ev[1].record()
+        torch.cuda.synchronize()
+    t_full = ev[0].elapsed_time(ev[1])
+    for _ in range(2):
+        ev[0].record()
+        plan.build(S, R, M)
+        c_q = ws.coefficients(plan, f)
+        d_q = plan.subtract(S, R, c_q)
+        ev[1].record()
+        torch.cuda.synchronize()
+    t_quick = ev[0].elapsed_time(ev[1])
+    rho = float(plan.residual(c_q).item())
+    t = time.perf_counter()
+    ws.subtract(plan, S, R, M, f)
+    torch.cuda.synchronize()
+    t_policy = 1e3 * (time.perf_counter() - t)
+    c_b = torch.from_numpy(np.asarray(base_mean, np.float64).copy()).cuda()
+    plan.fit_background(c_b)
+    d_b = plan.subtract(S, R, c_b)
+    ref = c_full.cpu().numpy()
+    cq, cb = c_q.cpu().numpy(), c_b.cpu().numpy()
+    df = d_full.cpu().numpy()
+    return (np.linalg.norm(cq[:nk] - ref[:nk]) / np.linalg.norm(ref[:nk]),
+            np.linalg.norm(cb[:nk] - ref[:nk]) / np.linalg.norm(ref[:nk]),
+            np.linalg.norm(d_q.cpu().numpy() - df) / np.linalg.norm(df),
+            np.linalg.norm(d_b.cpu().numpy() - df) / np.linalg.norm(df), rho, t_full, t_quick, t_policy)
+
+
+def _report(rows, ws, npairs, n, tau):
+    r = np.asarray(rows, np.float64)
+    med = lambda k: float(np.median(r[:, k]))  # noqa: E731
+    return dict(val_pairs=npairs, n=n, tau=tau,
+                e_kernel_net=med(0), e_kernel_mean=med(1),
+                e_diff_quicklook_net=med(2), e_diff_quicklook_mean=med(3),
+                rho_median=med(4), rho_min=float(r[:, 4].min()), fallback_rate=ws.fallback_rate,
+                ms_full=med(5), ms_quicklook=med(6), ms_policy=med(7),
+                pairs_per_s_full=1e3 / med(5), pairs_per_s_quicklook=1e3 / med(6))
+
+
 def evaluate(net, npairs, seed0, n=512, theta_ref=None, base_mean=None, tau=1e-5, log=None):
-    """Gain of the network on held-out frames: coefficient and quick-look errors
-    against the full solve, rho and fallback rate, and per-pair times."""
+    """Gain of the network on held-out frames (synth.pair_ws, host-rendered):
+    coefficient and quick-look errors against the full solve, rho and fallback
+    rate, and per-pair times."""
     import torch
     import synth
-    nk = net.dims[-1]
     ws = WarmStart(net, tau)
-    e_net, e_base, ed_net, ed_base, rhos, t_full, t_quick, t_policy = [], [], [], [], [], [], [], []
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    for i in range(npairs):
-        p = synth.pair_ws(seed0 + i, n=n, w=W, dk=DK, db=DB)
-        S = torch.from_numpy(p.sci).cuda()
-        R = torch.from_numpy(p.tmpl).cuda()
-        M = torch.from_numpy(p.mask).cuda()
-        f = pair_features(p)
-        plan = B.Plan(n, n, W, DK, DB, mode=B.SFFT_MODE_F64)
-        try:
-            for rep in range(2):                     # first pass warms up, second is timed
-                ev[0].record()
-                plan.build(S, R, M)
-                c_full, _ = plan.solve()
-                d_full = plan.subtract(S, R, c_full)
-                ev[1].record()
-                torch.cuda.synchronize()
-            t_full.append(ev[0].elapsed_time(ev[1]))
-            for rep in range(2):
-                ev[0].record()
-                plan.build(S, R, M)
-                c_q = ws.coefficients(plan, f)
-                d_q = plan.subtract(S, R, c_q)
-                ev[1].record()
-                torch.cuda.synchronize()
-            t_quick.append(ev[0].elapsed_time(ev[1]))
-            rho = float(plan.residual(c_q).item())
-            t = time.perf_counter()
-            ws.subtract(plan, S, R, M, f)
-            torch.cuda.synchronize()
-            t_policy.append(1e3 * (time.perf_counter() - t))
-            c_b = torch.from_numpy(np.asarray(base_mean, np.float64).copy()).cuda()
-            plan.fit_background(c_b)
-            d_b = plan.subtract(S, R, c_b)
-            ref = c_full.cpu().numpy()
-            cq, cb = c_q.cpu().numpy(), c_b.cpu().numpy()
-            e_net.append(np.linalg.norm(cq[:nk] - ref[:nk]) / np.linalg.norm(ref[:nk]))
-            e_base.append(np.linalg.norm(cb[:nk] - ref[:nk]) / np.linalg.norm(ref[:nk]))
-            df = d_full.cpu().numpy()
-            ed_net.append(np.linalg.norm(d_q.cpu().numpy() - df) / np.linalg.norm(df))
-            ed_base.append(np.linalg.norm(d_b.cpu().numpy() - df) / np.linalg.norm(df))
-            rhos.append(rho)
-        finally:
-            plan.close()
-    med = lambda v: float(np.median(v))  # noqa: E731
-    return dict(val_pairs=npairs, n=n, tau=tau,
-                e_kernel_net=med(e_net), e_kernel_mean=med(e_base),
-                e_diff_quicklook_net=med(ed_net), e_diff_quicklook_mean=med(ed_base),
-                rho_median=med(rhos), rho_min=float(np.min(rhos)), fallback_rate=ws.fallback_rate,
-                ms_full=med(t_full), ms_quicklook=med(t_quick), ms_policy=med(t_policy),
-                pairs_per_s_full=1e3 / med(t_full), pairs_per_s_quicklook=1e3 / med(t_quick))
+    rows = []
+    plan = B.Plan(n, n, W, DK, DB, mode=B.SFFT_MODE_F64)
+    try:
+        for i in range(npairs):
+            p = synth.pair_ws(seed0 + i, n=n, w=W, dk=DK, db=DB)
+            S = torch.from_numpy(p.sci).cuda()
+            R = torch.from_numpy(p.tmpl).cuda()
+            M = torch.from_numpy(p.mask).cuda()
+            rows.append(_eval_frame(plan, ws, S, R, M, pair_features(p), base_mean, net.dims[-1], ev))
+    finally:
+        plan.close()
+    return _report(rows, ws, npairs, n, tau)
+
+
+def evaluate_gpu(net, npairs, seed0, n=4088, base_mean=None, tau=1e-5, log=None):
+    """The same evaluation on frames rendered on the GPU (synth.ws_catalog recipe)."""
+    import torch
+    ws = WarmStart(net, tau)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    rows = []
+    rend = FrameRenderer(1, n)
+    plan = B.Plan(n, n, W, DK, DB, mode=B.SFFT_MODE_F64)
+    try:
+        for i in range(npairs):
+            _, small, arrays, start = ws_frame_host((seed0 + i, n))
+            rend.render(0, small, arrays, start)
+            rend.settle()
+            f = features(small["stamp_s"], small["stamp_t"], small["X"], small["Y"])
+            rows.append(_eval_frame(plan, ws, rend.S[0], rend.R[0], rend.M[0], f, base_mean, net.dims[-1], ev))
+            if log and i % 16 == 15:
+                log(f"[learned] evaluated {i + 1}/{npairs}")
+    finally:
+        plan.close()
+    return _report(rows, ws, npairs, n, tau)
 
 
 if __name__ == "__main__":

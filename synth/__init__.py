@@ -370,3 +370,123 @@ def pair_ws(seed, n=512, w=9, dk=2, db=2, beta=3.0):
     return Pair(sci, tmpl, m.astype(np.uint8), w=w, dk=dk, db=db,
                 truth=dict(name="WS", X=float(X), Y=float(Y), stamp_s=psf_stamp(c_s, beta),
                            stamp_t=psf_stamp(c_t, beta), fwhm_s0=float(f_s0), fwhm_t0=float(f_t0)))
+
+
+# ---------------------------------------------------------------------------
+# counter-based noise and the 4088^2 warm-start recipe (rendered on the GPU
+# by the library's renderer; the numpy renderer below is its reference)
+# ---------------------------------------------------------------------------
+# Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy
+# as 1, 2, 3", SC 2011): a 4 x 32-bit counter and a 2 x 32-bit key, ten rounds
+# of two 32x32->64-bit multiplies with the published constants, the key bumped
+# by the Weyl increments between rounds.
+
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32(c0, c1, c2, c3, k0, k1):
+    """Philox4x32-10 of counter arrays (uint32) under key (k0, k1); returns four uint32 arrays."""
+    M = np.uint64(0xFFFFFFFF)
+    c0, c1, c2, c3 = (np.asarray(c, np.uint64) for c in (c0, c1, c2, c3))
+    k0, k1 = np.uint64(k0), np.uint64(k1)
+    for _ in range(10):
+        p0 = np.uint64(PHILOX_M0) * c0
+        p1 = np.uint64(PHILOX_M1) * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & M
+        hi1, lo1 = p1 >> np.uint64(32), p1 & M
+        c0, c1, c2, c3 = (hi1 ^ c1 ^ k0) & M, lo1, (hi0 ^ c3 ^ k1) & M, lo0
+        k0 = (k0 + np.uint64(PHILOX_W0)) & M
+        k1 = (k1 + np.uint64(PHILOX_W1)) & M
+    return tuple(x.astype(np.uint32) for x in (c0, c1, c2, c3))
+
+
+def philox_normals(index, stream, seed):
+    """Two standard normals per element of `index` (uint64 pixel index) for noise stream
+    `stream`: counter (index low, index high, stream, 0), key (seed low, seed high);
+    uniforms u = (hi 21 bits << 32 | lo 32 bits + 0.5) / 2^53 from word pairs, Box-Muller."""
+    index = np.asarray(index, np.uint64)
+    seed = int(seed)
+    w = philox4x32(index & np.uint64(0xFFFFFFFF), index >> np.uint64(32),
+                   np.full(index.shape, stream, np.uint64), np.zeros(index.shape, np.uint64),
+                   seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    def unif(hi, lo):
+        v = ((hi.astype(np.uint64) >> np.uint64(11)) << np.uint64(32)) | lo.astype(np.uint64)
+        return (v.astype(np.float64) + 0.5) / float(1 << 53)
+    u1, u2 = unif(w[0], w[1]), unif(w[2], w[3])
+    r = np.sqrt(-2.0 * np.log(u1))
+    return r * np.cos(2.0 * np.pi * u2), r * np.sin(2.0 * np.pi * u2)
+
+
+WS_BETA_RANGE = (2.5, 4.0)
+WS_FWHM_S_RANGE = (1.9, 2.6)
+WS_FWHM_T_RANGE = (1.6, 2.0)
+WS_HALF = 12            # star stamps of the warm-start frames are 25 x 25
+
+
+def ws_catalog(seed, n=4088, density=2.39e-3, fmin=5e2, fmax=5e6):
+    """Everything random in one warm-start frame (host side, PCG64): focal-plane
+    position, seeing, Moffat beta, stars, background coefficients and the noise seed.
+    The frame covers +-WS_SPAN of the focal plane around (X, Y); the FWHM of each
+    image varies quadratically over the focal plane as in pair_ws."""
+    rng = np.random.default_rng(seed)
+    X, Y = rng.uniform(-1.0, 1.0, 2)
+    f_s0 = rng.uniform(*WS_FWHM_S_RANGE)
+    f_t0 = rng.uniform(*WS_FWHM_T_RANGE)
+    beta = rng.uniform(*WS_BETA_RANGE)
+    nstar = int(round(density * n * n))
+    xs = rng.uniform(-5.0, n + 4.0, nstar)
+    ys = rng.uniform(-5.0, n + 4.0, nstar)
+    flux = powerlaw_fluxes(rng, nstar, fmin, fmax)
+    bc = rng.normal(0.0, 1.0, 6)
+    noise_seed = int(rng.integers(0, 2 ** 63))
+    Xf = X + WS_SPAN * _norm_coords(xs, n)
+    Yf = Y + WS_SPAN * _norm_coords(ys, n)
+    fw_s = f_s0 * (1.0 + WS_CURV_S * (Xf * Xf + Yf * Yf))
+    fw_t = f_t0 * (1.0 + WS_CURV_T * (Xf * Xf + Yf * Yf))
+    alpha_t = moffat_alpha(fw_t, beta)
+    peak = flux * (beta - 1.0) / (math.pi * alpha_t * alpha_t)
+    bright = peak > 5e4
+    c_s = f_s0 * (1.0 + WS_CURV_S * (X * X + Y * Y))
+    c_t = f_t0 * (1.0 + WS_CURV_T * (X * X + Y * Y))
+    return dict(n=n, X=float(X), Y=float(Y), fwhm_s0=float(f_s0), fwhm_t0=float(f_t0), beta=float(beta),
+                xs=xs, ys=ys, flux=flux, fw_s=fw_s, fw_t=fw_t, bc=bc, noise_seed=noise_seed,
+                mask_r=np.where(bright, 3.0 * fw_s, 0.0),
+                stamp_s=psf_stamp(c_s, beta), stamp_t=psf_stamp(c_t, beta))
+
+
+WS_SKY, WS_READ = 1000.0, 8.0
+
+
+def ws_background(cat):
+    """The science image's quadratic background of a warm-start frame (e-)."""
+    n = cat["n"]
+    gx = _norm_coords(np.arange(n), n)[None, :]
+    gy = _norm_coords(np.arange(n), n)[:, None]
+    bc = cat["bc"]
+    return 5.0 * (bc[0] + bc[1] * gx + bc[2] * gy + 0.5 * (bc[3] * gx * gx + bc[4] * gx * gy + bc[5] * gy * gy))
+
+
+def render_ws_reference(cat):
+    """Reference rendering of a catalogue (what the GPU renderer computes): Moffat
+    stars normalised over their 25 x 25 stamps, the background, and noise
+    lam + sqrt(lam) z1 + 8 z2 - sky with lam = model + sky (the normal limit of
+    Poisson(lam) at lam >= 1000 e-) from philox_normals (stream 0: science,
+    1: template); mask of the bright-star disks.  Returns (sci, tmpl, mask)."""
+    n = cat["n"]
+    beta = cat["beta"]
+    fw_s, fw_t = cat["fw_s"], cat["fw_t"]
+    tm = render_stars(n, n, cat["xs"], cat["ys"], cat["flux"],
+                      lambda dx, dy, i: moffat_stamp(dx, dy, fw_t[i][:, None, None], beta), half=WS_HALF)
+    sm = render_stars(n, n, cat["xs"], cat["ys"], cat["flux"],
+                      lambda dx, dy, i: moffat_stamp(dx, dy, fw_s[i][:, None, None], beta), half=WS_HALF)
+    sm = sm + ws_background(cat)
+    idx = np.arange(n * n, dtype=np.uint64)
+    out = []
+    for stream, model in ((0, sm), (1, tm)):
+        z1, z2 = philox_normals(idx, stream, cat["noise_seed"])
+        lam = np.maximum(model.ravel(), 0.0) + WS_SKY
+        out.append((lam + np.sqrt(lam) * z1 + WS_READ * z2 - WS_SKY).reshape(n, n))
+    b = cat["mask_r"] > 0.0
+    mask = disk_mask(n, n, cat["xs"][b], cat["ys"][b], cat["mask_r"][b])
+    return out[0], out[1], mask.astype(np.uint8)

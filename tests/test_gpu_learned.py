@@ -1,13 +1,18 @@
 """The learned warm start on the GPU.
 
 The network is trained by the library's own forward/backward/Adam kernels on
-solutions the library itself computes (512^2 frames at random focal-plane
-positions, w = 9, DK = DB = 2), then compared on held-out frames with the
-method without it, i.e. the mean kernel of the training set: coefficient
-error and quick-look difference-image error against the full FP64 solve,
-the residual judge rho and the fallback rate, and the per-pair times.  The
-fallback policy is checked to return exactly the plain solve when rho is
-above the threshold, and exactly the completed guess when it is below."""
+solutions the library itself computes: frames rendered on the GPU by
+sfft_render_ws_frame (the warm-start recipe of synth.ws_catalog: Roman-like
+star fields whose PSF varies with the focal-plane position, the seeing and
+the Moffat exponent), solved in FP64 batches (w = 9, DK = DB = 2).  On
+held-out frames it is compared with the method without it, i.e. the mean
+kernel of the training set: coefficient error and quick-look difference-image
+error against the full FP64 solve, the residual judge rho and the fallback
+rate, and the per-pair times.  The gain bar asks for at least 64 % of the
+kernels' spread about the mean kernel (e_net <= 0.6 e_mean, 2048^2 frames); a
+network that explains 1 % of it gives e_net ~ 0.995 e_mean and fails.  The fallback policy
+is checked to return exactly the plain solve when rho is above the threshold,
+and exactly the completed guess when it is below."""
 import json
 import os
 
@@ -27,17 +32,18 @@ NK = L.DIMS[-1]
 
 
 def test_trained_network_gains_over_the_mean_kernel(tmp_path):
-    feats, th, info = L.make_dataset(384, seed0=700000, n=512)
+    n = 2048
+    feats, th, info = L.make_dataset_gpu(6144, seed0=700000, n=n)
     assert (info == 0).all()
-    net = L.Net(L.DIMS, max_batch=64, seed=1)
+    net = L.Net(L.DIMS, max_batch=128, seed=1)
     try:
-        hist = net.train(feats, th[:, :NK], epochs=100, batch=64)
-        rep = L.evaluate(net, 16, seed0=800000, n=512, base_mean=th.mean(axis=0))
+        hist = net.train(feats, th[:, :NK], epochs=60, batch=128)
+        rep = L.evaluate_gpu(net, 12, seed0=800000, n=n, base_mean=th.mean(axis=0))
         rep.update(loss_first=hist[0], loss_last=hist[-1])
         print(json.dumps(rep))
         assert hist[-1] < hist[0]
-        assert rep["e_kernel_net"] <= 0.92 * rep["e_kernel_mean"]
-        assert rep["e_diff_quicklook_net"] < rep["e_diff_quicklook_mean"]
+        assert rep["e_kernel_net"] <= 0.6 * rep["e_kernel_mean"]
+        assert rep["e_diff_quicklook_net"] <= 0.5 * rep["e_diff_quicklook_mean"]
         assert rep["ms_quicklook"] < rep["ms_full"]
         assert 0.0 <= rep["fallback_rate"] <= 1.0
         # checkpoint round trip: same parameters, Adam state and predictions
