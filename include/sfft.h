@@ -68,7 +68,8 @@ typedef struct {
   int32_t dk, db;        /* polynomial degree of the kernel's / background's spatial variation */
   int32_t mode;          /* SFFT_MODE_F64 or SFFT_MODE_F32C                                    */
   int32_t refine_steps;  /* iterative-refinement steps after the Cholesky solve; -1 = 1        */
-  int32_t flags;         /* assembly route, one of SFFT_FLAG_ASSEMBLY_* (other bits must be 0) */
+  int32_t flags;         /* assembly route, one of SFFT_FLAG_ASSEMBLY_* (bits 0-1), optionally
+                            | SFFT_FLAG_CONST_RATIO; other bits must be 0                       */
 } sfft_desc;
 
 /* How the lag windows of Omega and beta are computed (sfft_desc.flags).
@@ -92,6 +93,22 @@ enum {
   SFFT_FLAG_ASSEMBLY_DIRECT = 2,
   SFFT_FLAG_ASSEMBLY_MFMA = 3
 };
+
+/* Constant photometric ratio (sfft_desc.flags bit 4).  Left free, the sum of
+ * the kernel -- the template-to-science flux ratio a point source at z sees,
+ * sum_a m_a(z) s_a with s_a = sum_u k_{a,u} -- varies across the frame with
+ * the kernel's shape ("Statement of need": a spatially varying kernel).  With
+ * this flag the fit keeps it constant: the least-squares minimum under the
+ * nK - 1 equality constraints s_a = 0 (a >= 1), computed from the same
+ * factor as theta0 = Omega^{-1} beta:
+ *   Z = Omega^{-1} C^T,  (C Z) lambda = C theta0,  theta = theta0 - Z lambda,
+ * C (nK - 1 rows) summing the coefficients of each non-constant monomial.
+ * Z's nK - 1 columns are extra right-hand sides of the same substitution and
+ * refinement launches; the small system is solved by Cholesky on the device.
+ * The background is not constrained.  sfft_residual still measures the free
+ * normal equations, which a constrained theta does not satisfy.  No effect
+ * when DK = 0. */
+enum { SFFT_FLAG_CONST_RATIO = 16 };
 
 typedef struct sfft_plan_s* sfft_handle;
 

@@ -585,4 +585,93 @@ __global__ __launch_bounds__(256) void fit_background_kernel(const double* __res
   for (int i = 0; i < nb; ++i) x[nkk + i] = rhs[i];
 }
 
+
+// Constant photometric ratio.  The kernel's flux ratio at a point source at z
+// is sum_a m_a(z) s_a with s_a = sum_u k_{a,u}; it is the same everywhere
+// exactly when s_a = 0 for every non-constant monomial a >= 1.  With those
+// nc = nK - 1 constraints C theta = 0 the least-squares minimum is
+//   theta = theta0 - Z lambda,  Z = Omega^{-1} C^T,  (C Z) lambda = C theta0,
+// theta0 = Omega^{-1} beta the free solution.  The columns of Z are solved
+// by substitution jobs that share the factor (right-hand sides: the columns
+// of C^T, the indicators of the kernel blocks a = 1..nc).
+constexpr int RATIO_MAXC = 14;   // nK - 1 for DK <= 4
+struct RatioJob {
+  double* theta;   // theta0 in, the constrained solution out
+  double* Z;       // nc columns of n (theta of the constraint jobs)
+  double* E;       // nc columns of n: C^T (beta of the constraint jobs)
+  const int* info;
+  int n, L2, nc;
+};
+
+// E[c][i] = [i lies in kernel block c + 1]; grid (ceil(n / 256), jobs)
+__global__ void ratio_rhs_kernel(const RatioJob* __restrict__ jobs) {
+  const RatioJob J = jobs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= J.n) return;
+  const int a = i / J.L2;   // >= nK (never c + 1) on the background coefficients
+  for (int c = 0; c < J.nc; ++c) J.E[(int64_t)c * J.n + i] = (a == c + 1) ? 1.0 : 0.0;
+}
+
+// One block of 256 per job: M = C Z and C theta0 as block sums (a wave per
+// entry), the nc x nc SPD system by Cholesky on one thread (FP64; a
+// non-positive pivot leaves NaN in theta), then theta -= Z lambda.
+__global__ __launch_bounds__(256) void ratio_project_kernel(const RatioJob* __restrict__ jobs) {
+  __shared__ double M[RATIO_MAXC][RATIO_MAXC + 1];   // [C Z | C theta0]
+  __shared__ double lam[RATIO_MAXC];
+  __shared__ int ok;
+  const RatioJob J = jobs[blockIdx.x];
+  if (*J.info != 0) return;
+  const int nc = J.nc, n = J.n, L2 = J.L2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = wave; q < nc * (nc + 1); q += 4) {
+    const int a = q / (nc + 1), b = q - a * (nc + 1);
+    const double* __restrict__ v = (b < nc ? J.Z + (int64_t)b * n : J.theta) + (int64_t)(a + 1) * L2;
+    double acc = 0.0;
+    for (int u = lane; u < L2; u += 64) acc += v[u];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) M[a][b] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    for (int j = 0; j < nc && ok; ++j) {      // M = G G^T in the lower triangle
+      double d = M[j][j];
+      for (int k = 0; k < j; ++k) d -= M[j][k] * M[j][k];
+      if (!(d > 0.0)) {
+        ok = 0;
+        break;
+      }
+      d = sqrt(d);
+      M[j][j] = d;
+      for (int i = j + 1; i < nc; ++i) {
+        double t = M[i][j];
+        for (int k = 0; k < j; ++k) t -= M[i][k] * M[j][k];
+        M[i][j] = t / d;
+      }
+    }
+    if (ok) {
+      for (int i = 0; i < nc; ++i) {            // G y = C theta0
+        double t = M[i][nc];
+        for (int k = 0; k < i; ++k) t -= M[i][k] * lam[k];
+        lam[i] = t / M[i][i];
+      }
+      for (int i = nc - 1; i >= 0; --i) {       // G^T lambda = y
+        double t = lam[i];
+        for (int k = i + 1; k < nc; ++k) t -= M[k][i] * lam[k];
+        lam[i] = t / M[i][i];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double t = J.theta[i];
+    if (ok) {
+      for (int c = 0; c < nc; ++c) t -= J.Z[(int64_t)c * n + i] * lam[c];
+    } else {
+      t = __builtin_nan("");
+    }
+    J.theta[i] = t;
+  }
+}
+
 }  // namespace sfft

@@ -74,7 +74,7 @@ constexpr int MAX_VROWS = JMAX * MAX_ITEMS;
 
 struct Layout {
   size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, w, kp, flags, tw32, tw64, items, wrows, drows,
-      mtiles, job;
+      mtiles, ratio, job, rjob;
   size_t total;
 };
 
@@ -95,6 +95,7 @@ struct Derived {
   FixedVec<CorrItem, MAX_ITEMS> items;
   FixedVec<WinRow, MAX_VROWS> wrows;
   int route;                      // Route: transforms, direct sums or matrix-core products
+  int nratio;                     // constant photometric ratio: nK - 1 constraints, else 0
   FixedVec<DirectRow, MAX_VROWS> drows;
   FixedVec<MfmaTile, MAX_MTILES> mtiles;
   int mfma_nxc, mfma_band, mfma_nband;   // MFMA route: column chunks, rows per band, bands
@@ -129,7 +130,7 @@ int validate(const sfft_desc* d) {
   if (d->ny > (1 << MAX_LOG_P) || d->nx > (1 << MAX_LOG_P)) return SFFT_EINVAL;
   if (d->mode != SFFT_MODE_F64 && d->mode != SFFT_MODE_F32C) return SFFT_EINVAL;
   if (d->refine_steps < -1 || d->refine_steps > 10) return SFFT_EINVAL;
-  if ((d->flags & ~3) != 0) return SFFT_EINVAL;
+  if ((d->flags & ~(3 | SFFT_FLAG_CONST_RATIO)) != 0) return SFFT_EINVAL;
   if ((d->flags & 3) == SFFT_FLAG_ASSEMBLY_DIRECT && (d->nx > DIR_MAX_NX || 2 * d->w > DIR_HWMAX)) return SFFT_EINVAL;
   const int L = 2 * d->w + 1;
   const int nk = (d->dk + 1) * (d->dk + 2) / 2, nb = (d->db + 1) * (d->db + 2) / 2;
@@ -152,6 +153,7 @@ int derive(const sfft_desc* d, Derived* D) {
   D->L = 2 * d->w + 1;
   D->nk = (d->dk + 1) * (d->dk + 2) / 2;
   D->nb = (d->db + 1) * (d->db + 2) / 2;
+  D->nratio = (d->flags & SFFT_FLAG_CONST_RATIO) ? D->nk - 1 : 0;
   D->nkk = D->L * D->L * D->nk;
   D->n = D->nkk + D->nb;
   D->lgPy = std::max(MIN_LOG_P, ilog2_ceil(d->ny));
@@ -423,7 +425,10 @@ Layout layout_of(const Derived& D) {
   Lo.wrows = take((size_t)D.wrows.size() * sizeof(WinRow));
   Lo.drows = take((size_t)D.drows.size() * sizeof(DirectRow));
   Lo.mtiles = take((size_t)D.mtiles.size() * sizeof(MfmaTile));
-  Lo.job = take(sizeof(SolveJob));
+  // constant photometric ratio: C^T, Z and the substitution vectors of each constraint column
+  Lo.ratio = take((size_t)6 * D.nratio * D.n * sizeof(double));
+  Lo.job = take((size_t)(1 + D.nratio) * sizeof(SolveJob));
+  Lo.rjob = take(sizeof(RatioJob));
   Lo.total = off;
   return Lo;
 }
@@ -568,8 +573,11 @@ struct sfft_plan_s {
   // stream) and a device table of their solve jobs
   bool is_batch = false;
   std::vector<sfft_plan_s*> members;
-  SolveJob* jobs_dev = nullptr;
+  SolveJob* jobs_dev = nullptr;     // [the pairs' jobs | their constraint-column jobs]
+  RatioJob* rjobs_dev = nullptr;    // projection jobs (pairs with a constant photometric ratio)
   std::vector<SolveJob> jobs_host;
+  RatioJob rjob_host;
+  int nsub = 0, nratio = 0;
   int max_n = 0, max_nblk = 0;
   // graph of one captured batch run (sfft_batch_capture / sfft_batch_launch)
   hipGraph_t graph = nullptr;
@@ -829,10 +837,22 @@ int build_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   return gather_impl(p, A, PS, np);
 }
 
+// The solve of a set of pairs: the first nfac jobs own a factor each; all
+// nsub jobs (those, then one per constraint column of the pairs with a
+// constant photometric ratio) are substituted and refined against them; the
+// nratio projection jobs then combine each such pair's columns.
+struct SolveTable {
+  const SolveJob* jobs;
+  int nfac, nsub;
+  const RatioJob* rjobs;
+  int nratio;
+};
+
 // FP64 Cholesky, triangular solves and refinement for a table of jobs: one
 // launch per block step serves every pair of the table.
-int solve_jobs(hipStream_t s, const SolveJob* jobs, int njobs, int max_n, int max_nblk, int refine,
-               StageTimer* tm) {
+int solve_jobs(hipStream_t s, const SolveTable& T, int max_n, int max_nblk, int refine, StageTimer* tm) {
+  const SolveJob* jobs = T.jobs;
+  const int njobs = T.nfac;
   tm->begin(SFFT_STAGE_FACTOR, s);
   reset_info_kernel<<<(njobs + 63) / 64, 64, 0, s>>>(jobs, njobs);
   LAUNCH_CHECK();
@@ -844,11 +864,11 @@ int solve_jobs(hipStream_t s, const SolveJob* jobs, int njobs, int max_n, int ma
   for (int k = 0; k < max_nblk; ++k) {
     potrf_diag_kernel<<<njobs, 64, 0, s>>>(jobs, k);
     LAUNCH_CHECK();
-    const int T = max_nblk - k - 1;
-    if (T > 0) {
-      trsm_kernel<<<dim3(T, njobs), 256, 0, s>>>(jobs, k);
+    const int T1 = max_nblk - k - 1;
+    if (T1 > 0) {
+      trsm_kernel<<<dim3(T1, njobs), 256, 0, s>>>(jobs, k);
       LAUNCH_CHECK();
-      const int ntile = T * (T + 1) / 2;
+      const int ntile = T1 * (T1 + 1) / 2;
       const int grid = ((njobs * ntile + 7) / 8) * 8;   // whole XCD rounds for the remap
       syrk_kernel<<<grid, 256, 0, s>>>(jobs, k, njobs, ntile);
       LAUNCH_CHECK();
@@ -856,18 +876,23 @@ int solve_jobs(hipStream_t s, const SolveJob* jobs, int njobs, int max_n, int ma
   }
   tm->end(s);
   tm->begin(SFFT_STAGE_SOLVE, s);
+  const int nsub = T.nsub;
+  if (T.nratio > 0) {
+    ratio_rhs_kernel<<<dim3((max_n + 255) / 256, T.nratio), 256, 0, s>>>(T.rjobs);
+    LAUNCH_CHECK();
+  }
   // blocked right-looking substitutions: one launch per block step, one
   // block per row block still to be updated
   auto solve_lower = [&](int which) -> int {
     for (int k = 0; k < max_nblk; ++k) {
-      trsv_lower_step_kernel<<<dim3(max_nblk - k, njobs), 256, 0, s>>>(jobs, k, which);
+      trsv_lower_step_kernel<<<dim3(max_nblk - k, nsub), 256, 0, s>>>(jobs, k, which);
       LAUNCH_CHECK();
     }
     return SFFT_OK;
   };
   auto solve_upper = [&](int which) -> int {
     for (int k = max_nblk - 1; k >= 0; --k) {
-      trsv_upper_step_kernel<<<dim3(k + 1, njobs), 256, 0, s>>>(jobs, k, which);
+      trsv_upper_step_kernel<<<dim3(k + 1, nsub), 256, 0, s>>>(jobs, k, which);
       LAUNCH_CHECK();
     }
     return SFFT_OK;
@@ -876,12 +901,16 @@ int solve_jobs(hipStream_t s, const SolveJob* jobs, int njobs, int max_n, int ma
   if (st == SFFT_OK) st = solve_upper(0);
   if (st != SFFT_OK) return st;
   for (int it = 0; it < refine; ++it) {
-    residual_jobs_kernel<<<dim3((max_n + 3) / 4, njobs), 256, 0, s>>>(jobs);
+    residual_jobs_kernel<<<dim3((max_n + 3) / 4, nsub), 256, 0, s>>>(jobs);
     LAUNCH_CHECK();
     st = solve_lower(1);
     if (st == SFFT_OK) st = solve_upper(1);
     if (st != SFFT_OK) return st;
-    axpy_jobs_kernel<<<dim3((max_n + 255) / 256, njobs), 256, 0, s>>>(jobs);
+    axpy_jobs_kernel<<<dim3((max_n + 255) / 256, nsub), 256, 0, s>>>(jobs);
+    LAUNCH_CHECK();
+  }
+  if (T.nratio > 0) {
+    ratio_project_kernel<<<T.nratio, 256, 0, s>>>(T.rjobs);
     LAUNCH_CHECK();
   }
   tm->end(s);
@@ -904,6 +933,56 @@ SolveJob job_of(sfft_plan_s* p) {
   J.n = p->D.n;
   J.nblk = p->D.nblk;
   return J;
+}
+
+// A plan's constraint-column jobs (constant photometric ratio, D.nratio of
+// them, sharing its factor) and its projection job.  The ratio region holds
+// six arrays of nratio x n: C^T, Z, and the y, r, d, w vectors of the jobs.
+void ratio_jobs_of(sfft_plan_s* p, std::vector<SolveJob>* cj, RatioJob* rj) {
+  const Derived& D = p->D;
+  const int nc = D.nratio, n = D.n;
+  double* base = p->at<double>(p->Lo.ratio);
+  auto arr = [&](int k) { return base + (size_t)k * nc * n; };
+  const SolveJob J0 = job_of(p);
+  for (int c = 0; c < nc; ++c) {
+    SolveJob J = J0;
+    J.beta = arr(0) + (size_t)c * n;
+    J.theta = arr(1) + (size_t)c * n;
+    J.y = arr(2) + (size_t)c * n;
+    J.r = arr(3) + (size_t)c * n;
+    J.d = arr(4) + (size_t)c * n;
+    J.w = arr(5) + (size_t)c * n;
+    cj->push_back(J);
+  }
+  rj->theta = J0.theta;
+  rj->Z = arr(1);
+  rj->E = arr(0);
+  rj->info = J0.info;
+  rj->n = n;
+  rj->L2 = D.L * D.L;
+  rj->nc = nc;
+}
+
+// A single plan's solve tables in its workspace: [its job, constraint jobs] and
+// the projection job.  Uploaded on `s` from `host` (kept alive by the caller
+// until the stream has run the copies).
+int upload_solve_tables(sfft_plan_s* p, hipStream_t s, std::vector<SolveJob>* host, RatioJob* rj) {
+  host->assign(1, job_of(p));
+  ratio_jobs_of(p, host, rj);
+  HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.job), host->data(), host->size() * sizeof(SolveJob),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.rjob), rj, sizeof(RatioJob), hipMemcpyHostToDevice, s));
+  return SFFT_OK;
+}
+
+SolveTable plan_table(sfft_plan_s* p) {
+  SolveTable T;
+  T.jobs = p->at<SolveJob>(p->Lo.job);
+  T.nfac = 1;
+  T.nsub = 1 + p->D.nratio;
+  T.rjobs = p->at<RatioJob>(p->Lo.rjob);
+  T.nratio = p->D.nratio > 0 ? 1 : 0;
+  return T;
 }
 
 // Convolve-and-subtract for the np pairs of PS (same descriptor and row pitch
@@ -1097,9 +1176,7 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
                        hipMemcpyHostToDevice, s) == hipSuccess;
   ok &= hipMemcpyAsync(p->at<void>(p->Lo.mtiles), p->D.mtiles.data(), p->D.mtiles.size() * sizeof(MfmaTile),
                        hipMemcpyHostToDevice, s) == hipSuccess;
-  p->jobs_host.assign(1, job_of(p));
-  ok &= hipMemcpyAsync(p->at<void>(p->Lo.job), p->jobs_host.data(), sizeof(SolveJob), hipMemcpyHostToDevice, s) ==
-        hipSuccess;
+  ok &= upload_solve_tables(p, s, &p->jobs_host, &p->rjob_host) == SFFT_OK;
   // host staging vectors of pageable memory: make sure the copies are done before returning
   ok &= hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
@@ -1139,7 +1216,7 @@ int sfft_solve(sfft_handle p, double* coeffs, int32_t* info) {
   const Derived& D = p->D;
   const Layout& Lo = p->Lo;
   hipStream_t s = p->stream;
-  int st = solve_jobs(s, p->at<SolveJob>(Lo.job), 1, D.n, D.nblk, D.refine, &p->timer);
+  int st = solve_jobs(s, plan_table(p), D.n, D.nblk, D.refine, &p->timer);
   if (st != SFFT_OK) return st;
   copy_out_kernel<<<(D.n + 255) / 256, 256, 0, s>>>(p->at<double>(Lo.theta), coeffs, D.n, p->at<int>(Lo.flags), info);
   LAUNCH_CHECK();
@@ -1296,14 +1373,19 @@ void sfft_destroy(sfft_handle p) {
 
 int sfft_batch_workspace_bytes(const sfft_desc* descs, int32_t npairs, size_t* bytes) {
   if (descs == nullptr || bytes == nullptr || npairs <= 0) return SFFT_EINVAL;
-  size_t tot = 0;
+  size_t tot = 0, njobs = 0, nratio = 0;
   for (int i = 0; i < npairs; ++i) {
     size_t b = 0;
     const int st = sfft_workspace_bytes(&descs[i], &b);
     if (st != SFFT_OK) return st;
     tot += b;
+    const int nk = (descs[i].dk + 1) * (descs[i].dk + 2) / 2;
+    const int nc = (descs[i].flags & SFFT_FLAG_CONST_RATIO) ? nk - 1 : 0;
+    njobs += 1 + nc;
+    nratio += nc > 0 ? 1 : 0;
   }
-  *bytes = tot + align256((size_t)npairs * sizeof(SolveJob));
+  // the job tables: every pair's jobs, then the projection jobs
+  *bytes = tot + align256(njobs * sizeof(SolveJob)) + std::max<size_t>(1, nratio) * sizeof(RatioJob);
   return SFFT_OK;
 }
 
@@ -1338,15 +1420,29 @@ int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sf
     b->max_n = std::max(b->max_n, m->D.n);
     b->max_nblk = std::max(b->max_nblk, m->D.nblk);
   }
+  // the constraint-column jobs after all pairs' own jobs, one projection job per such pair
+  std::vector<RatioJob> rjobs;
+  for (sfft_plan_s* m : b->members) {
+    if (m->D.nratio == 0) continue;
+    RatioJob rj;
+    ratio_jobs_of(m, &b->jobs_host, &rj);
+    rjobs.push_back(rj);
+  }
+  b->nsub = (int)b->jobs_host.size();
+  b->nratio = (int)rjobs.size();
+  const size_t job_bytes = align256(b->jobs_host.size() * sizeof(SolveJob));
   void* jd = nullptr;
-  if (hipMalloc(&jd, (size_t)npairs * sizeof(SolveJob)) != hipSuccess) {
+  if (hipMalloc(&jd, job_bytes + std::max<size_t>(1, rjobs.size()) * sizeof(RatioJob)) != hipSuccess) {
     (void)hipGetLastError();
     sfft_destroy(b);
     return SFFT_ENOMEM;
   }
   b->jobs_dev = reinterpret_cast<SolveJob*>(jd);
-  if (hipMemcpy(b->jobs_dev, b->jobs_host.data(), (size_t)npairs * sizeof(SolveJob), hipMemcpyHostToDevice) !=
-      hipSuccess) {
+  b->rjobs_dev = reinterpret_cast<RatioJob*>(static_cast<unsigned char*>(jd) + job_bytes);
+  if (hipMemcpy(b->jobs_dev, b->jobs_host.data(), b->jobs_host.size() * sizeof(SolveJob), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      (!rjobs.empty() &&
+       hipMemcpy(b->rjobs_dev, rjobs.data(), rjobs.size() * sizeof(RatioJob), hipMemcpyHostToDevice) != hipSuccess)) {
     sfft_destroy(b);
     return SFFT_EHIP;
   }
@@ -1411,7 +1507,13 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
     for (int i : g) b->members[i]->built = true;
   }
   // one batched factorisation and solve for all pairs
-  int st = solve_jobs(s, b->jobs_dev, np, b->max_n, b->max_nblk, b->members[0]->D.refine, &b->timer);
+  SolveTable T;
+  T.jobs = b->jobs_dev;
+  T.nfac = np;
+  T.nsub = b->nsub;
+  T.rjobs = b->rjobs_dev;
+  T.nratio = b->nratio;
+  int st = solve_jobs(s, T, b->max_n, b->max_nblk, b->members[0]->D.refine, &b->timer);
   if (st != SFFT_OK) return st;
   for (const auto& g : groups) {
     const sfft_plan_s* lead = b->members[g[0]];
@@ -1641,7 +1743,7 @@ int noalloc_run(sfft_plan_s* p, const void* sci, const void* tmpl, const uint8_t
   if (st != SFFT_OK) return st;
   const Derived& D = p->D;
   hipStream_t s = p->stream;
-  st = solve_jobs(s, p->at<SolveJob>(p->Lo.job), 1, D.n, D.nblk, D.refine, &p->timer);
+  st = solve_jobs(s, plan_table(p), D.n, D.nblk, D.refine, &p->timer);
   if (st != SFFT_OK) return st;
   copy_out_group_kernel<<<dim3((D.n + 255) / 256, 1, 1), 256, 0, s>>>(PS, ws_offsets(D, p->Lo), D.n);
   LAUNCH_CHECK();
@@ -1710,9 +1812,11 @@ int sfft_subtract_pair_noalloc(const sfft_desc* d, void* hip_stream, const void*
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.mtiles), D.mtiles.data(), (size_t)D.mtiles.size() * sizeof(MfmaTile),
                            hipMemcpyHostToDevice, s));
-    const SolveJob job = job_of(p);
-    HIP_TRY(hipMemcpyAsync(p->at<void>(p->Lo.job), &job, sizeof(job), hipMemcpyHostToDevice, s));
-    // the host tables (and `job`) may change once the copies have been made
+    std::vector<SolveJob> jobs;
+    RatioJob rj;
+    st = upload_solve_tables(p, s, &jobs, &rj);
+    if (st != SFFT_OK) return st;
+    // the host tables (and `jobs`, `rj`) may change once the copies have been made
     HIP_TRY(hipStreamSynchronize(s));
     g.desc = *d;
     g.have_desc = true;

@@ -35,6 +35,11 @@ def test_num_coeffs_and_workspace():
              for f in (B.SFFT_FLAG_ASSEMBLY_AUTO, B.SFFT_FLAG_ASSEMBLY_FFT, B.SFFT_FLAG_ASSEMBLY_DIRECT,
                        B.SFFT_FLAG_ASSEMBLY_MFMA)}
     assert len(set(sizes.values())) == 1
+    # the constant photometric ratio adds its constraint columns (nK - 1 = 5 here, six vectors each)
+    cr = B.make_desc(1024, 1024, 9, 2, 2, B.SFFT_MODE_F32C, flags=B.SFFT_FLAG_CONST_RATIO | B.SFFT_FLAG_ASSEMBLY_FFT)
+    assert B.sfft_num_coeffs(cr) == 2172
+    extra = B.sfft_workspace_bytes(cr) - sizes[B.SFFT_FLAG_ASSEMBLY_FFT]
+    assert 6 * 5 * 2172 * 8 <= extra <= 6 * 5 * 2172 * 8 + 4096
 
 
 @pytest.mark.parametrize("bad", [
@@ -46,6 +51,7 @@ def test_num_coeffs_and_workspace():
     dict(ny=64, nx=64, w=2, dk=1, db=1, mode=7),
     dict(ny=64, nx=64, w=2, dk=1, db=1, flags=7),        # route bits plus an unknown bit
     dict(ny=64, nx=64, w=2, dk=1, db=1, flags=4),        # unknown flag bit
+    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=32),       # unknown flag bit above the ratio flag
     dict(ny=64, nx=2048, w=2, dk=1, db=1, flags=2),      # direct sums limited to nx <= 1024
     dict(ny=64, nx=64, w=10, dk=1, db=1, flags=2),       # ... and to w <= 9
     dict(ny=4096, nx=4096, w=15, dk=3, db=3),     # more unknowns than the solver holds
