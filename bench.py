@@ -457,6 +457,93 @@ def route_leg(B, torch, p, mode_name, log):
     return out
 
 
+def next_leg(B, torch, p, mode_name, log, reps=10):
+    """The pipeline steps around the subtraction on pair 0, each timed with HIP
+    events on the stream it runs on (torch's current stream): alignment of the
+    template and its mask (step 4) by a small rotation, scale and shift;
+    cross-convolution of the science image with a PSF stamp (step 5); the
+    constant-photometric-ratio solve against the free one; the decorrelation
+    kernel and its application to the difference image (step 7).  Algorithmic
+    bytes: alignment reads the template and mask and writes both (2 N^2 (e + 1),
+    e the image element size); a convolution reads and writes one image
+    (2 N^2 e)."""
+    import math
+    import synth
+    mode = B.SFFT_MODE_F64 if mode_name == "f64" else B.SFFT_MODE_F32C
+    dt = torch.float64 if mode == B.SFFT_MODE_F64 else torch.float32
+    es = 8 if mode == B.SFFT_MODE_F64 else 4
+    S = torch.from_numpy(p.sci).to("cuda", dt)
+    R = torch.from_numpy(p.tmpl).to("cuda", dt)
+    M = torch.from_numpy(p.mask).cuda()
+    n = p.sci.shape[0]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    def hbm(ms, byt):
+        g = byt / (ms * 1e-3) / 1e9
+        return dict(bound="hbm", ms=round(ms, 4), bytes=int(byt), achieved_gbs=round(g, 1), peak=HBM_PEAK_GBS,
+                    frac=round(g / HBM_PEAK_GBS, 4))
+
+    out = {}
+    th = 0.0015
+    c, sn = math.cos(th), math.sin(th)
+    pmap = B.make_map([n / 2 + 0.37, 1.0002 * c, -1.0002 * sn], [n / 2 - 0.21, 1.0002 * sn, 1.0002 * c],
+                      (n / 2, n / 2))
+    Ra, Ma = torch.empty_like(R), torch.empty_like(M)
+    out["align"] = hbm(timed(lambda: B.sfft_align_image(pmap, mode, R, M, Ra, Ma)), 2 * n * n * (es + 1))
+    out["align"]["kernel"] = "align_image_kernel"
+    sp = 12
+    pr = synth.psf_stamp(1.8, 3.0, half=sp)
+    ps = synth.psf_stamp(2.2, 3.0, half=sp)
+    prd, psd = torch.from_numpy(pr.ravel()).cuda(), torch.from_numpy(ps.ravel()).cuda()
+    cplan = B.Plan(n, n, sp, 0, 0, mode=mode)
+    try:
+        Sx = torch.empty_like(S)
+        out["cross_convolution"] = hbm(timed(lambda: cplan.apply_kernel(S, prd, Sx)), 2 * n * n * es)
+        out["cross_convolution"]["stamp"] = 2 * sp + 1
+    finally:
+        cplan.close()
+    solve_ms = {}
+    for name, fl in (("free", 0), ("constrained", B.SFFT_FLAG_CONST_RATIO)):
+        plan = B.Plan(n, n, p.w, p.dk, p.db, mode=mode, flags=fl)
+        try:
+            plan.build(S, R, M)
+            coeffs = torch.zeros(plan.n, dtype=torch.float64, device="cuda")
+            info = torch.zeros(1, dtype=torch.int32, device="cuda")
+            solve_ms[name] = timed(lambda: plan.solve(coeffs, info))
+            if fl:
+                D = plan.subtract(S, R, coeffs)
+                t = 12
+                psi = torch.empty((2 * t + 1) ** 2, dtype=torch.float64, device="cuda")
+                kms = timed(lambda: B.sfft_decorrelation_kernel(plan.handle, coeffs, psd, prd, sp, 32.0, 32.0, t, psi))
+                dplan = B.Plan(n, n, t, 0, 0, mode=mode)
+                try:
+                    Dd = torch.empty_like(D)
+                    app = hbm(timed(lambda: dplan.apply_kernel(D, psi, Dd)), 2 * n * n * es)
+                finally:
+                    dplan.close()
+                out["decorrelation"] = dict(kernel_ms=round(kms, 4), grid=64, taps=2 * t + 1, apply=app)
+        finally:
+            plan.close()
+    out["const_ratio"] = dict(solve_ms_free=round(solve_ms["free"], 4),
+                              solve_ms_constrained=round(solve_ms["constrained"], 4),
+                              overhead_ms=round(solve_ms["constrained"] - solve_ms["free"], 4),
+                              constraints=(p.dk + 1) * (p.dk + 2) // 2 - 1)
+    log(f"[bench] pipeline steps 4-7 on pair 0 ({mode_name}): {out}")
+    del S, R, M, Ra, Ma
+    torch.cuda.empty_cache()
+    return out
+
+
 def roofline_of(stage, D, mode_f64, ms, pairs=1.0):
     """Algorithmic amount of `pairs` pairs over `ms` milliseconds against the peak."""
     bound, amount = stage_cost(stage, D, mode_f64)
@@ -487,6 +574,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default correlation chunk")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--no-routes", action="store_true", help="skip the assembly-route timings")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the timings of the steps around the subtraction (alignment, cross-convolution, "
+                         "constant ratio, decorrelation)")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -529,6 +619,9 @@ def main():
     routes = None
     if not args.no_routes and len({(p.sci.shape, p.w, p.dk, p.db) for p in pairs}) == 1:
         routes = route_leg(B, torch, pairs[0], args.mode, log)
+    steps = None
+    if not args.no_next:
+        steps = next_leg(B, torch, pairs[0], args.mode, log)
 
     # ---- CPU baseline and accuracy (the oracle) ----
     cpu = cond = None
@@ -616,6 +709,7 @@ def main():
         "stages_ms_per_pair": {k: round(v, 4) for k, v in head["stages_ms_per_pair"].items()},
         "stage_rooflines": stage_roofs,
         "assembly_routes": routes,
+        "pipeline_steps": steps,
     }
     print(json.dumps(out), flush=True)
 

@@ -58,6 +58,27 @@ class sfft_ws_frame(ctypes.Structure):
                 ("tile_start", ctypes.c_void_p)]
 
 
+class sfft_pixel_map(ctypes.Structure):
+    """Science-to-template pixel map (include/sfft_align.h): polynomial of degree deg in
+    (x - x_ref, y - y_ref), monomials 1; u, v; u^2, uv, v^2; u^3, u^2 v, u v^2, v^3."""
+    _fields_ = [("deg", ctypes.c_int32), ("x_ref", ctypes.c_double), ("y_ref", ctypes.c_double),
+                ("cx", ctypes.c_double * 10), ("cy", ctypes.c_double * 10)]
+
+
+def make_map(cx, cy, ref=(0.0, 0.0)) -> sfft_pixel_map:
+    """A pixel map from coefficient lists of length 1, 3, 6 or 10."""
+    deg = {1: 0, 3: 1, 6: 2, 10: 3}[len(cx)]
+    if len(cy) != len(cx):
+        raise ValueError("cx and cy need the same number of coefficients")
+    m = sfft_pixel_map()
+    m.deg = deg
+    m.x_ref, m.y_ref = float(ref[0]), float(ref[1])
+    for j in range(len(cx)):
+        m.cx[j] = float(cx[j])
+        m.cy[j] = float(cy[j])
+    return m
+
+
 _lib = None
 
 
@@ -101,6 +122,10 @@ def lib():
         "sfft_autotune_route": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_float),
                                                ctypes.POINTER(i32)]),
         "sfft_render_ws_frame": (ctypes.c_int, [ctypes.POINTER(sfft_ws_frame), vp, vp, vp, vp, i64, vp, vp]),
+        "sfft_align_image": (ctypes.c_int, [ctypes.POINTER(sfft_pixel_map), i32, vp, vp, vp, i32, i32, i64, vp, vp,
+                                            i32, i32, i64]),
+        "sfft_align_psf": (ctypes.c_int, [ctypes.POINTER(sfft_pixel_map), ctypes.c_double, ctypes.c_double, vp, vp,
+                                          i32, vp, i32]),
         "sfft_destroy": (None, [vp]),
         "sfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sfft_mlp_create": (ctypes.c_int, [ctypes.POINTER(i32), i32, i32, vp, ctypes.POINTER(vp)]),
@@ -307,6 +332,27 @@ def sfft_render_ws_frame(frame: sfft_ws_frame, sci, tmpl, mask, ld: int, norm_sc
     _check(lib().sfft_render_ws_frame(ctypes.byref(frame), _stream_handle(stream), _ptr(sci), _ptr(tmpl),
                                       _ptr(mask), int(ld), _ptr(norm_scratch), _ptr(overflow)),
            "sfft_render_ws_frame")
+
+
+def sfft_align_image(pmap: sfft_pixel_map, mode: int, tmpl, tmpl_mask, out, out_mask, stream=None):
+    """Resample the template (and mask) onto the science grid of `out` (device tensors, row pitch = stride(0))."""
+    nyt, nxt = tmpl.shape
+    ny, nx = out.shape
+    if out_mask.shape != out.shape or out_mask.stride(0) != out.stride(0):
+        raise ValueError("out_mask must have the shape and row pitch of out")
+    if tmpl_mask is not None and (tmpl_mask.shape != tmpl.shape or tmpl_mask.stride(0) != tmpl.stride(0)):
+        raise ValueError("tmpl_mask must have the shape and row pitch of tmpl")
+    _check(lib().sfft_align_image(ctypes.byref(pmap), int(mode), _stream_handle(stream), _ptr(tmpl), _ptr(tmpl_mask),
+                                  int(nyt), int(nxt), int(tmpl.stride(0)), _ptr(out), _ptr(out_mask), int(ny),
+                                  int(nx), int(out.stride(0))), "sfft_align_image")
+
+
+def sfft_align_psf(pmap: sfft_pixel_map, x0: float, y0: float, psf_t, psf_out, stream=None):
+    """Aligned PSF stamp (device double, side 2s+1) from the template stamp at science point (x0, y0)."""
+    st = (psf_t.shape[0] - 1) // 2
+    s = (psf_out.shape[0] - 1) // 2
+    _check(lib().sfft_align_psf(ctypes.byref(pmap), float(x0), float(y0), _stream_handle(stream), _ptr(psf_t),
+                                int(st), _ptr(psf_out), int(s)), "sfft_align_psf")
 
 
 def sfft_batch_launch(handle):

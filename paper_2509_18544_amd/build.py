@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libsfft.so")
-SOURCES = ("sfft.hip", "mlp.hip", "render.hip")
+SOURCES = ("sfft.hip", "mlp.hip", "render.hip", "align.hip")
 
 ARCH = "gfx950"
 FLAGS = [

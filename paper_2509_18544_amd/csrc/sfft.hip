@@ -401,7 +401,9 @@ Layout layout_of(const Derived& D) {
     // direct and MFMA route partial sums (per band, per chunk and band)
     const size_t dir_bytes = (size_t)D.dir_nband * D.nwin * sizeof(double);
     const size_t mfma_bytes = (size_t)D.mfma_nxc * D.mfma_nband * D.nwin * sizeof(double);
-    Lo.U = take(std::max(std::max(asm_bytes, sub_bytes), std::max(dir_bytes, mfma_bytes)));
+    // (also the decorrelation kernel's grid spectrum)
+    const size_t dec_bytes = (size_t)DEC_ND * DEC_ND * sizeof(double);
+    Lo.U = take(std::max(std::max(std::max(asm_bytes, sub_bytes), std::max(dir_bytes, mfma_bytes)), dec_bytes));
   }
   Lo.V = take((size_t)(D.H + 1) * D.vrows * sizeof(cplx<double>));
   Lo.win = take((size_t)D.nwin * sizeof(double));
@@ -1291,7 +1293,13 @@ int sfft_decorrelation_kernel(sfft_handle p, const double* coeffs, const double*
     Q.kpx[i] = D.kpoly.px[i];
     Q.kqy[i] = D.kpoly.qy[i];
   }
-  decorr_kernel<<<1, DEC_THREADS, 0, p->stream>>>(Q, coeffs, psf_sci, psf_tmpl, p->at<cplx<double>>(p->Lo.tw64), psi);
+  // the grid spectrum Psi^ goes to the head of the spectra region (free between calls)
+  double* spec = p->at<double>(p->Lo.U);
+  decorr_spec_kernel<<<DEC_SPEC_BLOCKS, DEC_SPEC_THREADS, 0, p->stream>>>(
+      Q, coeffs, psf_sci, psf_tmpl, p->at<cplx<double>>(p->Lo.tw64), spec);
+  LAUNCH_CHECK();
+  decorr_inv_kernel<<<(2 * t + 1) * (2 * t + 1), DEC_INV_THREADS, 0, p->stream>>>(
+      Q, spec, p->at<cplx<double>>(p->Lo.tw64), psi);
   LAUNCH_CHECK();
   return SFFT_OK;
 }

@@ -130,3 +130,32 @@ def test_caller_workspace_too_small_is_enomem():
     # a misaligned workspace is rejected first
     st = B.lib().sfft_plan(ctypes.byref(d), None, ctypes.c_void_p(0x100010), need, ctypes.byref(h))
     assert st == B.SFFT_EINVAL and not h.value
+
+
+def test_align_argument_checks():
+    lib = B.lib()
+    m = B.make_map([0.0, 1.0, 0.0], [0.0, 0.0, 1.0])
+    P = ctypes.c_void_p
+    a, b = P(1 << 20), P(1 << 30)      # never dereferenced: every call below fails its checks first
+    ok_args = lambda **k: dict(dict(map=ctypes.byref(m), mode=B.SFFT_MODE_F64, tmpl=a, nyt=64, nxt=64,  # noqa: E731
+                                    ldt=64, out=b, ny=64, nx=64, ld=64), **k)
+
+    def call(d):
+        return lib.sfft_align_image(d["map"], d["mode"], None, d["tmpl"], None, d["nyt"], d["nxt"], d["ldt"],
+                                    d["out"], b if d["out"] is not None else None, d["ny"], d["nx"], d["ld"])
+    assert call(ok_args(map=None)) == B.SFFT_EINVAL
+    assert call(ok_args(mode=5)) == B.SFFT_EINVAL
+    assert call(ok_args(tmpl=None)) == B.SFFT_EINVAL
+    assert call(ok_args(ldt=63)) == B.SFFT_EINVAL
+    assert call(ok_args(ld=10)) == B.SFFT_EINVAL
+    assert call(ok_args(ny=0)) == B.SFFT_EINVAL
+    assert call(ok_args(nxt=70000, ldt=70000)) == B.SFFT_EINVAL
+    assert call(ok_args(out=P((1 << 20) + 8 * 100))) == B.SFFT_EINVAL      # output overlaps the template
+    bad = B.make_map([0.0, 1.0, 0.0], [0.0, 0.0, 1.0])
+    bad.deg = 4
+    assert call(ok_args(map=ctypes.byref(bad))) == B.SFFT_EINVAL
+    assert lib.sfft_align_psf(ctypes.byref(m), 0.0, 0.0, None, a, 32, b, 10) == B.SFFT_EINVAL
+    assert lib.sfft_align_psf(ctypes.byref(m), 0.0, 0.0, None, a, 10, b, -1) == B.SFFT_EINVAL
+    assert lib.sfft_align_psf(ctypes.byref(m), 0.0, 0.0, None, None, 10, b, 10) == B.SFFT_EINVAL
+    with pytest.raises(KeyError):
+        B.make_map([0.0, 1.0], [0.0, 1.0])
