@@ -61,95 +61,137 @@ __device__ __forceinline__ void tile_abt(const double (*A)[NB + 1], const double
   }
 }
 
-// The diagonal-block kernel is a single wave: its LDS accesses execute in
-// program order, so lanes exchange values through LDS with no barrier; this
-// only stops the compiler from moving memory accesses across the point.
-__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+// Cross-lane read of a double held by lane l (two 32-bit reads into scalar registers).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
 
-// Diagonal block: one wave of 64 lanes.
-//  A partial last block (nb < 64 rows) is padded with the identity, whose
-//  factor and inverse are the identity again, so every loop below runs over
-//  the full 64 with static bounds and no predicates.
-//  Factorisation: lane i holds row i of the block in registers.  At column j
-//  every lane publishes its A[i][j] in LDS; the pivot d = A[j][j] is read back
-//  by all lanes, lanes i > j scale their entry by 1/sqrt(d) and publish it
-//  again, then every lane applies A[i][l] -= L[i][j] L[l][j] for l > j with
-//  L[l][j] read as an LDS broadcast.  L[i][j] is 0 on lanes i <= j, and the
-//  updates of a lane's upper part (l > i) are never read, so no lane is masked.
-//  Inverse X = L^{-1}: lane c holds column c, initialised to e_c, and the
-//  right-looking sweep X[j][c] /= L[j][j]; X[i][c] -= L[i][j] X[j][c] (i > j)
-//  reads L[i][j] as a broadcast from LDS.  Loops over the block are fully
-//  unrolled so that register indices are static.
-__global__ __launch_bounds__(64) void potrf_diag_kernel(const SolveJob* __restrict__ jobs, int k) {
-  __shared__ double Ls[NB][NB + 1];
-  __shared__ double col[NB];
-  const SolveJob J = jobs[blockIdx.x];
-  if (k >= J.nblk || *J.info != 0) return;
-  double* __restrict__ F = J.F;
-  const int n = J.n;
-  const int k0 = k * NB;
-  double* __restrict__ Linv = J.Linv + (size_t)k * NB * NB;
-  int* __restrict__ info = J.info;
-  const int lane = threadIdx.x;
-  const int nb = min(NB, n - k0);
-  // coalesced load of the block through LDS (one row per step, lanes along it),
-  // identity padding; unrolled so that the row loads overlap
-#pragma unroll 16
-  for (int r = 0; r < NB; ++r) {
-    double v = (lane == r) ? 1.0 : 0.0;
-    if (r < nb) v = (lane <= r) ? F[(int64_t)(k0 + r) * n + k0 + lane] : 0.0;
-    Ls[r][lane] = v;
-  }
-  wave_sync();
-  double row[NB];
+// Factor a 64 x 64 diagonal block with a block of 256 threads (4 waves).
+//  T: the block in LDS (lower triangle read; rows and columns >= nb are
+//  replaced by the identity, whose factor and inverse are the identity, so
+//  every loop runs over the full 64 with static bounds); cb0, cb1, dv: 64
+//  doubles of LDS each; sflag: 2 ints of LDS.  On success L goes to F (rows
+//  and columns < nb, lower triangle, global offset k0, row pitch n) and
+//  L^{-1} to Linv (64 x 64 row-major, zero outside nb); returns 0.  A
+//  non-positive or non-finite pivot at column j returns j + 1 and stores
+//  nothing (the factorisation loop still runs to its end on meaningless
+//  values, so that every wave takes every barrier).  Every thread of the
+//  block must call it; the return value is the same on every thread.
+//  Factorisation: wave q owns columns 16q..16q+15 of every row (lane = row).
+//  At column j the owning wave reads the pivot from lane j across lanes,
+//  scales its column and publishes it (and the outcome) in LDS; after one
+//  barrier every wave applies the rank-1 update to its columns > j.  The
+//  column buffer and the outcome alternate between two slots, so one barrier
+//  per column suffices: a slot is rewritten two columns later, after every
+//  wave has passed the barrier that follows its last read.
+//  Inverse X = L^{-1} (lane = column c, wave q owns rows 16q..16q+15): at
+//  step j the wave owning row j finishes X[j][.] (times 1 / L[j][j],
+//  computed beforehand) and publishes it; after a barrier every wave
+//  applies X[i][c] -= L[i][j] X[j][c] to its rows i > j, L[i][j] read from
+//  the tile as a broadcast.
+__device__ __forceinline__ int potrf_block64(double (*T)[NB + 1], double* cb0, double* cb1, double* dv, int* sflag,
+                                             int nb, double* __restrict__ F, int n, int k0,
+                                             double* __restrict__ Linv) {
+  const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+  const int c0 = q * 16;
+  double a[16];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) row[c] = Ls[lane][c];
-  wave_sync();
-  int fail = 0;
+  for (int m = 0; m < 16; ++m) {
+    const int c = c0 + m;
+    a[m] = (lane < nb && c < nb) ? (c <= lane ? T[lane][c] : 0.0) : (lane == c ? 1.0 : 0.0);
+  }
+  int fail = 0;   // the first bad pivot (the same on every thread); the loop runs on regardless
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (fail == 0) {
-      col[lane] = row[j];
-      wave_sync();
-      const double d = col[j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        fail = j + 1;
-      } else {
-        const double sd = sqrt(d);
-        const double rs = 1.0 / sd;
-        if (lane > j) row[j] *= rs;
-        if (lane == j) row[j] = sd;
-        wave_sync();
-        col[lane] = row[j];
-        wave_sync();
-        const double lij = (lane > j) ? row[j] : 0.0;
+    double* __restrict__ col = (j & 1) ? cb1 : cb0;
+    if (q == (j >> 4)) {
+      const double v = a[j & 15];
+      const double d = readlane_f64(v, j);
+      const bool bad = !(d > 0.0) || !isfinite(d);
+      if (lane == 0) sflag[j & 1] = bad ? j + 1 : 0;
+      const double sd = sqrt(d);
+      const double l = lane > j ? v * (1.0 / sd) : (lane == j ? sd : 0.0);
+      a[j & 15] = l;
+      col[lane] = l;
+    }
+    __syncthreads();
+    if (fail == 0) fail = sflag[j & 1];
+    if (c0 + 15 > j) {
+      const double lij = col[lane];
 #pragma unroll
-        for (int l = j + 1; l < NB; ++l) row[l] -= lij * col[l];
-      }
-      wave_sync();
+      for (int m = 0; m < 16; ++m)
+        if (c0 + m > j) a[m] -= lij * col[c0 + m];
     }
   }
-  if (fail) {
-    if (lane == 0) *info = k0 + fail;
-    return;
+  if (fail != 0) return fail;
+  // L into the tile (the upper part holds values that are never read)
+#pragma unroll
+  for (int m = 0; m < 16; ++m) T[lane][c0 + m] = a[m];
+  __syncthreads();
+  if (q == 0) dv[lane] = 1.0 / T[lane][lane];
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    if (r < nb && c <= r) F[(int64_t)(k0 + r) * n + k0 + c] = T[r][c];
   }
+  __syncthreads();
+  double x[16];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) Ls[lane][c] = row[c];
-  wave_sync();
-  // coalesced store of the factor's lower triangle
-  for (int r = 0; r < nb; ++r)
-    if (lane <= r) F[(int64_t)(k0 + r) * n + k0 + lane] = Ls[r][lane];
-  double xc[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) xc[i] = (i == lane) ? 1.0 : 0.0;
+  for (int m = 0; m < 16; ++m) x[m] = (c0 + m == lane) ? 1.0 : 0.0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    xc[j] *= 1.0 / Ls[j][j];
+    double* __restrict__ xr = (j & 1) ? cb1 : cb0;
+    if (q == (j >> 4)) {
+      x[j & 15] *= dv[j];
+      xr[lane] = x[j & 15];
+    }
+    __syncthreads();
+    if (c0 + 15 > j) {
+      const double xj = xr[lane];
 #pragma unroll
-    for (int i = j + 1; i < NB; ++i) xc[i] -= Ls[i][j] * xc[j];
+      for (int m = 0; m < 16; ++m)
+        if (c0 + m > j) x[m] -= T[c0 + m][j] * xj;
+    }
   }
 #pragma unroll
-  for (int i = 0; i < NB; ++i) Linv[i * NB + lane] = (i < nb && lane < nb) ? xc[i] : 0.0;
+  for (int m = 0; m < 16; ++m) {
+    const int i = c0 + m;
+    Linv[i * NB + lane] = (i < nb && lane < nb) ? x[m] : 0.0;
+  }
+  return 0;
+}
+
+// Diagonal block k of every job (one block of 256 per job): the first block
+// of each factorisation; the later ones are factored inside syrk_kernel.
+__global__ __launch_bounds__(256) void potrf_diag_kernel(const SolveJob* __restrict__ jobs, int k) {
+  __shared__ double T[NB][NB + 1];
+  __shared__ double cb[3][NB];
+  __shared__ int sflag[2];
+  const SolveJob J = jobs[blockIdx.x];
+  if (k >= J.nblk || *J.info != 0) return;
+  const int n = J.n;
+  const int k0 = k * NB;
+  const int nb = min(NB, n - k0);
+  const int tid = threadIdx.x;
+  {
+    // every load of the thread is issued (clamped into the block) before any is stored
+    constexpr int PER = NB * NB / 256;
+    double v[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + t * 256, r = e >> 6, c = e & 63;
+      v[t] = J.F[(int64_t)(k0 + min(r, nb - 1)) * n + k0 + min(c, nb - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + t * 256, r = e >> 6, c = e & 63;
+      T[r][c] = v[t];
+    }
+  }
+  __syncthreads();
+  const int f = potrf_block64(T, cb[0], cb[1], cb[2], sflag, nb, J.F, n, k0, J.Linv + (size_t)k * NB * NB);
+  if (f != 0 && tid == 0) *J.info = k0 + f;
 }
 
 // Row block bi (after block k): L = A Linv^T, 64 x 64 x 64 in LDS.
@@ -204,17 +246,37 @@ __global__ __launch_bounds__(256) void trsm_kernel(const SolveJob* __restrict__ 
       }
 }
 
-// Lower tiles (I >= J) of the trailing matrix: A_IJ -= L_I L_J^T.  One block
-// per (job, tile), ntile tiles per job, through xcd_remap: an XCD takes a
+// Lower tiles (I >= J) of the trailing matrix: A_IJ -= L_I L_J^T.  With
+// fuse_diag, the first njobs blocks take tile (0, 0) of each job -- the next
+// diagonal block -- and factor it as soon as it is updated (look-ahead: the
+// factorisation of step k + 1 runs while the rest of step k's update does);
+// the other blocks take the remaining tiles, ntile - 1 per job.  Without it,
+// one block per (job, tile).  Both through xcd_remap: an XCD takes a
 // contiguous run of tiles, so tiles of one row I (sharing the panel L_I) and
 // of neighbouring rows find the panels in its L2.
-__global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ jobs, int k, int njobs, int ntile) {
+__global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ jobs, int k, int njobs, int ntile,
+                                                   int fuse_diag) {
   __shared__ double A[NB][NB + 1];
   __shared__ double B[NB][NB + 1];
-  const int id = xcd_remap(blockIdx.x, gridDim.x);
-  if (id >= njobs * ntile) return;
-  const int jb = id / ntile;
-  const int b = id - jb * ntile;
+  __shared__ int sflag[2];
+  int jb, b;
+  if (fuse_diag) {
+    if ((int)blockIdx.x < njobs) {
+      jb = blockIdx.x;
+      b = 0;
+    } else {
+      const int per = ntile - 1;
+      const int id = xcd_remap(blockIdx.x - njobs, gridDim.x - njobs);
+      if (per <= 0 || id >= njobs * per) return;
+      jb = id / per;
+      b = 1 + (id - jb * per);
+    }
+  } else {
+    const int id = xcd_remap(blockIdx.x, gridDim.x);
+    if (id >= njobs * ntile) return;
+    jb = id / ntile;
+    b = id - jb * ntile;
+  }
   const SolveJob job = jobs[jb];
   if (k >= job.nblk - 1 || *job.info != 0) return;
   double* __restrict__ F = job.F;
@@ -272,15 +334,29 @@ __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ 
         const int i = min(wm + 16 * a + lk + 4 * r, ni - 1), j = min(wn + 16 * c + lr, nj - 1);
         fv[a][c][r] = F[(int64_t)(ri + i) * n + rj + j];
       }
+  if (!(fuse_diag && b == 0)) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = wm + 16 * a + lk + 4 * r, j = wn + 16 * c + lr;
+          if (i < ni && j < nj && (I != J || j <= i)) F[(int64_t)(ri + i) * n + rj + j] = fv[a][c][r] - acc[a][c][r];
+        }
+    return;
+  }
+  // the next diagonal block: updated tile into LDS, then factored here
+  __syncthreads();   // every wave is done reading A and B
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = wm + 16 * a + lk + 4 * r, j = wn + 16 * c + lr;
-        if (i < ni && j < nj && (I != J || j <= i)) F[(int64_t)(ri + i) * n + rj + j] = fv[a][c][r] - acc[a][c][r];
-      }
+      for (int r = 0; r < 4; ++r) A[wm + 16 * a + lk + 4 * r][wn + 16 * c + lr] = fv[a][c][r] - acc[a][c][r];
+  __syncthreads();
+  const int f = potrf_block64(A, B[0], B[1], B[2], sflag, ni, F, n, ri, job.Linv + (size_t)(k + 1) * NB * NB);
+  if (f != 0 && tid == 0) *job.info = ri + f;
 }
 
 // Blocked right-looking substitutions, one launch per block step k; block

@@ -863,18 +863,17 @@ int solve_jobs(hipStream_t s, const SolveTable& T, int max_n, int max_nblk, int 
     copy_omega_kernel<<<g, 256, 0, s>>>(jobs);
     LAUNCH_CHECK();
   }
-  for (int k = 0; k < max_nblk; ++k) {
-    potrf_diag_kernel<<<njobs, 64, 0, s>>>(jobs, k);
-    LAUNCH_CHECK();
+  // diagonal block 0; block k + 1 is factored inside the trailing update of step k
+  potrf_diag_kernel<<<njobs, 256, 0, s>>>(jobs, 0);
+  LAUNCH_CHECK();
+  for (int k = 0; k + 1 < max_nblk; ++k) {
     const int T1 = max_nblk - k - 1;
-    if (T1 > 0) {
-      trsm_kernel<<<dim3(T1, njobs), 256, 0, s>>>(jobs, k);
-      LAUNCH_CHECK();
-      const int ntile = T1 * (T1 + 1) / 2;
-      const int grid = ((njobs * ntile + 7) / 8) * 8;   // whole XCD rounds for the remap
-      syrk_kernel<<<grid, 256, 0, s>>>(jobs, k, njobs, ntile);
-      LAUNCH_CHECK();
-    }
+    trsm_kernel<<<dim3(T1, njobs), 256, 0, s>>>(jobs, k);
+    LAUNCH_CHECK();
+    const int ntile = T1 * (T1 + 1) / 2;
+    const int grid = njobs + ((njobs * (ntile - 1) + 7) / 8) * 8;   // diagonal blocks, then whole XCD rounds
+    syrk_kernel<<<grid, 256, 0, s>>>(jobs, k, njobs, ntile, 1);
+    LAUNCH_CHECK();
   }
   tm->end(s);
   tm->begin(SFFT_STAGE_SOLVE, s);
