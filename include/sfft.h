@@ -258,6 +258,28 @@ int sfft_batch_workspace_bytes(const sfft_desc* descs, int32_t npairs, size_t* b
  * sfft_destroy accept it. */
 int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sfft_handle* out);
 
+/* A batch plan whose pairs may share a template (S science images against
+ * one template and mask: the S x T pairing of "Pipeline steps", step 1).
+ * tmpl_of: HOST int32[npairs]; tmpl_of[i] is the pair whose template and
+ * mask pair i uses -- i itself (pair i owns them), or an earlier pair o < i
+ * that owns them (tmpl_of[o] == o) and has the same descriptor, else
+ * SFFT_EINVAL.
+ *   Omega depends only on the template and the mask (its entries are
+ * correlations of the planes m_a G_R R and G m_b), so every pair sharing a
+ * template has the same Omega and the same factor: a sharing pair transforms
+ * its science image alone, forms beta from it and the owner's template
+ * spectra, and is solved with the owner's factor (its own substitutions and
+ * refinement); its subtraction reuses the owner's row spectra of the
+ * template.  The results equal those of sfft_batch_plan on the same pairs
+ * (the shared quantities are computed once instead of once per pair).
+ *   sfft_batch_run/capture on such a plan require tmpl[i] == tmpl[o],
+ * mask[i] == mask[o] (as pointers; both NULL allowed) and ld[i] == ld[o] for
+ * every sharing pair, else SFFT_EINVAL.  The info of a sharing pair is its
+ * owner's factorisation outcome.  The workspace is at most
+ * sfft_batch_workspace_bytes of the same descriptors. */
+int sfft_batch_plan_shared(const sfft_desc* descs, const int32_t* tmpl_of, int32_t npairs, void* hip_stream,
+                           sfft_handle* out);
+
 /* Enqueue build + solve + subtract for every pair.  sci, tmpl, mask, ld,
  * coeffs, diff: HOST arrays of npairs entries holding DEVICE pointers (mask
  * array or entries may be NULL) and row pitches; info: device int32[npairs]

@@ -108,6 +108,7 @@ def lib():
         "sfft_timing_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "sfft_batch_workspace_bytes": (ctypes.c_int, [D, i32, ctypes.POINTER(sz)]),
         "sfft_batch_plan": (ctypes.c_int, [D, i32, vp, ctypes.POINTER(vp)]),
+        "sfft_batch_plan_shared": (ctypes.c_int, [D, ctypes.POINTER(i32), i32, vp, ctypes.POINTER(vp)]),
         "sfft_batch_run": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                           ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "sfft_batch_capture": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -286,6 +287,15 @@ def sfft_batch_plan(descs, stream=None):
     h = ctypes.c_void_p(0)
     _check(lib().sfft_batch_plan(_desc_array(descs), len(descs), _stream_handle(stream), ctypes.byref(h)),
            "sfft_batch_plan")
+    return h.value
+
+
+def sfft_batch_plan_shared(descs, tmpl_of, stream=None):
+    """tmpl_of[i]: the pair whose template and mask pair i uses (i, or an earlier owner)."""
+    n = len(descs)
+    h = ctypes.c_void_p(0)
+    _check(lib().sfft_batch_plan_shared(_desc_array(descs), (ctypes.c_int32 * n)(*[int(v) for v in tmpl_of]), n,
+                                        _stream_handle(stream), ctypes.byref(h)), "sfft_batch_plan_shared")
     return h.value
 
 

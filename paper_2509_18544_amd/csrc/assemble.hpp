@@ -81,6 +81,16 @@ struct AsmParams {
   int njlo;              // distinct first lag rows and their values
   int16_t jlo_list[MAX_JLO];
   int dir_tpr;           // direct route: threads per image row (power of two)
+  // Which planes a build transforms and stages.  A full build transforms
+  // every base row and stages all nplanes planes from its own workspace.  A
+  // build of the right-hand side only (a pair that shares its template and
+  // mask with another pair) transforms the science base alone and stages
+  // nstaged = nK + 1 planes: the nK template planes from the sharing pair's
+  // workspace (PS.tws), then its own science plane (plane nK + nB).
+  int base_lo;           // first base row transformed (0, or nbase - 1)
+  int nstaged;           // planes staged by the correlation kernel
+  int nshared;           // of those, how many are read from PS.tws (the rest from PS.ws)
+  int plane_skip;        // own-workspace plane of staged plane s >= nshared: s + plane_skip
 };
 
 // ---------------------------------------------------------------------------
@@ -151,7 +161,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kerne
     good |= ((uint32_t)g0 << (2 * i)) | ((uint32_t)g1 << (2 * i + 1));
     gint |= ((uint32_t)i0 << (2 * i)) | ((uint32_t)i1 << (2 * i + 1));
   }
-  for (int b = 0; b < P.nbase; ++b) {
+  for (int b = P.base_lo; b < P.nbase; ++b) {
     __syncthreads();   // the previous base's split has read the buffer
     // packed base rows z(j) = x(2j) + i x(2j+1)
     const int kind = b < P.nbk ? 0 : (b < P.nbk + P.nbb ? 1 : 2);
@@ -249,9 +259,9 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kerne
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int npairs = P.H / 2;           // pairs 0 .. H/2-1
   const int id = xcd_remap(blockIdx.x, gridDim.x);
-  if (id >= npairs * P.nbase) return;
-  const int b = id / npairs;
-  const int c = id - b * npairs;
+  if (id >= npairs * (P.nbase - P.base_lo)) return;
+  const int b = P.base_lo + id / npairs;
+  const int c = id - (b - P.base_lo) * npairs;
   constexpr int lgPy = LGPY;
   constexpr int Py = 1 << LGPY;
   const int H = P.H;
@@ -375,6 +385,7 @@ template <typename T, int THREADS>
 __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet PS, WsOff O, int C1, int C1dc) {
   const int pr = blockIdx.z;
   const cplx<T>* __restrict__ U = ws_at<const cplx<T>>(PS, pr, O.U);
+  const cplx<T>* __restrict__ Ut = reinterpret_cast<const cplx<T>*>(PS.tws[pr] + O.U);   // template-side planes
   const CorrItem* __restrict__ items = ws_at<const CorrItem>(PS, pr, O.items);
   cplx<double>* __restrict__ V = ws_at<cplx<double>>(PS, pr, O.V);
   const cplx<double>* __restrict__ twd = ws_at<const cplx<double>>(PS, pr, O.tw64);
@@ -397,7 +408,7 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
   const int nwaves = (nitems + ipw - 1) / ipw;
   const int64_t pstride = (int64_t)(H + 1) * Py;
   const int C = pk ? C1dc : C1;                // residues per chunk of this block
-  const int nst = pk ? 2 * P.nplanes : P.nplanes;   // staged planes (block 0: column 0, then column H)
+  const int nst = pk ? 2 * P.nstaged : P.nstaged;   // staged planes (block 0: column 0, then column H)
   const int per_plane = corr_plane_stride(C);
   // outer twiddles e^{2 pi i k1 (jlo + t)/Py} of the chunk, per distinct jlo, after the spectra
   cplx<double>* twc = stage + nst * per_plane;              // [njlo][C][JMAX]
@@ -441,9 +452,12 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
           const int e = min(e0 + b * THREADS, ntot - 1);   // a valid element; the copy is dropped below
           const int pl = e / npr;
           const int o = 2 * (e - pl * npr);
-          const bool hi = pl >= P.nplanes;                 // block 0: the Nyquist column's planes
+          const bool hi = pl >= P.nstaged;                 // block 0: the Nyquist column's planes
           const int col = hi ? H : kx;
-          const cplx<T>* src = U + (pl - (hi ? P.nplanes : 0)) * pstride + (int64_t)col * Py + (int64_t)k1c * P2 + o;
+          const int sp = pl - (hi ? P.nstaged : 0);        // staged plane -> workspace and plane
+          const bool sh = sp < P.nshared;
+          const cplx<T>* src = (sh ? Ut : U) + (sh ? sp : sp + P.plane_skip) * pstride + (int64_t)col * Py +
+                               (int64_t)k1c * P2 + o;
           if constexpr (sizeof(T) == sizeof(float)) {
             const float4 f = *reinterpret_cast<const float4*>(src);
             q[b][0] = mk(f.x, f.y);
@@ -492,8 +506,8 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
         for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(xa[k2], xb[k2]);
         if (pk) {
           // + i Z_H: the Nyquist column's product on the imaginary axis
-          const cplx<double>* ya = xa + P.nplanes * per_plane;
-          const cplx<double>* yb = xb + P.nplanes * per_plane;
+          const cplx<double>* ya = xa + P.nstaged * per_plane;
+          const cplx<double>* yb = xb + P.nstaged * per_plane;
 #pragma unroll
           for (int k2 = 0; k2 < P2; ++k2) z[k2] = z[k2] + rot90<double, true>(cmulc(ya[k2], yb[k2]));
         }
@@ -1023,6 +1037,23 @@ __global__ void gather_kernel(GatherParams G, PairSet PS, WsOff O) {
     } else {
       beta[r] = bb[r - G.nkk];
     }
+  }
+}
+
+// beta alone (a build of the right-hand side only: Omega is the sharing pair's)
+__global__ void gather_beta_kernel(GatherParams G, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const double* __restrict__ win = ws_at<const double>(PS, pr, O.win);
+  const double* __restrict__ bb = ws_at<const double>(PS, pr, O.bb);
+  double* __restrict__ beta = ws_at<double>(PS, pr, O.beta);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= G.n) return;
+  const int L2 = G.L * G.L;
+  if (r < G.nkk) {
+    const int a = r / L2, ur = r - a * L2;
+    beta[r] = win[G.ks_off[a] + ur];
+  } else {
+    beta[r] = bb[r - G.nkk];
   }
 }
 

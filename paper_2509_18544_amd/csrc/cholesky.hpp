@@ -572,7 +572,7 @@ __global__ void copy_out_kernel(const double* __restrict__ src, double* __restri
 __global__ void copy_out_group_kernel(PairSet PS, WsOff O, int n) {
   const int pr = blockIdx.z;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int inf = ws_at<const int>(PS, pr, O.flags)[0];
+  const int inf = reinterpret_cast<const int*>(PS.tws[pr] + O.flags)[0];   // the outcome of the factor used
   if (i == 0 && PS.info[pr] != nullptr) *PS.info[pr] = inf;
   if (inf != 0) return;
   if (i < n) PS.coeffs[pr][i] = ws_at<const double>(PS, pr, O.theta)[i];

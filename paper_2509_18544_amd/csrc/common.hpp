@@ -377,6 +377,10 @@ struct PairSet {
   const void* tmpl[MAX_GROUP];
   const uint8_t* mask[MAX_GROUP];   // entries may be null (no mask)
   unsigned char* ws[MAX_GROUP];     // the pair's workspace
+  // workspace holding the pair's template-side data (template spectra and
+  // row spectra, normal matrix, factor, solve outcome): ws itself, or the
+  // workspace of the pair whose template and mask this pair shares
+  unsigned char* tws[MAX_GROUP];
   double* coeffs[MAX_GROUP];        // theta: read by the subtraction, written by the solve's copy-out
   void* diff[MAX_GROUP];
   int32_t* info[MAX_GROUP];         // per-pair solve outcome (entries may be null)

@@ -84,6 +84,11 @@ struct Derived {
   int lgPy, lgPx, Py, Px, H;
   int nplanes;
   int nbase, nbk, nbb;
+  // right-hand side only: the template and mask are another pair's, whose
+  // template spectra, normal matrix and factor this plan uses (its own build
+  // transforms the science base and forms beta alone)
+  bool rhs_only;
+  int base_lo, nstaged, nshared, plane_skip;
   int8_t base_first[MAX_BASE], base_count[MAX_BASE], out_plane[MAX_PLANES], out_q[MAX_PLANES];
   int rows_per_block, nrowblk;
   int nmom;
@@ -139,8 +144,9 @@ int validate(const sfft_desc* d) {
   return SFFT_OK;
 }
 
-// Everything about a plan that depends only on the descriptor.
-int derive(const sfft_desc* d, Derived* D) {
+// Everything about a plan that depends only on the descriptor (and, for a
+// plan of the right-hand side only, on that role).
+int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   int st = validate(d);
   if (st != SFFT_OK) return st;
   D->ny = d->ny;
@@ -162,10 +168,18 @@ int derive(const sfft_desc* d, Derived* D) {
   D->Px = 1 << D->lgPx;
   D->H = D->Px / 2;
   D->nplanes = D->nk + D->nb + 1;
+  D->rhs_only = rhs_only;
   // base rows and the output planes built from each (plane index, y-power)
   D->nbk = d->dk + 1;
   D->nbb = d->db + 1;
   D->nbase = D->nbk + D->nbb + 1;
+  // planes of a full build: every base, all planes staged from the own
+  // workspace; right-hand side only: the science base, and the nK template
+  // planes (shared) followed by the own science plane nK + nB
+  D->base_lo = rhs_only ? D->nbase - 1 : 0;
+  D->nstaged = rhs_only ? D->nk + 1 : D->nplanes;
+  D->nshared = rhs_only ? D->nk : D->nplanes;
+  D->plane_skip = rhs_only ? D->nb : 0;
   {
     int cursor = 0;
     for (int b = 0; b < D->nbase; ++b) {
@@ -215,12 +229,14 @@ int derive(const sfft_desc* d, Derived* D) {
   D->mtiles.clear();
   int vrow = 0, wo = 0;
   bool fits = true;   // every table stayed within its capacity
+  // planes are numbered 0..nplanes-1; the correlation items name staged planes
+  auto staged = [&](int plane) { return plane >= D->nshared ? plane - D->plane_skip : plane; };
   auto add_pair = [&](int left, int right, int hw) {
     const int h = 2 * hw + 1;
     for (int j = -hw; j <= hw; j += JMAX) {
       CorrItem it;
-      it.left = (int16_t)left;
-      it.right = (int16_t)right;
+      it.left = (int16_t)staged(left);
+      it.right = (int16_t)staged(right);
       it.jlo = (int16_t)j;
       it.nj = (int16_t)std::min(JMAX, hw - j + 1);
       it.vrow = vrow + (j + hw);
@@ -257,10 +273,12 @@ int derive(const sfft_desc* d, Derived* D) {
     return off;
   };
   const int w = d->w;
-  for (int a = 0; a < D->nk; ++a)
-    for (int b = a; b < D->nk; ++b) D->gp.kk_off[a * D->nk + b] = add_pair(a, b, 2 * w);
-  for (int a = 0; a < D->nk; ++a)
-    for (int b = 0; b < D->nb; ++b) D->gp.kb_off[a * D->nb + b] = add_pair(a, D->nk + b, w);
+  if (!rhs_only) {
+    for (int a = 0; a < D->nk; ++a)
+      for (int b = a; b < D->nk; ++b) D->gp.kk_off[a * D->nk + b] = add_pair(a, b, 2 * w);
+    for (int a = 0; a < D->nk; ++a)
+      for (int b = 0; b < D->nb; ++b) D->gp.kb_off[a * D->nb + b] = add_pair(a, D->nk + b, w);
+  }
   for (int a = 0; a < D->nk; ++a) D->gp.ks_off[a] = add_pair(a, D->nk + D->nb, w);
   if (!fits) return SFFT_EINVAL;   // more correlation items than the kernels take
   // items sorted by their residue rotation (jlo mod P2) so that a wave of the
@@ -575,11 +593,15 @@ struct sfft_plan_s {
   // stream) and a device table of their solve jobs
   bool is_batch = false;
   std::vector<sfft_plan_s*> members;
-  SolveJob* jobs_dev = nullptr;     // [the pairs' jobs | their constraint-column jobs]
+  // a batch member that shares its template and mask: the member that owns
+  // them (its template spectra, normal matrix, factor and row spectra)
+  sfft_plan_s* tplan = nullptr;
+  std::vector<int> tmpl_of;         // batch: per pair, the pair whose template and mask it uses
+  SolveJob* jobs_dev = nullptr;     // [jobs owning a factor | jobs sharing one | constraint-column jobs]
   RatioJob* rjobs_dev = nullptr;    // projection jobs (pairs with a constant photometric ratio)
   std::vector<SolveJob> jobs_host;
   RatioJob rjob_host;
-  int nsub = 0, nratio = 0;
+  int nfac = 0, nsub = 0, nratio = 0;
   int max_n = 0, max_nblk = 0;
   // graph of one captured batch run (sfft_batch_capture / sfft_batch_launch)
   hipGraph_t graph = nullptr;
@@ -629,6 +651,10 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
   A.corr_lanes = D.corr_lanes;
   A.njlo = D.njlo;
   A.dir_tpr = D.dir_tpr;
+  A.base_lo = D.base_lo;
+  A.nstaged = D.nstaged;
+  A.nshared = D.nshared;
+  A.plane_skip = D.plane_skip;
   for (int i = 0; i < MAX_JLO; ++i) A.jlo_list[i] = i < D.njlo ? D.jlo_list[i] : 0;
   A.vrows = D.vrows;
   A.kpoly = D.kpoly;
@@ -693,9 +719,9 @@ int corr_dc_chunk(int C1) { return std::max(1, C1 / 2); }
 size_t corr_lds_bytes(const Derived& D, int C1) {
   const size_t steps = (size_t)corr_step_elems(D.njlo) * sizeof(cplx<double>);
   const int cd = corr_dc_chunk(C1);
-  const size_t stage = ((size_t)D.nplanes * corr_plane_stride(C1) + (size_t)D.njlo * C1 * JMAX) * sizeof(cplx<double>);
+  const size_t stage = ((size_t)D.nstaged * corr_plane_stride(C1) + (size_t)D.njlo * C1 * JMAX) * sizeof(cplx<double>);
   const size_t stage_dc =
-      ((size_t)2 * D.nplanes * corr_plane_stride(cd) + (size_t)D.njlo * cd * JMAX) * sizeof(cplx<double>);
+      ((size_t)2 * D.nstaged * corr_plane_stride(cd) + (size_t)D.njlo * cd * JMAX) * sizeof(cplx<double>);
   const size_t red = (size_t)ASM_THREADS * ((JMAX + 1) / 2) * sizeof(cplx<double>);
   return steps + std::max(std::max(stage, stage_dc), red);
 }
@@ -734,7 +760,10 @@ int gather_impl(sfft_plan_s* p, const AsmParams& A, const PairSet& PS, int np) {
   p->timer.begin(SFFT_STAGE_GATHER, s);
   moments_reduce_kernel<ASM_THREADS><<<dim3(D.nb * D.nb + D.nb, 1, np), ASM_THREADS, 0, s>>>(A, PS, O);
   LAUNCH_CHECK();
-  gather_kernel<<<dim3((D.n + 255) / 256, D.n, np), 256, 0, s>>>(D.gp, PS, O);
+  if (D.rhs_only)
+    gather_beta_kernel<<<dim3((D.n + 255) / 256, 1, np), 256, 0, s>>>(D.gp, PS, O);
+  else
+    gather_kernel<<<dim3((D.n + 255) / 256, D.n, np), 256, 0, s>>>(D.gp, PS, O);
   LAUNCH_CHECK();
   p->timer.end(s);
   return SFFT_OK;
@@ -806,7 +835,7 @@ int build_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   }
   {
     const size_t lds = (size_t)lds_padded_size(2 * D.Py) * sizeof(cplx<T>);
-    const int nblk = (D.H / 2) * D.nbase;
+    const int nblk = (D.H / 2) * (D.nbase - D.base_lo);
     const int grid = ((nblk + 7) / 8) * 8;
     p->timer.begin(SFFT_STAGE_COL_FWD, s);
     switch (D.lgPy) {
@@ -918,19 +947,22 @@ int solve_jobs(hipStream_t s, const SolveTable& T, int max_n, int max_nblk, int 
   return SFFT_OK;
 }
 
+// A plan's solve job; a plan that shares its template takes the normal
+// matrix, the factor and the outcome of the plan that owns the template.
 SolveJob job_of(sfft_plan_s* p) {
   const Layout& Lo = p->Lo;
+  const sfft_plan_s* t = p->tplan != nullptr ? p->tplan : p;
   SolveJob J;
-  J.F = p->at<double>(Lo.F);
-  J.Linv = p->at<double>(Lo.Linv);
-  J.omega = p->at<double>(Lo.omega);
+  J.F = t->at<double>(t->Lo.F);
+  J.Linv = t->at<double>(t->Lo.Linv);
+  J.omega = t->at<double>(t->Lo.omega);
   J.beta = p->at<double>(Lo.beta);
   J.theta = p->at<double>(Lo.theta);
   J.y = p->at<double>(Lo.y);
   J.r = p->at<double>(Lo.r);
   J.d = p->at<double>(Lo.d);
   J.w = p->at<double>(Lo.w);
-  J.info = p->at<int>(Lo.flags);
+  J.info = t->at<int>(t->Lo.flags);
   J.n = p->D.n;
   J.nblk = p->D.nblk;
   return J;
@@ -990,8 +1022,11 @@ SolveTable plan_table(sfft_plan_s* p) {
 // as the plan p): D = S - model - background with theta from PS.coeffs; with
 // apply_only, the model K * R alone (PS.tmpl = the image, PS.coeffs = the
 // kernel coefficients, no science image).
+// With shared_rows, the pairs' template row spectra are those of the pairs
+// whose templates they share (PS.tws), already formed: the row pass is skipped.
 template <typename T>
-int subtract_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld, bool apply_only = false) {
+int subtract_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld, bool apply_only = false,
+                  bool shared_rows = false) {
   const Derived& D = p->D;
   const WsOff O = ws_offsets(D, p->Lo);
   hipStream_t s = p->stream;
@@ -1031,7 +1066,9 @@ int subtract_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld, bool ap
     LAUNCH_CHECK();
   }
   const size_t lds = (size_t)lds_padded_size(S.rows_per_block * D.H) * sizeof(cplx<double>);
-  switch (D.lgPx - 1) {
+  switch (shared_rows ? -1 : D.lgPx - 1) {
+    case -1:
+      break;
 #define SUBF_CASE(LG)                                                                                       \
   case LG: {                                                                                                \
     auto kf = sub_rowfwd_kernel<T, FFT_THREADS, SUB_NMAX, LG>;                                              \
@@ -1095,6 +1132,7 @@ PairSet pair_set_one(const sfft_plan_s* p, const void* sci, const void* tmpl, co
   S.tmpl[0] = tmpl;
   S.mask[0] = mask;
   S.ws[0] = p->ws;
+  S.tws[0] = p->ws;
   S.coeffs[0] = const_cast<double*>(coeffs);
   S.diff[0] = diff;
   S.info[0] = info;
@@ -1124,19 +1162,38 @@ int sfft_workspace_bytes(const sfft_desc* d, size_t* bytes) {
   return st;
 }
 
-int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t workspace_bytes, sfft_handle* out) {
-  RoctxScope range_("sfft_plan");
+// A plan of one pair; with rhs_only, a batch member that forms only its
+// right-hand side (its template and mask are another member's).
+static int plan_create(const sfft_desc* d, void* hip_stream, void* workspace, size_t workspace_bytes, bool rhs_only,
+                       sfft_handle* out) {
   if (out == nullptr) return SFFT_EINVAL;
   *out = nullptr;
   sfft_plan_s* p = new (std::nothrow) sfft_plan_s();
   if (p == nullptr) return SFFT_ENOMEM;
-  int st = derive(d, &p->D);
+  int st = derive(d, &p->D, rhs_only);
   if (st != SFFT_OK) {
     delete p;
     return st;
   }
   p->desc = *d;
   p->Lo = layout_of(p->D);
+  if (rhs_only) {
+    // the layout of a full plan of the same descriptor (its tables are the
+    // larger ones), so that every buffer a sharing pair reads from its
+    // owner's workspace sits at the offset of its own
+    Derived* Df = new (std::nothrow) Derived();   // tables held inline: too large for the stack
+    if (Df == nullptr) {
+      delete p;
+      return SFFT_ENOMEM;
+    }
+    st = derive(d, Df, false);
+    if (st == SFFT_OK) p->Lo = layout_of(*Df);
+    delete Df;
+    if (st != SFFT_OK) {
+      delete p;
+      return st;
+    }
+  }
   p->stream = reinterpret_cast<hipStream_t>(hip_stream);
   p->built = false;
   if (workspace != nullptr) {
@@ -1187,6 +1244,11 @@ int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t work
   }
   *out = p;
   return SFFT_OK;
+}
+
+int sfft_plan(const sfft_desc* d, void* hip_stream, void* workspace, size_t workspace_bytes, sfft_handle* out) {
+  RoctxScope range_("sfft_plan");
+  return plan_create(d, hip_stream, workspace, workspace_bytes, false, out);
 }
 
 int sfft_build_system(sfft_handle p, const void* sci, const void* tmpl, const uint8_t* mask, int64_t ld) {
@@ -1312,6 +1374,8 @@ int sfft_status(sfft_handle p, int32_t* info_out, int32_t* nonfinite_out) {
     for (sfft_plan_s* m : p->members) {
       int f[2] = {0, 0};
       HIP_TRY(hipMemcpy(f, m->at<int>(m->Lo.flags), sizeof(f), hipMemcpyDeviceToHost));
+      if (m->tplan != nullptr)   // the factor's outcome is recorded by the template's owner
+        HIP_TRY(hipMemcpy(f, m->tplan->at<int>(m->tplan->Lo.flags), sizeof(int), hipMemcpyDeviceToHost));
       if (flags[0] == 0) flags[0] = f[0];
       flags[1] |= f[1];
     }
@@ -1396,8 +1460,10 @@ int sfft_batch_workspace_bytes(const sfft_desc* descs, int32_t npairs, size_t* b
   return SFFT_OK;
 }
 
-int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sfft_handle* out) {
-  RoctxScope range_("sfft_batch_plan");
+// A batch plan; tmpl_of (may be null) names for each pair the pair whose
+// template and mask it uses (itself, or an earlier pair that uses its own).
+static int batch_create(const sfft_desc* descs, const int32_t* tmpl_of, int32_t npairs, void* hip_stream,
+                        sfft_handle* out) {
   if (out == nullptr || descs == nullptr || npairs <= 0) return SFFT_EINVAL;
   *out = nullptr;
   for (int i = 0; i < npairs; ++i) {
@@ -1407,6 +1473,11 @@ int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sf
     const int r0 = descs[0].refine_steps < 0 ? 1 : descs[0].refine_steps;
     const int ri = descs[i].refine_steps < 0 ? 1 : descs[i].refine_steps;
     if (ri != r0) return SFFT_EINVAL;
+    if (tmpl_of != nullptr) {
+      const int o = tmpl_of[i];
+      if (o < 0 || o > i || tmpl_of[o] != o) return SFFT_EINVAL;
+      if (o != i && std::memcmp(&descs[o], &descs[i], sizeof(sfft_desc)) != 0) return SFFT_EINVAL;
+    }
   }
   sfft_plan_s* b = new (std::nothrow) sfft_plan_s();
   if (b == nullptr) return SFFT_ENOMEM;
@@ -1416,18 +1487,27 @@ int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sf
   b->owns_ws = false;
   b->built = false;
   for (int i = 0; i < npairs; ++i) {
+    const int o = tmpl_of != nullptr ? tmpl_of[i] : i;
     sfft_handle m = nullptr;
-    const int st = sfft_plan(&descs[i], hip_stream, nullptr, 0, &m);
+    const int st = plan_create(&descs[i], hip_stream, nullptr, 0, o != i, &m);
     if (st != SFFT_OK) {
       sfft_destroy(b);
       return st;
     }
+    if (o != i) m->tplan = b->members[o];
     b->members.push_back(m);
-    b->jobs_host.push_back(job_of(m));
+    b->tmpl_of.push_back(o);
     b->max_n = std::max(b->max_n, m->D.n);
     b->max_nblk = std::max(b->max_nblk, m->D.nblk);
   }
-  // the constraint-column jobs after all pairs' own jobs, one projection job per such pair
+  // jobs: the pairs that own a factor (their own template), then the pairs
+  // that use another pair's factor, then the constraint-column jobs; one
+  // projection job per pair with a constant photometric ratio
+  for (sfft_plan_s* m : b->members)
+    if (m->tplan == nullptr) b->jobs_host.push_back(job_of(m));
+  b->nfac = (int)b->jobs_host.size();
+  for (sfft_plan_s* m : b->members)
+    if (m->tplan != nullptr) b->jobs_host.push_back(job_of(m));
   std::vector<RatioJob> rjobs;
   for (sfft_plan_s* m : b->members) {
     if (m->D.nratio == 0) continue;
@@ -1457,6 +1537,18 @@ int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sf
   return SFFT_OK;
 }
 
+int sfft_batch_plan(const sfft_desc* descs, int32_t npairs, void* hip_stream, sfft_handle* out) {
+  RoctxScope range_("sfft_batch_plan");
+  return batch_create(descs, nullptr, npairs, hip_stream, out);
+}
+
+int sfft_batch_plan_shared(const sfft_desc* descs, const int32_t* tmpl_of, int32_t npairs, void* hip_stream,
+                           sfft_handle* out) {
+  RoctxScope range_("sfft_batch_plan_shared");
+  if (tmpl_of == nullptr) return SFFT_EINVAL;
+  return batch_create(descs, tmpl_of, npairs, hip_stream, out);
+}
+
 int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmpl, const uint8_t* const* mask,
                    const int64_t* ld, double* const* coeffs, void* const* diff, int32_t* info) {
   RoctxScope range_("sfft_batch_run");
@@ -1468,6 +1560,16 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
     if (sci[i] == nullptr || tmpl[i] == nullptr || coeffs[i] == nullptr || diff[i] == nullptr ||
         ld[i] < b->members[i]->D.nx)
       return SFFT_EINVAL;
+  // a pair that shares a template must be given that pair's template, mask
+  // and row pitch; it assembles with the same route
+  for (int i = 0; i < np; ++i) {
+    const int o = b->tmpl_of[i];
+    if (o == i) continue;
+    const uint8_t* mi = mask ? mask[i] : nullptr;
+    const uint8_t* mo = mask ? mask[o] : nullptr;
+    if (tmpl[i] != tmpl[o] || mi != mo || ld[i] != ld[o]) return SFFT_EINVAL;
+    b->members[i]->D.route = b->members[o]->D.route;
+  }
   hipStream_t s = b->stream;
   // groups of pairs with the same descriptor, row pitch and correlation
   // chunk, at most MAX_GROUP each: every launch of a group serves all of its
@@ -1480,6 +1582,7 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
     for (auto& g : groups) {
       const sfft_plan_s* mj = b->members[g[0]];
       if ((int)g.size() < MAX_GROUP && ld[g[0]] == ld[i] && mj->corr_c1 == mi->corr_c1 &&
+          mj->D.rhs_only == mi->D.rhs_only && mj->D.route == mi->D.route &&
           std::memcmp(&mj->desc, &mi->desc, sizeof(sfft_desc)) == 0) {
         g.push_back(i);
         placed = true;
@@ -1497,26 +1600,30 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
       S.tmpl[k] = tmpl[i];
       S.mask[k] = mask ? mask[i] : nullptr;
       S.ws[k] = b->members[i]->ws;
+      S.tws[k] = b->members[b->tmpl_of[i]]->ws;
       S.coeffs[k] = coeffs[i];
       S.diff[k] = diff[i];
       S.info[k] = info ? info + i : nullptr;
     }
     return S;
   };
-  // assembly, one group at a time
-  for (const auto& g : groups) {
-    sfft_plan_s* lead = b->members[g[0]];
-    const PairSet PS = set_of(g);
-    const int n = (int)g.size();
-    const int st = lead->D.mode == SFFT_MODE_F64 ? build_impl<double>(lead, PS, n, ld[g[0]])
-                                                 : build_impl<float>(lead, PS, n, ld[g[0]]);
-    if (st != SFFT_OK) return st;
-    for (int i : g) b->members[i]->built = true;
-  }
-  // one batched factorisation and solve for all pairs
+  // assembly, one group at a time: the groups that own their templates
+  // first (the others read their template spectra)
+  for (int pass = 0; pass < 2; ++pass)
+    for (const auto& g : groups) {
+      sfft_plan_s* lead = b->members[g[0]];
+      if (lead->D.rhs_only != (pass == 1)) continue;
+      const PairSet PS = set_of(g);
+      const int n = (int)g.size();
+      const int st = lead->D.mode == SFFT_MODE_F64 ? build_impl<double>(lead, PS, n, ld[g[0]])
+                                                   : build_impl<float>(lead, PS, n, ld[g[0]]);
+      if (st != SFFT_OK) return st;
+      for (int i : g) b->members[i]->built = true;
+    }
+  // one batched factorisation (one per template) and solve for all pairs
   SolveTable T;
   T.jobs = b->jobs_dev;
-  T.nfac = np;
+  T.nfac = b->nfac;
   T.nsub = b->nsub;
   T.rjobs = b->rjobs_dev;
   T.nratio = b->nratio;
@@ -1528,15 +1635,19 @@ int sfft_batch_run(sfft_handle b, const void* const* sci, const void* const* tmp
         set_of(g), ws_offsets(lead->D, lead->Lo), lead->D.n);
     LAUNCH_CHECK();
   }
-  // convolve-and-subtract, one group at a time
-  for (const auto& g : groups) {
-    sfft_plan_s* lead = b->members[g[0]];
-    const PairSet PS = set_of(g);
-    const int n = (int)g.size();
-    st = lead->D.mode == SFFT_MODE_F64 ? subtract_impl<double>(lead, PS, n, ld[g[0]])
-                                       : subtract_impl<float>(lead, PS, n, ld[g[0]]);
-    if (st != SFFT_OK) return st;
-  }
+  // convolve-and-subtract, one group at a time: the template owners first
+  // (their row spectra of the template serve the pairs that share it)
+  for (int pass = 0; pass < 2; ++pass)
+    for (const auto& g : groups) {
+      sfft_plan_s* lead = b->members[g[0]];
+      const bool shared = lead->D.rhs_only;
+      if (shared != (pass == 1)) continue;
+      const PairSet PS = set_of(g);
+      const int n = (int)g.size();
+      st = lead->D.mode == SFFT_MODE_F64 ? subtract_impl<double>(lead, PS, n, ld[g[0]], false, shared)
+                                         : subtract_impl<float>(lead, PS, n, ld[g[0]], false, shared);
+      if (st != SFFT_OK) return st;
+    }
   return SFFT_OK;
 }
 

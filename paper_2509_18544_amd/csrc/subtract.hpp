@@ -224,7 +224,8 @@ __host__ __device__ constexpr size_t sub_conv_lds_bytes(int w) {
 template <int W>
 __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P, PairSet PS, WsOff O) {
   const int pr = blockIdx.z;
-  const cplx<double>* __restrict__ Uq = ws_at<const cplx<double>>(PS, pr, O.Uq);
+  // the template's x-power row spectra: this pair's, or those of the pair whose template it shares
+  const cplx<double>* __restrict__ Uq = reinterpret_cast<const cplx<double>*>(PS.tws[pr] + O.Uq);
   const cplx<double>* __restrict__ G = ws_at<const cplx<double>>(PS, pr, O.G);
   cplx<double>* __restrict__ Mh = ws_at<cplx<double>>(PS, pr, O.Mh);
   constexpr int L = 2 * W + 1;

@@ -159,3 +159,19 @@ def test_align_argument_checks():
     assert lib.sfft_align_psf(ctypes.byref(m), 0.0, 0.0, None, None, 10, b, 10) == B.SFFT_EINVAL
     with pytest.raises(KeyError):
         B.make_map([0.0, 1.0], [0.0, 1.0])
+
+
+@pytest.mark.parametrize("tmpl_of,descs_same", [
+    ([1, 1], True),        # a pair may only share an earlier pair's template
+    ([0, 2, 0], True),     # ... not a later one
+    ([0, 0, 1], True),     # the owner must use its own template (tmpl_of[o] == o)
+    ([-1, 0], True),
+    ([0, 0], False),       # a sharing pair needs the owner's descriptor
+])
+def test_shared_batch_plan_rejects_bad_tables(tmpl_of, descs_same):
+    d0 = B.make_desc(64, 64, 2, 1, 1, B.SFFT_MODE_F32C)
+    d1 = d0 if descs_same else B.make_desc(64, 64, 3, 1, 1, B.SFFT_MODE_F32C)
+    descs = [d0] + [d1] * (len(tmpl_of) - 1)
+    with pytest.raises(B.SfftError) as e:
+        B.sfft_batch_plan_shared(descs, tmpl_of, stream=0)
+    assert e.value.status == B.SFFT_EINVAL
