@@ -12,3 +12,5 @@ from .kernel_oracle import (apply_kernel, centre_kernel, convolve, decorrelation
 from . import ratio_oracle  # noqa: F401,E402
 from .ratio_oracle import kernel_sums, ratio_constraints, ratio_map, solve_const_ratio  # noqa: F401,E402
 from . import align_oracle  # noqa: F401,E402
+from . import outmask_oracle  # noqa: F401,E402
+from .outmask_oracle import fit_outmask, masked_rows, normal_system_outmask  # noqa: F401,E402
