@@ -59,7 +59,11 @@ WORKLOADS = {
     "c2": dict(seed0=1002, label="1024x1024 pairs, 19x19 delta kernel, DK=2, DB=2, 3000 stars, 5% saturation mask"),
     "c1": dict(seed0=1001, label="256x256 pairs, 11x11 delta kernel, DK=1, DB=1, ~400 stars"),
     "c4": dict(seed0=4000, label="S x T = 8 x 16 uneven cutouts, N in {512,1024,2048}, w in 5..9, DK in {1,2}, DB=DK"),
+    "st": dict(seed0=6000, label="S x T template groups: 16 science epochs per 4088x4088 template and mask "
+                                 "(19x19 delta kernel, w=9, DK=2, DB=2), the template spectra, normal matrix, "
+                                 "factor and template row spectra shared within a group"),
 }
+ST_EPOCHS = 16   # science epochs per template in the template-group workload
 
 
 # ---------------------------------------------------------------------------
@@ -75,6 +79,8 @@ def _generate(workload, i):
         return synth.pair_c2(seed=seed0 + i)
     if workload == "c1":
         return synth.pair_c1(seed=seed0 + i)
+    if workload == "st":
+        return synth.template_group_pair(seed0 + i // ST_EPOCHS, 4088, i % ST_EPOCHS, ST_EPOCHS)
     return synth.pair_c4(synth.batch_c4_descriptors()[i])
 
 
@@ -301,19 +307,33 @@ def copy_bandwidth(torch, dev, log, gib=2, reps=10):
     return gbs
 
 
-def run_leg(B, torch, pairs, mode_name, args, log):
-    """Time one precision mode on the batch; returns figures and the host copies of the outputs."""
+def run_leg(B, torch, pairs, mode_name, args, log, tmpl_of=None):
+    """Time one precision mode on the batch; returns figures and the host copies of
+    the outputs.  With tmpl_of, pair i uses pair tmpl_of[i]'s template and mask
+    (a shared-template batch plan, one device copy of each template)."""
     import numpy as np
     mode = B.SFFT_MODE_F64 if mode_name == "f64" else B.SFFT_MODE_F32C
     dt = torch.float64 if mode == B.SFFT_MODE_F64 else torch.float32
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     descs = [B.make_desc(p.sci.shape[0], p.sci.shape[1], p.w, p.dk, p.db, mode) for p in pairs]
-    handle = B.sfft_batch_plan(descs, stream)
+    handle = B.sfft_batch_plan(descs, stream) if tmpl_of is None else B.sfft_batch_plan_shared(descs, tmpl_of, stream)
     with torch.cuda.stream(stream):
         S = [torch.from_numpy(p.sci).to(dev, dt) for p in pairs]
-        R = [torch.from_numpy(p.tmpl).to(dev, dt) for p in pairs]
-        M = [torch.from_numpy(p.mask).to(dev) for p in pairs]
+        if tmpl_of is None:
+            R = [torch.from_numpy(p.tmpl).to(dev, dt) for p in pairs]
+            M = [torch.from_numpy(p.mask).to(dev) for p in pairs]
+        else:
+            R, M = [], []
+            for i, p in enumerate(pairs):
+                o = tmpl_of[i]
+                if o == i:
+                    R.append(torch.from_numpy(p.tmpl).to(dev, dt))
+                    M.append(torch.from_numpy(p.mask).to(dev))
+                else:
+                    assert np.array_equal(p.tmpl, pairs[o].tmpl) and np.array_equal(p.mask, pairs[o].mask)
+                    R.append(R[o])
+                    M.append(M[o])
         Dd = [torch.empty_like(x) for x in S]
         C = [torch.zeros(B.sfft_num_coeffs(d), dtype=torch.float64, device=dev) for d in descs]
         info = torch.zeros(len(pairs), dtype=torch.int32, device=dev)
@@ -587,6 +607,8 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         args.batch = min(args.batch, 128) if args.batch != 32 else 128
+    if args.workload == "st":
+        args.batch = max(ST_EPOCHS, (args.batch // ST_EPOCHS) * ST_EPOCHS)   # whole template groups
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
     wl = WORKLOADS[args.workload]
     legs = [args.mode] + ([] if args.no_f64 or args.mode == "f64" else ["f64"])
@@ -602,7 +624,11 @@ def main():
     counter = ctx.Value("i", 0)
     with cf.ProcessPoolExecutor(max_workers=nwork, mp_context=ctx, initializer=_pin_worker,
                                 initargs=(cores, counter)) as ex:
-        res = list(ex.map(_prepare, [(args.workload, i, tags) for i in range(args.batch)]))
+        res = []
+        for r in ex.map(_prepare, [(args.workload, i, tags) for i in range(args.batch)]):
+            res.append(r)
+            if len(res) % 4 == 0 or len(res) == args.batch:
+                log(f"[bench] {len(res)}/{args.batch} pairs ready ({time.perf_counter() - t0:.0f}s)")
     pairs = [r[0] for r in res]
     refs = [r[1] for r in res]
     log(f"[bench] generated {len(pairs)} {args.workload} pairs"
@@ -615,7 +641,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     copy_gbs = copy_bandwidth(torch, dev, log)
-    results = {m: run_leg(B, torch, pairs, m, args, log) for m in legs}
+    tmpl_of = [ST_EPOCHS * (i // ST_EPOCHS) for i in range(len(pairs))] if args.workload == "st" else None
+    results = {m: run_leg(B, torch, pairs, m, args, log, tmpl_of) for m in legs}
+    unshared = None
+    if tmpl_of is not None:
+        # the same pairs with every template handled on its own, for comparison
+        r = run_leg(B, torch, pairs, args.mode, args, log)
+        unshared = dict(value=round(r["value"], 3), unit="pairs/s", ms_per_step=round(r["ms_per_step"], 3),
+                        stages_ms_per_pair={k: round(v, 4) for k, v in r["stages_ms_per_pair"].items()})
+        log(f"[bench] the same batch unshared: {r['value']:.2f} pairs/s")
     routes = None
     if not args.no_routes and len({(p.sci.shape, p.w, p.dk, p.db) for p in pairs}) == 1:
         routes = route_leg(B, torch, pairs[0], args.mode, log)
@@ -642,8 +676,11 @@ def main():
     head = results[args.mode]
     D = shape_info(pairs[0])
     mode_f64 = args.mode == "f64"
-    uniform = len({(p.sci.shape, p.w, p.dk, p.db) for p in pairs}) == 1
-    # per-launch flops depend on the pair's shape: priced only for a uniform batch
+    # per-launch flops and per-pair bytes depend on the pair's shape, and a
+    # sharing pair does less than a full one: priced only for a uniform,
+    # unshared batch
+    same_shape = len({(p.sci.shape, p.w, p.dk, p.db) for p in pairs}) == 1
+    uniform = same_shape and tmpl_of is None
     ppl = head["corr_pairs_per_launch"]
     roof = roofline_of("corr", D, mode_f64, head["corr_ms_per_launch"], ppl) if uniform else None
     src = kernel_source_hash()
@@ -678,8 +715,8 @@ def main():
             stage_roofs[k] = {kk: rr[kk] for kk in ("bound", "frac", "achieved", "unit")}
     config = {"workload": wl["label"] + f"; {args.mode.upper()} mode; batch of {args.batch} distinct pairs per step "
                                        f"(one batched run)",
-              "global_batch": args.batch, "frame": D["N"] if uniform else "mixed", "fft_size": D["P"] if uniform else "= N",
-              "coefficients": D["ncoef"] if uniform else "mixed",
+              "global_batch": args.batch, "frame": D["N"] if same_shape else "mixed",
+              "fft_size": D["P"] if same_shape else "= N", "coefficients": D["ncoef"] if same_shape else "mixed",
               "corr_chunk_autotune": head["corr_chunk_autotune"]}
     out = {
         "metric": METRIC,
@@ -711,6 +748,10 @@ def main():
         "assembly_routes": routes,
         "pipeline_steps": steps,
     }
+    if tmpl_of is not None:
+        out["config"]["templates"] = len(set(tmpl_of))
+        out["config"]["epochs_per_template"] = ST_EPOCHS
+        out["unshared"] = unshared
     print(json.dumps(out), flush=True)
 
 

@@ -35,6 +35,7 @@ SFFT_FLAG_ASSEMBLY_FFT = 1
 SFFT_FLAG_ASSEMBLY_DIRECT = 2
 SFFT_FLAG_ASSEMBLY_MFMA = 3
 SFFT_FLAG_CONST_RATIO = 16   # constant photometric ratio (spatial kernel sums vanish)
+SFFT_FLAG_OUTPUT_MASK = 32   # least squares over the good output pixels only
 ROUTES = ("fft", "direct", "mfma")
 
 
@@ -241,7 +242,7 @@ def sfft_status(handle):
     return st, info.value, nf.value
 
 
-STAGES = ("moments", "row_fwd", "col_fwd", "corr", "row_win", "gather", "factor", "solve", "subtract")
+STAGES = ("moments", "row_fwd", "col_fwd", "corr", "row_win", "gather", "factor", "solve", "subtract", "outmask")
 
 
 SFFT_TIMING_ALL = (1 << 9) - 1

@@ -22,6 +22,7 @@
 #include "common.hpp"
 #include "decorr.hpp"
 #include "subtract.hpp"
+#include "outmask.hpp"
 
 using namespace sfft;
 
@@ -74,7 +75,7 @@ constexpr int MAX_VROWS = JMAX * MAX_ITEMS;
 
 struct Layout {
   size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, w, kp, flags, tw32, tw64, items, wrows, drows,
-      mtiles, ratio, job, rjob;
+      mtiles, ratio, job, rjob, om_planes, om_cnt, om_offs, om_list;
   size_t total;
 };
 
@@ -89,6 +90,7 @@ struct Derived {
   // transforms the science base and forms beta alone)
   bool rhs_only;
   int base_lo, nstaged, nshared, plane_skip;
+  bool omask;   // output-masked fit: the excluded pixels' rows are taken out of Omega
   int8_t base_first[MAX_BASE], base_count[MAX_BASE], out_plane[MAX_PLANES], out_q[MAX_PLANES];
   int rows_per_block, nrowblk;
   int nmom;
@@ -135,7 +137,7 @@ int validate(const sfft_desc* d) {
   if (d->ny > (1 << MAX_LOG_P) || d->nx > (1 << MAX_LOG_P)) return SFFT_EINVAL;
   if (d->mode != SFFT_MODE_F64 && d->mode != SFFT_MODE_F32C) return SFFT_EINVAL;
   if (d->refine_steps < -1 || d->refine_steps > 10) return SFFT_EINVAL;
-  if ((d->flags & ~(3 | SFFT_FLAG_CONST_RATIO)) != 0) return SFFT_EINVAL;
+  if ((d->flags & ~(3 | SFFT_FLAG_CONST_RATIO | SFFT_FLAG_OUTPUT_MASK)) != 0) return SFFT_EINVAL;
   if ((d->flags & 3) == SFFT_FLAG_ASSEMBLY_DIRECT && (d->nx > DIR_MAX_NX || 2 * d->w > DIR_HWMAX)) return SFFT_EINVAL;
   const int L = 2 * d->w + 1;
   const int nk = (d->dk + 1) * (d->dk + 2) / 2, nb = (d->db + 1) * (d->db + 2) / 2;
@@ -169,6 +171,7 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   D->H = D->Px / 2;
   D->nplanes = D->nk + D->nb + 1;
   D->rhs_only = rhs_only;
+  D->omask = (d->flags & SFFT_FLAG_OUTPUT_MASK) != 0;
   // base rows and the output planes built from each (plane index, y-power)
   D->nbk = d->dk + 1;
   D->nbb = d->db + 1;
@@ -449,6 +452,14 @@ Layout layout_of(const Derived& D) {
   Lo.ratio = take((size_t)6 * D.nratio * D.n * sizeof(double));
   Lo.job = take((size_t)(1 + D.nratio) * sizeof(SolveJob));
   Lo.rjob = take(sizeof(RatioJob));
+  // output-masked fit: padded FP64 template planes, row counts and offsets, the excluded pixels
+  {
+    const size_t plane = (size_t)(D.ny + 2 * D.w) * (D.nx + 2 * D.w);
+    Lo.om_planes = take(D.omask ? (size_t)D.nk * plane * sizeof(double) : 0);
+    Lo.om_cnt = take(D.omask ? (size_t)D.ny * sizeof(int) : 0);
+    Lo.om_offs = take(D.omask ? (size_t)(D.ny + 1) * sizeof(int) : 0);
+    Lo.om_list = take(D.omask ? (size_t)D.ny * D.nx * sizeof(int) : 0);
+  }
   Lo.total = off;
   return Lo;
 }
@@ -500,7 +511,7 @@ struct RoctxScope {
 
 namespace {
 const char* const kStageNames[SFFT_NUM_STAGES] = {"moments", "row_fwd", "col_fwd", "corr", "row_win",
-                                                  "gather", "factor", "solve", "subtract"};
+                                                  "gather", "factor", "solve", "subtract", "outmask"};
 }
 
 // Optional per-stage device timing with events recorded on the plan's stream.
@@ -769,11 +780,70 @@ int gather_impl(sfft_plan_s* p, const AsmParams& A, const PairSet& PS, int np) {
   return SFFT_OK;
 }
 
+// Output-masked fit: the excluded pixels' rows taken out of the assembled
+// (zero-filled) Omega of the np pairs of PS.
+template <typename T>
+int omask_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
+  const Derived& D = p->D;
+  const Layout& Lo = p->Lo;
+  hipStream_t s = p->stream;
+  OmaskParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.ny = D.ny;
+  P.nx = D.nx;
+  P.w = D.w;
+  P.nk = D.nk;
+  P.L = D.L;
+  P.nkk = D.nkk;
+  P.n = D.n;
+  P.pitch = D.nx + 2 * D.w;
+  P.plane = (int64_t)(D.ny + 2 * D.w) * P.pitch;
+  P.ld = ld;
+  P.sx = 2.0 / (double)(D.nx - 1);
+  P.sy = 2.0 / (double)(D.ny - 1);
+  for (int i = 0; i < D.nk; ++i) {
+    P.px[i] = D.kpoly.px[i];
+    P.qy[i] = D.kpoly.qy[i];
+  }
+  P.ntile = (D.nkk + NB - 1) / NB;
+  OmaskOff O;
+  O.planes = Lo.om_planes;
+  O.cnt = Lo.om_cnt;
+  O.offs = Lo.om_offs;
+  O.list = Lo.om_list;
+  O.omega = Lo.omega;
+  p->timer.begin(SFFT_STAGE_OUTMASK, s);
+  om_planes_kernel<T><<<dim3((unsigned)((P.plane + 255) / 256), D.nk, np), 256, 0, s>>>(P, PS, O);
+  LAUNCH_CHECK();
+  om_count_kernel<<<dim3(D.ny, 1, np), 256, 0, s>>>(P, PS, O);
+  LAUNCH_CHECK();
+  om_scan_kernel<<<dim3(1, 1, np), 1024, 0, s>>>(P, PS, O);
+  LAUNCH_CHECK();
+  om_list_kernel<<<dim3(D.ny, 1, np), 256, 0, s>>>(P, PS, O);
+  LAUNCH_CHECK();
+  om_syrk_kernel<<<dim3(P.ntile * (P.ntile + 1) / 2, 1, np), 256, 0, s>>>(P, PS, O);
+  LAUNCH_CHECK();
+  p->timer.end(s);
+  return SFFT_OK;
+}
+
 // Assembly of Omega and beta for the np pairs of PS, which share the plan
 // p's descriptor and row pitch (p is one of them: its sizes, tables and
 // workspace offsets are every pair's).
 template <typename T>
+int build_core(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld);
+
+template <typename T>
 int build_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
+  int st = build_core<T>(p, PS, np, ld);
+  // a pair that shares its template uses its owner's (corrected) Omega, and
+  // its beta needs no correction (the target is zero at excluded pixels)
+  if (st == SFFT_OK && p->D.omask && !p->D.rhs_only) st = omask_impl<T>(p, PS, np, ld);
+  return st;
+}
+
+template <typename T>
+int build_core(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   const Derived& D = p->D;
   hipStream_t s = p->stream;
   const AsmParams A = asm_params(p, ld);

@@ -277,21 +277,9 @@ def pair_c4(desc):
                 truth=dict(name="C4", **desc))
 
 
-def template_group(seed, n, nsci, w=9, dk=2, db=2, nstar=None):
-    """One template and ``nsci`` science epochs of the same field (the S x T pairing).
-
-    The template is rendered once as in the 4088^2 recipe (Moffat beta=3,
-    FWHM 1.8 at the centre, sky 1000 e- with Poisson noise, read noise 8 e-,
-    sky-subtracted).  Science epoch j sees the same stars through its own
-    PSF (FWHM_s,j = 2.0 + 0.6 j / max(1, nsci - 1) at the centre, the same
-    quadratic variation), its own noise, its own DB=2 background of amplitude
-    ~5 e- and a transient of 2e5 e- at its own position.  The mask is the
-    template's: a disk of radius 3*FWHM_t,max = 3*2.6 around every star whose
-    template peak exceeds 5e4 e-; it is the same array for every epoch.
-    Returns a list of ``nsci`` Pairs whose ``tmpl`` and ``mask`` are the same
-    objects.
-    """
-    rng = np.random.default_rng(seed)
+def template_frame(seed, n, nstar=None):
+    """The template of a template group and its mask (see template_group)."""
+    rng = np.random.default_rng([seed, 0])
     if nstar is None:
         nstar = int(round(2.39e-3 * n * n))
     beta, sky, rn, psf_var, fwhm_t = 3.0, 1000.0, 8.0, 0.05, 1.8
@@ -306,26 +294,60 @@ def template_group(seed, n, nsci, w=9, dk=2, db=2, nstar=None):
     peak = flux * (beta - 1.0) / (math.pi * alpha * alpha)
     bright = peak > 5e4
     mask = disk_mask(n, n, xs[bright], ys[bright], np.full(int(bright.sum()), 3.0 * 2.6)).astype(np.uint8)
+    cat = dict(xs=xs, ys=ys, flux=flux, vary=vary, beta=beta, sky=sky, read_noise=rn, psf_var=psf_var)
+    return tmpl, mask, cat
+
+
+def template_epoch(seed, n, cat, j, nsci):
+    """Science epoch j of a template group (see template_group)."""
+    rng = np.random.default_rng([seed, j + 1])
+    beta, sky, rn, psf_var = cat["beta"], cat["sky"], cat["read_noise"], cat["psf_var"]
+    xs, ys, flux = cat["xs"], cat["ys"], cat["flux"]
+    fwhm_s = 2.0 + 0.6 * j / max(1, nsci - 1)
+    fw_s = fwhm_s * cat["vary"]
+    smodel = render_stars(n, n, xs, ys, flux, lambda dx, dy, i: moffat_stamp(dx, dy, fw_s[i][:, None, None], beta))
     gx = _norm_coords(np.arange(n), n)[None, :]
     gy = _norm_coords(np.arange(n), n)[:, None]
+    c = rng.normal(0.0, 0.3, 5)
+    smodel = smodel + 5.0 * (0.6 + c[0] + (0.5 + c[1]) * gx - (0.4 + c[2]) * gy + 0.3 * gx * gx
+                             - (0.2 + c[3]) * gx * gy + (0.25 + c[4]) * gy * gy)
+    tx, ty = rng.uniform(0.1 * n, 0.9 * n, 2)
+    tv = 1.0 + psf_var * (_norm_coords(tx, n) ** 2 + _norm_coords(ty, n) ** 2)
+    smodel = smodel + render_stars(n, n, np.array([tx]), np.array([ty]), np.array([2.0e5]),
+                                   lambda dx, dy, i: moffat_stamp(dx, dy, fwhm_s * tv, beta))
+    sci = rng.poisson(smodel + sky).astype(np.float64) + rng.normal(0.0, rn, (n, n)) - sky
+    return sci, dict(epoch=j, fwhm_s=fwhm_s, transient_xy=(float(tx), float(ty)))
+
+
+def template_group(seed, n, nsci, w=9, dk=2, db=2, nstar=None):
+    """One template and ``nsci`` science epochs of the same field (the S x T pairing).
+
+    The template is rendered once as in the 4088^2 recipe (Moffat beta=3,
+    FWHM 1.8 at the centre varying by 5 % quadratically to the corners, sky
+    1000 e- with Poisson noise, read noise 8 e-, sky-subtracted).  Science
+    epoch j sees the same stars through its own PSF (FWHM_s,j = 2.0 +
+    0.6 j / max(1, nsci - 1) at the centre, the same variation), its own
+    noise, its own quadratic background of amplitude ~5 e- and a transient of
+    2e5 e- at its own position.  The mask is the template's: a disk of radius
+    3 * 2.6 around every star whose template peak exceeds 5e4 e-; it is the
+    same array for every epoch.  The template depends on ``seed`` alone and
+    epoch j on (``seed``, j), so one epoch can be rendered on its own
+    (template_group_pair).  Returns a list of ``nsci`` Pairs whose ``tmpl``
+    and ``mask`` are the same objects.
+    """
+    tmpl, mask, cat = template_frame(seed, n, nstar)
     out = []
     for j in range(nsci):
-        fwhm_s = 2.0 + 0.6 * j / max(1, nsci - 1)
-        fw_s = fwhm_s * vary
-        smodel = render_stars(n, n, xs, ys, flux,
-                              lambda dx, dy, i: moffat_stamp(dx, dy, fw_s[i][:, None, None], beta))
-        c = rng.normal(0.0, 0.3, 6)
-        smodel = smodel + 5.0 * (0.6 + c[0] + (0.5 + c[1]) * gx - (0.4 + c[2]) * gy + 0.3 * gx * gx
-                                 - (0.2 + c[3]) * gx * gy + (0.25 + c[4]) * gy * gy)
-        tx, ty = rng.uniform(0.1 * n, 0.9 * n, 2)
-        tv = 1.0 + psf_var * (_norm_coords(tx, n) ** 2 + _norm_coords(ty, n) ** 2)
-        smodel = smodel + render_stars(n, n, np.array([tx]), np.array([ty]), np.array([2.0e5]),
-                                       lambda dx, dy, i: moffat_stamp(dx, dy, fwhm_s * tv, beta))
-        sci = rng.poisson(smodel + sky).astype(np.float64) + rng.normal(0.0, rn, (n, n)) - sky
-        out.append(Pair(sci, tmpl, mask, w=w, dk=dk, db=db,
-                        truth=dict(name="template group", seed=seed, epoch=j, fwhm_s=fwhm_s,
-                                   transient_xy=(float(tx), float(ty)))))
+        sci, info = template_epoch(seed, n, cat, j, nsci)
+        out.append(Pair(sci, tmpl, mask, w=w, dk=dk, db=db, truth=dict(name="template group", seed=seed, **info)))
     return out
+
+
+def template_group_pair(seed, n, j, nsci, w=9, dk=2, db=2, nstar=None):
+    """Epoch j of template_group(seed, n, nsci, ...) alone (the same arrays)."""
+    tmpl, mask, cat = template_frame(seed, n, nstar)
+    sci, info = template_epoch(seed, n, cat, j, nsci)
+    return Pair(sci, tmpl, mask, w=w, dk=dk, db=db, truth=dict(name="template group", seed=seed, **info))
 
 
 def random_pair(seed, ny, nx, w, dk, db, mask_frac=0.1, stars=True):

@@ -51,7 +51,7 @@ def test_num_coeffs_and_workspace():
     dict(ny=64, nx=64, w=2, dk=1, db=1, mode=7),
     dict(ny=64, nx=64, w=2, dk=1, db=1, flags=7),        # route bits plus an unknown bit
     dict(ny=64, nx=64, w=2, dk=1, db=1, flags=4),        # unknown flag bit
-    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=32),       # unknown flag bit above the ratio flag
+    dict(ny=64, nx=64, w=2, dk=1, db=1, flags=64),       # unknown flag bit above the output-mask flag
     dict(ny=64, nx=2048, w=2, dk=1, db=1, flags=2),      # direct sums limited to nx <= 1024
     dict(ny=64, nx=64, w=10, dk=1, db=1, flags=2),       # ... and to w <= 9
     dict(ny=4096, nx=4096, w=15, dk=3, db=3),     # more unknowns than the solver holds
