@@ -554,6 +554,30 @@ def next_leg(B, torch, p, mode_name, log, reps=10):
                 out["decorrelation"] = dict(kernel_ms=round(kms, 4), grid=64, taps=2 * t + 1, apply=app)
         finally:
             plan.close()
+    # output-masked fit: the rank-|M| correction of the kernel block on the
+    # FP64 matrix cores, timed by the plan's stage events over `reps` builds
+    plan = B.Plan(n, n, p.w, p.dk, p.db, mode=mode, flags=B.SFFT_FLAG_OUTPUT_MASK)
+    try:
+        plan.build(S, R, M)
+        B.sfft_timing_enable(plan.handle, ["outmask"])
+        for _ in range(3):
+            plan.build(S, R, M)
+        oms, cnt = B.sfft_timing_read(plan.handle)["outmask"]
+        B.sfft_timing_enable(plan.handle, False)
+        om_ms = oms / cnt
+        nkk = (2 * p.w + 1) ** 2 * (p.dk + 1) * (p.dk + 2) // 2
+        nexcl = int((p.mask != 0).sum())
+        nt = -(-nkk // 64)
+        executed = nt * (nt + 1) // 2 * 64 * 64 * 2 * (-(-nexcl // 64) * 64)
+        useful = nkk * nkk * nexcl          # 2 flops per multiply-add over the symmetric half
+        out["output_mask"] = dict(bound="mfma", kernel="om_syrk_kernel (+ planes, count, scan, list)", ms=round(om_ms, 3),
+                                  excluded_pixels=nexcl, kernel_block=nkk, executed_tflop=round(executed / 1e12, 4),
+                                  useful_tflop=round(useful / 1e12, 4),
+                                  achieved_tflops=round(executed / (om_ms * 1e-3) / 1e12, 2),
+                                  peak=MFMA_F64_PEAK_TFLOPS,
+                                  frac=round(executed / (om_ms * 1e-3) / 1e12 / MFMA_F64_PEAK_TFLOPS, 4))
+    finally:
+        plan.close()
     out["const_ratio"] = dict(solve_ms_free=round(solve_ms["free"], 4),
                               solve_ms_constrained=round(solve_ms["constrained"], 4),
                               overhead_ms=round(solve_ms["constrained"] - solve_ms["free"], 4),

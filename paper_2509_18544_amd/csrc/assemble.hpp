@@ -133,7 +133,8 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kerne
   constexpr int H = 1 << LGH;            // H = Px / 2
   constexpr int RB = row_pass_rows(NMAX, LGH);
   constexpr int NPT = (RB * H) / THREADS;
-  static_assert(NPT * THREADS == RB * H && NPT >= 1 && NPT <= 16, "whole pairs per thread, flags in 32 bits");
+  static_assert(NPT * THREADS == RB * H && NPT >= 2 && NPT <= 16 && NPT % 2 == 0,
+                "whole pairs per thread (an even number: two outputs per store), flags in 32 bits");
   const int rb = xcd_remap(blockIdx.x, gridDim.x);
   if (rb >= P.nrowblk) return;
   const int y0 = rb * RB;
@@ -204,31 +205,34 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kerne
     fft_run<T, NMAX, THREADS, false, true, true, LGH, 4, decltype(lds), decltype(lds), ROW_RPAD>(buf, RB, tw, lds,
                                                                                                  lds);
     __syncthreads();
-    // split and write: consecutive threads fill one (column pair, row block) segment
+    // split and write: a thread forms both values of one (column pair, row)
+    // and stores them together; consecutive threads take consecutive rows of
+    // one column pair, whose RB rows form one contiguous segment
     cplx<T>* Ub = U + (int64_t)b * pstride;
-    constexpr int seg = 2 * RB;
-#pragma unroll 4
-    for (int i = 0; i < NPT; ++i) {
-      const int e = tid + i * THREADS;
-      const int c = e / seg;
-      const int rem = e - c * seg;
-      const int r = rem >> 1;
-      const int k = 2 * c + (rem & 1);
-      const int y = y0 + r;
-      if (y >= ny) continue;
+    auto split = [&](int r, int k) -> cplx<T> {
       const cplx<T> zk = buf[lds.at(r, k)];
       const cplx<T> zm = conjg(buf[lds.at(r, (H - k) & (H - 1))]);
-      cplx<T> out;
-      if (k == 0) {
-        // E(0) = Re Z0, O(0) = Im Z0; X(0) = E + O, X(H) = E - O
-        out = mk(zk.x + zk.y, zk.x - zk.y);
+      if (k == 0) return mk(zk.x + zk.y, zk.x - zk.y);   // E(0) = Re Z0, O(0) = Im Z0: (X(0), X(H))
+      const cplx<T> e2 = zk + zm;                        // 2 E
+      const cplx<T> o2 = rot90<T, false>(zk - zm);       // 2 O = -i (Z - conj Z(H-k))
+      const cplx<T> t = twid<T, false>(tw, k << twsx);
+      return scale(e2 + t * o2, (T)0.5);
+    };
+#pragma unroll 4
+    for (int i = 0; i < NPT / 2; ++i) {
+      const int e = tid + i * THREADS;
+      const int c = e / RB;
+      const int r = e - c * RB;
+      const int y = y0 + r;
+      if (y >= ny) continue;
+      const cplx<T> o0 = split(r, 2 * c), o1 = split(r, 2 * c + 1);
+      cplx<T>* dst = Ub + ((int64_t)c * Py + y) * 2;
+      if constexpr (sizeof(T) == sizeof(float)) {
+        *reinterpret_cast<float4*>(dst) = make_float4(o0.x, o0.y, o1.x, o1.y);
       } else {
-        const cplx<T> e2 = zk + zm;                   // 2 E
-        const cplx<T> o2 = rot90<T, false>(zk - zm);  // 2 O = -i (Z - conj Z(H-k))
-        const cplx<T> t = twid<T, false>(tw, k << twsx);
-        out = scale(e2 + t * o2, (T)0.5);
+        dst[0] = o0;
+        dst[1] = o1;
       }
-      Ub[((int64_t)c * Py + y) * 2 + (k & 1)] = out;
     }
   }
 }
@@ -445,19 +449,27 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
       // converted and stored, so their latencies overlap.
       const int npr = nc * (P2 / 2);
       const int ntot = nst * npr;
+      // plane of element e: floor(e / npr) as the truncation of (e + 1/2) / npr
+      // in FP32.  That quotient is at least 1/(2 npr) >= 2^-12 away from an
+      // integer (npr <= 8 P1 <= 2048), and FP32 moves it by less than
+      // 62 planes x 2^-23 (e < 2^23 is exact in FP32), so the truncation is
+      // exact; it replaces two integer divisions per element.
+      const float inv_npr = 1.0f / (float)npr;
+      auto plane_of = [&](int e) { return (int)(((float)e + 0.5f) * inv_npr); };
       for (int e0 = tid; e0 < ntot; e0 += CORR_LB * THREADS) {
         cplx<T> q[CORR_LB][2];
 #pragma unroll
         for (int b = 0; b < CORR_LB; ++b) {
           const int e = min(e0 + b * THREADS, ntot - 1);   // a valid element; the copy is dropped below
-          const int pl = e / npr;
+          const int pl = plane_of(e);
           const int o = 2 * (e - pl * npr);
           const bool hi = pl >= P.nstaged;                 // block 0: the Nyquist column's planes
           const int col = hi ? H : kx;
           const int sp = pl - (hi ? P.nstaged : 0);        // staged plane -> workspace and plane
           const bool sh = sp < P.nshared;
-          const cplx<T>* src = (sh ? Ut : U) + (sh ? sp : sp + P.plane_skip) * pstride + (int64_t)col * Py +
-                               (int64_t)k1c * P2 + o;
+          // element offsets fit in 32 bits: at most 31 planes of 2049 x 4096
+          const cplx<T>* src = (sh ? Ut : U) + (uint32_t)((sh ? sp : sp + P.plane_skip) * (int)pstride +
+                                                          col * Py + k1c * P2 + o);
           if constexpr (sizeof(T) == sizeof(float)) {
             const float4 f = *reinterpret_cast<const float4*>(src);
             q[b][0] = mk(f.x, f.y);
@@ -471,7 +483,7 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
         for (int b = 0; b < CORR_LB; ++b) {
           const int e = e0 + b * THREADS;
           if (e < ntot) {
-            const int pl = e / npr;
+            const int pl = plane_of(e);
             const int o = 2 * (e - pl * npr);
             cplx<double>* dst = stage + pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1));
             dst[0] = mk((double)q[b][0].x, (double)q[b][0].y);

@@ -348,6 +348,10 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
     }
     if (!fits) return SFFT_EINVAL;
     D->items = padded;
+    // every wave of the correlation kernel takes ipw consecutive items: they
+    // must share one rotation (the kernel reads it from the wave's first item)
+    for (int i = 0; i < D->items.size(); ++i)
+      if (((D->items[i].jlo % P2) + P2) % P2 != ((D->items[(i / ipw) * ipw].jlo % P2) + P2) % P2) return SFFT_EINVAL;
   }
   D->nitems = (int)D->items.size();
   // distinct first lag rows (the correlation kernel tabulates their twiddles per chunk)

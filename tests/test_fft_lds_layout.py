@@ -71,3 +71,16 @@ def test_passes_tile_every_length():
             ps = passes(lgn, lgm)
             assert sum(lgr for lgr, _ in ps) == lgn
             assert all(lgr == lgm for lgr, _ in ps[1:])
+
+
+def test_corr_staging_plane_index_is_exact():
+    """The correlation kernel's staging finds the plane of staged element e as
+    the FP32 truncation of (e + 1/2) / npr instead of an integer division; it
+    must equal floor(e / npr) for every chunk width (npr = 8 residues' pairs,
+    up to 8 x 256) and every element of up to 62 staged planes."""
+    import numpy as np
+    for npr in range(8, 2049, 8):
+        e = np.arange(0, 62 * npr, dtype=np.int64)
+        inv = np.float32(1.0) / np.float32(npr)
+        q = ((e.astype(np.float32) + np.float32(0.5)) * inv).astype(np.int32)
+        assert np.array_equal(q, e // npr), npr
