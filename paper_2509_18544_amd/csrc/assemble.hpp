@@ -52,7 +52,7 @@ struct CorrItem {
   int16_t jlo, nj;       // first lag row (signed) and count (<= JMAX)
   int32_t vrow;          // row in V where lag row jlo goes
   int16_t jidx;          // index of jlo in the list of distinct first lag rows
-  int16_t pad_;
+  int16_t skip;          // the first `skip` lag rows are accumulated but not kept
 };
 
 constexpr int MAX_JLO = 8;  // distinct first lag rows among the items
@@ -75,8 +75,10 @@ struct AsmParams {
   int nitems;            // correlation items
   int vrows;             // rows of V (sum over pairs of window heights)
   PolyTab kpoly, bpoly;
-  int nmom;              // per-row moments: (2DB+1) G-moments + (DB+1) S-moments
+  int nmom;              // per-row moments: (2DB+1) G-moments + (DB+1) S-moments + (DK+DB+1) G_R R moments
   int db;
+  int na;                // DK + DB + 1: x powers of the G_R R moments
+  int nmu;               // monomials of degree <= DK + DB
   int corr_lanes;        // threads per correlation item (divides into 64)
   int njlo;              // distinct first lag rows and their values
   int16_t jlo_list[MAX_JLO];
@@ -557,6 +559,7 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
         for (int t = 0; t < HALF; ++t) {
           const int tt = h * HALF + t;
           if (tt >= it.nj) break;
+          if (tt < it.skip) continue;
           cplx<double> sum = mk(0.0, 0.0);
           for (int l = 0; l < lanes; ++l) sum = sum + red[(tid + l) * HALF + t];
           V[(int64_t)kx * P.vrows + it.vrow + tt] = sum;
@@ -894,6 +897,7 @@ __global__ __launch_bounds__(THREADS) void row_win_kernel(AsmParams P, PairSet P
 // ---------------------------------------------------------------------------
 // mom[y][p]          = sum_x G xh^p,      p in [0, 2DB]
 // mom[y][2DB+1+p]    = sum_x G S xh^p,    p in [0, DB]
+// mom[y][3DB+2+p]    = sum_x G_R R xh^p,  p in [0, DK+DB]   (G_R R: the template side, w-strip excluded)
 template <typename T, int THREADS>
 __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet PS, WsOff O) {
   const int pr = blockIdx.z;
@@ -904,13 +908,15 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet P
   int* __restrict__ nonfinite = ws_at<int>(PS, pr, O.flags) + 1;
   constexpr int NG_MAX = 2 * MAX_DEG + 1;
   constexpr int NS_MAX = MAX_DEG + 1;
-  constexpr int NM = NG_MAX + NS_MAX;
+  constexpr int NA_MAX = 2 * MAX_DEG + 1;
+  constexpr int NM = NG_MAX + NS_MAX + NA_MAX;
   constexpr int NW = THREADS / 64;
   __shared__ double red[NW][NM];
   const int y = blockIdx.x;
   const int tid = threadIdx.x;
   const int nG = 2 * P.db + 1;
   const int nS = P.db + 1;
+  const bool inty = y >= P.w && y < P.ny - P.w;
   double acc[NM];
 #pragma unroll
   for (int i = 0; i < NM; ++i) acc[i] = 0.0;
@@ -926,12 +932,14 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet P
     bad |= !isfinite(sv) || !isfinite(rv);
     const double g = good ? 1.0 : 0.0;
     const double s = good ? (double)sv : 0.0;
+    const double r = (good && inty && x >= P.w && x < P.nx - P.w) ? (double)rv : 0.0;
     const double xh = (double)x * P.sx - 1.0;
     double pw = 1.0;
 #pragma unroll
     for (int p = 0; p < NG_MAX; ++p) {
       acc[p] += g * pw;
       if (p < NS_MAX) acc[NG_MAX + p] += s * pw;
+      acc[NG_MAX + NS_MAX + p] += r * pw;
       pw *= xh;
     }
   }
@@ -950,13 +958,25 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet P
     const int i = tid;
     if (i < NG_MAX) {
       if (i < nG) mom[(int64_t)y * P.nmom + i] = v;
-    } else if (i - NG_MAX < nS) {
-      mom[(int64_t)y * P.nmom + nG + (i - NG_MAX)] = v;
+    } else if (i < NG_MAX + NS_MAX) {
+      if (i - NG_MAX < nS) mom[(int64_t)y * P.nmom + nG + (i - NG_MAX)] = v;
+    } else if (i - NG_MAX - NS_MAX < P.na) {
+      mom[(int64_t)y * P.nmom + nG + nS + (i - NG_MAX - NS_MAX)] = v;
     }
   }
 }
 
-// Omega_BB and beta_B from the per-row moments: one block per output, fixed
+// (p, q) of monomial c in the graded order (degree d = p + q, then q ascending)
+__host__ __device__ inline void mono_of(int c, int* p, int* q) {
+  int d = 0;
+  while ((d + 1) * (d + 2) / 2 <= c) ++d;
+  *q = c - d * (d + 1) / 2;
+  *p = d - *q;
+}
+__host__ __device__ constexpr int mono_index(int p, int q) { return (p + q) * (p + q + 1) / 2 + q; }
+
+// Omega_BB, beta_B and the template moments mu(p, q) = sum G_R R xh^p yh^q
+// (p + q <= DK + DB) from the per-row moments: one block per output, fixed
 // summation order (deterministic).
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, PairSet PS, WsOff O) {
@@ -964,6 +984,7 @@ __global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, Pa
   const double* __restrict__ mom = ws_at<const double>(PS, pr, O.mom);
   double* __restrict__ obb = ws_at<double>(PS, pr, O.obb);
   double* __restrict__ bb = ws_at<double>(PS, pr, O.bb);
+  double* __restrict__ amom = ws_at<double>(PS, pr, O.amom);
   __shared__ double red[THREADS / 64];
   const int tid = threadIdx.x;
   const int nb = P.nb;
@@ -975,10 +996,15 @@ __global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, Pa
     const int b = q / nb, c = q % nb;
     col = P.bpoly.px[b] + P.bpoly.px[c];
     e = P.bpoly.qy[b] + P.bpoly.qy[c];
-  } else {
+  } else if (q < nb * nb + nb) {
     const int b = q - nb * nb;
     col = nG + P.bpoly.px[b];
     e = P.bpoly.qy[b];
+  } else {
+    int pc, qc;
+    mono_of(q - nb * nb - nb, &pc, &qc);
+    col = nG + (P.db + 1) + pc;
+    e = qc;
   }
 #pragma unroll 4
   for (int y = tid; y < P.ny; y += THREADS) {
@@ -992,7 +1018,8 @@ __global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, Pa
     double v = 0.0;
     for (int k = 0; k < THREADS / 64; ++k) v += red[k];
     if (q < nb * nb) obb[q] = v;
-    else bb[q - nb * nb] = v;
+    else if (q < nb * nb + nb) bb[q - nb * nb] = v;
+    else amom[q - nb * nb - nb] = v;
   }
 }
 
@@ -1001,6 +1028,7 @@ __global__ __launch_bounds__(THREADS) void moments_reduce_kernel(AsmParams P, Pa
 // ---------------------------------------------------------------------------
 struct GatherParams {
   int n, nkk, L, w, nk, nb;
+  int kb_dense;                 // Omega_KB from kbd[(a,u) nB + b] (transform route) instead of windows
   int kk_off[MAX_NB * MAX_NB];  // window offset of C_ab for a <= b (index a*nk + b)
   int kb_off[MAX_NB * MAX_NB];  // window offset of corr(A_a, G m_b) (index a*nb + b)
   int ks_off[MAX_NB];           // window offset of corr(A_a, S_m)
@@ -1013,6 +1041,7 @@ __global__ void gather_kernel(GatherParams G, PairSet PS, WsOff O) {
   const double* __restrict__ bb = ws_at<const double>(PS, pr, O.bb);
   double* __restrict__ omega = ws_at<double>(PS, pr, O.omega);
   double* __restrict__ beta = ws_at<double>(PS, pr, O.beta);
+  const double* __restrict__ kbd = ws_at<const double>(PS, pr, O.kbd);
   const int r = blockIdx.y;
   const int L = G.L, w = G.w;
   const int L2 = L * L;
@@ -1032,11 +1061,11 @@ __global__ void gather_kernel(GatherParams G, PairSet PS, WsOff O) {
     } else if (r < G.nkk) {
       const int a = r / L2, ur = r - a * L2;
       const int b = c - G.nkk;
-      v = win[G.kb_off[a * G.nb + b] + ur];
+      v = G.kb_dense ? kbd[(int64_t)r * G.nb + b] : win[G.kb_off[a * G.nb + b] + ur];
     } else if (c < G.nkk) {
       const int a = c / L2, uc = c - a * L2;
       const int b = r - G.nkk;
-      v = win[G.kb_off[a * G.nb + b] + uc];
+      v = G.kb_dense ? kbd[(int64_t)c * G.nb + b] : win[G.kb_off[a * G.nb + b] + uc];
     } else {
       v = obb[(r - G.nkk) * G.nb + (c - G.nkk)];
     }

@@ -1,0 +1,172 @@
+// The template-background block of the normal matrix without correlations.
+//
+//   Omega[(a,u), b] = sum_z A_a(z - u) G(z) m_b(z),   A_a = m_a G_R R.
+//
+// Split G = 1 - (1 - G):
+//   * the whole-frame part, with z' = z - u (A_a vanishes within w of the
+//     edge, so z' + u stays in the frame) and the binomial expansion of
+//     m_b(z' + u) = (xh' + u_x sx)^p_b (yh' + u_y sy)^q_b, is
+//       sum_{i<=p_b, j<=q_b} C(p_b,i) C(q_b,j) (u_x sx)^(p_b-i) (u_y sy)^(q_b-j) mu(p_a+i, q_a+j),
+//     mu(p, q) = sum_z G_R R xh^p yh^q: FP64 moments of the template over
+//     the frame (moments_kernel / moments_reduce_kernel);
+//   * the excluded part, sum over the excluded pixels z of A_a(z - u) m_b(z),
+//     with m_a(z - u) expanded around z the same way, is
+//       sum_{p'<=p_a, q'<=q_a} C(p_a,p') C(q_a,q') (-u_x sx)^(p_a-p') (-u_y sy)^(q_a-q') T(p'+p_b, q'+q_b)(u),
+//     T(p, q)(u) = sum_{z excluded} (G_R R)(z - u) xh(z)^p yh(z)^q: one sum
+//     per lag u and monomial of degree <= DK + DB over the excluded pixels.
+// The transform route thus needs no background planes: their forward
+// transforms and their nK nB correlation windows are replaced by these sums,
+// whose cost follows the number of excluded pixels.
+//
+// Kernels (per pair, after the excluded-pixel list of outmask.hpp):
+//   kb_plane   : G_R R on the frame padded by w zeros on every side (the
+//                input type), so that (G_R R)(z - u) is one load;
+//   kb_mask    : T(c)(u) partial sums, one block per (chunk of the excluded
+//                pixels, up to 512 lags); the chunks are fixed, so the grid
+//                does not depend on the data;
+//   kb_reduce  : T = sum of the chunks' partial sums, chunks in order;
+//   kb_combine : the two parts above into kbd[(a,u) nB + b] (FP64), which the
+//                gather copies into both triangles of Omega.
+#pragma once
+
+#include "assemble.hpp"
+#include "outmask.hpp"
+
+namespace sfft {
+
+constexpr int KB_CHUNKS = 128;   // excluded-pixel chunks per pair (fixed grid)
+constexpr int KB_SUB = 64;       // excluded pixels staged in LDS per step
+constexpr int KB_MAX_THREADS = 512;   // lags per block (at most)
+
+struct KbParams {
+  int ny, nx, w, L, nk, nb, nkk, nmu;
+  int pitch;                      // padded-frame row of the excluded-pixel list (nx + 2w)
+  int64_t ld;
+  double sx, sy;
+  int8_t kpx[MAX_NB], kqy[MAX_NB];
+  int8_t bpx[MAX_NB], bqy[MAX_NB];
+};
+
+__device__ __forceinline__ double kb_binom(int n, int k) {
+  constexpr double tab[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0}, {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+  return tab[n][k];
+}
+
+// grp = G_R R on the frame padded by w zeros: grp[(y + w) pitch + x + w]
+template <typename T>
+__global__ __launch_bounds__(256) void kb_plane_kernel(KbParams P, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
+  const uint8_t* __restrict__ mask = PS.mask[pr];
+  T* __restrict__ grp = ws_at<T>(PS, pr, O.kbgrp);
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)(P.ny + 2 * P.w) * P.pitch) return;
+  const int py = (int)(e / P.pitch), px = (int)(e - (int64_t)py * P.pitch);
+  const int y = py - P.w, x = px - P.w;
+  const bool in = y >= P.w && y < P.ny - P.w && x >= P.w && x < P.nx - P.w;
+  T v = (T)0;
+  if (in) {
+    const int64_t o = (int64_t)y * P.ld + x;
+    if (mask == nullptr || mask[o] == 0) v = tmpl[o];
+  }
+  grp[e] = v;
+}
+
+// part[chunk][c][u] = sum over the chunk's excluded pixels z of (G_R R)(z - u) m_c(z),
+// m_c the monomials of degree <= DSUM = DK + DB (graded order).  A thread
+// owns one lag u; the pixels of a step and their monomials are staged in LDS
+// (the monomials padded to an even count, read as pairs).
+template <typename T, int DSUM>
+__global__ __launch_bounds__(KB_MAX_THREADS) void kb_mask_kernel(KbParams P, PairSet PS, WsOff O, OmaskOff M) {
+  constexpr int NMU = (DSUM + 1) * (DSUM + 2) / 2;
+  constexpr int NMP = (NMU + 1) & ~1;
+  const int pr = blockIdx.z;
+  const T* __restrict__ grp = ws_at<const T>(PS, pr, O.kbgrp);
+  const uint8_t* __restrict__ mask = PS.mask[pr];
+  const int* __restrict__ list = ws_at<const int>(PS, pr, M.list);
+  double* __restrict__ part = ws_at<double>(PS, pr, O.kbpart);
+  const int count = mask == nullptr ? 0 : ws_at<const int>(PS, pr, M.offs)[P.ny];
+  __shared__ int spo[KB_SUB];
+  __shared__ __align__(16) double smo[KB_SUB][NMP];
+  const int tid = threadIdx.x;
+  const int L2 = P.L * P.L;
+  const int ui = blockIdx.y * blockDim.x + tid;
+  const bool uok = ui < L2;
+  const int uu = min(ui, L2 - 1);
+  const int uy = uu / P.L - P.w, ux = uu % P.L - P.w;
+  const int uoff = uy * P.pitch + ux;   // (z - u) = pix(z) - uoff in the padded frame
+  const int per = (count + KB_CHUNKS - 1) / KB_CHUNKS;
+  const int k0 = min(count, (int)blockIdx.x * per), k1 = min(count, k0 + per);
+  double acc[NMU];
+#pragma unroll
+  for (int c = 0; c < NMU; ++c) acc[c] = 0.0;
+  for (int kb = k0; kb < k1; kb += KB_SUB) {
+    __syncthreads();   // the previous step's pixels have been read
+    if (tid < KB_SUB) {
+      const int k = kb + tid;
+      const int p = k < k1 ? list[k] : list[k0];   // padded-frame offset of the pixel
+      const int y = p / P.pitch - P.w;
+      const int x = p - (y + P.w) * P.pitch - P.w;
+      spo[tid] = p;
+      const double xh = (double)x * P.sx - 1.0, yh = (double)y * P.sy - 1.0;
+#pragma unroll
+      for (int c = 0; c < NMP; ++c) {
+        int pc, qc;
+        mono_of(c, &pc, &qc);
+        smo[tid][c] = c < NMU ? ipow(xh, pc) * ipow(yh, qc) : 0.0;
+      }
+    }
+    __syncthreads();
+    const int nsub = min(KB_SUB, k1 - kb);
+    for (int j = 0; j < nsub; ++j) {
+      const double v = (double)grp[spo[j] - uoff];   // zero on the w-strip, at excluded pixels, outside
+#pragma unroll
+      for (int c = 0; c < NMU; ++c) acc[c] = fma(v, smo[j][c], acc[c]);
+    }
+  }
+  if (!uok) return;
+#pragma unroll
+  for (int c = 0; c < NMU; ++c) part[((int64_t)blockIdx.x * NMU + c) * L2 + ui] = acc[c];
+}
+
+// T[c][u] = sum over the chunks of part[chunk][c][u], chunks in order
+__global__ void kb_reduce_kernel(KbParams P, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const double* __restrict__ part = ws_at<const double>(PS, pr, O.kbpart);
+  double* __restrict__ Tm = ws_at<double>(PS, pr, O.kbT);
+  const int L2 = P.L * P.L;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.nmu * L2) return;
+  double v = 0.0;
+  for (int ch = 0; ch < KB_CHUNKS; ++ch) v += part[(int64_t)ch * P.nmu * L2 + i];
+  Tm[i] = v;
+}
+
+// kbd[(a,u) nB + b] = whole-frame part - excluded part (see the top of the file)
+__global__ void kb_combine_kernel(KbParams P, PairSet PS, WsOff O) {
+  const int pr = blockIdx.z;
+  const double* __restrict__ amom = ws_at<const double>(PS, pr, O.amom);
+  const double* __restrict__ Tm = ws_at<const double>(PS, pr, O.kbT);
+  double* __restrict__ kbd = ws_at<double>(PS, pr, O.kbd);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P.nkk * P.nb) return;
+  const int i = e / P.nb, b = e - i * P.nb;
+  const int L2 = P.L * P.L;
+  const int a = i / L2, u = i - a * L2;
+  const int uy = u / P.L - P.w, ux = u % P.L - P.w;
+  const double dx = (double)ux * P.sx, dy = (double)uy * P.sy;
+  const int pa = P.kpx[a], qa = P.kqy[a], pb = P.bpx[b], qb = P.bqy[b];
+  double whole = 0.0;
+  for (int ii = 0; ii <= pb; ++ii)
+    for (int jj = 0; jj <= qb; ++jj)
+      whole += kb_binom(pb, ii) * kb_binom(qb, jj) * ipow(dx, pb - ii) * ipow(dy, qb - jj) *
+               amom[mono_index(pa + ii, qa + jj)];
+  double excl = 0.0;
+  for (int pp = 0; pp <= pa; ++pp)
+    for (int qq = 0; qq <= qa; ++qq)
+      excl += kb_binom(pa, pp) * kb_binom(qa, qq) * ipow(-dx, pa - pp) * ipow(-dy, qa - qq) *
+              Tm[(int64_t)mono_index(pp + pb, qq + qb) * L2 + u];
+  kbd[e] = whole - excl;
+}
+
+}  // namespace sfft

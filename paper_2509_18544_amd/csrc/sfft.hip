@@ -23,6 +23,7 @@
 #include "decorr.hpp"
 #include "subtract.hpp"
 #include "outmask.hpp"
+#include "kbmom.hpp"
 
 using namespace sfft;
 
@@ -75,7 +76,7 @@ constexpr int MAX_VROWS = JMAX * MAX_ITEMS;
 
 struct Layout {
   size_t Ub, U, V, win, mom, obb, bb, omega, beta, F, Linv, theta, y, r, d, w, kp, flags, tw32, tw64, items, wrows, drows,
-      mtiles, ratio, job, rjob, om_planes, om_cnt, om_offs, om_list;
+      mtiles, ratio, job, rjob, om_planes, om_cnt, om_offs, om_list, amom, kbpart, kbT, kbd, kbgrp;
   size_t total;
 };
 
@@ -84,6 +85,7 @@ struct Derived {
   int L, nk, nb, nkk, n;
   int lgPy, lgPx, Py, Px, H;
   int nplanes;
+  int nmu;   // monomials of degree <= DK + DB (moments of G_R R, excluded-pixel sums)
   int nbase, nbk, nbb;
   // right-hand side only: the template and mask are another pair's, whose
   // template spectra, normal matrix and factor this plan uses (its own build
@@ -169,20 +171,25 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   D->Py = 1 << D->lgPy;
   D->Px = 1 << D->lgPx;
   D->H = D->Px / 2;
-  D->nplanes = D->nk + D->nb + 1;
+  // planes of the transform route: the nK template planes A_a and the
+  // masked science image S_m (plane nK).  The template-background block
+  // Omega_KB comes from FP64 moments and the excluded pixels instead of
+  // correlations with the background planes G m_b (kb_* kernels).
+  D->nplanes = D->nk + 1;
+  D->nmu = (d->dk + d->db + 1) * (d->dk + d->db + 2) / 2;
   D->rhs_only = rhs_only;
   D->omask = (d->flags & SFFT_FLAG_OUTPUT_MASK) != 0;
   // base rows and the output planes built from each (plane index, y-power)
   D->nbk = d->dk + 1;
-  D->nbb = d->db + 1;
+  D->nbb = 0;   // no background bases (Omega_KB from moments)
   D->nbase = D->nbk + D->nbb + 1;
   // planes of a full build: every base, all planes staged from the own
   // workspace; right-hand side only: the science base, and the nK template
-  // planes (shared) followed by the own science plane nK + nB
+  // planes (shared) followed by the own science plane nK
   D->base_lo = rhs_only ? D->nbase - 1 : 0;
-  D->nstaged = rhs_only ? D->nk + 1 : D->nplanes;
+  D->nstaged = D->nplanes;
   D->nshared = rhs_only ? D->nk : D->nplanes;
-  D->plane_skip = rhs_only ? D->nb : 0;
+  D->plane_skip = 0;
   {
     int cursor = 0;
     for (int b = 0; b < D->nbase; ++b) {
@@ -208,7 +215,7 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
               ++cnt;
             }
       } else {
-        D->out_plane[cursor] = (int8_t)(D->nk + D->nb);
+        D->out_plane[cursor] = (int8_t)D->nk;
         D->out_q[cursor] = 0;
         ++cursor;
         cnt = 1;
@@ -220,7 +227,8 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   const int rowmax = d->mode == SFFT_MODE_F64 ? ROW_NMAX_F64 : ROW_NMAX_F32;
   D->rows_per_block = row_pass_rows(rowmax, D->lgPx - 1);   // fixed per transform size (the kernel's own constant)
   D->nrowblk = (d->ny + D->rows_per_block - 1) / D->rows_per_block;
-  D->nmom = (2 * d->db + 1) + (d->db + 1);
+  // per-row moments: (2DB+1) of G, (DB+1) of G S, (DK+DB+1) of G_R R
+  D->nmom = (2 * d->db + 1) + (d->db + 1) + (d->dk + d->db + 1);
   D->nblk = (D->n + NB - 1) / NB;
   monomial_table(d->dk, &D->kpoly);
   monomial_table(d->db, &D->bpoly);
@@ -233,26 +241,38 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   int vrow = 0, wo = 0;
   bool fits = true;   // every table stayed within its capacity
   // planes are numbered 0..nplanes-1; the correlation items name staged planes
-  auto staged = [&](int plane) { return plane >= D->nshared ? plane - D->plane_skip : plane; };
-  auto add_pair = [&](int left, int right, int hw) {
+  // (the transform route stages the template planes and the science plane, nK)
+  auto staged = [&](int plane) { return plane == D->nk + D->nb ? D->nk : plane; };
+  // a window of lags |d| <= hw of planes (left, right): correlation items and
+  // window rows of the transform route (when fft), rows and tiles of the
+  // direct and matrix-core routes (always)
+  auto add_pair = [&](int left, int right, int hw, bool fft) {
     const int h = 2 * hw + 1;
-    for (int j = -hw; j <= hw; j += JMAX) {
+    // items start on the grid -2w + k JMAX of the widest windows (|d| <= 2w),
+    // so that every item has one of their rotations jlo mod P2: an item of a
+    // narrower window accumulates its JMAX rows from such a start and keeps
+    // the rows [skip, nj) that fall inside it
+    for (int j = -2 * d->w; fft && j <= hw; j += JMAX) {
+      const int lo = std::max(j, -hw), hi = std::min(j + JMAX - 1, hw);
+      if (lo > hi) continue;
       CorrItem it;
       it.left = (int16_t)staged(left);
       it.right = (int16_t)staged(right);
       it.jlo = (int16_t)j;
-      it.nj = (int16_t)std::min(JMAX, hw - j + 1);
-      it.vrow = vrow + (j + hw);
+      it.nj = (int16_t)(hi - j + 1);
+      it.vrow = vrow + (j + hw);   // V row of lag row j (rows below skip are never written)
       it.jidx = 0;
-      it.pad_ = 0;
+      it.skip = (int16_t)(lo - j);
       fits &= D->items.push_back(it);
     }
     for (int j = 0; j < h; ++j) {
-      WinRow r;
-      r.vrow = vrow + j;
-      r.out = wo + j * h;
-      r.hw = hw;
-      fits &= D->wrows.push_back(r);
+      if (fft) {
+        WinRow r;
+        r.vrow = vrow + j;
+        r.out = wo + j * h;
+        r.hw = hw;
+        fits &= D->wrows.push_back(r);
+      }
       DirectRow q;
       q.left = (int16_t)left;
       q.right = (int16_t)right;
@@ -271,18 +291,19 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
       fits &= D->mtiles.push_back(t);
     }
     const int off = wo;
-    vrow += h;
+    if (fft) vrow += h;
     wo += h * h;
     return off;
   };
   const int w = d->w;
   if (!rhs_only) {
     for (int a = 0; a < D->nk; ++a)
-      for (int b = a; b < D->nk; ++b) D->gp.kk_off[a * D->nk + b] = add_pair(a, b, 2 * w);
+      for (int b = a; b < D->nk; ++b) D->gp.kk_off[a * D->nk + b] = add_pair(a, b, 2 * w, true);
+    // the template-background windows: direct and matrix-core routes only
     for (int a = 0; a < D->nk; ++a)
-      for (int b = 0; b < D->nb; ++b) D->gp.kb_off[a * D->nb + b] = add_pair(a, D->nk + b, w);
+      for (int b = 0; b < D->nb; ++b) D->gp.kb_off[a * D->nb + b] = add_pair(a, D->nk + b, w, false);
   }
-  for (int a = 0; a < D->nk; ++a) D->gp.ks_off[a] = add_pair(a, D->nk + D->nb, w);
+  for (int a = 0; a < D->nk; ++a) D->gp.ks_off[a] = add_pair(a, D->nk + D->nb, w, true);
   if (!fits) return SFFT_EINVAL;   // more correlation items than the kernels take
   // items sorted by their residue rotation (jlo mod P2) so that a wave of the
   // correlation kernel normally takes a single case of its rotation switch
@@ -460,10 +481,17 @@ Layout layout_of(const Derived& D) {
   {
     const size_t plane = (size_t)(D.ny + 2 * D.w) * (D.nx + 2 * D.w);
     Lo.om_planes = take(D.omask ? (size_t)D.nk * plane * sizeof(double) : 0);
-    Lo.om_cnt = take(D.omask ? (size_t)D.ny * sizeof(int) : 0);
-    Lo.om_offs = take(D.omask ? (size_t)(D.ny + 1) * sizeof(int) : 0);
-    Lo.om_list = take(D.omask ? (size_t)D.ny * D.nx * sizeof(int) : 0);
+    // the excluded-pixel list also serves the template-background block
+    Lo.om_cnt = take((size_t)D.ny * sizeof(int));
+    Lo.om_offs = take((size_t)(D.ny + 1) * sizeof(int));
+    Lo.om_list = take((size_t)D.ny * D.nx * sizeof(int));
   }
+  // template-background block: moments, excluded-pixel partial sums and sums, the block
+  Lo.amom = take((size_t)D.nmu * sizeof(double));
+  Lo.kbpart = take((size_t)KB_CHUNKS * D.nmu * D.L * D.L * sizeof(double));
+  Lo.kbT = take((size_t)D.nmu * D.L * D.L * sizeof(double));
+  Lo.kbd = take((size_t)D.nkk * D.nb * sizeof(double));
+  Lo.kbgrp = take((size_t)(D.ny + 2 * D.w) * (D.nx + 2 * D.w) * (D.mode == SFFT_MODE_F64 ? 8 : 4));
   Lo.total = off;
   return Lo;
 }
@@ -676,6 +704,8 @@ AsmParams asm_params(const sfft_plan_s* p, int64_t ld) {
   A.bpoly = D.bpoly;
   A.nmom = D.nmom;
   A.db = D.db;
+  A.na = D.dk + D.db + 1;
+  A.nmu = D.nmu;
   A.nbase = D.nbase;
   A.nbk = D.nbk;
   A.nbb = D.nbb;
@@ -713,11 +743,93 @@ WsOff ws_offsets(const Derived& D, const Layout& Lo) {
   O.drows = Lo.drows;
   O.mtiles = Lo.mtiles;
   O.theta = Lo.theta;
+  O.amom = Lo.amom;
+  O.kbpart = Lo.kbpart;
+  O.kbT = Lo.kbT;
+  O.kbd = Lo.kbd;
+  O.kbgrp = Lo.kbgrp;
   // the subtraction's x-power spectra, model spectrum and filters reuse the U region
   O.Uq = Lo.U;
   O.Mh = O.Uq + align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>));
   O.G = O.Mh + align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>));
   return O;
+}
+
+KbParams kb_params(const sfft_plan_s* p, int64_t ld) {
+  const Derived& D = p->D;
+  KbParams K;
+  std::memset(&K, 0, sizeof(K));
+  K.ny = D.ny;
+  K.nx = D.nx;
+  K.w = D.w;
+  K.L = D.L;
+  K.nk = D.nk;
+  K.nb = D.nb;
+  K.nkk = D.nkk;
+  K.nmu = D.nmu;
+  K.pitch = D.nx + 2 * D.w;
+  K.ld = ld;
+  K.sx = 2.0 / (double)(D.nx - 1);
+  K.sy = 2.0 / (double)(D.ny - 1);
+  for (int i = 0; i < D.nk; ++i) {
+    K.kpx[i] = D.kpoly.px[i];
+    K.kqy[i] = D.kpoly.qy[i];
+  }
+  for (int i = 0; i < D.nb; ++i) {
+    K.bpx[i] = D.bpoly.px[i];
+    K.bqy[i] = D.bpoly.qy[i];
+  }
+  return K;
+}
+
+OmaskParams om_params(const sfft_plan_s* p, int64_t ld) {
+  const Derived& D = p->D;
+  OmaskParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.ny = D.ny;
+  P.nx = D.nx;
+  P.w = D.w;
+  P.nk = D.nk;
+  P.L = D.L;
+  P.nkk = D.nkk;
+  P.n = D.n;
+  P.pitch = D.nx + 2 * D.w;
+  P.plane = (int64_t)(D.ny + 2 * D.w) * P.pitch;
+  P.ld = ld;
+  P.sx = 2.0 / (double)(D.nx - 1);
+  P.sy = 2.0 / (double)(D.ny - 1);
+  for (int i = 0; i < D.nk; ++i) {
+    P.px[i] = D.kpoly.px[i];
+    P.qy[i] = D.kpoly.qy[i];
+  }
+  P.ntile = (D.nkk + NB - 1) / NB;
+  return P;
+}
+
+OmaskOff om_off(const sfft_plan_s* p) {
+  OmaskOff O;
+  O.planes = p->Lo.om_planes;
+  O.cnt = p->Lo.om_cnt;
+  O.offs = p->Lo.om_offs;
+  O.list = p->Lo.om_list;
+  O.omega = p->Lo.omega;
+  return O;
+}
+
+// The excluded pixels of the np pairs of PS, listed in row-major order
+// (row counts, their prefix, the list).
+int om_list_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
+  const Derived& D = p->D;
+  hipStream_t s = p->stream;
+  const OmaskParams P = om_params(p, ld);
+  const OmaskOff O = om_off(p);
+  om_count_kernel<<<dim3(D.ny, 1, np), 256, 0, s>>>(P, PS, O);
+  LAUNCH_CHECK();
+  om_scan_kernel<<<dim3(1, 1, np), 1024, 0, s>>>(P, PS, O);
+  LAUNCH_CHECK();
+  om_list_kernel<<<dim3(D.ny, 1, np), 256, 0, s>>>(P, PS, O);
+  LAUNCH_CHECK();
+  return SFFT_OK;
 }
 
 // The buffers of one pair on its plan's workspace, as a group of one.
@@ -773,12 +885,20 @@ int gather_impl(sfft_plan_s* p, const AsmParams& A, const PairSet& PS, int np) {
   const WsOff O = ws_offsets(D, p->Lo);
   hipStream_t s = p->stream;
   p->timer.begin(SFFT_STAGE_GATHER, s);
-  moments_reduce_kernel<ASM_THREADS><<<dim3(D.nb * D.nb + D.nb, 1, np), ASM_THREADS, 0, s>>>(A, PS, O);
+  moments_reduce_kernel<ASM_THREADS><<<dim3(D.nb * D.nb + D.nb + D.nmu, 1, np), ASM_THREADS, 0, s>>>(A, PS, O);
   LAUNCH_CHECK();
-  if (D.rhs_only)
-    gather_beta_kernel<<<dim3((D.n + 255) / 256, 1, np), 256, 0, s>>>(D.gp, PS, O);
-  else
-    gather_kernel<<<dim3((D.n + 255) / 256, D.n, np), 256, 0, s>>>(D.gp, PS, O);
+  GatherParams G = D.gp;
+  G.kb_dense = D.route == ROUTE_FFT ? 1 : 0;
+  if (D.rhs_only) {
+    gather_beta_kernel<<<dim3((D.n + 255) / 256, 1, np), 256, 0, s>>>(G, PS, O);
+  } else {
+    if (G.kb_dense) {
+      const KbParams K = kb_params(p, A.ld);
+      kb_combine_kernel<<<dim3((D.nkk * D.nb + 255) / 256, 1, np), 256, 0, s>>>(K, PS, O);
+      LAUNCH_CHECK();
+    }
+    gather_kernel<<<dim3((D.n + 255) / 256, D.n, np), 256, 0, s>>>(G, PS, O);
+  }
   LAUNCH_CHECK();
   p->timer.end(s);
   return SFFT_OK;
@@ -789,45 +909,56 @@ int gather_impl(sfft_plan_s* p, const AsmParams& A, const PairSet& PS, int np) {
 template <typename T>
 int omask_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   const Derived& D = p->D;
-  const Layout& Lo = p->Lo;
   hipStream_t s = p->stream;
-  OmaskParams P;
-  std::memset(&P, 0, sizeof(P));
-  P.ny = D.ny;
-  P.nx = D.nx;
-  P.w = D.w;
-  P.nk = D.nk;
-  P.L = D.L;
-  P.nkk = D.nkk;
-  P.n = D.n;
-  P.pitch = D.nx + 2 * D.w;
-  P.plane = (int64_t)(D.ny + 2 * D.w) * P.pitch;
-  P.ld = ld;
-  P.sx = 2.0 / (double)(D.nx - 1);
-  P.sy = 2.0 / (double)(D.ny - 1);
-  for (int i = 0; i < D.nk; ++i) {
-    P.px[i] = D.kpoly.px[i];
-    P.qy[i] = D.kpoly.qy[i];
-  }
-  P.ntile = (D.nkk + NB - 1) / NB;
-  OmaskOff O;
-  O.planes = Lo.om_planes;
-  O.cnt = Lo.om_cnt;
-  O.offs = Lo.om_offs;
-  O.list = Lo.om_list;
-  O.omega = Lo.omega;
+  const OmaskParams P = om_params(p, ld);
+  const OmaskOff O = om_off(p);
   p->timer.begin(SFFT_STAGE_OUTMASK, s);
   om_planes_kernel<T><<<dim3((unsigned)((P.plane + 255) / 256), D.nk, np), 256, 0, s>>>(P, PS, O);
   LAUNCH_CHECK();
-  om_count_kernel<<<dim3(D.ny, 1, np), 256, 0, s>>>(P, PS, O);
-  LAUNCH_CHECK();
-  om_scan_kernel<<<dim3(1, 1, np), 1024, 0, s>>>(P, PS, O);
-  LAUNCH_CHECK();
-  om_list_kernel<<<dim3(D.ny, 1, np), 256, 0, s>>>(P, PS, O);
-  LAUNCH_CHECK();
+  // the transform route has listed the excluded pixels already (template-background block)
+  if (D.route != ROUTE_FFT) {
+    const int st = om_list_impl(p, PS, np, ld);
+    if (st != SFFT_OK) return st;
+  }
   om_syrk_kernel<<<dim3(P.ntile * (P.ntile + 1) / 2, 1, np), 256, 0, s>>>(P, PS, O);
   LAUNCH_CHECK();
   p->timer.end(s);
+  return SFFT_OK;
+}
+
+// The template-background block of the transform route: excluded-pixel list,
+// the excluded-pixel sums T(c)(u), reduced over the chunks (kb_combine then
+// forms the block in the gather, after the template moments).
+template <typename T>
+int kb_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
+  const Derived& D = p->D;
+  hipStream_t s = p->stream;
+  int st = om_list_impl(p, PS, np, ld);
+  if (st != SFFT_OK) return st;
+  const KbParams K = kb_params(p, ld);
+  const WsOff O = ws_offsets(D, p->Lo);
+  const int L2 = D.L * D.L;
+  {
+    const int64_t np_px = (int64_t)(D.ny + 2 * D.w) * (D.nx + 2 * D.w);
+    kb_plane_kernel<T><<<dim3((unsigned)((np_px + 255) / 256), 1, np), 256, 0, s>>>(K, PS, O);
+    LAUNCH_CHECK();
+  }
+  // one thread per lag, in blocks of whole waves of at most 512 threads
+  const int nth = std::min(KB_MAX_THREADS, ((L2 + 63) / 64) * 64);
+  const dim3 g(KB_CHUNKS, (L2 + nth - 1) / nth, np);
+  switch (D.dk + D.db) {
+#define KB_CASE(DS)                                                                  \
+  case DS:                                                                           \
+    kb_mask_kernel<T, DS><<<g, nth, 0, s>>>(K, PS, O, om_off(p));                    \
+    break;
+    KB_CASE(0) KB_CASE(1) KB_CASE(2) KB_CASE(3) KB_CASE(4) KB_CASE(5) KB_CASE(6) KB_CASE(7) KB_CASE(8)
+#undef KB_CASE
+    default:
+      return SFFT_EINVAL;
+  }
+  LAUNCH_CHECK();
+  kb_reduce_kernel<<<dim3((D.nmu * L2 + 255) / 256, 1, np), 256, 0, s>>>(K, PS, O);
+  LAUNCH_CHECK();
   return SFFT_OK;
 }
 
@@ -939,6 +1070,12 @@ int build_core(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   }
   LAUNCH_CHECK();
   p->timer.end(s);
+  if (!D.rhs_only) {
+    p->timer.begin(SFFT_STAGE_GATHER, s);
+    const int st = kb_impl<T>(p, PS, np, ld);
+    p->timer.end(s);
+    if (st != SFFT_OK) return st;
+  }
   return gather_impl(p, A, PS, np);
 }
 

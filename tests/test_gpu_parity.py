@@ -335,15 +335,17 @@ def test_wide_kernels_and_high_degrees(case, mode):
 
 @pytest.mark.parametrize("mode", [F64, F32C])
 def test_autotune_wide_kernel_against_oracle(mode):
-    """Autotuning a w >= 10 plan (several passes of correlation items, every
-    chunk size the LDS allows) keeps Omega and theta at the oracle bar."""
-    p = synth.random_pair(311, 128, 120, 10, 1, 1, mask_frac=0.05, stars=True)
+    """Autotuning a w >= 10 plan with more correlation items than one pass of
+    the block takes (w = 10, DK = 3: 65 items of one rotation, one lane each,
+    two passes) over every chunk size the LDS allows keeps Omega and theta at
+    the oracle bar."""
+    p = synth.random_pair(311, 256, 240, 10, 3, 1, mask_frac=0.05, stars=True)
     s_in, r_in = inputs_as_seen(p, mode)
     dt = torch.float64 if mode == F64 else torch.float32
     S = torch.from_numpy(s_in).to("cuda", dt)
     R = torch.from_numpy(r_in).to("cuda", dt)
     Mk = torch.from_numpy(p.mask).cuda()
-    ref = oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db, mode="direct")
+    ref = oracle.fit(s_in, r_in, p.mask, p.w, p.dk, p.db, mode="fft")
     plan = B.Plan(*p.sci.shape, p.w, p.dk, p.db, mode=mode, flags=FFT_ROUTE)
     try:
         rep = B.sfft_autotune(plan.handle, S, R, Mk, S.stride(0))
