@@ -198,6 +198,13 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kerne
           const int y = y0 + r;
           const T t0 = tmpl[offs(y, x0)], t1 = tmpl[offs(y, x0 + 1)];
           z = mk(g0 ? (T)(p0 * (double)t0) : (T)0, g1 ? (T)(p1 * (double)t1) : (T)0);
+          if (b == 0 && y < ny) {
+            // G_R R itself into the frame padded by w (the template-background
+            // block's excluded-pixel sums read it; kb_pad_kernel clears the border)
+            T* g = ws_at<T>(PS, pr, O.kbgrp) + (int64_t)(y + w) * (nx + 2 * w) + w;
+            if (x0 < nx) g[x0] = z.x;
+            if (x0 + 1 < nx) g[x0 + 1] = z.y;
+          }
         } else
           z = mk(g0 ? (T)p0 : (T)0, g1 ? (T)p1 : (T)0);
       }
@@ -958,6 +965,8 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet P
     const int i = tid;
     if (i < NG_MAX) {
       if (i < nG) mom[(int64_t)y * P.nmom + i] = v;
+      // sum_x G is the row's count of good pixels: the rest are excluded
+      if (i == 0) ws_at<int>(PS, pr, O.omcnt)[y] = P.nx - (int)(v + 0.5);
     } else if (i < NG_MAX + NS_MAX) {
       if (i - NG_MAX < nS) mom[(int64_t)y * P.nmom + nG + (i - NG_MAX)] = v;
     } else if (i - NG_MAX - NS_MAX < P.na) {

@@ -390,6 +390,7 @@ struct WsOff {
   size_t Ub, U, V, win, mom, obb, bb, omega, beta, kp, flags, tw32, tw64, items, wrows, drows, mtiles, theta;
   size_t Uq, Mh, G;   // the subtraction's buffers (inside the U region)
   size_t amom, kbpart, kbT, kbd, kbgrp;   // template moments and the template-background block
+  size_t omcnt;                            // excluded pixels per image row
 };
 template <typename X>
 __device__ __forceinline__ X* ws_at(const PairSet& S, int pr, size_t off) {

@@ -19,8 +19,9 @@
 // whose cost follows the number of excluded pixels.
 //
 // Kernels (per pair, after the excluded-pixel list of outmask.hpp):
-//   kb_plane   : G_R R on the frame padded by w zeros on every side (the
-//                input type), so that (G_R R)(z - u) is one load;
+//   kb_pad     : the zero border of G_R R on the frame padded by w (the row
+//                pass writes the frame itself, in the input type), so that
+//                (G_R R)(z - u) is one load;
 //   kb_mask    : T(c)(u) partial sums, one block per (chunk of the excluded
 //                pixels, up to 512 lags); the chunks are fixed, so the grid
 //                does not depend on the data;
@@ -52,24 +53,26 @@ __device__ __forceinline__ double kb_binom(int n, int k) {
   return tab[n][k];
 }
 
-// grp = G_R R on the frame padded by w zeros: grp[(y + w) pitch + x + w]
+// The border of the padded frame of G_R R (the row pass writes the frame
+// itself): rows [0, w) and [ny + w, ny + 2w), and columns [0, w) and
+// [nx + w, nx + 2w) of the rows between.
 template <typename T>
-__global__ __launch_bounds__(256) void kb_plane_kernel(KbParams P, PairSet PS, WsOff O) {
+__global__ __launch_bounds__(256) void kb_pad_kernel(KbParams P, PairSet PS, WsOff O) {
   const int pr = blockIdx.z;
-  const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
-  const uint8_t* __restrict__ mask = PS.mask[pr];
   T* __restrict__ grp = ws_at<T>(PS, pr, O.kbgrp);
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)(P.ny + 2 * P.w) * P.pitch) return;
-  const int py = (int)(e / P.pitch), px = (int)(e - (int64_t)py * P.pitch);
-  const int y = py - P.w, x = px - P.w;
-  const bool in = y >= P.w && y < P.ny - P.w && x >= P.w && x < P.nx - P.w;
-  T v = (T)0;
-  if (in) {
-    const int64_t o = (int64_t)y * P.ld + x;
-    if (mask == nullptr || mask[o] == 0) v = tmpl[o];
+  const int64_t nrow = (int64_t)2 * P.w * P.pitch;   // whole border rows
+  if (e < nrow) {
+    const int r = (int)(e / P.pitch), c = (int)(e - (int64_t)r * P.pitch);
+    const int py = r < P.w ? r : P.ny + r;
+    grp[(int64_t)py * P.pitch + c] = (T)0;
+    return;
   }
-  grp[e] = v;
+  const int64_t f = e - nrow;
+  if (f >= (int64_t)2 * P.w * P.ny) return;
+  const int y = (int)(f / (2 * P.w)), c = (int)(f - (int64_t)y * 2 * P.w);
+  const int px = c < P.w ? c : P.nx + c;
+  grp[(int64_t)(y + P.w) * P.pitch + px] = (T)0;
 }
 
 // part[chunk][c][u] = sum over the chunk's excluded pixels z of (G_R R)(z - u) m_c(z),
@@ -117,9 +120,21 @@ __global__ __launch_bounds__(KB_MAX_THREADS) void kb_mask_kernel(KbParams P, Pai
       }
     }
     __syncthreads();
+    // pixels in groups of four: the four loads are issued before their
+    // products (the pixels are still summed one after another, in order)
     const int nsub = min(KB_SUB, k1 - kb);
-    for (int j = 0; j < nsub; ++j) {
-      const double v = (double)grp[spo[j] - uoff];   // zero on the w-strip, at excluded pixels, outside
+    int j = 0;
+    for (; j + 4 <= nsub; j += 4) {
+      double v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t] = (double)grp[spo[j + t] - uoff];   // zero on the w-strip, excluded, outside
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < NMU; ++c) acc[c] = fma(v[t], smo[j + t][c], acc[c]);
+    }
+    for (; j < nsub; ++j) {
+      const double v = (double)grp[spo[j] - uoff];
 #pragma unroll
       for (int c = 0; c < NMU; ++c) acc[c] = fma(v, smo[j][c], acc[c]);
     }

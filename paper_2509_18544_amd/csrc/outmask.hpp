@@ -14,7 +14,8 @@
 // Data flow (one pair, after the zero-filled Omega is assembled):
 //   om_planes : A_a = m_a G_R R in FP64 on frames padded by w zeros on every
 //               side, so that A_a(z - u) is one load without bounds checks;
-//   om_count  : excluded pixels per image row;
+//   (counts)  : excluded pixels per image row, from the build's moments pass
+//               (nx minus the row's sum of G);
 //   om_scan   : row offsets (exclusive prefix), total at offs[ny];
 //   om_list   : padded-frame offsets of the excluded pixels, row-major order;
 //   om_syrk   : one block per 64 x 64 tile of the lower triangle of the
@@ -66,22 +67,6 @@ __global__ __launch_bounds__(256) void om_planes_kernel(OmaskParams P, PairSet P
     v = ipow(xh, P.px[a]) * ipow(yh, P.qy[a]) * (double)tmpl[(int64_t)y * P.ld + x];
   }
   Ap[e] = v;
-}
-
-// excluded pixels of row y (nothing without a mask)
-__global__ __launch_bounds__(256) void om_count_kernel(OmaskParams P, PairSet PS, OmaskOff O) {
-  const int pr = blockIdx.z;
-  const uint8_t* __restrict__ mask = PS.mask[pr];
-  int* __restrict__ cnt = ws_at<int>(PS, pr, O.cnt);
-  __shared__ int red[4];
-  const int y = blockIdx.x, tid = threadIdx.x;
-  int c = 0;
-  if (mask != nullptr)
-    for (int x = tid; x < P.nx; x += 256) c += mask[(int64_t)y * P.ld + x] != 0;
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = c;
-  __syncthreads();
-  if (tid == 0) cnt[y] = red[0] + red[1] + red[2] + red[3];
 }
 
 // exclusive prefix of the row counts: offs[y], and the total at offs[ny]

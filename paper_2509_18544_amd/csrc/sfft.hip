@@ -748,6 +748,7 @@ WsOff ws_offsets(const Derived& D, const Layout& Lo) {
   O.kbT = Lo.kbT;
   O.kbd = Lo.kbd;
   O.kbgrp = Lo.kbgrp;
+  O.omcnt = Lo.om_cnt;
   // the subtraction's x-power spectra, model spectrum and filters reuse the U region
   O.Uq = Lo.U;
   O.Mh = O.Uq + align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>));
@@ -816,15 +817,14 @@ OmaskOff om_off(const sfft_plan_s* p) {
   return O;
 }
 
-// The excluded pixels of the np pairs of PS, listed in row-major order
-// (row counts, their prefix, the list).
+// The excluded pixels of the np pairs of PS, listed in row-major order (the
+// row counts come from the moments pass of the build: their prefix, then the
+// list).
 int om_list_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   const Derived& D = p->D;
   hipStream_t s = p->stream;
   const OmaskParams P = om_params(p, ld);
   const OmaskOff O = om_off(p);
-  om_count_kernel<<<dim3(D.ny, 1, np), 256, 0, s>>>(P, PS, O);
-  LAUNCH_CHECK();
   om_scan_kernel<<<dim3(1, 1, np), 1024, 0, s>>>(P, PS, O);
   LAUNCH_CHECK();
   om_list_kernel<<<dim3(D.ny, 1, np), 256, 0, s>>>(P, PS, O);
@@ -939,9 +939,11 @@ int kb_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   const WsOff O = ws_offsets(D, p->Lo);
   const int L2 = D.L * D.L;
   {
-    const int64_t np_px = (int64_t)(D.ny + 2 * D.w) * (D.nx + 2 * D.w);
-    kb_plane_kernel<T><<<dim3((unsigned)((np_px + 255) / 256), 1, np), 256, 0, s>>>(K, PS, O);
-    LAUNCH_CHECK();
+    const int64_t nb_px = (int64_t)2 * D.w * (D.nx + 2 * D.w) + (int64_t)2 * D.w * D.ny;
+    if (nb_px > 0) {
+      kb_pad_kernel<T><<<dim3((unsigned)((nb_px + 255) / 256), 1, np), 256, 0, s>>>(K, PS, O);
+      LAUNCH_CHECK();
+    }
   }
   // one thread per lag, in blocks of whole waves of at most 512 threads
   const int nth = std::min(KB_MAX_THREADS, ((L2 + 63) / 64) * 64);
