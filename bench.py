@@ -241,8 +241,9 @@ def shape_info(p):
     nk = (p.dk + 1) * (p.dk + 2) // 2
     nb = (p.db + 1) * (p.db + 2) // 2
     L = 2 * p.w + 1
-    return dict(N=n, P=P, nk=nk, nb=nb, w=p.w, ncoef=L * L * nk + nb, nbase=p.dk + p.db + 3,
-                nplanes=nk + nb + 1)
+    # the transform route: bases xh^p G_R R (p <= DK) and G S; planes A_a and S_m
+    return dict(N=n, P=P, nk=nk, nb=nb, w=p.w, ncoef=L * L * nk + nb, nbase=p.dk + 2,
+                nplanes=nk + 1)
 
 
 def stage_cost(stage, D, mode_f64):
@@ -251,7 +252,9 @@ def stage_cost(stage, D, mode_f64):
     Bytes count each algorithmic read or write once.  The correlation stage
     is priced in flops: per lag-window pair and residue k1, the P2 = 16
     spectral products (6 flops each), one 16-point inverse DFT (168 flops) and
-    8 flops per lag row kept; the pair count and lag rows follow the fit.
+    8 flops per lag row kept; the pairs are the template-template windows
+    (|d| <= 2w) and the template-science windows (|d| <= w) -- the
+    template-background block is formed from moments, not correlations.
     """
     n, P, H, planes = D["N"], D["P"], D["P"] // 2, D["nplanes"]
     s = 8 if mode_f64 else 4
@@ -267,7 +270,7 @@ def stage_cost(stage, D, mode_f64):
     if stage == "corr":
         residues = P // 16
         kk = nk * (nk + 1) // 2
-        per_res = kk * (96 + 168 + 8 * (4 * w + 1)) + (nk * nb + nk) * (96 + 168 + 8 * (2 * w + 1))
+        per_res = kk * (96 + 168 + 8 * (4 * w + 1)) + nk * (96 + 168 + 8 * (2 * w + 1))
         return "alu", float(per_res) * residues * (H + 1)
     if stage == "subtract":
         return "hbm", 3 * n * n * s
@@ -279,11 +282,11 @@ def stage_cost(stage, D, mode_f64):
 
 def path_bytes(D, mode_f64):
     """Algorithmic HBM bytes of one whole pair: inputs read once and D written once,
-    every spectrum (the forward planes plus the apply's one) written and read once,
-    Omega gathered, factored and read."""
+    every spectrum (the nK + 1 forward planes plus the apply's one) written and
+    read once, Omega gathered, factored and read."""
     n, P = D["N"], D["P"]
     s = 8 if mode_f64 else 4
-    nplanes = 2 * D["nk"] + D["nb"] + 2
+    nplanes = D["nk"] + 2
     return 3 * n * n * s + n * n + 2 * nplanes * P * (P // 2 + 1) * 2 * s + 4 * D["ncoef"] ** 2 * 8
 
 
