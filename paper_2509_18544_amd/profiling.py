@@ -61,15 +61,20 @@ def pmc(path: str, regex: str) -> None:
         print(f"{name:80s} {counter:14s} dispatches={len(vals):4d} avg_per_dispatch={sum(vals) / len(vals):.4g}")
 
 
-def trace_avg(path: str, regex: str, last: int) -> None:
-    """Average device time of the last `last` dispatches of the kernels matching regex
-    (the timed region of a run whose earlier dispatches were warm-up or tuning)."""
+def trace_avg(path: str, regex: str, last: int, min_us: float = 0.0) -> None:
+    """Average device time of the dispatches of the kernels matching regex: the
+    last `last` of them (the timed region of a run whose earlier dispatches were
+    warm-up or tuning), and those lasting at least `min_us` (the batch launches
+    of a run that also makes single-pair launches)."""
     rows = [r for r in csv.DictReader(open(path)) if re.search(regex, r["Kernel_Name"])]
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
     tail = d[-last:] if last > 0 else d
     print(f"{regex}: {len(d)} dispatches, all avg {sum(d) / max(1, len(d)):.1f} us; "
           f"last {len(tail)} avg {sum(tail) / max(1, len(tail)):.1f} us")
+    if min_us > 0:
+        big = [x for x in d if x >= min_us]
+        print(f"{regex}: {len(big)} dispatches of at least {min_us:.0f} us, avg {sum(big) / max(1, len(big)):.1f} us")
 
 
 def traffic(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str, regex: str,
@@ -112,6 +117,7 @@ def main(argv=None) -> None:
     t.add_argument("csv")
     t.add_argument("regex")
     t.add_argument("--last", type=int, default=0)
+    t.add_argument("--min-us", type=float, default=0.0)
     tr = sub.add_parser("traffic")
     tr.add_argument("fetch_csv")
     tr.add_argument("write_csv")
@@ -125,7 +131,7 @@ def main(argv=None) -> None:
     elif a.cmd == "stats":
         stats(a.csv, a.top)
     elif a.cmd == "trace":
-        trace_avg(a.csv, a.regex, a.last)
+        trace_avg(a.csv, a.regex, a.last, a.min_us)
     elif a.cmd == "traffic":
         traffic(a.fetch_csv, a.write_csv, a.copy_fetch_csv, a.copy_write_csv, a.regex, a.copy_mib)
     else:
