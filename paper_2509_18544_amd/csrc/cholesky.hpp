@@ -246,16 +246,21 @@ __global__ __launch_bounds__(256) void trsm_kernel(const SolveJob* __restrict__ 
       }
 }
 
-// Lower tiles (I >= J) of the trailing matrix: A_IJ -= L_I L_J^T.  With
-// fuse_diag, the first njobs blocks take tile (0, 0) of each job -- the next
-// diagonal block -- and factor it as soon as it is updated (look-ahead: the
-// factorisation of step k + 1 runs while the rest of step k's update does);
-// the other blocks take the remaining tiles, ntile - 1 per job.  Without it,
-// one block per (job, tile).  Both through xcd_remap: an XCD takes a
-// contiguous run of tiles, so tiles of one row I (sharing the panel L_I) and
-// of neighbouring rows find the panels in its L2.
+// Lower tiles (I >= J) of the trailing matrix after the npanel panels of
+// block columns k .. k + npanel - 1 (rows from t0 = (k + npanel) NB):
+// A_IJ -= sum over the panels of L_I L_J^T.  Two panels (a rank-128 update)
+// read and write the trailing matrix once for two block steps.  With colonly,
+// only the tiles (I, 0) of the first block column (one panel): the column a
+// two-panel step needs updated and factored before its second panel solve.
+// With fuse_diag, the first njobs blocks take tile (0, 0) of each job -- the
+// next diagonal block -- and factor it as soon as it is updated (look-ahead:
+// the next factorisation step runs while the rest of the update does); the
+// other blocks take the remaining tiles, ntile - 1 per job.  Without it, one
+// block per (job, tile).  Both through xcd_remap: an XCD takes a contiguous
+// run of tiles, so tiles of one row I (sharing the panel L_I) and of
+// neighbouring rows find the panels in its L2.
 __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ jobs, int k, int njobs, int ntile,
-                                                   int fuse_diag) {
+                                                   int fuse_diag, int npanel, int colonly) {
   __shared__ double A[NB][NB + 1];
   __shared__ double B[NB][NB + 1];
   __shared__ int sflag[2];
@@ -278,50 +283,64 @@ __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ 
     b = id - jb * ntile;
   }
   const SolveJob job = jobs[jb];
-  if (k >= job.nblk - 1 || *job.info != 0) return;
+  if (k + npanel >= job.nblk || *job.info != 0) return;   // no trailing matrix for this job
   double* __restrict__ F = job.F;
   const int n = job.n;
   const int k0 = k * NB;
-  {
-    const int T = job.nblk - k - 1;
-    if (b >= T * (T + 1) / 2) return;
-  }
+  const int T = job.nblk - k - npanel;   // trailing block rows
+  if (colonly ? b >= T : b >= T * (T + 1) / 2) return;
   const int tid = threadIdx.x;
-  const int nb = min(NB, n - k0);
-  const int t0 = k0 + NB;  // first trailing row
-  // triangular tile enumeration: b = I (I+1)/2 + J
-  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= b) ++I;
-  while (I * (I + 1) / 2 > b) --I;
-  const int J = b - I * (I + 1) / 2;
+  const int t0 = k0 + npanel * NB;  // first trailing row
+  // triangular tile enumeration: b = I (I+1)/2 + J (colonly: I = b, J = 0)
+  int I = b, J = 0;
+  if (!colonly) {
+    I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    while (I * (I + 1) / 2 > b) --I;
+    J = b - I * (I + 1) / 2;
+  }
   const int ri = t0 + I * NB, rj = t0 + J * NB;
   const int ni = min(NB, n - ri), nj = min(NB, n - rj);
   if (ni <= 0 || nj <= 0) return;
-  {
-    // every load of the thread is issued (clamped into the panels) before any is stored
-    constexpr int PER = NB * NB / 256;
-    double av[PER], bv[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * 256;
-      const int i = e / NB, m = min(e % NB, nb - 1);
-      av[q] = F[(int64_t)(ri + min(i, ni - 1)) * n + k0 + m];
-      bv[q] = F[(int64_t)(rj + min(i, nj - 1)) * n + k0 + m];
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * 256;
-      const int i = e / NB, m = e % NB;
-      A[i][m] = (i < ni && m < nb) ? av[q] : 0.0;
-      B[i][m] = (i < nj && m < nb) ? bv[q] : 0.0;
-    }
-  }
-  __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
   f64x4 acc[2][2];
-  tile_abt(A, B, wm, wn, lr, lk, acc);
+  for (int pa = 0; pa < npanel; ++pa) {
+    const int c0 = k0 + pa * NB;   // the panel's columns (a full block: the trailing matrix lies beyond it)
+    const int nb = min(NB, n - c0);
+    if (pa > 0) __syncthreads();   // the previous panel's tiles have been read
+    {
+      // every load of the thread is issued (clamped into the panels) before any is stored
+      constexpr int PER = NB * NB / 256;
+      double av[PER], bv[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * 256;
+        const int i = e / NB, m = min(e % NB, nb - 1);
+        av[q] = F[(int64_t)(ri + min(i, ni - 1)) * n + c0 + m];
+        bv[q] = F[(int64_t)(rj + min(i, nj - 1)) * n + c0 + m];
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * 256;
+        const int i = e / NB, m = e % NB;
+        A[i][m] = (i < ni && m < nb) ? av[q] : 0.0;
+        B[i][m] = (i < nj && m < nb) ? bv[q] : 0.0;
+      }
+    }
+    __syncthreads();
+    if (pa == 0) {
+      tile_abt(A, B, wm, wn, lr, lk, acc);
+    } else {
+      f64x4 acc2[2][2];
+      tile_abt(A, B, wm, wn, lr, lk, acc2);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = acc[a][c] + acc2[a][c];
+    }
+  }
   // read-modify-write of the tile: the reads are unconditional (clamped) so
   // that they are all in flight together; only the stores are predicated
   double fv[2][2][4];
@@ -355,7 +374,7 @@ __global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) A[wm + 16 * a + lk + 4 * r][wn + 16 * c + lr] = fv[a][c][r] - acc[a][c][r];
   __syncthreads();
-  const int f = potrf_block64(A, B[0], B[1], B[2], sflag, ni, F, n, ri, job.Linv + (size_t)(k + 1) * NB * NB);
+  const int f = potrf_block64(A, B[0], B[1], B[2], sflag, ni, F, n, ri, job.Linv + (size_t)(k + npanel) * NB * NB);
   if (f != 0 && tid == 0) *job.info = ri + f;
 }
 

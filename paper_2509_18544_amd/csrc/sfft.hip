@@ -1105,17 +1105,37 @@ int solve_jobs(hipStream_t s, const SolveTable& T, int max_n, int max_nblk, int 
     copy_omega_kernel<<<g, 256, 0, s>>>(jobs);
     LAUNCH_CHECK();
   }
-  // diagonal block 0; block k + 1 is factored inside the trailing update of step k
+  // diagonal block 0; each next diagonal block is factored inside the
+  // trailing update that completes it.  Block steps go in pairs: panel k,
+  // the update of block column k + 1 alone (and its factor), panel k + 1,
+  // then one rank-128 update of the rest with both panels (the trailing
+  // matrix is read and written once per two steps); a last odd step alone.
   potrf_diag_kernel<<<njobs, 256, 0, s>>>(jobs, 0);
   LAUNCH_CHECK();
-  for (int k = 0; k + 1 < max_nblk; ++k) {
-    const int T1 = max_nblk - k - 1;
-    trsm_kernel<<<dim3(T1, njobs), 256, 0, s>>>(jobs, k);
-    LAUNCH_CHECK();
-    const int ntile = T1 * (T1 + 1) / 2;
+  auto syrk = [&](int k, int npanel, int colonly) -> int {
+    const int T = max_nblk - k - npanel;
+    const int ntile = colonly ? T : T * (T + 1) / 2;
     const int grid = njobs + ((njobs * (ntile - 1) + 7) / 8) * 8;   // diagonal blocks, then whole XCD rounds
-    syrk_kernel<<<grid, 256, 0, s>>>(jobs, k, njobs, ntile, 1);
+    syrk_kernel<<<grid, 256, 0, s>>>(jobs, k, njobs, ntile, 1, npanel, colonly);
     LAUNCH_CHECK();
+    return SFFT_OK;
+  };
+  for (int k = 0; k + 1 < max_nblk;) {
+    trsm_kernel<<<dim3(max_nblk - k - 1, njobs), 256, 0, s>>>(jobs, k);
+    LAUNCH_CHECK();
+    if (k + 2 < max_nblk) {
+      int st = syrk(k, 1, 1);
+      if (st != SFFT_OK) return st;
+      trsm_kernel<<<dim3(max_nblk - k - 2, njobs), 256, 0, s>>>(jobs, k + 1);
+      LAUNCH_CHECK();
+      st = syrk(k, 2, 0);
+      if (st != SFFT_OK) return st;
+      k += 2;
+    } else {
+      const int st = syrk(k, 1, 0);
+      if (st != SFFT_OK) return st;
+      k += 1;
+    }
   }
   tm->end(s);
   tm->begin(SFFT_STAGE_SOLVE, s);
