@@ -35,7 +35,13 @@ namespace sfft {
 
 constexpr int P2 = 16;        // inner (register) transform length of the pruned inverse
 constexpr int LG_P2 = 4;
-constexpr int JMAX = 19;      // lag rows handled per correlation work item
+// lag rows per correlation work item: JROWS_WIDE when the template-template
+// windows (4w + 1 rows) are wider than JROWS_NARROW, so that one item covers
+// a whole window up to w = 9 and every item shares the rotation of -2w;
+// JROWS_NARROW otherwise (fewer accumulators left idle)
+constexpr int JROWS_NARROW = 19;
+constexpr int JROWS_WIDE = 37;
+constexpr int JMAX = JROWS_WIDE;   // the largest
 constexpr int MAX_DEG = 4;    // polynomial degree limit for DK and DB
 constexpr int MAX_NB = (MAX_DEG + 1) * (MAX_DEG + 2) / 2;   // 15 monomials
 constexpr int MAX_PLANES = 2 * MAX_NB + 1;
@@ -49,7 +55,7 @@ struct PolyTab {
 // One correlation work item: lag rows [jlo, jlo + nj) of pair (left, right).
 struct CorrItem {
   int16_t left, right;   // plane indices
-  int16_t jlo, nj;       // first lag row (signed) and count (<= JMAX)
+  int16_t jlo, nj;       // first lag row (signed) and count (<= the plan's rows per item)
   int32_t vrow;          // row in V where lag row jlo goes
   int16_t jidx;          // index of jlo in the list of distinct first lag rows
   int16_t skip;          // the first `skip` lag rows are accumulated but not kept
@@ -378,23 +384,24 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kerne
 // planes, over the LDS banks instead of piling them on one bank quad.
 constexpr int CORR_RS = P2 + 1;
 constexpr int CORR_LB = 8;   // staging loads in flight per thread
+constexpr int CORR_RED_ROWS = 10;   // lag rows per part of the lanes' reduction
 __host__ __device__ constexpr int corr_plane_stride(int c1) {
   return ((c1 * CORR_RS + 12) & ~15) + 3;
 }
 // complex elements reserved at the start of the correlation kernel's LDS for
-// the per-chunk twiddle steps (njlo x JMAX), rounded up to 256 bytes
-__host__ __device__ constexpr int corr_step_elems(int njlo) { return (njlo * JMAX + 15) & ~15; }
+// the per-chunk twiddle steps (njlo x jm), rounded up to 256 bytes
+__host__ __device__ constexpr int corr_step_elems(int njlo, int jm) { return (njlo * jm + 15) & ~15; }
 
-template <int S>
+template <int S, int JM>
 __device__ __forceinline__ void corr_accumulate(cplx<double>* acc, const cplx<double>* f,
                                                 const cplx<double>* __restrict__ tw) {
-  // all JMAX rows are accumulated (rows past the item's count are never written out);
+  // all JM rows are accumulated (rows past the item's count are never written out);
   // four FMAs per complex multiply-add
 #pragma unroll
-  for (int t = 0; t < JMAX; ++t) acc[t] = cmac(acc[t], tw[t], f[(S + t) & (P2 - 1)]);
+  for (int t = 0; t < JM; ++t) acc[t] = cmac(acc[t], tw[t], f[(S + t) & (P2 - 1)]);
 }
 
-template <typename T, int THREADS>
+template <typename T, int THREADS, int JM>
 __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet PS, WsOff O, int C1, int C1dc) {
   const int pr = blockIdx.z;
   const cplx<T>* __restrict__ U = ws_at<const cplx<T>>(PS, pr, O.U);
@@ -403,11 +410,11 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
   cplx<double>* __restrict__ V = ws_at<cplx<double>>(PS, pr, O.V);
   const cplx<double>* __restrict__ twd = ws_at<const cplx<double>>(PS, pr, O.tw64);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // LDS: [twstep: njlo x JMAX] [stage: spectra, then the chunk's outer twiddles].
+  // LDS: [twstep: njlo x JM] [stage: spectra, then the chunk's outer twiddles].
   // The lane reduction at the end of a pass of items overlays the stage only,
   // so the steps survive into the next pass.
-  cplx<double>* twstep = reinterpret_cast<cplx<double>*>(smem_raw);   // [njlo][JMAX]
-  cplx<double>* stage = twstep + corr_step_elems(P.njlo);
+  cplx<double>* twstep = reinterpret_cast<cplx<double>*>(smem_raw);   // [njlo][JM]
+  cplx<double>* stage = twstep + corr_step_elems(P.njlo, JM);
   const int kx = blockIdx.x;
   const bool pk = kx == 0;                     // the DC and Nyquist columns, packed
   const int H = P.H;
@@ -424,10 +431,10 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
   const int nst = pk ? 2 * P.nstaged : P.nstaged;   // staged planes (block 0: column 0, then column H)
   const int per_plane = corr_plane_stride(C);
   // outer twiddles e^{2 pi i k1 (jlo + t)/Py} of the chunk, per distinct jlo, after the spectra
-  cplx<double>* twc = stage + nst * per_plane;              // [njlo][C][JMAX]
+  cplx<double>* twc = stage + nst * per_plane;              // [njlo][C][JM]
   // e^{2 pi i C j / Py}: advancing k1 by one chunk multiplies each outer twiddle by it
-  for (int e = tid; e < P.njlo * JMAX; e += THREADS) {
-    const int ji = e / JMAX, t = e - ji * JMAX;
+  for (int e = tid; e < P.njlo * JM; e += THREADS) {
+    const int ji = e / JM, t = e - ji * JM;
     const int m = (C * ((int)P.jlo_list[ji] + t)) & (Py - 1);
     twstep[e] = conjg(twd[m << (TW_LOG - lgPy)]);
   }
@@ -446,9 +453,9 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
     it.vrow = 0;
     if (active) it = items[item_id];
     const int srot = ((int)it.jlo % P2 + P2) % P2;
-    cplx<double> acc[JMAX];
+    cplx<double> acc[JM];
 #pragma unroll
-    for (int t = 0; t < JMAX; ++t) acc[t] = mk(0.0, 0.0);
+    for (int t = 0; t < JM; ++t) acc[t] = mk(0.0, 0.0);
 
     for (int k1c = 0; k1c < P1; k1c += C) {
       const int nc = min(C, P1 - k1c);
@@ -504,21 +511,27 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
       // so the index is the product masked to [0, Py)), then by the FP64 step
       for (int ji = 0; ji < P.njlo; ++ji) {
         const int jlo = P.jlo_list[ji];
-        for (int r = tid; r < C * JMAX; r += THREADS) {
-          const int t = r % JMAX;
-          cplx<double>& w = twc[ji * C * JMAX + r];
+        int r0 = tid;
+        asm volatile("" : "+v"(r0));
+        for (int r = r0; r < C * JM; r += THREADS) {
+          const int t = r % JM;
+          cplx<double>& w = twc[ji * C * JM + r];
           if (k1c == 0) {
-            const int c = r / JMAX;
+            const int c = r / JM;
             const int m = (c * (jlo + t)) & (Py - 1);
             w = conjg(twd[m << (TW_LOG - lgPy)]);
           } else {
-            w = w * twstep[ji * JMAX + t];
+            w = w * twstep[ji * JM + t];
           }
         }
       }
       __syncthreads();
       if (!active) continue;
-      for (int c = lane; c < nc; c += lanes) {
+      // the item lane is formed again per chunk (from an opaque thread index)
+      // instead of being held across the staging
+      int tl = tid;
+      asm volatile("" : "+v"(tl));
+      for (int c = (tl & 63) % lanes; c < nc; c += lanes) {
         const int k1 = k1c + c;
         const cplx<double>* xa = stage + it.left * per_plane + c * CORR_RS;
         const cplx<double>* xb = stage + it.right * per_plane + c * CORR_RS;
@@ -533,12 +546,12 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
           for (int k2 = 0; k2 < P2; ++k2) z[k2] = z[k2] + rot90<double, true>(cmulc(ya[k2], yb[k2]));
         }
         dft16<double, true>(z);
-        const cplx<double>* twt = twc + ((int)it.jidx * C + c) * JMAX;
+        const cplx<double>* twt = twc + ((int)it.jidx * C + c) * JM;
         (void)k1;
         switch (srot) {
 #define CORR_CASE(SV) \
   case SV:            \
-    corr_accumulate<SV>(acc, z, twt); \
+    corr_accumulate<SV, JM>(acc, z, twt); \
     break;
           CORR_CASE(0) CORR_CASE(1) CORR_CASE(2) CORR_CASE(3) CORR_CASE(4) CORR_CASE(5) CORR_CASE(6) CORR_CASE(7)
           CORR_CASE(8) CORR_CASE(9) CORR_CASE(10) CORR_CASE(11) CORR_CASE(12) CORR_CASE(13) CORR_CASE(14)
@@ -547,29 +560,37 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
         }
       }
     }
-    // sum the lanes of each item through LDS, in two halves of the lag rows
+    // sum the lanes of each item through LDS, CORR_RED_ROWS lag rows at a time
     // (over the staged spectra, which are dead until the next pass restages them)
     cplx<double>* red = stage;
-    constexpr int HALF = (JMAX + 1) / 2;
+    constexpr int HALF = CORR_RED_ROWS;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < (JM + HALF - 1) / HALF; ++h) {
+      // the thread index and the item go through an empty asm, so that their
+      // addresses and fields are formed here rather than hoisted to the
+      // kernel's start and held (spilled) across the residue loop
+      int tr = tid;
+      asm volatile("" : "+v"(tr));
+      const int ir = min((wbase + (tr >> 6)) * ipw + (tr & 63) / lanes, nitems - 1);   // item_id
+      cplx<double>* mine = red + tr * HALF;
       __syncthreads();
       if (active) {
 #pragma unroll
         for (int t = 0; t < HALF; ++t) {
           const int tt = h * HALF + t;
-          if (tt < JMAX) red[tid * HALF + t] = acc[tt];
+          if (tt < JM) mine[t] = acc[tt];
         }
       }
       __syncthreads();
       if (active && lane == 0) {
+        const CorrItem iv = items[ir];
         for (int t = 0; t < HALF; ++t) {
           const int tt = h * HALF + t;
-          if (tt >= it.nj) break;
-          if (tt < it.skip) continue;
+          if (tt >= iv.nj) break;
+          if (tt < iv.skip) continue;
           cplx<double> sum = mk(0.0, 0.0);
-          for (int l = 0; l < lanes; ++l) sum = sum + red[(tid + l) * HALF + t];
-          V[(int64_t)kx * P.vrows + it.vrow + tt] = sum;
+          for (int l = 0; l < lanes; ++l) sum = sum + mine[l * HALF + t];
+          V[(int64_t)kx * P.vrows + iv.vrow + tt] = sum;
         }
       }
     }

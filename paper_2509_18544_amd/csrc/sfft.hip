@@ -98,6 +98,7 @@ struct Derived {
   int nmom;
   int nitems, vrows, nwin, nblk;
   int corr_lanes;
+  int jrows;   // lag rows per correlation item (JROWS_NARROW or JROWS_WIDE)
   int njlo;
   int16_t jlo_list[MAX_JLO];
   size_t csize;   // sizeof complex element of the transforms
@@ -233,7 +234,8 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   monomial_table(d->dk, &D->kpoly);
   monomial_table(d->db, &D->bpoly);
 
-  // correlation pairs -> items (lag rows in chunks of JMAX), window rows, gather offsets
+  // correlation pairs -> items (lag rows in chunks of jrows), window rows, gather offsets
+  D->jrows = 4 * d->w + 1 > JROWS_NARROW ? JROWS_WIDE : JROWS_NARROW;
   D->items.clear();
   D->wrows.clear();
   D->drows.clear();
@@ -248,12 +250,12 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   // direct and matrix-core routes (always)
   auto add_pair = [&](int left, int right, int hw, bool fft) {
     const int h = 2 * hw + 1;
-    // items start on the grid -2w + k JMAX of the widest windows (|d| <= 2w),
+    // items start on the grid -2w + k jrows of the widest windows (|d| <= 2w),
     // so that every item has one of their rotations jlo mod P2: an item of a
-    // narrower window accumulates its JMAX rows from such a start and keeps
+    // narrower window accumulates its jrows rows from such a start and keeps
     // the rows [skip, nj) that fall inside it
-    for (int j = -2 * d->w; fft && j <= hw; j += JMAX) {
-      const int lo = std::max(j, -hw), hi = std::min(j + JMAX - 1, hw);
+    for (int j = -2 * d->w; fft && j <= hw; j += D->jrows) {
+      const int lo = std::max(j, -hw), hi = std::min(j + D->jrows - 1, hw);
       if (lo > hi) continue;
       CorrItem it;
       it.left = (int16_t)staged(left);
@@ -844,12 +846,12 @@ PairSet pair_set_one(const sfft_plan_s* p, const void* sci, const void* tmpl, co
 // lane-reduction buffer that overlays them.
 int corr_dc_chunk(int C1) { return std::max(1, C1 / 2); }
 size_t corr_lds_bytes(const Derived& D, int C1) {
-  const size_t steps = (size_t)corr_step_elems(D.njlo) * sizeof(cplx<double>);
+  const size_t steps = (size_t)corr_step_elems(D.njlo, D.jrows) * sizeof(cplx<double>);
   const int cd = corr_dc_chunk(C1);
-  const size_t stage = ((size_t)D.nstaged * corr_plane_stride(C1) + (size_t)D.njlo * C1 * JMAX) * sizeof(cplx<double>);
+  const size_t stage = ((size_t)D.nstaged * corr_plane_stride(C1) + (size_t)D.njlo * C1 * D.jrows) * sizeof(cplx<double>);
   const size_t stage_dc =
-      ((size_t)2 * D.nstaged * corr_plane_stride(cd) + (size_t)D.njlo * cd * JMAX) * sizeof(cplx<double>);
-  const size_t red = (size_t)ASM_THREADS * ((JMAX + 1) / 2) * sizeof(cplx<double>);
+      ((size_t)2 * D.nstaged * corr_plane_stride(cd) + (size_t)D.njlo * cd * D.jrows) * sizeof(cplx<double>);
+  const size_t red = (size_t)ASM_THREADS * CORR_RED_ROWS * sizeof(cplx<double>);
   return steps + std::max(std::max(stage, stage_dc), red);
 }
 
@@ -870,7 +872,7 @@ int launch_corr(sfft_plan_s* p, const AsmParams& A, const PairSet& PS, int np, i
   const Derived& D = p->D;
   hipStream_t s = p->stream;
   const size_t lds = corr_lds_bytes(D, C1);
-  auto kfn = corr_kernel<T, ASM_THREADS>;
+  auto kfn = D.jrows == JROWS_WIDE ? corr_kernel<T, ASM_THREADS, JROWS_WIDE> : corr_kernel<T, ASM_THREADS, JROWS_NARROW>;
   HIP_TRY(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (timed) p->timer.begin(SFFT_STAGE_CORR, s);
   kfn<<<dim3(D.H, 1, np), ASM_THREADS, lds, s>>>(A, PS, ws_offsets(D, p->Lo), C1, corr_dc_chunk(C1));
