@@ -379,14 +379,17 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void col_fwd_kerne
 // threads that split the residues; at the end the lanes are summed in LDS.
 // Products, the inner transform and the accumulation are FP64 in both modes.
 // Staged spectra: residue c of plane pl at stage[pl * corr_plane_stride(C1) + c * CORR_RS].
-// The padded strides (17 complex values per residue, plane stride = 3 mod 16)
-// spread the 16-byte reads of a wave, whose lanes take different residues and
-// planes, over the LDS banks instead of piling them on one bank quad.
+// The padded strides spread the 16-byte reads of a wave, whose lanes take
+// different residues and planes, over the LDS banks: 17 complex values per
+// residue put the residues c of one plane on consecutive 16-byte slots (mod
+// 16), and a plane stride of 9 mod 16 slots keeps the 9 residues that the
+// lanes of one item read from overlapping those of the next item's plane
+// (neighbouring items mostly read neighbouring planes).
 constexpr int CORR_RS = P2 + 1;
 constexpr int CORR_LB = 8;   // staging loads in flight per thread
 constexpr int CORR_RED_ROWS = 10;   // lag rows per part of the lanes' reduction
 __host__ __device__ constexpr int corr_plane_stride(int c1) {
-  return ((c1 * CORR_RS + 12) & ~15) + 3;
+  return ((c1 * CORR_RS + 12) & ~15) + 9;
 }
 // complex elements reserved at the start of the correlation kernel's LDS for
 // the per-chunk twiddle steps (njlo x jm), rounded up to 256 bytes
