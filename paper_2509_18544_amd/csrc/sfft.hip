@@ -235,7 +235,10 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   monomial_table(d->db, &D->bpoly);
 
   // correlation pairs -> items (lag rows in chunks of jrows), window rows, gather offsets
-  D->jrows = 4 * d->w + 1 > JROWS_NARROW ? JROWS_WIDE : JROWS_NARROW;
+  // the widest windows: the template-template ones (|d| <= 2w), or in a
+  // right-hand-side-only plan the template-science ones (|d| <= w)
+  const int wmax = rhs_only ? d->w : 2 * d->w;
+  D->jrows = 2 * wmax + 1 > JROWS_NARROW ? JROWS_WIDE : JROWS_NARROW;
   D->items.clear();
   D->wrows.clear();
   D->drows.clear();
@@ -250,11 +253,11 @@ int derive(const sfft_desc* d, Derived* D, bool rhs_only = false) {
   // direct and matrix-core routes (always)
   auto add_pair = [&](int left, int right, int hw, bool fft) {
     const int h = 2 * hw + 1;
-    // items start on the grid -2w + k jrows of the widest windows (|d| <= 2w),
+    // items start on the grid -wmax + k jrows of the widest windows (|d| <= wmax),
     // so that every item has one of their rotations jlo mod P2: an item of a
     // narrower window accumulates its jrows rows from such a start and keeps
     // the rows [skip, nj) that fall inside it
-    for (int j = -2 * d->w; fft && j <= hw; j += D->jrows) {
+    for (int j = -wmax; fft && j <= hw; j += D->jrows) {
       const int lo = std::max(j, -hw), hi = std::min(j + D->jrows - 1, hw);
       if (lo > hi) continue;
       CorrItem it;
