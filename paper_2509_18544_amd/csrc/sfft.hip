@@ -446,7 +446,7 @@ Layout layout_of(const Derived& D) {
     // the subtraction's spectra reuse the assembly's spectra region (not live at the same time)
     const size_t asm_bytes = (size_t)D.nplanes * (D.H + 1) * D.Py * D.csize;
     // x-power spectra, model spectrum and filters G (FP64)
-    const size_t sub_bytes = align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>)) +
+    const size_t sub_bytes = align256(sub_xpow_off(D.dk + 1, D.ny, D.H, 0)) +
                              align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>)) +
                              align256((size_t)D.nk * D.L * (D.H + 1) * sizeof(cplx<double>));
     // direct and MFMA route partial sums (per band, per chunk and band)
@@ -756,7 +756,8 @@ WsOff ws_offsets(const Derived& D, const Layout& Lo) {
   O.omcnt = Lo.om_cnt;
   // the subtraction's x-power spectra, model spectrum and filters reuse the U region
   O.Uq = Lo.U;
-  O.Mh = O.Uq + align256((size_t)(D.dk + 1) * D.ny * (D.H + 1) * sizeof(cplx<double>));
+  // (the x-power spectra end at most at sub_xpow_off(dk + 1, .., xp32 = 0))
+  O.Mh = O.Uq + align256(sub_xpow_off(D.dk + 1, D.ny, D.H, 0));
   O.G = O.Mh + align256((size_t)D.ny * (D.H + 1) * sizeof(cplx<double>));
   return O;
 }
@@ -1287,6 +1288,7 @@ int subtract_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld, bool ap
   S.nrowblk = (D.ny + S.rows_per_block - 1) / S.rows_per_block;
   S.sx = 2.0 / (double)(D.nx - 1);
   S.sy = 2.0 / (double)(D.ny - 1);
+  S.xp32 = sizeof(T) == sizeof(float);   // FP32C: x-power spectra p >= 1 as complex64
   for (int i = 0; i < D.nk; ++i) {
     S.kpx[i] = D.kpoly.px[i];
     S.kqy[i] = D.kpoly.qy[i];

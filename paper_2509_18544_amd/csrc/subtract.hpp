@@ -41,20 +41,34 @@ struct SpecParams {
   double sx, sy;
   int8_t kpx[15], kqy[15];
   int8_t bpx[15], bqy[15];
+  int xp32;              // x-power spectra p >= 1 stored as complex64 (FP32C); p = 0 always complex128
 };
+
+// Byte offset of the x-power row spectra of power p in the subtraction's
+// buffer: power 0 as complex128, then powers 1.. as complex64 (xp32) or
+// complex128.  The powers p >= 1 enter the model multiplied by the spatial
+// variation of the kernel, so their FP32 rounding stays well below that of
+// the FP32 images (power 0 is kept in FP64: its rounding would be spread by
+// the inverse transform over every pixel of the row at the full model scale).
+__host__ __device__ inline size_t sub_xpow_off(int p, int ny, int H, int xp32) {
+  if (p == 0) return 0;
+  const size_t row = (size_t)ny * (H + 1);
+  return ((row * sizeof(cplx<double>) + 255) & ~(size_t)255) +
+         (size_t)(p - 1) * row * (xp32 ? sizeof(cplx<float>) : sizeof(cplx<double>));
+}
 
 constexpr int SUB_MAXP = 5;   // x powers of the background polynomial (degree <= 4)
 
 // rows per block of the subtraction's row transforms (a power of two)
 __host__ __device__ constexpr int sub_row_rows(int nmax, int lgh) { return (nmax >> lgh) < 64 ? (nmax >> lgh) : 64; }
 
-// R2C of the rows xh^p R (p = 0..DK) -> Uq[p][y][0..H]
+// R2C of the rows xh^p R (p = 0..DK) -> Uq[p][y][0..H] (layout: sub_xpow_off)
 template <typename T, int THREADS, int NMAX, int LGH>
 __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_kernel(SpecParams P, PairSet PS, WsOff O,
                                                                                      int npow) {
   const int pr = blockIdx.z;
   const T* __restrict__ tmpl = static_cast<const T*>(PS.tmpl[pr]);
-  cplx<double>* __restrict__ Uq = ws_at<cplx<double>>(PS, pr, O.Uq);
+  unsigned char* __restrict__ Ub = ws_at<unsigned char>(PS, pr, O.Uq);
   const cplx<double>* __restrict__ tw = ws_at<const cplx<double>>(PS, pr, O.tw64);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
@@ -102,6 +116,9 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_ke
     __syncthreads();
     fft_run<double, NMAX, THREADS, false, true, true, LGH, 4>(buf, RB, tw, lds, lds);
     __syncthreads();
+    const bool f32 = P.xp32 && p > 0;
+    cplx<double>* __restrict__ Uq = reinterpret_cast<cplx<double>*>(Ub + sub_xpow_off(p, P.ny, H, P.xp32));
+    cplx<float>* __restrict__ Uqf = reinterpret_cast<cplx<float>*>(Uq);
 #pragma unroll 3
     for (int e = tid; e < RB * (H + 1); e += THREADS) {
       const int r = e / (H + 1);
@@ -121,7 +138,11 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void sub_rowfwd_ke
         const cplx<double> o2 = rot90<double, false>(zk - zm);
         out = scale(e2 + twid<double, false>(tw, k << twsx) * o2, 0.5);
       }
-      Uq[((int64_t)p * P.ny + y) * (H + 1) + k] = out;
+      const int64_t o = (int64_t)y * (H + 1) + k;
+      if (f32)
+        Uqf[o] = mk((float)out.x, (float)out.y);
+      else
+        Uq[o] = out;
     }
   }
 }
@@ -225,7 +246,7 @@ template <int W>
 __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P, PairSet PS, WsOff O) {
   const int pr = blockIdx.z;
   // the template's x-power row spectra: this pair's, or those of the pair whose template it shares
-  const cplx<double>* __restrict__ Uq = reinterpret_cast<const cplx<double>*>(PS.tws[pr] + O.Uq);
+  const unsigned char* __restrict__ Ub = PS.tws[pr] + O.Uq;
   const cplx<double>* __restrict__ G = ws_at<const cplx<double>>(PS, pr, O.G);
   cplx<double>* __restrict__ Mh = ws_at<cplx<double>>(PS, pr, O.Mh);
   constexpr int L = 2 * W + 1;
@@ -254,13 +275,23 @@ __global__ __launch_bounds__(64 * SUBC_WAVES) void sub_conv_kernel(SpecParams P,
   int pmax = 0;
   for (int a = 0; a < P.nk; ++a) pmax = max(pmax, (int)P.kpx[a]);
   for (int p = 0; p <= pmax; ++p) {
-    const cplx<double>* Up = Uq + (int64_t)p * P.ny * (H + 1);
+    const bool f32 = P.xp32 && p > 0;
+    const cplx<double>* Up = reinterpret_cast<const cplx<double>*>(Ub + sub_xpow_off(p, P.ny, H, P.xp32));
+    const cplx<float>* Upf = reinterpret_cast<const cplx<float>*>(Up);
     __syncthreads();   // the previous power's rows have been read
     for (int e = tid; e < WINB * 64; e += 64 * SUBC_WAVES) {
       const int r = e >> 6, c = e & 63;
       const int ys = yb - W - SUBC_PADR + r;
       cplx<double> u = mk(0.0, 0.0);
-      if (ys >= 0 && ys < P.ny && kx0 + c <= H) u = Up[(int64_t)ys * (H + 1) + kx0 + c];
+      if (ys >= 0 && ys < P.ny && kx0 + c <= H) {
+        const int64_t o = (int64_t)ys * (H + 1) + kx0 + c;
+        if (f32) {
+          const cplx<float> v = Upf[o];
+          u = mk((double)v.x, (double)v.y);
+        } else {
+          u = Up[o];
+        }
+      }
       win[e] = u;
     }
     __syncthreads();
