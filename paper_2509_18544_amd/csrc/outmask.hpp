@@ -97,7 +97,12 @@ __global__ __launch_bounds__(1024) void om_scan_kernel(OmaskParams P, PairSet PS
   if (tid == 1023) offs[P.ny] = part[1023];
 }
 
-// padded-frame offsets (y + w) * pitch + (x + w) of the excluded pixels of row y, x ascending
+// padded-frame offsets (y + w) * pitch + (x + w) of the excluded pixels of row y, x ascending.
+// A thread takes OM_LPT consecutive pixels of a chunk of 256 OM_LPT (one
+// chunk per row up to 4096 columns): its mask bytes are loaded together, its
+// excluded pixels counted, and a prefix of the counts over the block (lanes by
+// shuffles, then the four waves) places them.
+constexpr int OM_LPT = 16;
 __global__ __launch_bounds__(256) void om_list_kernel(OmaskParams P, PairSet PS, OmaskOff O) {
   const int pr = blockIdx.z;
   const uint8_t* __restrict__ mask = PS.mask[pr];
@@ -106,20 +111,37 @@ __global__ __launch_bounds__(256) void om_list_kernel(OmaskParams P, PairSet PS,
   int* __restrict__ list = ws_at<int>(PS, pr, O.list);
   __shared__ int wsum[4];
   const int y = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint8_t* __restrict__ row = mask + (int64_t)y * P.ld;
   int base = offs[y];
-  for (int x0 = 0; x0 < P.nx; x0 += 256) {
-    const int x = x0 + tid;
-    const bool f = x < P.nx && mask[(int64_t)y * P.ld + x] != 0;
-    const uint64_t bal = __ballot(f);
-    const int below = __popcll(bal & ((1ull << lane) - 1ull));   // excluded lanes before this one
-    if (lane == 0) wsum[wv] = __popcll(bal);
+  for (int x0 = 0; x0 < P.nx; x0 += 256 * OM_LPT) {
+    const int xs = x0 + tid * OM_LPT;
+    uint8_t v[OM_LPT];
+#pragma unroll
+    for (int i = 0; i < OM_LPT; ++i) v[i] = row[min(xs + i, P.nx - 1)];   // clamped, then selected
+    uint32_t bits = 0;
+#pragma unroll
+    for (int i = 0; i < OM_LPT; ++i) bits |= (xs + i < P.nx && v[i] != 0) ? (1u << i) : 0u;
+    const int cnt = __popc(bits);
+    int inc = cnt;   // inclusive prefix over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(inc, d);
+      if (lane >= d) inc += t;
+    }
+    if (lane == 63) wsum[wv] = inc;
     __syncthreads();
     int before = 0;
     for (int k = 0; k < wv; ++k) before += wsum[k];
-    if (f) list[base + before + below] = (y + P.w) * P.pitch + (x + P.w);
     const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __syncthreads();   // wsum is rewritten by the next chunk
+    int at = base + before + inc - cnt;
+    const int o = (y + P.w) * P.pitch + xs + P.w;
+    while (bits != 0) {
+      const int i = __ffs(bits) - 1;
+      bits &= bits - 1;
+      list[at++] = o + i;
+    }
     base += tot;
+    __syncthreads();   // wsum is rewritten by the next chunk
   }
 }
 
