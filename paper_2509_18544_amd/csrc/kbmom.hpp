@@ -37,7 +37,8 @@ namespace sfft {
 
 constexpr int KB_CHUNKS = 128;   // excluded-pixel chunks per pair (fixed grid)
 constexpr int KB_SUB = 64;       // excluded pixels staged in LDS per step
-constexpr int KB_MAX_THREADS = 512;   // lags per block (at most)
+constexpr int KB_MAX_THREADS = 512;   // threads per block (at most)
+constexpr int KB_LPT = 2;              // lags per thread (each staged monomial read feeds both)
 
 struct KbParams {
   int ny, nx, w, L, nk, nb, nkk, nmu;
@@ -77,8 +78,9 @@ __global__ __launch_bounds__(256) void kb_pad_kernel(KbParams P, PairSet PS, WsO
 
 // part[chunk][c][u] = sum over the chunk's excluded pixels z of (G_R R)(z - u) m_c(z),
 // m_c the monomials of degree <= DSUM = DK + DB (graded order).  A thread
-// owns one lag u; the pixels of a step and their monomials are staged in LDS
-// (the monomials padded to an even count, read as pairs).
+// owns KB_LPT lags u (blockDim apart); the pixels of a step and their
+// monomials are staged in LDS (the monomials padded to an even count, read as
+// pairs), and each monomial read serves all the thread's lags.
 template <typename T, int DSUM>
 __global__ __launch_bounds__(KB_MAX_THREADS) void kb_mask_kernel(KbParams P, PairSet PS, WsOff O, OmaskOff M) {
   constexpr int NMU = (DSUM + 1) * (DSUM + 2) / 2;
@@ -93,16 +95,20 @@ __global__ __launch_bounds__(KB_MAX_THREADS) void kb_mask_kernel(KbParams P, Pai
   __shared__ __align__(16) double smo[KB_SUB][NMP];
   const int tid = threadIdx.x;
   const int L2 = P.L * P.L;
-  const int ui = blockIdx.y * blockDim.x + tid;
-  const bool uok = ui < L2;
-  const int uu = min(ui, L2 - 1);
-  const int uy = uu / P.L - P.w, ux = uu % P.L - P.w;
-  const int uoff = uy * P.pitch + ux;   // (z - u) = pix(z) - uoff in the padded frame
+  int ui[KB_LPT], uoff[KB_LPT];   // (z - u) = pix(z) - uoff in the padded frame
+#pragma unroll
+  for (int l = 0; l < KB_LPT; ++l) {
+    ui[l] = (blockIdx.y * KB_LPT + l) * blockDim.x + tid;
+    const int uu = min(ui[l], L2 - 1);
+    uoff[l] = (uu / P.L - P.w) * P.pitch + (uu % P.L - P.w);
+  }
   const int per = (count + KB_CHUNKS - 1) / KB_CHUNKS;
   const int k0 = min(count, (int)blockIdx.x * per), k1 = min(count, k0 + per);
-  double acc[NMU];
+  double acc[KB_LPT][NMU];
 #pragma unroll
-  for (int c = 0; c < NMU; ++c) acc[c] = 0.0;
+  for (int l = 0; l < KB_LPT; ++l)
+#pragma unroll
+    for (int c = 0; c < NMU; ++c) acc[l][c] = 0.0;
   for (int kb = k0; kb < k1; kb += KB_SUB) {
     __syncthreads();   // the previous step's pixels have been read
     if (tid < KB_SUB) {
@@ -125,23 +131,37 @@ __global__ __launch_bounds__(KB_MAX_THREADS) void kb_mask_kernel(KbParams P, Pai
     const int nsub = min(KB_SUB, k1 - kb);
     int j = 0;
     for (; j + 4 <= nsub; j += 4) {
-      double v[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) v[t] = (double)grp[spo[j + t] - uoff];   // zero on the w-strip, excluded, outside
+      double v[4][KB_LPT];
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int c = 0; c < NMU; ++c) acc[c] = fma(v[t], smo[j + t][c], acc[c]);
+        for (int l = 0; l < KB_LPT; ++l) v[t][l] = (double)grp[spo[j + t] - uoff[l]];   // zero on the w-strip, excluded, outside
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < NMU; ++c) {
+          const double m = smo[j + t][c];
+#pragma unroll
+          for (int l = 0; l < KB_LPT; ++l) acc[l][c] = fma(v[t][l], m, acc[l][c]);
+        }
     }
     for (; j < nsub; ++j) {
-      const double v = (double)grp[spo[j] - uoff];
+      double v[KB_LPT];
 #pragma unroll
-      for (int c = 0; c < NMU; ++c) acc[c] = fma(v, smo[j][c], acc[c]);
+      for (int l = 0; l < KB_LPT; ++l) v[l] = (double)grp[spo[j] - uoff[l]];
+#pragma unroll
+      for (int c = 0; c < NMU; ++c) {
+        const double m = smo[j][c];
+#pragma unroll
+        for (int l = 0; l < KB_LPT; ++l) acc[l][c] = fma(v[l], m, acc[l][c]);
+      }
     }
   }
-  if (!uok) return;
 #pragma unroll
-  for (int c = 0; c < NMU; ++c) part[((int64_t)blockIdx.x * NMU + c) * L2 + ui] = acc[c];
+  for (int l = 0; l < KB_LPT; ++l)
+    if (ui[l] < L2)
+#pragma unroll
+      for (int c = 0; c < NMU; ++c) part[((int64_t)blockIdx.x * NMU + c) * L2 + ui[l]] = acc[l][c];
 }
 
 // T[c][u] = sum over the chunks of part[chunk][c][u], chunks in order

@@ -951,9 +951,9 @@ int kb_impl(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
       LAUNCH_CHECK();
     }
   }
-  // one thread per lag, in blocks of whole waves of at most 512 threads
-  const int nth = std::min(KB_MAX_THREADS, ((L2 + 63) / 64) * 64);
-  const dim3 g(KB_CHUNKS, (L2 + nth - 1) / nth, np);
+  // KB_LPT lags per thread, in blocks of whole waves of at most 512 threads
+  const int nth = std::min(KB_MAX_THREADS, ((L2 + KB_LPT * 64 - 1) / (KB_LPT * 64)) * 64);
+  const dim3 g(KB_CHUNKS, (L2 + KB_LPT * nth - 1) / (KB_LPT * nth), np);
   switch (D.dk + D.db) {
 #define KB_CASE(DS)                                                                  \
   case DS:                                                                           \
