@@ -86,11 +86,12 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 //  column buffer and the outcome alternate between two slots, so one barrier
 //  per column suffices: a slot is rewritten two columns later, after every
 //  wave has passed the barrier that follows its last read.
-//  Inverse X = L^{-1} (lane = column c, wave q owns rows 16q..16q+15): at
-//  step j the wave owning row j finishes X[j][.] (times 1 / L[j][j],
-//  computed beforehand) and publishes it; after a barrier every wave
-//  applies X[i][c] -= L[i][j] X[j][c] to its rows i > j, L[i][j] read from
-//  the tile as a broadcast.
+//  Inverse X = L^{-1} on wave 0 alone (the columns are independent, so no
+//  barrier): lane c holds column c in registers; step j finishes X[j][c]
+//  (times 1 / L[j][j], computed beforehand) and applies
+//  X[i][c] -= L[i][j] X[j][c] to the rows i > j, L[i][j] read from the tile
+//  as a broadcast.  Spreading it over the four waves took a barrier per row
+//  and was slower.
 __device__ __forceinline__ int potrf_block64(double (*T)[NB + 1], double* cb0, double* cb1, double* dv, int* sflag,
                                              int nb, double* __restrict__ F, int n, int k0,
                                              double* __restrict__ Linv) {
@@ -136,29 +137,21 @@ __device__ __forceinline__ int potrf_block64(double (*T)[NB + 1], double* cb0, d
     if (r < nb && c <= r) F[(int64_t)(k0 + r) * n + k0 + c] = T[r][c];
   }
   __syncthreads();
-  double x[16];
+  // the inverse on one wave: its columns are independent, so lane c forms
+  // column c by right-looking substitution with no barrier (L read from the
+  // tile as a broadcast); the other waves are done
+  if (q != 0) return 0;
+  double x[NB];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) x[m] = (c0 + m == lane) ? 1.0 : 0.0;
+  for (int i = 0; i < NB; ++i) x[i] = (i == lane) ? 1.0 : 0.0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    double* __restrict__ xr = (j & 1) ? cb1 : cb0;
-    if (q == (j >> 4)) {
-      x[j & 15] *= dv[j];
-      xr[lane] = x[j & 15];
-    }
-    __syncthreads();
-    if (c0 + 15 > j) {
-      const double xj = xr[lane];
+    x[j] *= dv[j];
 #pragma unroll
-      for (int m = 0; m < 16; ++m)
-        if (c0 + m > j) x[m] -= T[c0 + m][j] * xj;
-    }
+    for (int i = j + 1; i < NB; ++i) x[i] -= T[i][j] * x[j];
   }
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int i = c0 + m;
-    Linv[i * NB + lane] = (i < nb && lane < nb) ? x[m] : 0.0;
-  }
+  for (int i = 0; i < NB; ++i) Linv[i * NB + lane] = (i < nb && lane < nb) ? x[i] : 0.0;
   return 0;
 }
 
@@ -259,7 +252,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(const SolveJob* __restrict__ 
 // block per (job, tile).  Both through xcd_remap: an XCD takes a contiguous
 // run of tiles, so tiles of one row I (sharing the panel L_I) and of
 // neighbouring rows find the panels in its L2.
-__global__ __launch_bounds__(256) void syrk_kernel(const SolveJob* __restrict__ jobs, int k, int njobs, int ntile,
+__global__ __launch_bounds__(256, 2) void syrk_kernel(const SolveJob* __restrict__ jobs, int k, int njobs, int ntile,
                                                    int fuse_diag, int npanel, int colonly) {
   __shared__ double A[NB][NB + 1];
   __shared__ double B[NB][NB + 1];
