@@ -170,6 +170,21 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kerne
     good |= ((uint32_t)g0 << (2 * i)) | ((uint32_t)g1 << (2 * i + 1));
     gint |= ((uint32_t)i0 << (2 * i)) | ((uint32_t)i1 << (2 * i + 1));
   }
+  // FP64: the thread's template pairs, read once for all the x-power bases
+  // (in FP32 the 32 registers they take would spill at four waves per SIMD,
+  // so each base reads them again)
+  constexpr bool CACHE_T = sizeof(T) == sizeof(double);
+  T tv[CACHE_T ? NPT : 1][2];
+  if constexpr (CACHE_T) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int e = tid + i * THREADS;
+      const int y = y0 + (e >> LGH);
+      const int x0 = 2 * (e & (H - 1));
+      tv[i][0] = tmpl[offs(y, x0)];
+      tv[i][1] = tmpl[offs(y, x0 + 1)];
+    }
+  }
   for (int b = P.base_lo; b < P.nbase; ++b) {
     __syncthreads();   // the previous base's split has read the buffer
     // packed base rows z(j) = x(2j) + i x(2j+1)
@@ -202,7 +217,14 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 4 : 2) void row_fwd_kerne
         }
         if (kind == 0) {
           const int y = y0 + r;
-          const T t0 = tmpl[offs(y, x0)], t1 = tmpl[offs(y, x0 + 1)];
+          T t0, t1;
+          if constexpr (CACHE_T) {
+            t0 = tv[i][0];
+            t1 = tv[i][1];
+          } else {
+            t0 = tmpl[offs(y, x0)];
+            t1 = tmpl[offs(y, x0 + 1)];
+          }
           z = mk(g0 ? (T)(p0 * (double)t0) : (T)0, g1 ? (T)(p1 * (double)t1) : (T)0);
           if (b == 0 && y < ny) {
             // G_R R itself into the frame padded by w (the template-background
