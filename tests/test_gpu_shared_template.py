@@ -174,3 +174,34 @@ def test_shared_template_graph_replays_equal_eager(mode):
             stream.synchronize()
     finally:
         B.sfft_destroy(h)
+
+
+@pytest.mark.parametrize("mode", [F64, F32C])
+def test_shared_template_wide_kernel(mode):
+    """w = 10: the sharing pairs' template-science windows have 21 lag rows,
+    more than a narrow correlation item takes, so their right-hand-side-only
+    plans use the wide items; the pairs still meet the oracle bar and agree
+    with the unshared batch."""
+    pairs = synth.template_group(34, 112, 3, w=10, dk=1, db=1, nstar=140)
+    tmpl_of = [0, 0, 0]
+    dt = torch.float64 if mode == F64 else torch.float32
+    descs = [B.make_desc(p.sci.shape[0], p.sci.shape[1], p.w, p.dk, p.db, mode) for p in pairs]
+    S, R, M = _buffers(pairs, tmpl_of, dt)
+    hs = B.sfft_batch_plan_shared(descs, tmpl_of)
+    hu = B.sfft_batch_plan(descs)
+    try:
+        Cs, Ds, infs = _run(hs, S, R, M, descs)
+        Cu, Du, infu = _run(hu, S, R, M, descs)
+        assert infs == [0] * len(pairs) and infu == [0] * len(pairs)
+        cast = np.float64 if mode == F64 else np.float32
+        tol = 1e-9 if mode == F64 else 1e-5
+        agree = 1e-12 if mode == F64 else 1e-6
+        for i, p in enumerate(pairs):
+            ref = oracle.fit(p.sci.astype(cast).astype(np.float64), p.tmpl.astype(cast).astype(np.float64),
+                             p.mask, p.w, p.dk, p.db)
+            assert oracle.rel_err(Cs[i], ref["theta"]) <= tol, i
+            assert oracle.rel_err(Ds[i], ref["diff"]) <= tol, i
+            assert oracle.rel_err(Cs[i], Cu[i]) <= agree, i
+    finally:
+        B.sfft_destroy(hs)
+        B.sfft_destroy(hu)
