@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void om_syrk_kernel(OmaskParams P, PairSet PS,
   double* __restrict__ omega = ws_at<double>(PS, pr, O.omega);
   if (count == 0) return;
   __shared__ double A[NB][NB + 1], B[NB][NB + 1];
-  __shared__ int pix[OM_KC];
+  __shared__ int pix[2][OM_KC];
   // tile (ti, tj), ti >= tj, from the block index t = ti (ti + 1) / 2 + tj
   const int t = blockIdx.x;
   int ti = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -182,29 +182,51 @@ __global__ __launch_bounds__(256) void om_syrk_kernel(OmaskParams P, PairSet PS,
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc[a][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < count; k0 += OM_KC) {
-    __syncthreads();   // the previous chunk's tiles have been read
-    if (tid < OM_KC) pix[tid] = k0 + tid < count ? list[k0 + tid] : -1;
-    __syncthreads();
-    // every load is issued before any is stored (clamped to pixel 0 of the
-    // chunk, then selected)
-    double va[OM_KC / 4], vb[OM_KC / 4];
+  // Chunk c's gathers are issued while the matrix cores work on chunk c - 1
+  // (registers va, vb), and the pixel list is staged two chunks ahead in a
+  // double buffer, so the scattered loads overlap the products.
+  const int nch = (count + OM_KC - 1) / OM_KC;
+  double va[OM_KC / 4], vb[OM_KC / 4];
+  auto stage_pix = [&](int c, int* dst) {
+    if (tid < OM_KC) {
+      const int k = c * OM_KC + tid;
+      dst[tid] = k < count ? list[k] : -1;
+    }
+  };
+  auto gather = [&](const int* px) {
+    // every load is issued before any is used (clamped to pixel 0 of the chunk)
 #pragma unroll
     for (int m = 0; m < OM_KC / 4; ++m) {
-      const int k = kq + 4 * m;
-      const int p = pix[k];
-      const int64_t q = p >= 0 ? p : pix[0];
+      const int p = px[kq + 4 * m];
+      const int64_t q = p >= 0 ? p : px[0];
       va[m] = Ap[offA + q];
       vb[m] = Ap[offB + q];
     }
+  };
+  stage_pix(0, pix[0]);
+  if (nch > 1) stage_pix(1, pix[1]);
+  __syncthreads();
+  gather(pix[0]);
+  for (int c = 0; c < nch; ++c) {
+    const int* px = pix[c & 1];
+    __syncthreads();   // the previous chunk's tiles have been read; pix[(c + 1) & 1] is staged
 #pragma unroll
     for (int m = 0; m < OM_KC / 4; ++m) {
       const int k = kq + 4 * m;
-      const bool live = pix[k] >= 0;
+      const bool live = px[k] >= 0;
       A[r][k] = (live && okA) ? va[m] : 0.0;
       B[r][k] = (live && okB) ? vb[m] : 0.0;
     }
     __syncthreads();
+    // chunk c + 2's list entry is loaded before the gathers and stored after
+    // the products, so that waiting for it does not wait for them
+    const bool stage = tid < OM_KC && c + 2 < nch;
+    int pnext = -1;
+    if (stage) {
+      const int k = (c + 2) * OM_KC + tid;
+      pnext = k < count ? list[k] : -1;
+    }
+    if (c + 1 < nch) gather(pix[(c + 1) & 1]);
 #pragma unroll 4
     for (int m0 = 0; m0 < OM_KC; m0 += 4) {
       const int kk = m0 + lk;
@@ -215,6 +237,7 @@ __global__ __launch_bounds__(256) void om_syrk_kernel(OmaskParams P, PairSet PS,
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if (stage) pix[c & 1][tid] = pnext;   // chunk c's list is no longer read
   }
   // Omega[i][j] -= acc and, off the diagonal tiles, Omega[j][i] likewise
   // (a diagonal tile holds both triangles itself): every entry once
