@@ -413,6 +413,11 @@ constexpr int CORR_RED_ROWS = 10;   // lag rows per part of the lanes' reduction
 __host__ __device__ constexpr int corr_plane_stride(int c1) {
   return ((c1 * CORR_RS + 12) & ~15) + 9;
 }
+// elements of the staged spectra of nst planes (element size esize), rounded
+// up to a whole 16 bytes: the chunk's FP64 outer twiddles follow them
+__host__ __device__ constexpr int corr_stage_elems(int nst, int per_plane, int esize) {
+  return esize == 16 ? nst * per_plane : ((nst * per_plane + 1) & ~1);
+}
 // complex elements reserved at the start of the correlation kernel's LDS for
 // the per-chunk twiddle steps (njlo x jm), rounded up to 256 bytes
 __host__ __device__ constexpr int corr_step_elems(int njlo, int jm) { return (njlo * jm + 15) & ~15; }
@@ -439,7 +444,10 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
   // The lane reduction at the end of a pass of items overlays the stage only,
   // so the steps survive into the next pass.
   cplx<double>* twstep = reinterpret_cast<cplx<double>*>(smem_raw);   // [njlo][JM]
-  cplx<double>* stage = twstep + corr_step_elems(P.njlo, JM);
+  // the spectra are staged in their input precision (converted to FP64 as
+  // they are read): in FP32C that halves the stage, so a chunk holds more
+  // residues
+  cplx<T>* stage = reinterpret_cast<cplx<T>*>(twstep + corr_step_elems(P.njlo, JM));
   const int kx = blockIdx.x;
   const bool pk = kx == 0;                     // the DC and Nyquist columns, packed
   const int H = P.H;
@@ -456,7 +464,7 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
   const int nst = pk ? 2 * P.nstaged : P.nstaged;   // staged planes (block 0: column 0, then column H)
   const int per_plane = corr_plane_stride(C);
   // outer twiddles e^{2 pi i k1 (jlo + t)/Py} of the chunk, per distinct jlo, after the spectra
-  cplx<double>* twc = stage + nst * per_plane;              // [njlo][C][JM]
+  cplx<double>* twc = reinterpret_cast<cplx<double>*>(stage + corr_stage_elems(nst, per_plane, (int)sizeof(cplx<T>)));   // [njlo][C][JM]
   // e^{2 pi i C j / Py}: advancing k1 by one chunk multiplies each outer twiddle by it
   for (int e = tid; e < P.njlo * JM; e += THREADS) {
     const int ji = e / JM, t = e - ji * JM;
@@ -526,9 +534,9 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
           if (e < ntot) {
             const int pl = plane_of(e);
             const int o = 2 * (e - pl * npr);
-            cplx<double>* dst = stage + pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1));
-            dst[0] = mk((double)q[b][0].x, (double)q[b][0].y);
-            dst[1] = mk((double)q[b][1].x, (double)q[b][1].y);
+            cplx<T>* dst = stage + pl * per_plane + (o >> LG_P2) * CORR_RS + (o & (P2 - 1));
+            dst[0] = q[b][0];
+            dst[1] = q[b][1];
           }
         }
       }
@@ -558,17 +566,18 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
       asm volatile("" : "+v"(tl));
       for (int c = (tl & 63) % lanes; c < nc; c += lanes) {
         const int k1 = k1c + c;
-        const cplx<double>* xa = stage + it.left * per_plane + c * CORR_RS;
-        const cplx<double>* xb = stage + it.right * per_plane + c * CORR_RS;
+        const cplx<T>* xa = stage + it.left * per_plane + c * CORR_RS;
+        const cplx<T>* xb = stage + it.right * per_plane + c * CORR_RS;
+        auto d64 = [](cplx<T> v) { return mk((double)v.x, (double)v.y); };
         cplx<double> z[P2];
 #pragma unroll
-        for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(xa[k2], xb[k2]);
+        for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(d64(xa[k2]), d64(xb[k2]));
         if (pk) {
           // + i Z_H: the Nyquist column's product on the imaginary axis
-          const cplx<double>* ya = xa + P.nstaged * per_plane;
-          const cplx<double>* yb = xb + P.nstaged * per_plane;
+          const cplx<T>* ya = xa + P.nstaged * per_plane;
+          const cplx<T>* yb = xb + P.nstaged * per_plane;
 #pragma unroll
-          for (int k2 = 0; k2 < P2; ++k2) z[k2] = z[k2] + rot90<double, true>(cmulc(ya[k2], yb[k2]));
+          for (int k2 = 0; k2 < P2; ++k2) z[k2] = z[k2] + rot90<double, true>(cmulc(d64(ya[k2]), d64(yb[k2])));
         }
         dft16<double, true>(z);
         const cplx<double>* twt = twc + ((int)it.jidx * C + c) * JM;
@@ -587,7 +596,7 @@ __global__ __launch_bounds__(THREADS, 2) void corr_kernel(AsmParams P, PairSet P
     }
     // sum the lanes of each item through LDS, CORR_RED_ROWS lag rows at a time
     // (over the staged spectra, which are dead until the next pass restages them)
-    cplx<double>* red = stage;
+    cplx<double>* red = reinterpret_cast<cplx<double>*>(stage);
     constexpr int HALF = CORR_RED_ROWS;
 #pragma unroll
     for (int h = 0; h < (JM + HALF - 1) / HALF; ++h) {

@@ -852,9 +852,11 @@ int corr_dc_chunk(int C1) { return std::max(1, C1 / 2); }
 size_t corr_lds_bytes(const Derived& D, int C1) {
   const size_t steps = (size_t)corr_step_elems(D.njlo, D.jrows) * sizeof(cplx<double>);
   const int cd = corr_dc_chunk(C1);
-  const size_t stage = ((size_t)D.nstaged * corr_plane_stride(C1) + (size_t)D.njlo * C1 * D.jrows) * sizeof(cplx<double>);
+  const size_t stage = (size_t)corr_stage_elems(D.nstaged, corr_plane_stride(C1), (int)D.csize) * D.csize +
+                       (size_t)D.njlo * C1 * D.jrows * sizeof(cplx<double>);
   const size_t stage_dc =
-      ((size_t)2 * D.nstaged * corr_plane_stride(cd) + (size_t)D.njlo * cd * D.jrows) * sizeof(cplx<double>);
+      (size_t)corr_stage_elems(2 * D.nstaged, corr_plane_stride(cd), (int)D.csize) * D.csize +
+      (size_t)D.njlo * cd * D.jrows * sizeof(cplx<double>);
   const size_t red = (size_t)ASM_THREADS * CORR_RED_ROWS * sizeof(cplx<double>);
   return steps + std::max(std::max(stage, stage_dc), red);
 }
