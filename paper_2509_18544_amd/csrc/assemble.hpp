@@ -960,7 +960,11 @@ __global__ __launch_bounds__(THREADS) void row_win_kernel(AsmParams P, PairSet P
 // mom[y][p]          = sum_x G xh^p,      p in [0, 2DB]
 // mom[y][2DB+1+p]    = sum_x G S xh^p,    p in [0, DB]
 // mom[y][3DB+2+p]    = sum_x G_R R xh^p,  p in [0, DK+DB]   (G_R R: the template side, w-strip excluded)
-template <typename T, int THREADS>
+// Per-row moments, the polynomial degrees DB (background) and DK (kernel)
+// fixed at compile time so that only the powers in use are summed:
+// G xh^p (p <= 2 DB), G S xh^p (p <= DB), G_R R xh^p (p <= DK + DB); the
+// row's count of excluded pixels; a flag for non-finite inputs.
+template <typename T, int THREADS, int DB, int DK>
 __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet PS, WsOff O) {
   const int pr = blockIdx.z;
   const T* __restrict__ sci = static_cast<const T*>(PS.sci[pr]);
@@ -968,16 +972,15 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet P
   const uint8_t* __restrict__ mask = PS.mask[pr];
   double* __restrict__ mom = ws_at<double>(PS, pr, O.mom);
   int* __restrict__ nonfinite = ws_at<int>(PS, pr, O.flags) + 1;
-  constexpr int NG_MAX = 2 * MAX_DEG + 1;
-  constexpr int NS_MAX = MAX_DEG + 1;
-  constexpr int NA_MAX = 2 * MAX_DEG + 1;
-  constexpr int NM = NG_MAX + NS_MAX + NA_MAX;
+  constexpr int NG = 2 * DB + 1;
+  constexpr int NS = DB + 1;
+  constexpr int NA = DK + DB + 1;
+  constexpr int NM = NG + NS + NA;       // the row's moments, in this order (the layout of mom)
+  constexpr int NP = NG > NA ? NG : NA;  // powers of xh in use
   constexpr int NW = THREADS / 64;
   __shared__ double red[NW][NM];
   const int y = blockIdx.x;
   const int tid = threadIdx.x;
-  const int nG = 2 * P.db + 1;
-  const int nS = P.db + 1;
   const bool inty = y >= P.w && y < P.ny - P.w;
   double acc[NM];
 #pragma unroll
@@ -998,10 +1001,10 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet P
     const double xh = (double)x * P.sx - 1.0;
     double pw = 1.0;
 #pragma unroll
-    for (int p = 0; p < NG_MAX; ++p) {
-      acc[p] += g * pw;
-      if (p < NS_MAX) acc[NG_MAX + p] += s * pw;
-      acc[NG_MAX + NS_MAX + p] += r * pw;
+    for (int p = 0; p < NP; ++p) {
+      if (p < NG) acc[p] += g * pw;
+      if (p < NS) acc[NG + p] += s * pw;
+      if (p < NA) acc[NG + NS + p] += r * pw;
       pw *= xh;
     }
   }
@@ -1017,16 +1020,9 @@ __global__ __launch_bounds__(THREADS) void moments_kernel(AsmParams P, PairSet P
   if (tid < NM) {
     double v = 0.0;
     for (int k = 0; k < NW; ++k) v += red[k][tid];
-    const int i = tid;
-    if (i < NG_MAX) {
-      if (i < nG) mom[(int64_t)y * P.nmom + i] = v;
-      // sum_x G is the row's count of good pixels: the rest are excluded
-      if (i == 0) ws_at<int>(PS, pr, O.omcnt)[y] = P.nx - (int)(v + 0.5);
-    } else if (i < NG_MAX + NS_MAX) {
-      if (i - NG_MAX < nS) mom[(int64_t)y * P.nmom + nG + (i - NG_MAX)] = v;
-    } else if (i - NG_MAX - NS_MAX < P.na) {
-      mom[(int64_t)y * P.nmom + nG + nS + (i - NG_MAX - NS_MAX)] = v;
-    }
+    mom[(int64_t)y * P.nmom + tid] = v;
+    // sum_x G is the row's count of good pixels: the rest are excluded
+    if (tid == 0) ws_at<int>(PS, pr, O.omcnt)[y] = P.nx - (int)(v + 0.5);
   }
 }
 

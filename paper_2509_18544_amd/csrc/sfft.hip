@@ -997,7 +997,18 @@ int build_core(sfft_plan_s* p, const PairSet& PS, int np, int64_t ld) {
   clear_nonfinite_kernel<<<dim3(1, 1, np), 64, 0, s>>>(PS, O);
   LAUNCH_CHECK();
   p->timer.begin(SFFT_STAGE_MOMENTS, s);
-  moments_kernel<T, ASM_THREADS><<<dim3(D.ny, 1, np), ASM_THREADS, 0, s>>>(A, PS, O);
+  switch (D.db * (MAX_DEG + 1) + D.dk) {
+#define MOM_CASE(DBV, DKV)                                                                        \
+  case DBV * (MAX_DEG + 1) + DKV:                                                                 \
+    moments_kernel<T, ASM_THREADS, DBV, DKV><<<dim3(D.ny, 1, np), ASM_THREADS, 0, s>>>(A, PS, O); \
+    break;
+#define MOM_ROW(DBV) MOM_CASE(DBV, 0) MOM_CASE(DBV, 1) MOM_CASE(DBV, 2) MOM_CASE(DBV, 3) MOM_CASE(DBV, 4)
+    MOM_ROW(0) MOM_ROW(1) MOM_ROW(2) MOM_ROW(3) MOM_ROW(4)
+#undef MOM_ROW
+#undef MOM_CASE
+    default:
+      return SFFT_EINVAL;
+  }
   LAUNCH_CHECK();
   p->timer.end(s);
 
